@@ -1,0 +1,213 @@
+/*
+ * libgs - the photorealistic-mapping hot path of Photo-SLAM (Huang et al.,
+ * CVPR 2024, arXiv 2311.16728) for AMD Instinct MI355X (gfx950).
+ *
+ * The mapper optimises a map of 3D Gaussian primitives (position, rotation,
+ * scale, density and spherical-harmonic colour; Section 3.1) by rendering
+ * keyframes with a tile-based rasteriser (Section 3.3, Eq. 3), scoring them
+ * with the photometric loss of Eq. 4 against a Gaussian pyramid of the
+ * keyframe image (Section 3.4, Eq. 5), back-propagating, and taking a
+ * fixed-learning-rate gradient step (Section 4.1).  Each call below is one
+ * step of that loop; all of them run on the GPU.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Device pointers are marked (device); host pointers (host).  Every device
+ *   buffer is owned by the caller; the library never allocates or frees
+ *   device memory and keeps no state between calls.
+ * - `stream` is a hipStream_t passed as void*.  Calls only enqueue work on it
+ *   (stream-ordered, asynchronous) and never synchronise, so a sequence of
+ *   calls can be captured into a HIP graph.  NULL means the default stream.
+ * - Parameter store `params`: float32 [59][n_cap] (structure of arrays, row r
+ *   of Gaussian g at params[r * n_cap + g]).  Rows 0-2 mean (world, metres),
+ *   3-5 log-scale, 6-9 rotation quaternion (w, x, y, z; need not be
+ *   normalised), 10 opacity logit, 11 + 3k + ch SH coefficient k (0..15) of
+ *   colour channel ch (R, G, B).  Columns n..n_cap-1 are ignored.
+ *   n_cap must be a positive multiple of 64 and n <= n_cap.
+ * - Cameras: pinhole, world-to-camera rotation R (row-major) and translation
+ *   t, +z forward, +y down; pixel (i, j) has its centre at (i, j).
+ * - Images: planar float32 [3][H][W] per target, packed back to back at
+ *   3 * pix_offset floats; per-pixel planes [H][W] at pix_offset.
+ * - Errors: every call validates its arguments on the host and returns a
+ *   non-zero gs_status without enqueuing anything when they are invalid.
+ *   Launch failures return GS_ERR_HIP.  Conditions only the device can see
+ *   (tile-pair buffer overflow) are reported through the device status word
+ *   named in the call.  No C++ exception crosses this interface.
+ */
+#ifndef GS_H
+#define GS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GS_OK = 0,
+    GS_ERR_INVALID_ARGUMENT = 1,
+    GS_ERR_CAPACITY = 2,      /* a buffer is too small for the request */
+    GS_ERR_NOT_SUPPORTED = 3,
+    GS_ERR_HIP = 4
+} gs_status;
+
+/* Bits of the device status word written by gs_bin_sort. */
+#define GS_STATUS_PAIR_OVERFLOW 1u
+
+#define GS_NUM_ROWS 59
+#define GS_TILE 16            /* pixels per tile side */
+
+/* Rasteriser settings.  Defaults (gs_default_settings): alpha_min 1/255,
+ * alpha_max 0.99, t_min 1e-4, znear 0.2, dilation 0.3 px^2, fov_clamp 1.3,
+ * sh_degree 3, batch 256.  A pixel composites a Gaussian iff its opacity
+ * there, o * exp(power), reaches alpha_min; the contribution uses
+ * min(alpha_max, .); compositing stops before the Gaussian that would take
+ * the transmittance below t_min (Eq. 3). */
+typedef struct {
+    float alpha_min, alpha_max, t_min, znear, dilation, fov_clamp;
+    int32_t sh_degree;   /* 0..3 */
+    int32_t batch;       /* Gaussians staged per LDS round: 64, 128 or 256 */
+} gs_settings;
+
+/* A keyframe pose with its level-0 intrinsics and image size. */
+typedef struct {
+    float R[9];
+    float t[3];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+} gs_view;
+
+/* A render target: one pyramid level of one view.  Level l renders at
+ * ceil(size / 2^l) with intrinsics divided by 2^l (Eq. 5).  tile_offset and
+ * pix_offset are filled by gs_targets_layout. */
+typedef struct {
+    int32_t view;        /* index into the view array */
+    int32_t level;       /* pyramid level, 0 = full resolution */
+    int32_t width, height;
+    int32_t tiles_x, tiles_y;
+    int32_t tile_offset; /* first global tile index of this target */
+    int32_t pad0;
+    int64_t pix_offset;  /* first pixel of this target in packed images */
+    float bg[3];         /* background colour */
+    float weight;        /* weight of this target's loss in the total */
+} gs_target;
+
+/* Workspace sizes in bytes (from gs_workspace_query). */
+typedef struct {
+    size_t proj_bytes;   /* per-(view, Gaussian) projection records */
+    size_t sort_bytes;   /* binning + radix sort + tile ranges */
+    size_t accum_bytes;  /* per-(view, Gaussian) 2D gradient accumulators */
+    size_t loss_bytes;   /* loss partial sums and SSIM maps */
+} gs_sizes;
+
+/* Human-readable name of a status code (static string). */
+const char *gs_status_string(gs_status s);
+
+/* Fills *s with the defaults listed above. */
+void gs_default_settings(gs_settings *s);
+
+/* (host) Completes targets[0..n_targets): derives width/height from the
+ * view's size and the level, the tile grid, tile_offset and pix_offset
+ * (targets packed in order).  Writes the totals.  views is host memory. */
+gs_status gs_targets_layout(const gs_view *views, int32_t n_views, gs_target *targets,
+                            int32_t n_targets, int64_t *total_pixels, int32_t *total_tiles);
+
+/* (host) Workspace sizes for a problem: n_cap Gaussian columns, n_views
+ * views, targets (host array, already laid out), pair_cap tile/Gaussian
+ * pairs. */
+gs_status gs_workspace_query(const gs_settings *s, int64_t n_cap, int32_t n_views,
+                             const gs_target *targets, int32_t n_targets, int64_t pair_cap,
+                             gs_sizes *out);
+
+/* Projection (Eq. 3's splat G, Section 3.3): for every view v and Gaussian
+ * g < n, the camera-frame depth, the level-0 2D mean, the undilated 2D
+ * covariance J W Sigma W^T J^T, the opacity sigmoid(raw) and the SH colour
+ * seen from the view's centre (max(0, 0.5 + sum_k Y_k c_k)).  Gaussians with
+ * depth <= znear are marked invalid.  params (device) as above; views
+ * (device) n_views entries; proj_ws (device) proj_bytes. */
+gs_status gs_preprocess(const gs_settings *s, const float *params, int64_t n, int64_t n_cap,
+                        const gs_view *views, int32_t n_views, void *proj_ws, void *stream);
+
+/* Tile binning: for every target, each valid Gaussian whose cutoff ellipse
+ * {alpha >= alpha_min} overlaps a 16x16 tile is paired with that tile; the
+ * pairs are sorted by (target tile, depth, Gaussian index) with a device
+ * radix sort and each tile's range of pairs is recorded.  targets (device,
+ * laid out), total_tiles from gs_targets_layout.  sort_ws (device)
+ * sort_bytes.  d_status (device, uint32): GS_STATUS_PAIR_OVERFLOW is OR-ed in
+ * when the pairs exceed pair_cap (the tile lists are then incomplete; retry
+ * with a larger pair_cap).  d_status is not cleared by the call. */
+gs_status gs_bin_sort(const gs_settings *s, const void *proj_ws, int64_t n, int64_t n_cap,
+                      int32_t n_views, const gs_target *targets, int32_t n_targets,
+                      int32_t total_tiles, void *sort_ws, int64_t pair_cap, uint32_t *d_status,
+                      void *stream);
+
+/* Forward rasterisation (Eq. 3): front-to-back alpha compositing of every
+ * tile's sorted list, one pixel per thread.  proj_ws and sort_ws as filled by
+ * gs_preprocess and gs_bin_sort with the same n_cap, n_views, targets and
+ * pair_cap.  Writes, per target,
+ * out_rgb (device, 3 * total_pixels floats, C + T_final * bg), out_T (device,
+ * total_pixels, final transmittance), out_last (device, total_pixels, one
+ * past the tile-list position of the last composited Gaussian; the backward
+ * restarts from it) and, when not NULL, out_ncontrib (device, total_pixels,
+ * number of composited Gaussians). */
+gs_status gs_render_fwd(const gs_settings *s, const void *proj_ws, int64_t n_cap,
+                        int32_t n_views, const void *sort_ws, int64_t pair_cap,
+                        const gs_target *targets,
+                        int32_t n_targets, int32_t total_tiles, float *out_rgb, float *out_T,
+                        int32_t *out_last, int32_t *out_ncontrib, void *stream);
+
+/* Backward of Eq. 3 through the projection to the raw parameters.
+ * The rasteriser pass recomputes compositing back to front from out_T and
+ * out_last (no per-pixel lists are stored) and accumulates per-(view,
+ * Gaussian) 2D gradients in accum_ws (device, accum_bytes; cleared by this
+ * call); the per-Gaussian pass applies the chain rule through the 2D
+ * covariance, projection, rotation/scale, opacity sigmoid and SH basis and
+ * ADDS the result to grad (device, [59][n_cap]).  dL_drgb (device) has the
+ * layout of out_rgb. */
+gs_status gs_render_bwd(const gs_settings *s, const float *params, int64_t n, int64_t n_cap,
+                        const gs_view *views, int32_t n_views, const void *proj_ws,
+                        const void *sort_ws, int64_t pair_cap, const gs_target *targets,
+                        int32_t n_targets, int32_t total_tiles, const float *out_T,
+                        const int32_t *out_last, const float *dL_drgb, void *accum_ws,
+                        float *grad, void *stream);
+
+/* Gaussian pyramid of one planar image (Section 3.4): level l+1 is level l
+ * smoothed by the 5x5 binomial kernel (1 4 6 4 1)^2/256 with mirrored
+ * borders (edge sample not repeated) and decimated to even rows and columns,
+ * sizes ceil(H/2) x ceil(W/2).  img (device) [C][H][W]; out (device) receives
+ * levels 0..levels-1 packed back to back (level 0 is a copy). */
+gs_status gs_pyramid_build(const float *img, int32_t C, int32_t H, int32_t W, int32_t levels,
+                           float *out, void *stream);
+
+/* Photometric loss of Eq. 4 for every target:
+ *   L_t = (1 - lambda) mean|I_r - I_gt| + lambda (1 - mean SSIM(I_r, I_gt)),
+ * SSIM with an 11x11 Gaussian window (sigma 1.5) and zero padding, per
+ * channel, C1 = 0.01^2, C2 = 0.03^2.  render, target (device) packed like
+ * out_rgb.  Writes d_loss (device, n_targets floats, L_t) and d_total
+ * (device, 1 float, sum_t weight_t L_t) and dL_drender (device, like render,
+ * the gradient of the total).  loss_ws (device) loss_bytes. */
+gs_status gs_pyramid_loss(const float *render, const float *target, const gs_target *targets,
+                          int32_t n_targets, int32_t total_tiles, int64_t total_pixels,
+                          float lambda, void *loss_ws, float *d_loss, float *d_total,
+                          float *dL_drender, void *stream);
+
+/* Adam step on the parameter store (Section 4.1 fixed learning rate; torch's
+ * bias-corrected update): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr[row] * (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ * params, grad, m, v (device) [59][n_cap]; lr_rows (host) 59 floats;
+ * beta1, beta2 in [0, 1), eps >= 0 (double so 1 - beta is formed before
+ * rounding); step >= 1.  Only columns < n are updated. */
+gs_status gs_adam_step(float *params, const float *grad, float *m, float *v, int64_t n,
+                       int64_t n_cap, const float *lr_rows, double beta1, double beta2, double eps,
+                       int32_t step, void *stream);
+
+/* Fills dst (device, count floats) with value (a kernel, not a memset, so a
+ * captured graph replays it faithfully). */
+gs_status gs_fill(float *dst, int64_t count, float value, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS_H */

@@ -79,13 +79,18 @@ def _f64(a):
 
 
 def cam_vec(cam: dict) -> np.ndarray:
-    """Flatten a camera dict to the oracle's 21 doubles."""
-    v = np.zeros(21, np.float64)
+    """Flatten a camera dict to the oracle's 23 doubles.
+
+    Optional keys ``tan_half_fov_x``/``tan_half_fov_y`` set the field-of-view
+    clamp explicitly (a pyramid level keeps its keyframe's level-0 values)."""
+    v = np.zeros(23, np.float64)
     v[0:9] = np.asarray(cam["R"], np.float64).reshape(9)
     v[9:12] = np.asarray(cam["t"], np.float64)
     v[12:16] = [cam["fx"], cam["fy"], cam["cx"], cam["cy"]]
     v[16:18] = [cam["width"], cam["height"]]
     v[18:21] = np.asarray(cam.get("bg", (0, 0, 0)), np.float64)
+    v[21] = cam.get("tan_half_fov_x", 0.0)
+    v[22] = cam.get("tan_half_fov_y", 0.0)
     return v
 
 

@@ -55,6 +55,7 @@ typedef struct {
     double R[9], t[3], fx, fy, cx, cy;
     int W, H;
     double bg[3];
+    double limx, limy;   /* FOV clamp of the Jacobian, |x/z| <= limx, |y/z| <= limy */
 } cam_t;
 
 typedef struct {
@@ -69,6 +70,10 @@ static cam_t read_cam(const double *c) {
     k.fx = c[12]; k.fy = c[13]; k.cx = c[14]; k.cy = c[15];
     k.W = (int)c[16]; k.H = (int)c[17];
     k.bg[0] = c[18]; k.bg[1] = c[19]; k.bg[2] = c[20];
+    /* c[21], c[22]: half field of view tan used by the clamp (a pyramid level
+     * keeps its keyframe's full-resolution field of view); 0 = from W, H */
+    k.limx = c[21] > 0 ? c[21] : 0.5 * k.W / k.fx;
+    k.limy = c[22] > 0 ? c[22] : 0.5 * k.H / k.fy;
     return k;
 }
 
@@ -202,8 +207,8 @@ static void gauss_forward(const double *P, int64_t ncap, int64_t g, const cam_t 
     /* first-order (EWA) projection with the field-of-view clamp of the Jacobian */
     G->u = G->xc[0] / z;
     G->v = G->xc[1] / z;
-    const double limx = st->fov_clamp * (0.5 * cam->W / cam->fx);
-    const double limy = st->fov_clamp * (0.5 * cam->H / cam->fy);
+    const double limx = st->fov_clamp * cam->limx;
+    const double limy = st->fov_clamp * cam->limy;
     G->ubar = G->u; G->vbar = G->v;
     if (G->u < -limx) { G->ubar = -limx; G->clampx = 1; }
     if (G->u > limx) { G->ubar = limx; G->clampx = 1; }

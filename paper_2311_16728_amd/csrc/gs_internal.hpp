@@ -1,0 +1,189 @@
+// Internal definitions shared by the libgs HIP sources (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gs.h"
+
+namespace gs {
+
+constexpr int kWave = 64;
+constexpr int kRows = GS_NUM_ROWS;
+constexpr int kTile = GS_TILE;
+constexpr int kTilePix = kTile * kTile;          // 256 pixels, one thread each
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;   // 4096 elements per block
+constexpr int kRadixBits = 8;
+constexpr int kRadixBins = 1 << kRadixBits;
+
+static inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ---------------------------------------------------------------------------
+// Workspace layouts.  All sub-buffers are 256-byte aligned.
+// ---------------------------------------------------------------------------
+struct ProjLayout {
+    size_t mean, cov_o, rgb_z, bytes;   // double2, float4, float4 per record
+    static ProjLayout make(int64_t records) {
+        ProjLayout L;
+        size_t o = 0;
+        L.mean = o;  o = align_up(o + sizeof(double) * 2 * records, 256);
+        L.cov_o = o; o = align_up(o + sizeof(float) * 4 * records, 256);
+        L.rgb_z = o; o = align_up(o + sizeof(float) * 4 * records, 256);
+        L.bytes = o;
+        return L;
+    }
+};
+
+struct Proj {
+    double2 *mean;   // level-0 2D mean (pixels), kept in FP64 so that pixel
+                     // offsets staged relative to a tile carry ~1e-6 px error
+    float4 *cov_o;   // undilated 2D covariance (s00, s01, s11) and opacity
+    float4 *rgb_z;   // colour and camera depth (depth <= 0 marks invalid)
+};
+
+static inline Proj proj_at(void *ws, int64_t records) {
+    ProjLayout L = ProjLayout::make(records);
+    char *b = static_cast<char *>(ws);
+    return Proj{reinterpret_cast<double2 *>(b + L.mean), reinterpret_cast<float4 *>(b + L.cov_o),
+                reinterpret_cast<float4 *>(b + L.rgb_z)};
+}
+
+// Counters at the head of the sort workspace.
+enum Counter { kVisible = 0, kPairs = 1, kPairsClamped = 2, kNumCounters = 16 };
+
+struct SortLayout {
+    size_t counters, counts, vis_key0, vis_key1, vis_val0, vis_val1, vis_off, pair_key0,
+        pair_key1, pair_val0, pair_val1, ranges, bsum, hist, digit, bytes;
+    int64_t sources, pair_cap, max_blocks;
+    static SortLayout make(int64_t sources, int64_t pair_cap, int64_t total_tiles) {
+        SortLayout L;
+        L.sources = sources;
+        L.pair_cap = pair_cap;
+        int64_t big = sources > pair_cap ? sources : pair_cap;
+        L.max_blocks = (big + kScanTile - 1) / kScanTile + 1;
+        size_t o = 0;
+        auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
+        L.counters = take(sizeof(uint32_t) * kNumCounters);
+        L.counts = take(sizeof(uint32_t) * sources);
+        L.vis_key0 = take(sizeof(uint32_t) * sources);
+        L.vis_key1 = take(sizeof(uint32_t) * sources);
+        L.vis_val0 = take(sizeof(uint32_t) * sources);
+        L.vis_val1 = take(sizeof(uint32_t) * sources);
+        L.vis_off = take(sizeof(uint32_t) * (sources + 1));
+        L.pair_key0 = take(sizeof(uint32_t) * pair_cap);
+        L.pair_key1 = take(sizeof(uint32_t) * pair_cap);
+        L.pair_val0 = take(sizeof(uint32_t) * pair_cap);
+        L.pair_val1 = take(sizeof(uint32_t) * pair_cap);
+        L.ranges = take(sizeof(uint32_t) * 2 * (total_tiles > 0 ? total_tiles : 1));
+        L.bsum = take(sizeof(uint32_t) * (L.max_blocks + 1));
+        L.hist = take(sizeof(uint32_t) * kRadixBins * L.max_blocks);
+        L.digit = take(sizeof(uint32_t) * (kRadixBins + 1));
+        L.bytes = o;
+        return L;
+    }
+};
+
+// Number of 8-bit radix passes that order global tile indices < total_tiles.
+static inline int tile_sort_passes(int32_t total_tiles) {
+    int bits = 1;
+    while ((int64_t(1) << bits) < total_tiles) ++bits;
+    return (bits + kRadixBits - 1) / kRadixBits;
+}
+
+// Sorted pair buffers after binning: the tile sort ends in buffer (passes & 1).
+struct Sorted {
+    const uint32_t *pair_val;   // source index t * n_cap + g, per pair
+    const uint2 *ranges;        // [start, end) of each global tile
+};
+
+static inline Sorted sorted_at(const void *ws, int64_t sources, int64_t pair_cap,
+                               int32_t total_tiles) {
+    SortLayout L = SortLayout::make(sources, pair_cap, total_tiles);
+    const char *b = static_cast<const char *>(ws);
+    int passes = tile_sort_passes(total_tiles);
+    size_t val = (passes & 1) ? L.pair_val1 : L.pair_val0;
+    return Sorted{reinterpret_cast<const uint32_t *>(b + val),
+                  reinterpret_cast<const uint2 *>(b + L.ranges)};
+}
+
+// Per-(view, Gaussian) accumulators of 2D gradients, 9 rows of `records`:
+// d mean x, d mean y (level-0 pixels), d cov00, d cov01, d cov11 (undilated
+// level-0 covariance, symmetric-matrix entries), d opacity, d r, d g, d b.
+constexpr int kAccRows = 9;
+static inline size_t accum_bytes(int64_t records) {
+    return align_up(sizeof(float) * kAccRows * records, 256);
+}
+
+// Loss workspace: per-tile partial sums (L1, SSIM) and three SSIM partial maps
+// per pixel and channel.
+struct LossLayout {
+    size_t partial, maps, bytes;
+    static LossLayout make(int64_t total_pixels, int64_t total_tiles) {
+        LossLayout L;
+        size_t o = 0;
+        L.partial = o; o = align_up(o + sizeof(float) * 2 * (total_tiles > 0 ? total_tiles : 1), 256);
+        L.maps = o;    o = align_up(o + sizeof(float) * 9 * total_pixels, 256);
+        L.bytes = o;
+        return L;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0));
+}
+
+// Number of set bits of mask below this lane.
+__device__ __forceinline__ int mask_rank(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0));
+}
+
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        uint32_t u = __shfl_up(v, d, kWave);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+// Exclusive scan over a 256-thread block; returns the prefix of this thread
+// and writes the block total to *total.  lds needs 4 + 1 words.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *lds,
+                                                         uint32_t *total) {
+    const int lane = lane_id();
+    const int wave = threadIdx.x / kWave;
+    uint32_t inc = wave_inclusive_scan(v);
+    if (lane == kWave - 1) lds[wave] = inc;
+    __syncthreads();
+    uint32_t base = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / kWave; ++w) {
+        uint32_t s = lds[w];
+        base += (w < wave) ? s : 0u;
+        all += s;
+    }
+    __syncthreads();
+    *total = all;
+    return base + inc - v;
+}
+
+}  // namespace gs
+
+#define GS_CHECK_LAUNCH()                                   \
+    do {                                                    \
+        if (hipGetLastError() != hipSuccess) return GS_ERR_HIP; \
+    } while (0)

@@ -1,0 +1,313 @@
+// Gaussian pyramid (Section 3.4) and the photometric loss of Eq. 4 with its
+// gradient, over every render target at once.
+//
+// The loss uses the same 16x16 tiling as the rasteriser: one 256-thread
+// workgroup per tile stages the tile plus a 5-pixel halo of render and target
+// in LDS, runs the separable 11-tap Gaussian window horizontally then
+// vertically for the five SSIM moments, and writes per-pixel partial
+// derivatives of the SSIM map (with respect to the window mean, the second
+// moment and the cross moment).  A second pass filters those three maps with
+// the same (self-adjoint) window and forms dL/dI.  Partial sums are reduced
+// per tile and then per target in a fixed order, so the loss is deterministic.
+#include "gs_internal.hpp"
+
+namespace gs {
+
+constexpr int kR = 5;                       // SSIM window radius (11 taps)
+constexpr int kHalo = kTile + 2 * kR;       // 26
+
+struct Window {
+    float w[2 * kR + 1];
+};
+
+static Window ssim_window() {
+    Window W;
+    double v[2 * kR + 1], s = 0;
+    for (int i = -kR; i <= kR; ++i) {
+        v[i + kR] = std::exp(-double(i * i) / (2.0 * 1.5 * 1.5));
+        s += v[i + kR];
+    }
+    for (int i = 0; i < 2 * kR + 1; ++i) W.w[i] = float(v[i] / s);
+    return W;
+}
+
+__device__ __forceinline__ int find_target_loss(const gs_target *__restrict__ targets, int n,
+                                                int tile) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (targets[mid].tile_offset <= tile) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Loads a (16 + 2R)^2 window of one channel plane into LDS, zero outside.
+__device__ __forceinline__ void load_halo(const float *__restrict__ plane, int W, int H, int x0,
+                                          int y0, float (*dst)[kHalo]) {
+    for (int i = threadIdx.x; i < kHalo * kHalo; i += blockDim.x) {
+        const int yy = i / kHalo, xx = i % kHalo;
+        const int gx = x0 - kR + xx, gy = y0 - kR + yy;
+        dst[yy][xx] = (gx >= 0 && gx < W && gy >= 0 && gy < H) ? plane[int64_t(gy) * W + gx] : 0.f;
+    }
+}
+
+__global__ void __launch_bounds__(256) ssim_fwd_kernel(const float *__restrict__ render,
+                                                       const float *__restrict__ target,
+                                                       const gs_target *__restrict__ targets,
+                                                       int n_targets, Window win,
+                                                       float *__restrict__ maps,
+                                                       float *__restrict__ partial) {
+    __shared__ float sx[kHalo][kHalo];
+    __shared__ float sy[kHalo][kHalo];
+    __shared__ float h[5][kHalo][kTile];
+    __shared__ float red[2][kTilePix / kWave];
+    const float C1 = 0.01f * 0.01f, C2 = 0.03f * 0.03f;
+    const int tile = blockIdx.x, tid = threadIdx.x;
+    const gs_target t = targets[find_target_loss(targets, n_targets, tile)];
+    const int local = tile - t.tile_offset;
+    const int x0 = (local % t.tiles_x) * kTile, y0 = (local / t.tiles_x) * kTile;
+    const int lx = tid % kTile, ly = tid / kTile;
+    const int px = x0 + lx, py = y0 + ly;
+    const bool inside = px < t.width && py < t.height;
+    const int64_t HW = int64_t(t.width) * t.height;
+    const int64_t pix = int64_t(py) * t.width + px;
+    float l1 = 0.f, ss = 0.f;
+    for (int c = 0; c < 3; ++c) {
+        const float *xp = render + 3 * t.pix_offset + c * HW;
+        const float *yp = target + 3 * t.pix_offset + c * HW;
+        __syncthreads();
+        load_halo(xp, t.width, t.height, x0, y0, sx);
+        load_halo(yp, t.width, t.height, x0, y0, sy);
+        __syncthreads();
+        for (int i = tid; i < kHalo * kTile; i += blockDim.x) {
+            const int r = i / kTile, cc = i % kTile;
+            float m1 = 0, m2 = 0, e11 = 0, e22 = 0, e12 = 0;
+#pragma unroll
+            for (int k = 0; k < 2 * kR + 1; ++k) {
+                const float a = sx[r][cc + k], b = sy[r][cc + k], w = win.w[k];
+                m1 = fmaf(w, a, m1);
+                m2 = fmaf(w, b, m2);
+                e11 = fmaf(w, a * a, e11);
+                e22 = fmaf(w, b * b, e22);
+                e12 = fmaf(w, a * b, e12);
+            }
+            h[0][r][cc] = m1; h[1][r][cc] = m2; h[2][r][cc] = e11; h[3][r][cc] = e22; h[4][r][cc] = e12;
+        }
+        __syncthreads();
+        float mx = 0, my = 0, exx = 0, eyy = 0, exy = 0;
+#pragma unroll
+        for (int k = 0; k < 2 * kR + 1; ++k) {
+            const float w = win.w[k];
+            mx = fmaf(w, h[0][ly + k][lx], mx);
+            my = fmaf(w, h[1][ly + k][lx], my);
+            exx = fmaf(w, h[2][ly + k][lx], exx);
+            eyy = fmaf(w, h[3][ly + k][lx], eyy);
+            exy = fmaf(w, h[4][ly + k][lx], exy);
+        }
+        if (inside) {
+            const float vx = exx - mx * mx, vy = eyy - my * my, cxy = exy - mx * my;
+            const float A1 = 2.f * mx * my + C1, A2 = 2.f * cxy + C2;
+            const float B1 = mx * mx + my * my + C1, B2 = vx + vy + C2;
+            const float iB1B2 = 1.f / (B1 * B2);
+            const float S = A1 * A2 * iB1B2;
+            ss += S;
+            l1 += fabsf(sx[ly + kR][lx + kR] - sy[ly + kR][lx + kR]);
+            float *mp = maps + 9 * t.pix_offset + (3 * c) * HW;
+            mp[pix] = 2.f * my * (A2 - A1) * iB1B2 - 2.f * mx * S * (1.f / B1 - 1.f / B2);
+            mp[HW + pix] = -S / B2;
+            mp[2 * HW + pix] = 2.f * A1 * iB1B2;
+        }
+    }
+    l1 = wave_sum(l1);
+    ss = wave_sum(ss);
+    if (lane_id() == 0) { red[0][tid / kWave] = l1; red[1][tid / kWave] = ss; }
+    __syncthreads();
+    if (tid == 0) {
+        float a = 0, b = 0;
+        for (int w = 0; w < kTilePix / kWave; ++w) { a += red[0][w]; b += red[1][w]; }
+        partial[2 * int64_t(tile)] = a;
+        partial[2 * int64_t(tile) + 1] = b;
+    }
+}
+
+__global__ void __launch_bounds__(256) ssim_bwd_kernel(const float *__restrict__ render,
+                                                       const float *__restrict__ target,
+                                                       const gs_target *__restrict__ targets,
+                                                       int n_targets, Window win, float lambda,
+                                                       const float *__restrict__ maps,
+                                                       float *__restrict__ dL) {
+    __shared__ float sm[3][kHalo][kHalo];
+    __shared__ float h[3][kHalo][kTile];
+    const int tile = blockIdx.x, tid = threadIdx.x;
+    const gs_target t = targets[find_target_loss(targets, n_targets, tile)];
+    const int local = tile - t.tile_offset;
+    const int x0 = (local % t.tiles_x) * kTile, y0 = (local / t.tiles_x) * kTile;
+    const int lx = tid % kTile, ly = tid / kTile;
+    const int px = x0 + lx, py = y0 + ly;
+    const bool inside = px < t.width && py < t.height;
+    const int64_t HW = int64_t(t.width) * t.height;
+    const int64_t pix = int64_t(py) * t.width + px;
+    const float inv = 1.f / (3.f * float(HW));
+    for (int c = 0; c < 3; ++c) {
+        const float *mp = maps + 9 * t.pix_offset + (3 * c) * HW;
+        __syncthreads();
+        for (int k = 0; k < 3; ++k) load_halo(mp + k * HW, t.width, t.height, x0, y0, sm[k]);
+        __syncthreads();
+        for (int i = tid; i < kHalo * kTile; i += blockDim.x) {
+            const int r = i / kTile, cc = i % kTile;
+            float a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+            for (int k = 0; k < 2 * kR + 1; ++k) {
+                const float w = win.w[k];
+                a0 = fmaf(w, sm[0][r][cc + k], a0);
+                a1 = fmaf(w, sm[1][r][cc + k], a1);
+                a2 = fmaf(w, sm[2][r][cc + k], a2);
+            }
+            h[0][r][cc] = a0; h[1][r][cc] = a1; h[2][r][cc] = a2;
+        }
+        __syncthreads();
+        float f0 = 0, f1 = 0, f2 = 0;
+#pragma unroll
+        for (int k = 0; k < 2 * kR + 1; ++k) {
+            const float w = win.w[k];
+            f0 = fmaf(w, h[0][ly + k][lx], f0);
+            f1 = fmaf(w, h[1][ly + k][lx], f1);
+            f2 = fmaf(w, h[2][ly + k][lx], f2);
+        }
+        if (inside) {
+            const float x = render[3 * t.pix_offset + c * HW + pix];
+            const float y = target[3 * t.pix_offset + c * HW + pix];
+            const float d = x - y;
+            const float sgn = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
+            const float dssim = f0 + 2.f * x * f1 + y * f2;
+            dL[3 * t.pix_offset + c * HW + pix] =
+                t.weight * inv * ((1.f - lambda) * sgn - lambda * dssim);
+        }
+    }
+}
+
+// One block: per-target means from the tile partials (fixed order), then the
+// weighted total.
+__global__ void __launch_bounds__(256) loss_finalize_kernel(const gs_target *__restrict__ targets,
+                                                            int n_targets, float lambda,
+                                                            const float *__restrict__ partial,
+                                                            float *__restrict__ d_loss,
+                                                            float *__restrict__ d_total) {
+    __shared__ double red[2][kTilePix / kWave];
+    __shared__ double total;
+    if (threadIdx.x == 0) total = 0.0;
+    for (int ti = 0; ti < n_targets; ++ti) {
+        const gs_target t = targets[ti];
+        const int nt = t.tiles_x * t.tiles_y;
+        double a = 0, b = 0;
+        for (int i = threadIdx.x; i < nt; i += blockDim.x) {
+            a += partial[2 * int64_t(t.tile_offset + i)];
+            b += partial[2 * int64_t(t.tile_offset + i) + 1];
+        }
+        a = wave_sum(a);
+        b = wave_sum(b);
+        __syncthreads();
+        if (lane_id() == 0) { red[0][threadIdx.x / kWave] = a; red[1][threadIdx.x / kWave] = b; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double sa = 0, sb = 0;
+            for (int w = 0; w < kTilePix / kWave; ++w) { sa += red[0][w]; sb += red[1][w]; }
+            const double n = 3.0 * double(t.width) * double(t.height);
+            const double L = (1.0 - lambda) * sa / n + lambda * (1.0 - sb / n);
+            if (d_loss) d_loss[ti] = float(L);
+            total += double(t.weight) * L;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && d_total) *d_total = float(total);
+}
+
+// One pyramid level down: 5x5 binomial, reflected borders (edge not repeated),
+// even rows/columns kept.
+__device__ __forceinline__ int refl101(int i, int n) {
+    if (n == 1) return 0;
+    while (i < 0 || i >= n) {
+        if (i < 0) i = -i;
+        if (i >= n) i = 2 * (n - 1) - i;
+    }
+    return i;
+}
+
+__global__ void __launch_bounds__(256) pyr_down_kernel(const float *__restrict__ in, int C, int H, int W,
+                                                       float *__restrict__ out) {
+    const int Ho = (H + 1) / 2, Wo = (W + 1) / 2;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= int64_t(C) * Ho * Wo) return;
+    const int c = int(i / (int64_t(Ho) * Wo));
+    const int rem = int(i - int64_t(c) * Ho * Wo);
+    const int oy = rem / Wo, ox = rem % Wo;
+    const float k[5] = {1.f / 16, 4.f / 16, 6.f / 16, 4.f / 16, 1.f / 16};
+    const float *src = in + int64_t(c) * H * W;
+    float acc = 0.f;
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+        const int yy = refl101(2 * oy + a - 2, H);
+        float row = 0.f;
+#pragma unroll
+        for (int b = 0; b < 5; ++b) row = fmaf(k[b], src[int64_t(yy) * W + refl101(2 * ox + b - 2, W)], row);
+        acc = fmaf(k[a], row, acc);
+    }
+    out[i] = acc;
+}
+
+__global__ void copy_f32_kernel(const float *__restrict__ a, float *__restrict__ b, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+}  // namespace gs
+
+extern "C" gs_status gs_pyramid_build(const float *img, int32_t C, int32_t H, int32_t W,
+                                      int32_t levels, float *out, void *stream) {
+    using namespace gs;
+    if (!img || !out || C <= 0 || H <= 0 || W <= 0 || levels <= 0 || levels > 16)
+        return GS_ERR_INVALID_ARGUMENT;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t n0 = int64_t(C) * H * W;
+    hipLaunchKernelGGL(copy_f32_kernel, dim3((n0 + 255) / 256), dim3(256), 0, st, img, out, n0);
+    const float *prev = out;
+    float *cur = out + n0;
+    int h = H, w = W;
+    for (int l = 1; l < levels; ++l) {
+        const int ho = (h + 1) / 2, wo = (w + 1) / 2;
+        const int64_t no = int64_t(C) * ho * wo;
+        hipLaunchKernelGGL(pyr_down_kernel, dim3((no + 255) / 256), dim3(256), 0, st, prev, C, h, w, cur);
+        prev = cur;
+        cur += no;
+        h = ho;
+        w = wo;
+    }
+    GS_CHECK_LAUNCH();
+    return GS_OK;
+}
+
+extern "C" gs_status gs_pyramid_loss(const float *render, const float *target,
+                                     const gs_target *targets, int32_t n_targets,
+                                     int32_t total_tiles, int64_t total_pixels, float lambda,
+                                     void *loss_ws, float *d_loss, float *d_total,
+                                     float *dL_drender, void *stream) {
+    using namespace gs;
+    if (!render || !target || !targets || !loss_ws || n_targets <= 0 || total_tiles <= 0 ||
+        total_pixels <= 0 || !(lambda >= 0.f && lambda <= 1.f))
+        return GS_ERR_INVALID_ARGUMENT;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    LossLayout L = LossLayout::make(total_pixels, total_tiles);
+    char *b = static_cast<char *>(loss_ws);
+    float *partial = reinterpret_cast<float *>(b + L.partial);
+    float *maps = reinterpret_cast<float *>(b + L.maps);
+    const Window win = ssim_window();
+    hipLaunchKernelGGL(ssim_fwd_kernel, dim3(total_tiles), dim3(kTilePix), 0, st, render, target,
+                       targets, n_targets, win, maps, partial);
+    if (dL_drender)
+        hipLaunchKernelGGL(ssim_bwd_kernel, dim3(total_tiles), dim3(kTilePix), 0, st, render, target,
+                           targets, n_targets, win, lambda, maps, dL_drender);
+    hipLaunchKernelGGL(loss_finalize_kernel, dim3(1), dim3(256), 0, st, targets, n_targets, lambda,
+                       partial, d_loss, d_total);
+    GS_CHECK_LAUNCH();
+    return GS_OK;
+}

@@ -1,0 +1,449 @@
+// Projection of the Gaussian map into views, and its reverse mode.
+//
+// Forward (gs_preprocess): Section 3.3, Eq. 3 -- the splat G of each primitive
+// in a keyframe: camera-frame mean, first-order (EWA) projection of the 3D
+// covariance through the perspective Jacobian, 2D mean, opacity from the
+// density logit, and the colour converted from degree-3 spherical harmonics
+// (Section 3.1).  Backward (launched by gs_render_bwd): the chain rule from the
+// per-view 2D gradients to the raw parameters (position, log-scale,
+// quaternion, opacity logit, SH), summed over views.
+//
+// One thread per Gaussian; the thread loads the Gaussian's 59 parameters once
+// (row-major SoA, so each load instruction is coalesced across the wave) and
+// loops over the views.  Both kernels are HBM-bound: 236 B read per Gaussian
+// plus 40 B written per (view, Gaussian) forward; 236 B read, 36 B of
+// accumulators read per view and 236 B read-modify-written backward.
+#include "gs_internal.hpp"
+
+namespace gs {
+
+struct Cam {
+    float R[9], t[3], C[3];
+    float fx, fy, cx, cy, limx, limy;
+};
+
+__device__ __forceinline__ Cam load_cam(const gs_view &v, float fov_clamp) {
+    Cam c;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) c.R[i] = v.R[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) c.t[i] = v.t[i];
+    // camera centre -R^T t
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        c.C[i] = -(c.R[i] * c.t[0] + c.R[3 + i] * c.t[1] + c.R[6 + i] * c.t[2]);
+    c.fx = v.fx; c.fy = v.fy; c.cx = v.cx; c.cy = v.cy;
+    c.limx = fov_clamp * 0.5f * static_cast<float>(v.width) / v.fx;
+    c.limy = fov_clamp * 0.5f * static_cast<float>(v.height) / v.fy;
+    return c;
+}
+
+// Real SH normalisation constants (orthonormal real basis, degree <= 3).
+struct ShK {
+    float k0, k1, k2a, k2b, k2c, k3a, k3b, k3c, k3d, k3e;
+};
+__device__ __forceinline__ ShK sh_consts() {
+    const float pi = 3.14159265358979323846f;
+    return ShK{0.5f * sqrtf(1.f / pi),          0.5f * sqrtf(3.f / pi),
+               0.5f * sqrtf(15.f / pi),         0.25f * sqrtf(5.f / pi),
+               0.25f * sqrtf(15.f / pi),        0.25f * sqrtf(35.f / (2.f * pi)),
+               0.5f * sqrtf(105.f / pi),        0.25f * sqrtf(21.f / (2.f * pi)),
+               0.25f * sqrtf(7.f / pi),         0.25f * sqrtf(105.f / pi)};
+}
+
+// Y_k(d) for k < 16 (index l*l + l + m); entries beyond the degree are zero.
+__device__ __forceinline__ void sh_eval(int deg, float x, float y, float z, float Y[16]) {
+    const ShK k = sh_consts();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) Y[i] = 0.f;
+    Y[0] = k.k0;
+    if (deg < 1) return;
+    Y[1] = -k.k1 * y;
+    Y[2] = k.k1 * z;
+    Y[3] = -k.k1 * x;
+    if (deg < 2) return;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = k.k2a * x * y;
+    Y[5] = -k.k2a * y * z;
+    Y[6] = k.k2b * (2.f * zz - xx - yy);
+    Y[7] = -k.k2a * x * z;
+    Y[8] = k.k2c * (xx - yy);
+    if (deg < 3) return;
+    Y[9] = -k.k3a * y * (3.f * xx - yy);
+    Y[10] = k.k3b * x * y * z;
+    Y[11] = -k.k3c * y * (4.f * zz - xx - yy);
+    Y[12] = k.k3d * z * (2.f * zz - 3.f * xx - 3.f * yy);
+    Y[13] = -k.k3c * x * (4.f * zz - xx - yy);
+    Y[14] = k.k3e * z * (xx - yy);
+    Y[15] = -k.k3a * x * (xx - 3.f * yy);
+}
+
+// Gradient of sum_k w_k Y_k with respect to the (unnormalised) direction
+// components, as polynomials in x, y, z.
+__device__ __forceinline__ void sh_grad(int deg, float x, float y, float z, const float w[16],
+                                        float g[3]) {
+    const ShK k = sh_consts();
+    g[0] = g[1] = g[2] = 0.f;
+    if (deg < 1) return;
+    g[1] += -k.k1 * w[1];
+    g[2] += k.k1 * w[2];
+    g[0] += -k.k1 * w[3];
+    if (deg < 2) return;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    g[0] += k.k2a * y * w[4];             g[1] += k.k2a * x * w[4];
+    g[1] += -k.k2a * z * w[5];            g[2] += -k.k2a * y * w[5];
+    g[0] += -2.f * k.k2b * x * w[6];      g[1] += -2.f * k.k2b * y * w[6];
+    g[2] += 4.f * k.k2b * z * w[6];
+    g[0] += -k.k2a * z * w[7];            g[2] += -k.k2a * x * w[7];
+    g[0] += 2.f * k.k2c * x * w[8];       g[1] += -2.f * k.k2c * y * w[8];
+    if (deg < 3) return;
+    g[0] += -6.f * k.k3a * x * y * w[9];  g[1] += -3.f * k.k3a * (xx - yy) * w[9];
+    g[0] += k.k3b * y * z * w[10];        g[1] += k.k3b * x * z * w[10];
+    g[2] += k.k3b * x * y * w[10];
+    g[0] += 2.f * k.k3c * x * y * w[11];  g[1] += -k.k3c * (4.f * zz - xx - 3.f * yy) * w[11];
+    g[2] += -8.f * k.k3c * y * z * w[11];
+    g[0] += -6.f * k.k3d * x * z * w[12]; g[1] += -6.f * k.k3d * y * z * w[12];
+    g[2] += k.k3d * (6.f * zz - 3.f * xx - 3.f * yy) * w[12];
+    g[0] += -k.k3c * (4.f * zz - 3.f * xx - yy) * w[13];
+    g[1] += 2.f * k.k3c * x * y * w[13];  g[2] += -8.f * k.k3c * x * z * w[13];
+    g[0] += 2.f * k.k3e * x * z * w[14];  g[1] += -2.f * k.k3e * y * z * w[14];
+    g[2] += k.k3e * (xx - yy) * w[14];
+    g[0] += -3.f * k.k3a * (xx - yy) * w[15];
+    g[1] += 6.f * k.k3a * x * y * w[15];
+}
+
+// Per-Gaussian quantities independent of the view.
+struct Gauss {
+    float mu[3], s[3], q[4], qinv, o;
+    float Rq[9], M[9], Sig[6];   // Sig: 00 01 02 11 12 22
+};
+
+__device__ __forceinline__ void load_gauss(const float *__restrict__ P, int64_t n_cap, int64_t g,
+                                           Gauss &G) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) G.mu[i] = P[(0 + i) * n_cap + g];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) G.s[i] = __expf(P[(3 + i) * n_cap + g]);
+    float q[4], qq = 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { q[i] = P[(6 + i) * n_cap + g]; qq += q[i] * q[i]; }
+    G.qinv = rsqrtf(qq);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) G.q[i] = q[i] * G.qinv;
+    G.o = 1.f / (1.f + __expf(-P[10 * n_cap + g]));
+    const float w = G.q[0], x = G.q[1], y = G.q[2], z = G.q[3];
+    G.Rq[0] = 1.f - 2.f * (y * y + z * z); G.Rq[1] = 2.f * (x * y - w * z); G.Rq[2] = 2.f * (x * z + w * y);
+    G.Rq[3] = 2.f * (x * y + w * z); G.Rq[4] = 1.f - 2.f * (x * x + z * z); G.Rq[5] = 2.f * (y * z - w * x);
+    G.Rq[6] = 2.f * (x * z - w * y); G.Rq[7] = 2.f * (y * z + w * x); G.Rq[8] = 1.f - 2.f * (x * x + y * y);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) G.M[3 * i + j] = G.Rq[3 * i + j] * G.s[j];
+    auto dot3 = [&](int a, int b) {
+        return G.M[3 * a] * G.M[3 * b] + G.M[3 * a + 1] * G.M[3 * b + 1] + G.M[3 * a + 2] * G.M[3 * b + 2];
+    };
+    G.Sig[0] = dot3(0, 0); G.Sig[1] = dot3(0, 1); G.Sig[2] = dot3(0, 2);
+    G.Sig[3] = dot3(1, 1); G.Sig[4] = dot3(1, 2); G.Sig[5] = dot3(2, 2);
+}
+
+// View-dependent projection of one Gaussian.
+struct Proj2 {
+    float xc[3], ub, vb;
+    bool clampx, clampy;
+    float T[6];      // J W, 2x3
+    float cov[3];    // undilated 2D covariance 00 01 11
+    double md[2];    // 2D mean (pixels)
+};
+
+__device__ __forceinline__ bool project(const Gauss &G, const Cam &c, float znear, Proj2 &p) {
+    // Camera-frame mean and 2D mean in FP64: their rounding would otherwise move
+    // every pixel offset of a large image by up to 1e-3 px.
+    double xd[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        xd[i] = double(c.R[3 * i]) * G.mu[0] + double(c.R[3 * i + 1]) * G.mu[1] +
+                double(c.R[3 * i + 2]) * G.mu[2] + double(c.t[i]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) p.xc[i] = float(xd[i]);
+    const float z = p.xc[2];
+    if (!(z > znear)) return false;
+    const double ud = xd[0] / xd[2], vd = xd[1] / xd[2];
+    p.md[0] = double(c.fx) * ud + double(c.cx);
+    p.md[1] = double(c.fy) * vd + double(c.cy);
+    const float iz = 1.f / z;
+    const float u = float(ud), v = float(vd);
+    p.ub = fminf(fmaxf(u, -c.limx), c.limx);
+    p.vb = fminf(fmaxf(v, -c.limy), c.limy);
+    p.clampx = (u < -c.limx) || (u > c.limx);
+    p.clampy = (v < -c.limy) || (v > c.limy);
+    const float J00 = c.fx * iz, J02 = -c.fx * p.ub * iz;
+    const float J11 = c.fy * iz, J12 = -c.fy * p.vb * iz;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        p.T[j] = J00 * c.R[j] + J02 * c.R[6 + j];
+        p.T[3 + j] = J11 * c.R[3 + j] + J12 * c.R[6 + j];
+    }
+    // T Sigma T^T
+    const float *S = G.Sig;
+    float TS[6];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const float a = p.T[3 * r], b = p.T[3 * r + 1], d = p.T[3 * r + 2];
+        TS[3 * r + 0] = a * S[0] + b * S[1] + d * S[2];
+        TS[3 * r + 1] = a * S[1] + b * S[3] + d * S[4];
+        TS[3 * r + 2] = a * S[2] + b * S[4] + d * S[5];
+    }
+    p.cov[0] = TS[0] * p.T[0] + TS[1] * p.T[1] + TS[2] * p.T[2];
+    p.cov[1] = TS[0] * p.T[3] + TS[1] * p.T[4] + TS[2] * p.T[5];
+    p.cov[2] = TS[3] * p.T[3] + TS[4] * p.T[4] + TS[5] * p.T[5];
+    return true;
+}
+
+__global__ void __launch_bounds__(256) preprocess_kernel(gs_settings s, const float *__restrict__ P,
+                                                         int64_t n, int64_t n_cap,
+                                                         const gs_view *__restrict__ views,
+                                                         int32_t n_views, Proj out) {
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    Gauss G;
+    load_gauss(P, n_cap, g, G);
+    float sh[16][3];
+    const int nk = (s.sh_degree + 1) * (s.sh_degree + 1);
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) sh[k][ch] = (k < nk) ? P[(11 + 3 * k + ch) * n_cap + g] : 0.f;
+    for (int v = 0; v < n_views; ++v) {
+        const int64_t r = int64_t(v) * n_cap + g;
+        const Cam c = load_cam(views[v], s.fov_clamp);
+        Proj2 p;
+        if (!project(G, c, s.znear, p)) {
+            out.mean[r] = make_double2(0.0, 0.0);
+            out.cov_o[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+            out.rgb_z[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+            continue;
+        }
+        float d[3] = {G.mu[0] - c.C[0], G.mu[1] - c.C[1], G.mu[2] - c.C[2]};
+        const float dinv = rsqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        float Y[16];
+        sh_eval(s.sh_degree, d[0] * dinv, d[1] * dinv, d[2] * dinv, Y);
+        float rgb[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float acc = 0.5f;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) acc += Y[k] * sh[k][ch];
+            rgb[ch] = fmaxf(acc, 0.f);
+        }
+        out.mean[r] = make_double2(p.md[0], p.md[1]);
+        out.cov_o[r] = make_float4(p.cov[0], p.cov[1], p.cov[2], G.o);
+        out.rgb_z[r] = make_float4(rgb[0], rgb[1], rgb[2], p.xc[2]);
+    }
+}
+
+// Chain rule from the accumulated 2D gradients of every view to the 59 raw
+// parameter gradients (added to grad).
+__global__ void __launch_bounds__(256) project_backward_kernel(
+    gs_settings s, const float *__restrict__ P, int64_t n, int64_t n_cap,
+    const gs_view *__restrict__ views, int32_t n_views, const float *__restrict__ acc,
+    int64_t records, float *__restrict__ grad) {
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    Gauss G;
+    load_gauss(P, n_cap, g, G);
+    const int nk = (s.sh_degree + 1) * (s.sh_degree + 1);
+    float gmu[3] = {0, 0, 0}, gs_[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gop = 0.f;
+    float gsh[16][3];
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) gsh[k][ch] = 0.f;
+    float dSig[6] = {0, 0, 0, 0, 0, 0};   // accumulated over views: 00 01 02 11 12 22 (matrix entries)
+    float sh[16][3];
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) sh[k][ch] = (k < nk) ? P[(11 + 3 * k + ch) * n_cap + g] : 0.f;
+
+    for (int v = 0; v < n_views; ++v) {
+        const int64_t r = int64_t(v) * n_cap + g;
+        float a[kAccRows];
+#pragma unroll
+        for (int i = 0; i < kAccRows; ++i) a[i] = acc[i * records + r];
+        bool any = false;
+#pragma unroll
+        for (int i = 0; i < kAccRows; ++i) any |= (a[i] != 0.f);
+        if (!any) continue;
+        const Cam c = load_cam(views[v], s.fov_clamp);
+        Proj2 p;
+        if (!project(G, c, s.znear, p)) continue;
+        const float z = p.xc[2], iz = 1.f / z, iz2 = iz * iz;
+
+        // colour: rgb = max(0, raw), raw = 0.5 + sum_k Y_k(d) sh_k
+        float d[3] = {G.mu[0] - c.C[0], G.mu[1] - c.C[1], G.mu[2] - c.C[2]};
+        const float dinv = rsqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        const float dx = d[0] * dinv, dy = d[1] * dinv, dz = d[2] * dinv;
+        float Y[16];
+        sh_eval(s.sh_degree, dx, dy, dz, Y);
+        float draw[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float raw = 0.5f;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) raw += Y[k] * sh[k][ch];
+            draw[ch] = raw < 0.f ? 0.f : a[6 + ch];
+        }
+        float wk[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            float w = 0.f;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                gsh[k][ch] += Y[k] * draw[ch];
+                w += draw[ch] * sh[k][ch];
+            }
+            wk[k] = w;
+        }
+        float gd[3];
+        sh_grad(s.sh_degree, dx, dy, dz, wk, gd);
+        {   // unit-vector normalisation: (I - d d^T) / |mu - C|
+            const float dot = gd[0] * dx + gd[1] * dy + gd[2] * dz;
+            gmu[0] += (gd[0] - dx * dot) * dinv;
+            gmu[1] += (gd[1] - dy * dot) * dinv;
+            gmu[2] += (gd[2] - dz * dot) * dinv;
+        }
+
+        // 2D covariance cov = T Sigma T^T, T = J W.
+        const float G00 = a[2], G01 = a[3], G11 = a[4];
+        // dL/dSigma = T^T G T
+        {
+            float GT[6];   // G T, 2x3
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                GT[j] = G00 * p.T[j] + G01 * p.T[3 + j];
+                GT[3 + j] = G01 * p.T[j] + G11 * p.T[3 + j];
+            }
+            auto e = [&](int i, int j) { return p.T[i] * GT[j] + p.T[3 + i] * GT[3 + j]; };
+            dSig[0] += e(0, 0); dSig[1] += e(0, 1); dSig[2] += e(0, 2);
+            dSig[3] += e(1, 1); dSig[4] += e(1, 2); dSig[5] += e(2, 2);
+        }
+        // dL/dT = 2 G T Sigma; dL/dJ = dL/dT W^T
+        float TS[6];
+        {
+            const float *S = G.Sig;
+#pragma unroll
+            for (int r2 = 0; r2 < 2; ++r2) {
+                const float a0 = p.T[3 * r2], b0 = p.T[3 * r2 + 1], d0 = p.T[3 * r2 + 2];
+                TS[3 * r2 + 0] = a0 * S[0] + b0 * S[1] + d0 * S[2];
+                TS[3 * r2 + 1] = a0 * S[1] + b0 * S[3] + d0 * S[4];
+                TS[3 * r2 + 2] = a0 * S[2] + b0 * S[4] + d0 * S[5];
+            }
+        }
+        float dT[6];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            dT[j] = 2.f * (G00 * TS[j] + G01 * TS[3 + j]);
+            dT[3 + j] = 2.f * (G01 * TS[j] + G11 * TS[3 + j]);
+        }
+        // T0j = J00 W0j + J02 W2j, T1j = J11 W1j + J12 W2j
+        const float dJ00 = dT[0] * c.R[0] + dT[1] * c.R[1] + dT[2] * c.R[2];
+        const float dJ02 = dT[0] * c.R[6] + dT[1] * c.R[7] + dT[2] * c.R[8];
+        const float dJ11 = dT[3] * c.R[3] + dT[4] * c.R[4] + dT[5] * c.R[5];
+        const float dJ12 = dT[3] * c.R[6] + dT[4] * c.R[7] + dT[5] * c.R[8];
+        float gx[3] = {0.f, 0.f, 0.f};
+        // J00 = fx/z, J11 = fy/z, J02 = -fx ub/z, J12 = -fy vb/z
+        gx[2] += -(dJ00 * c.fx + dJ11 * c.fy) * iz2 + (dJ02 * c.fx * p.ub + dJ12 * c.fy * p.vb) * iz2;
+        if (!p.clampx) {
+            gx[0] += -dJ02 * c.fx * iz2;
+            gx[2] += dJ02 * c.fx * p.xc[0] * iz2 * iz;
+        }
+        if (!p.clampy) {
+            gx[1] += -dJ12 * c.fy * iz2;
+            gx[2] += dJ12 * c.fy * p.xc[1] * iz2 * iz;
+        }
+        // 2D mean (fx x/z + cx, fy y/z + cy)
+        gx[0] += a[0] * c.fx * iz;
+        gx[1] += a[1] * c.fy * iz;
+        gx[2] += -(a[0] * c.fx * p.xc[0] + a[1] * c.fy * p.xc[1]) * iz2;
+        // x_c = W mu + t
+#pragma unroll
+        for (int i = 0; i < 3; ++i) gmu[i] += c.R[i] * gx[0] + c.R[3 + i] * gx[1] + c.R[6 + i] * gx[2];
+        gop += a[5];
+    }
+
+    // Sigma = M M^T, M = Rq diag(s): dM = 2 dSigma M (dSigma symmetric)
+    const float D[9] = {dSig[0], dSig[1], dSig[2], dSig[1], dSig[3], dSig[4], dSig[2], dSig[4], dSig[5]};
+    float dM[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            dM[3 * i + j] = 2.f * (D[3 * i] * G.M[j] + D[3 * i + 1] * G.M[3 + j] + D[3 * i + 2] * G.M[6 + j]);
+    float dR[9];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        float acc_s = 0.f;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            acc_s += dM[3 * i + j] * G.Rq[3 * i + j];
+            dR[3 * i + j] = dM[3 * i + j] * G.s[j];
+        }
+        gs_[j] = acc_s * G.s[j];   // d/d log-scale
+    }
+    {
+        const float w = G.q[0], x = G.q[1], y = G.q[2], z = G.q[3];
+        float dq[4];
+        dq[0] = 2.f * (z * (dR[3] - dR[1]) + y * (dR[2] - dR[6]) + x * (dR[7] - dR[5]));
+        dq[1] = 2.f * (y * (dR[1] + dR[3]) + z * (dR[2] + dR[6]) + w * (dR[7] - dR[5]) -
+                       2.f * x * (dR[4] + dR[8]));
+        dq[2] = 2.f * (x * (dR[1] + dR[3]) + w * (dR[2] - dR[6]) + z * (dR[5] + dR[7]) -
+                       2.f * y * (dR[0] + dR[8]));
+        dq[3] = 2.f * (w * (dR[3] - dR[1]) + x * (dR[2] + dR[6]) + y * (dR[5] + dR[7]) -
+                       2.f * z * (dR[0] + dR[4]));
+        const float dot = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) gq[i] = (dq[i] - G.q[i] * dot) * G.qinv;
+    }
+    float out[kRows];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) out[i] = gmu[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) out[3 + i] = gs_[i];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) out[6 + i] = gq[i];
+    out[10] = gop * G.o * (1.f - G.o);
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) out[11 + 3 * k + ch] = gsh[k][ch];
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) grad[r * n_cap + g] += out[r];
+}
+
+gs_status launch_project_backward(const gs_settings &s, const float *params, int64_t n,
+                                  int64_t n_cap, const gs_view *views, int32_t n_views,
+                                  const float *acc, float *grad, hipStream_t st) {
+    if (n == 0) return GS_OK;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(project_backward_kernel, dim3(blocks), dim3(256), 0, st, s, params, n, n_cap,
+                       views, n_views, acc, int64_t(n_views) * n_cap, grad);
+    GS_CHECK_LAUNCH();
+    return GS_OK;
+}
+
+}  // namespace gs
+
+extern "C" gs_status gs_preprocess(const gs_settings *s, const float *params, int64_t n,
+                                   int64_t n_cap, const gs_view *views, int32_t n_views,
+                                   void *proj_ws, void *stream) {
+    if (!s || !params || !views || !proj_ws || n < 0 || n_cap <= 0 || n > n_cap || n_cap % 64 ||
+        n_views <= 0 || s->sh_degree < 0 || s->sh_degree > 3)
+        return GS_ERR_INVALID_ARGUMENT;
+    if (n == 0) return GS_OK;
+    gs::Proj out = gs::proj_at(proj_ws, int64_t(n_views) * n_cap);
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(gs::preprocess_kernel, dim3(blocks), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), *s, params, n, n_cap, views, n_views, out);
+    GS_CHECK_LAUNCH();
+    return GS_OK;
+}

@@ -1,0 +1,424 @@
+// Tile binning for the tile-based renderer (Section 3.3): every (target,
+// Gaussian) whose cutoff ellipse touches a 16x16 tile becomes a (tile,
+// Gaussian) pair, and each tile's pairs are put in front-to-back order.
+//
+// The order is built in two stable LSD radix sorts instead of one wide-key
+// sort: (1) the visible (target, Gaussian) records are compacted and sorted by
+// their camera depth (32-bit keys, four 8-bit passes over V records); (2) the
+// records emit their pairs in that depth order and the pairs are sorted by
+// global tile index alone (ceil(log2(tiles)/8) passes, two at 1200x680).
+// Because both sorts are stable and records are compacted in (target,
+// Gaussian) order, each tile's list is ordered by (depth, Gaussian index).
+// Pair counts are data dependent; every kernel reads them from device
+// counters so the whole sequence is launch-shape static and graph-capturable.
+#include "gs_internal.hpp"
+
+namespace gs {
+
+// Conservative pixel bounding box of {alpha >= alpha_min} for a record at a
+// pyramid level.  Returns false when the record cannot reach any pixel.
+struct Rect {
+    int x0, x1, y0, y1;   // inclusive tile ranges
+};
+
+__device__ __forceinline__ bool tile_rect(const gs_settings &s, double2 md, float4 cov_o, float z,
+                                          const gs_target &t, Rect &r) {
+    if (!(z > 0.f)) return false;
+    const float o = cov_o.w;
+    if (!(o >= s.alpha_min)) return false;
+    const float sc = ldexpf(1.f, -t.level);
+    const float mx = float(md.x) * sc, my = float(md.y) * sc;
+    const float c00 = cov_o.x * sc * sc + s.dilation;
+    const float c11 = cov_o.z * sc * sc + s.dilation;
+    const float tq = 2.f * logf(o / s.alpha_min);
+    float ex = sqrtf(tq * c00), ey = sqrtf(tq * c11);
+    ex += 0.05f + 1e-3f * ex;
+    ey += 0.05f + 1e-3f * ey;
+    const float fx0 = ceilf(mx - ex), fx1 = floorf(mx + ex);
+    const float fy0 = ceilf(my - ey), fy1 = floorf(my + ey);
+    if (!(fx1 >= 0.f) || !(fy1 >= 0.f) || !(fx0 <= float(t.width - 1)) ||
+        !(fy0 <= float(t.height - 1)) || !(fx0 <= fx1) || !(fy0 <= fy1))
+        return false;
+    const int px0 = max(0, int(fx0)), px1 = min(t.width - 1, int(fx1));
+    const int py0 = max(0, int(fy0)), py1 = min(t.height - 1, int(fy1));
+    r.x0 = px0 / kTile; r.x1 = px1 / kTile;
+    r.y0 = py0 / kTile; r.y1 = py1 / kTile;
+    return true;
+}
+
+// counts[t * n_cap + g] = number of tiles of target t touched by Gaussian g.
+__global__ void __launch_bounds__(256) count_kernel(gs_settings s, Proj proj, int64_t n, int64_t n_cap,
+                                                    const gs_target *__restrict__ targets,
+                                                    uint32_t *__restrict__ counts) {
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int ti = blockIdx.y;
+    if (g >= n_cap) return;
+    uint32_t c = 0;
+    if (g < n) {
+        const gs_target t = targets[ti];
+        const int64_t r = int64_t(t.view) * n_cap + g;
+        Rect rc;
+        if (tile_rect(s, proj.mean[r], proj.cov_o[r], proj.rgb_z[r].w, t, rc))
+            c = uint32_t(rc.x1 - rc.x0 + 1) * uint32_t(rc.y1 - rc.y0 + 1);
+    }
+    counts[int64_t(ti) * n_cap + g] = c;
+}
+
+// ---------------------------------------------------------------------------
+// Block-sum / scan machinery over blocks of kScanTile elements.  Element e of
+// block b is processed in round e / 256 by thread e % 256, so loads are
+// coalesced and the block order is the element order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t active_blocks(uint32_t n) {
+    return (int64_t(n) + kScanTile - 1) / kScanTile;
+}
+
+// Per-block sum of f(e) for e < n; f is a value functor.
+template <typename F>
+__device__ __forceinline__ void block_reduce_to(uint32_t n, uint32_t *bsum, F f) {
+    __shared__ uint32_t lds[8];
+    const int64_t base = int64_t(blockIdx.x) * kScanTile;
+    if (base >= n) return;
+    uint32_t acc = 0;
+#pragma unroll 4
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t e = base + k * kScanThreads + threadIdx.x;
+        if (e < n) acc += f(e);
+    }
+    uint32_t total;
+    block_exclusive_scan(acc, lds, &total);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// Exclusive scan of bsum[0..nb) in place (one block of 1024 threads); the
+// total goes to *total_out.
+__global__ void __launch_bounds__(1024) scan_bsums_kernel(const uint32_t *__restrict__ n_ptr,
+                                                          uint32_t *bsum, uint32_t *total_out,
+                                                          int64_t n_fixed) {
+    __shared__ uint32_t lds[16];
+    const uint32_t n = n_ptr ? *n_ptr : uint32_t(n_fixed);
+    const int64_t nb = active_blocks(n);
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t lo = int64_t(threadIdx.x) * per;
+    uint32_t local = 0;
+    for (int64_t i = lo; i < lo + per && i < nb; ++i) local += bsum[i];
+    // block scan over 1024 threads (16 waves)
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    uint32_t inc = wave_inclusive_scan(local);
+    if (lane == kWave - 1) lds[wave] = inc;
+    __syncthreads();
+    uint32_t wbase = 0, all = 0;
+    for (int w = 0; w < 16; ++w) {
+        const uint32_t v = lds[w];
+        wbase += (w < wave) ? v : 0u;
+        all += v;
+    }
+    uint32_t run = wbase + inc - local;
+    for (int64_t i = lo; i < lo + per && i < nb; ++i) {
+        const uint32_t v = bsum[i];
+        bsum[i] = run;
+        run += v;
+    }
+    if (threadIdx.x == 0) *total_out = all;
+}
+
+// Compaction of visible sources: flags from counts, values = source index,
+// keys = depth bits (positive floats order like their bit patterns).
+__global__ void __launch_bounds__(256) compact_reduce_kernel(const uint32_t *__restrict__ counts,
+                                                             int64_t S, uint32_t *bsum) {
+    block_reduce_to(uint32_t(S), bsum, [&](int64_t e) { return counts[e] ? 1u : 0u; });
+}
+
+__global__ void __launch_bounds__(256) compact_scatter_kernel(const uint32_t *__restrict__ counts,
+                                                              int64_t S, int64_t n_cap,
+                                                              const gs_target *__restrict__ targets,
+                                                              Proj proj, const uint32_t *__restrict__ bsum,
+                                                              uint32_t *__restrict__ vis_key,
+                                                              uint32_t *__restrict__ vis_val) {
+    __shared__ uint32_t lds[8];
+    const int64_t base = int64_t(blockIdx.x) * kScanTile;
+    if (base >= S) return;
+    uint32_t run = bsum[blockIdx.x];
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t e = base + k * kScanThreads + threadIdx.x;
+        const uint32_t f = (e < S && counts[e]) ? 1u : 0u;
+        uint32_t total;
+        const uint32_t pre = block_exclusive_scan(f, lds, &total);
+        if (f) {
+            const int64_t ti = e / n_cap, g = e - ti * n_cap;
+            const int64_t r = int64_t(targets[ti].view) * n_cap + g;
+            vis_key[run + pre] = __float_as_uint(proj.rgb_z[r].w);
+            vis_val[run + pre] = uint32_t(e);
+        }
+        run += total;
+    }
+}
+
+// Exclusive scan of counts[vis_val[j]] over the sorted visible list.
+__global__ void __launch_bounds__(256) offsets_reduce_kernel(const uint32_t *__restrict__ n_ptr,
+                                                             const uint32_t *__restrict__ counts,
+                                                             const uint32_t *__restrict__ vis_val,
+                                                             uint32_t *bsum) {
+    block_reduce_to(*n_ptr, bsum, [&](int64_t e) { return counts[vis_val[e]]; });
+}
+
+__global__ void __launch_bounds__(256) offsets_scatter_kernel(const uint32_t *__restrict__ n_ptr,
+                                                              const uint32_t *__restrict__ counts,
+                                                              const uint32_t *__restrict__ vis_val,
+                                                              const uint32_t *__restrict__ bsum,
+                                                              uint32_t *__restrict__ vis_off) {
+    __shared__ uint32_t lds[8];
+    const uint32_t n = *n_ptr;
+    const int64_t base = int64_t(blockIdx.x) * kScanTile;
+    if (base >= n) return;
+    uint32_t run = bsum[blockIdx.x];
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t e = base + k * kScanThreads + threadIdx.x;
+        const uint32_t c = (e < n) ? counts[vis_val[e]] : 0u;
+        uint32_t total;
+        const uint32_t pre = block_exclusive_scan(c, lds, &total);
+        if (e < n) vis_off[e] = run + pre;
+        run += total;
+    }
+}
+
+// One thread per sorted visible record writes its (tile, source) pairs.
+__global__ void __launch_bounds__(256) emit_kernel(gs_settings s, Proj proj, int64_t n_cap,
+                                                   const gs_target *__restrict__ targets,
+                                                   uint32_t *__restrict__ counters,
+                                                   const uint32_t *__restrict__ vis_val,
+                                                   const uint32_t *__restrict__ vis_off,
+                                                   int64_t pair_cap, uint32_t *__restrict__ pkey,
+                                                   uint32_t *__restrict__ pval,
+                                                   uint32_t *__restrict__ d_status) {
+    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const uint32_t V = counters[kVisible];
+    if (j == 0) {
+        const uint32_t P = counters[kPairs];
+        const bool over = int64_t(P) > pair_cap;
+        counters[kPairsClamped] = over ? uint32_t(pair_cap) : P;
+        if (over && d_status) atomicOr(d_status, GS_STATUS_PAIR_OVERFLOW);
+    }
+    if (j >= V) return;
+    const uint32_t src = vis_val[j];
+    const int64_t ti = src / n_cap, g = src - ti * n_cap;
+    const gs_target t = targets[ti];
+    const int64_t r = int64_t(t.view) * n_cap + g;
+    Rect rc;
+    if (!tile_rect(s, proj.mean[r], proj.cov_o[r], proj.rgb_z[r].w, t, rc)) return;
+    int64_t o = vis_off[j];
+    for (int ty = rc.y0; ty <= rc.y1; ++ty)
+        for (int tx = rc.x0; tx <= rc.x1; ++tx, ++o) {
+            if (o >= pair_cap) return;
+            pkey[o] = uint32_t(t.tile_offset + ty * t.tiles_x + tx);
+            pval[o] = src;
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort pass (8-bit digit at `shift`) over n = *n_ptr pairs.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) radix_hist_kernel(const uint32_t *__restrict__ n_ptr,
+                                                         const uint32_t *__restrict__ keys, int shift,
+                                                         uint32_t *__restrict__ hist,
+                                                         int64_t max_blocks) {
+    __shared__ uint32_t h[kRadixBins];
+    const uint32_t n = *n_ptr;
+    const int64_t base = int64_t(blockIdx.x) * kScanTile;
+    if (base >= n) return;
+    h[threadIdx.x] = 0;
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t e = base + k * kScanThreads + threadIdx.x;
+        if (e < n) atomicAdd(&h[(keys[e] >> shift) & (kRadixBins - 1)], 1u);
+    }
+    __syncthreads();
+    hist[int64_t(threadIdx.x) * max_blocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Block d: exclusive scan of row d of hist over the active blocks; row total
+// to digit[d].
+__global__ void __launch_bounds__(256) radix_rowscan_kernel(const uint32_t *__restrict__ n_ptr,
+                                                            uint32_t *__restrict__ hist,
+                                                            int64_t max_blocks,
+                                                            uint32_t *__restrict__ digit) {
+    __shared__ uint32_t lds[8];
+    const int64_t nb = active_blocks(*n_ptr);
+    uint32_t *row = hist + int64_t(blockIdx.x) * max_blocks;
+    uint32_t run = 0;
+    for (int64_t c = 0; c < nb; c += 256) {
+        const int64_t i = c + threadIdx.x;
+        const uint32_t v = (i < nb) ? row[i] : 0u;
+        uint32_t total;
+        const uint32_t pre = block_exclusive_scan(v, lds, &total);
+        if (i < nb) row[i] = run + pre;
+        run += total;
+    }
+    if (threadIdx.x == 0) digit[blockIdx.x] = run;
+}
+
+__global__ void __launch_bounds__(256) radix_scatter_kernel(
+    const uint32_t *__restrict__ n_ptr, const uint32_t *__restrict__ kin,
+    const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+    int shift, const uint32_t *__restrict__ hist, int64_t max_blocks,
+    const uint32_t *__restrict__ digit) {
+    constexpr int kWaves = kScanThreads / kWave;
+    __shared__ uint32_t off[kRadixBins];
+    __shared__ uint32_t wcnt[kWaves][kRadixBins];
+    __shared__ uint32_t lds[8];
+    const uint32_t n = *n_ptr;
+    const int64_t base = int64_t(blockIdx.x) * kScanTile;
+    if (base >= n) return;
+    const int tid = threadIdx.x, wave = tid / kWave;
+    {
+        uint32_t total;
+        const uint32_t dbase = block_exclusive_scan(digit[tid], lds, &total);
+        off[tid] = dbase + hist[int64_t(tid) * max_blocks + blockIdx.x];
+    }
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t e = base + k * kScanThreads + tid;
+        const bool valid = e < n;
+        uint32_t key = 0, val = 0, d = 0;
+        if (valid) {
+            key = kin[e];
+            val = vin[e];
+            d = (key >> shift) & (kRadixBins - 1);
+        }
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const int rank = mask_rank(peers);
+        if (valid && rank == 0) wcnt[wave][d] = uint32_t(__popcll(peers));
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = off[d] + uint32_t(rank);
+            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) { add += wcnt[w][tid]; wcnt[w][tid] = 0; }
+        off[tid] += add;
+        __syncthreads();
+    }
+}
+
+struct SortBufs {
+    uint32_t *counters, *counts, *vk[2], *vv[2], *voff, *pk[2], *pv[2], *bsum, *hist, *digit;
+    uint2 *ranges;
+    int64_t max_blocks;
+};
+
+static SortBufs sort_bufs(void *ws, int64_t S, int64_t pair_cap, int32_t total_tiles) {
+    SortLayout L = SortLayout::make(S, pair_cap, total_tiles);
+    char *b = static_cast<char *>(ws);
+    auto u = [&](size_t o) { return reinterpret_cast<uint32_t *>(b + o); };
+    SortBufs B;
+    B.counters = u(L.counters);
+    B.counts = u(L.counts);
+    B.vk[0] = u(L.vis_key0); B.vk[1] = u(L.vis_key1);
+    B.vv[0] = u(L.vis_val0); B.vv[1] = u(L.vis_val1);
+    B.voff = u(L.vis_off);
+    B.pk[0] = u(L.pair_key0); B.pk[1] = u(L.pair_key1);
+    B.pv[0] = u(L.pair_val0); B.pv[1] = u(L.pair_val1);
+    B.bsum = u(L.bsum);
+    B.hist = u(L.hist);
+    B.digit = u(L.digit);
+    B.ranges = reinterpret_cast<uint2 *>(b + L.ranges);
+    B.max_blocks = L.max_blocks;
+    return B;
+}
+
+// Sorts (kbuf[cur], vbuf[cur]) in place of the two buffers over `passes`
+// 8-bit digits starting at bit 0; returns the buffer index holding the result.
+static int radix_sort(const uint32_t *n_ptr, uint32_t *kbuf[2], uint32_t *vbuf[2], int cur,
+                      int first_bit, int passes, int64_t blocks, const SortBufs &B,
+                      hipStream_t st) {
+    for (int p = 0; p < passes; ++p) {
+        const int shift = first_bit + p * kRadixBits;
+        hipLaunchKernelGGL(radix_hist_kernel, dim3(blocks), dim3(256), 0, st, n_ptr, kbuf[cur],
+                           shift, B.hist, B.max_blocks);
+        hipLaunchKernelGGL(radix_rowscan_kernel, dim3(kRadixBins), dim3(256), 0, st, n_ptr, B.hist,
+                           B.max_blocks, B.digit);
+        hipLaunchKernelGGL(radix_scatter_kernel, dim3(blocks), dim3(256), 0, st, n_ptr, kbuf[cur],
+                           vbuf[cur], kbuf[cur ^ 1], vbuf[cur ^ 1], shift, B.hist, B.max_blocks,
+                           B.digit);
+        cur ^= 1;
+    }
+    return cur;
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, int64_t count, uint32_t v) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+__global__ void __launch_bounds__(256) ranges_kernel(const uint32_t *__restrict__ counters,
+                                                     const uint32_t *__restrict__ keys,
+                                                     uint2 *__restrict__ ranges) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const uint32_t P = counters[kPairsClamped];
+    if (i >= P) return;
+    const uint32_t k = keys[i];
+    if (i == 0 || keys[i - 1] != k) ranges[k].x = uint32_t(i);
+    if (i == P - 1 || keys[i + 1] != k) ranges[k].y = uint32_t(i + 1);
+}
+
+}  // namespace gs
+
+extern "C" gs_status gs_bin_sort(const gs_settings *s, const void *proj_ws, int64_t n,
+                                 int64_t n_cap, int32_t n_views, const gs_target *targets,
+                                 int32_t n_targets, int32_t total_tiles, void *sort_ws,
+                                 int64_t pair_cap, uint32_t *d_status, void *stream) {
+    using namespace gs;
+    if (!s || !proj_ws || !targets || !sort_ws || n < 0 || n_cap <= 0 || n > n_cap || n_cap % 64 ||
+        n_views <= 0 || n_targets <= 0 || total_tiles <= 0 || pair_cap <= 0 ||
+        pair_cap > 0x7fffffffLL || int64_t(n_targets) * n_cap > 0xffffffffLL)
+        return GS_ERR_INVALID_ARGUMENT;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t S = int64_t(n_targets) * n_cap;
+    SortBufs B = sort_bufs(sort_ws, S, pair_cap, total_tiles);
+    Proj proj = proj_at(const_cast<void *>(proj_ws), int64_t(n_views) * n_cap);
+
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, B.counters, int64_t(kNumCounters), 0u);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((2 * int64_t(total_tiles) + 255) / 256), dim3(256), 0, st,
+                       reinterpret_cast<uint32_t *>(B.ranges), 2 * int64_t(total_tiles), 0u);
+    hipLaunchKernelGGL(count_kernel, dim3((n_cap + 255) / 256, n_targets), dim3(256), 0, st, *s, proj,
+                       n, n_cap, targets, B.counts);
+    // compact visible records
+    const int64_t sblocks = (S + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(compact_reduce_kernel, dim3(sblocks), dim3(256), 0, st, B.counts, S, B.bsum);
+    hipLaunchKernelGGL(scan_bsums_kernel, dim3(1), dim3(1024), 0, st, nullptr, B.bsum,
+                       B.counters + kVisible, S);
+    hipLaunchKernelGGL(compact_scatter_kernel, dim3(sblocks), dim3(256), 0, st, B.counts, S, n_cap,
+                       targets, proj, B.bsum, B.vk[0], B.vv[0]);
+    // depth order (4 passes: result back in buffer 0)
+    int cur = radix_sort(B.counters + kVisible, B.vk, B.vv, 0, 0, 4, sblocks, B, st);
+    // pair offsets in depth order
+    hipLaunchKernelGGL(offsets_reduce_kernel, dim3(sblocks), dim3(256), 0, st, B.counters + kVisible,
+                       B.counts, B.vv[cur], B.bsum);
+    hipLaunchKernelGGL(scan_bsums_kernel, dim3(1), dim3(1024), 0, st, B.counters + kVisible, B.bsum,
+                       B.counters + kPairs, int64_t(0));
+    hipLaunchKernelGGL(offsets_scatter_kernel, dim3(sblocks), dim3(256), 0, st, B.counters + kVisible,
+                       B.counts, B.vv[cur], B.bsum, B.voff);
+    hipLaunchKernelGGL(emit_kernel, dim3(sblocks * (kScanTile / 256)), dim3(256), 0, st, *s, proj, n_cap,
+                       targets, B.counters, B.vv[cur], B.voff, pair_cap, B.pk[0], B.pv[0], d_status);
+    // tile order
+    const int64_t pblocks = (pair_cap + kScanTile - 1) / kScanTile;
+    const int passes = tile_sort_passes(total_tiles);
+    int pc = radix_sort(B.counters + kPairsClamped, B.pk, B.pv, 0, 0, passes, pblocks, B, st);
+    hipLaunchKernelGGL(ranges_kernel, dim3((pair_cap + 255) / 256), dim3(256), 0, st, B.counters,
+                       B.pk[pc], B.ranges);
+    GS_CHECK_LAUNCH();
+    return GS_OK;
+}

@@ -1,0 +1,211 @@
+"""ctypes binding of libgs (the C interface in include/gs.h).
+
+Argument marshalling only: every function here forwards torch device
+pointers and the current HIP stream to the same-named C entry point and turns
+a non-zero status into an exception.  All arithmetic runs in the HIP kernels;
+if libgs.so is missing the import of this module fails.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgs.so")
+
+NUM_ROWS = 59
+TILE = 16
+STATUS_PAIR_OVERFLOW = 1
+
+
+class GsError(RuntimeError):
+    pass
+
+
+class gs_settings(C.Structure):
+    _fields_ = [("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float),
+                ("znear", C.c_float), ("dilation", C.c_float), ("fov_clamp", C.c_float),
+                ("sh_degree", C.c_int32), ("batch", C.c_int32)]
+
+
+class gs_view(C.Structure):
+    _fields_ = [("R", C.c_float * 9), ("t", C.c_float * 3), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class gs_target(C.Structure):
+    _fields_ = [("view", C.c_int32), ("level", C.c_int32), ("width", C.c_int32),
+                ("height", C.c_int32), ("tiles_x", C.c_int32), ("tiles_y", C.c_int32),
+                ("tile_offset", C.c_int32), ("pad0", C.c_int32), ("pix_offset", C.c_int64),
+                ("bg", C.c_float * 3), ("weight", C.c_float)]
+
+
+class gs_sizes(C.Structure):
+    _fields_ = [("proj_bytes", C.c_size_t), ("sort_bytes", C.c_size_t),
+                ("accum_bytes", C.c_size_t), ("loss_bytes", C.c_size_t)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2311_16728_amd.build.build() first")
+    lib = C.CDLL(LIB_PATH)
+    vp, i64, i32, f32 = C.c_void_p, C.c_int64, C.c_int32, C.c_float
+    S, V, T = C.POINTER(gs_settings), C.POINTER(gs_view), C.POINTER(gs_target)
+    sig = {
+        "gs_status_string": ([C.c_int], C.c_char_p),
+        "gs_default_settings": ([S], None),
+        "gs_targets_layout": ([V, i32, T, i32, C.POINTER(C.c_int64), C.POINTER(C.c_int32)], C.c_int),
+        "gs_workspace_query": ([S, i64, i32, T, i32, i64, C.POINTER(gs_sizes)], C.c_int),
+        "gs_preprocess": ([S, vp, i64, i64, vp, i32, vp, vp], C.c_int),
+        "gs_bin_sort": ([S, vp, i64, i64, i32, vp, i32, i32, vp, i64, vp, vp], C.c_int),
+        "gs_render_fwd": ([S, vp, i64, i32, vp, i64, vp, i32, i32, vp, vp, vp, vp, vp], C.c_int),
+        "gs_render_bwd": ([S, vp, i64, i64, vp, i32, vp, vp, i64, vp, i32, i32, vp, vp, vp, vp,
+                           vp, vp], C.c_int),
+        "gs_pyramid_build": ([vp, i32, i32, i32, i32, vp, vp], C.c_int),
+        "gs_pyramid_loss": ([vp, vp, vp, i32, i32, i64, f32, vp, vp, vp, vp, vp], C.c_int),
+        "gs_adam_step": ([vp, vp, vp, vp, i64, i64, C.POINTER(C.c_float), C.c_double, C.c_double,
+                          C.c_double, i32, vp], C.c_int),
+        "gs_fill": ([vp, i64, f32, vp], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_lib = _load()
+EXPORTED = ["gs_status_string", "gs_default_settings", "gs_targets_layout", "gs_workspace_query",
+            "gs_preprocess", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd", "gs_pyramid_build",
+            "gs_pyramid_loss", "gs_adam_step", "gs_fill"]
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise GsError(f"{what}: {_lib.gs_status_string(status).decode()} ({status})")
+
+
+def _p(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise GsError("expected a device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def default_settings(**overrides) -> gs_settings:
+    s = gs_settings()
+    _lib.gs_default_settings(C.byref(s))
+    for k, v in overrides.items():
+        setattr(s, k, v)
+    return s
+
+
+def make_view(cam: dict) -> gs_view:
+    v = gs_view()
+    R = [float(x) for x in list(_flat(cam["R"]))]
+    for i in range(9):
+        v.R[i] = R[i]
+    t = [float(x) for x in list(_flat(cam["t"]))]
+    for i in range(3):
+        v.t[i] = t[i]
+    v.fx, v.fy, v.cx, v.cy = float(cam["fx"]), float(cam["fy"]), float(cam["cx"]), float(cam["cy"])
+    v.width, v.height = int(cam["width"]), int(cam["height"])
+    return v
+
+
+def _flat(a):
+    try:
+        import numpy as np
+
+        return np.asarray(a, dtype=np.float64).reshape(-1)
+    except Exception:  # pragma: no cover
+        return a
+
+
+def gs_targets_layout(views, specs):
+    """specs: list of (view, level, bg(3), weight).  Returns (targets array, total_pixels, total_tiles)."""
+    nv = len(views)
+    varr = (gs_view * nv)(*views)
+    tarr = (gs_target * len(specs))()
+    for i, (view, level, bg, weight) in enumerate(specs):
+        tarr[i].view, tarr[i].level, tarr[i].weight = int(view), int(level), float(weight)
+        for c in range(3):
+            tarr[i].bg[c] = float(bg[c])
+    tp, tt = C.c_int64(), C.c_int32()
+    _check(_lib.gs_targets_layout(varr, nv, tarr, len(specs), C.byref(tp), C.byref(tt)),
+           "gs_targets_layout")
+    return tarr, int(tp.value), int(tt.value)
+
+
+def gs_workspace_query(settings, n_cap, n_views, targets, pair_cap) -> gs_sizes:
+    out = gs_sizes()
+    _check(_lib.gs_workspace_query(C.byref(settings), n_cap, n_views, targets, len(targets),
+                                   pair_cap, C.byref(out)), "gs_workspace_query")
+    return out
+
+
+def to_device_struct_array(arr, device="cuda") -> torch.Tensor:
+    """Copies a ctypes struct array into a device byte tensor."""
+    raw = bytes(C.string_at(C.addressof(arr), C.sizeof(arr)))
+    host = torch.frombuffer(bytearray(raw), dtype=torch.uint8)
+    return host.to(device)
+
+
+def gs_preprocess(settings, params, n, views_dev, n_views, proj_ws, stream=None):
+    _check(_lib.gs_preprocess(C.byref(settings), _p(params), n, params.shape[1], _p(views_dev),
+                              n_views, _p(proj_ws), _stream(stream)), "gs_preprocess")
+
+
+def gs_bin_sort(settings, proj_ws, n, n_cap, n_views, targets_dev, n_targets, total_tiles, sort_ws,
+                pair_cap, status_dev=None, stream=None):
+    _check(_lib.gs_bin_sort(C.byref(settings), _p(proj_ws), n, n_cap, n_views, _p(targets_dev),
+                            n_targets, total_tiles, _p(sort_ws), pair_cap, _p(status_dev),
+                            _stream(stream)), "gs_bin_sort")
+
+
+def gs_render_fwd(settings, proj_ws, n_cap, n_views, sort_ws, pair_cap, targets_dev, n_targets,
+                  total_tiles, out_rgb, out_T, out_last, out_ncontrib=None, stream=None):
+    _check(_lib.gs_render_fwd(C.byref(settings), _p(proj_ws), n_cap, n_views, _p(sort_ws), pair_cap,
+                              _p(targets_dev), n_targets, total_tiles, _p(out_rgb), _p(out_T),
+                              _p(out_last), _p(out_ncontrib), _stream(stream)), "gs_render_fwd")
+
+
+def gs_render_bwd(settings, params, n, views_dev, n_views, proj_ws, sort_ws, pair_cap, targets_dev,
+                  n_targets, total_tiles, out_T, out_last, dL_drgb, accum_ws, grad, stream=None):
+    _check(_lib.gs_render_bwd(C.byref(settings), _p(params), n, params.shape[1], _p(views_dev),
+                              n_views, _p(proj_ws), _p(sort_ws), pair_cap, _p(targets_dev),
+                              n_targets, total_tiles, _p(out_T), _p(out_last), _p(dL_drgb),
+                              _p(accum_ws), _p(grad), _stream(stream)), "gs_render_bwd")
+
+
+def gs_pyramid_build(img, levels, out, stream=None):
+    Cc, H, W = img.shape
+    _check(_lib.gs_pyramid_build(_p(img), Cc, H, W, levels, _p(out), _stream(stream)),
+           "gs_pyramid_build")
+
+
+def gs_pyramid_loss(render, target, targets_dev, n_targets, total_tiles, total_pixels, lam, loss_ws,
+                    d_loss, d_total, dL_drender, stream=None):
+    _check(_lib.gs_pyramid_loss(_p(render), _p(target), _p(targets_dev), n_targets, total_tiles,
+                                total_pixels, lam, _p(loss_ws), _p(d_loss), _p(d_total),
+                                _p(dL_drender), _stream(stream)), "gs_pyramid_loss")
+
+
+def gs_adam_step(params, grad, m, v, n, lr_rows, step, beta1=0.9, beta2=0.999, eps=1e-15,
+                 stream=None):
+    lr = (C.c_float * NUM_ROWS)(*[float(x) for x in lr_rows])
+    _check(_lib.gs_adam_step(_p(params), _p(grad), _p(m), _p(v), n, params.shape[1], lr, beta1,
+                             beta2, eps, step, _stream(stream)), "gs_adam_step")
+
+
+def gs_fill(dst, value, stream=None):
+    _check(_lib.gs_fill(_p(dst), dst.numel(), float(value), _stream(stream)), "gs_fill")

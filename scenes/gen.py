@@ -56,8 +56,9 @@ def pinhole(width: int, height: int, fx: float, fy: float | None = None, cx: flo
     cy = height / 2.0 if cy is None else cy
     R = np.eye(3) if R is None else np.asarray(R, np.float64)
     t = np.zeros(3) if t is None else np.asarray(t, np.float64)
-    return dict(R=R.astype(np.float32), t=t.astype(np.float32), fx=float(fx), fy=float(fy),
-                cx=float(cx), cy=float(cy), width=int(width), height=int(height),
+    f32 = lambda x: float(np.float32(x))   # both consumers see the same float32 values
+    return dict(R=R.astype(np.float32), t=t.astype(np.float32), fx=f32(fx), fy=f32(fy),
+                cx=f32(cx), cy=f32(cy), width=int(width), height=int(height),
                 bg=np.asarray(bg, np.float32))
 
 
@@ -69,7 +70,9 @@ def level_camera(cam: dict, level: int) -> dict:
         w, h = (w + 1) // 2, (h + 1) // 2
     s = 0.5 ** level
     out.update(fx=cam["fx"] * s, fy=cam["fy"] * s, cx=cam["cx"] * s, cy=cam["cy"] * s,
-               width=w, height=h, level=level)
+               width=w, height=h, level=level,
+               tan_half_fov_x=0.5 * cam["width"] / cam["fx"],
+               tan_half_fov_y=0.5 * cam["height"] / cam["fy"])
     return out
 
 

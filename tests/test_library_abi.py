@@ -1,0 +1,93 @@
+"""CPU checks of the C interface: the library loads and exports every entry point
+that include/gs.h declares, host-only helpers behave, and invalid arguments
+are rejected before any device work.  No kernel is launched."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2311_16728_amd", "libgs.so")
+HEADER = os.path.join(ROOT, "include", "gs.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2311_16728_amd import build
+
+        build.build()
+    return C.CDLL(LIB)
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(gs_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 12
+    for nm in names:
+        assert hasattr(lib, nm), nm
+
+
+def test_binding_names_match_header():
+    from paper_2311_16728_amd import gs
+
+    assert sorted(gs.EXPORTED) == declared_functions()
+
+
+def test_default_settings_and_status(lib):
+    from paper_2311_16728_amd import gs
+
+    s = gs.default_settings()
+    assert s.alpha_min == pytest.approx(1 / 255) and s.alpha_max == pytest.approx(0.99)
+    assert s.t_min == pytest.approx(1e-4) and s.sh_degree == 3 and s.batch == 256
+    lib.gs_status_string.restype = C.c_char_p
+    assert lib.gs_status_string(0) == b"ok"
+
+
+def test_targets_layout_offsets():
+    from paper_2311_16728_amd import gs
+    import scenes
+
+    cams = [scenes.pinhole(1200, 680, 600.0), scenes.pinhole(75, 33, 40.0)]
+    views = [gs.make_view(c) for c in cams]
+    specs = [(0, 0, (0, 0, 0), 1.0), (0, 1, (0, 0, 0), 1.0), (0, 2, (0, 0, 0), 1.0),
+             (1, 0, (0, 0, 0), 1.0), (1, 1, (0, 0, 0), 1.0)]
+    t, pix, tiles = gs.gs_targets_layout(views, specs)
+    sizes = [(t[i].width, t[i].height) for i in range(5)]
+    assert sizes == [(1200, 680), (600, 340), (300, 170), (75, 33), (38, 17)]
+    exp_tiles = [75 * 43, 38 * 22, 19 * 11, 5 * 3, 3 * 2]
+    assert [t[i].tiles_x * t[i].tiles_y for i in range(5)] == exp_tiles
+    assert [t[i].tile_offset for i in range(5)] == list(np.cumsum([0] + exp_tiles[:-1]))
+    assert [t[i].pix_offset for i in range(5)] == list(np.cumsum([0] + [w * h for w, h in sizes[:-1]]))
+    assert pix == sum(w * h for w, h in sizes) and tiles == sum(exp_tiles)
+
+
+def test_invalid_arguments_rejected():
+    from paper_2311_16728_amd import gs
+    import scenes
+
+    views = [gs.make_view(scenes.pinhole(64, 64, 64.0))]
+    with pytest.raises(gs.GsError):
+        gs.gs_targets_layout(views, [(1, 0, (0, 0, 0), 1.0)])      # view out of range
+    t, _, _ = gs.gs_targets_layout(views, [(0, 0, (0, 0, 0), 1.0)])
+    s = gs.default_settings()
+    with pytest.raises(gs.GsError):
+        gs.gs_workspace_query(s, 100, 1, t, 1 << 10)                 # n_cap not a multiple of 64
+    sizes = gs.gs_workspace_query(s, 256, 1, t, 1 << 10)
+    assert sizes.proj_bytes >= 40 * 256 and sizes.accum_bytes >= 36 * 256
+    # null device pointers fail validation on the host without touching a GPU
+    lib = gs._lib
+    assert lib.gs_preprocess(C.byref(s), None, 10, 256, None, 1, None, None) == 1
+    assert lib.gs_adam_step(None, None, None, None, 10, 256, None, 0.9, 0.999, 1e-15, 1, None) == 1
+    assert lib.gs_pyramid_build(None, 3, 10, 10, 3, None, None) == 1
+    bad = gs.default_settings(batch=100)
+    assert lib.gs_render_fwd(C.byref(bad), C.c_void_p(1), 256, 1, C.c_void_p(1), 1024, C.c_void_p(1),
+                             1, 16, C.c_void_p(1), C.c_void_p(1), C.c_void_p(1), None, None) == 1
