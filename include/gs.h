@@ -157,20 +157,55 @@ gs_status gs_render_fwd(const gs_settings *s, const void *proj_ws, int64_t n_cap
                         int32_t n_targets, int32_t total_tiles, float *out_rgb, float *out_T,
                         int32_t *out_last, int32_t *out_ncontrib, void *stream);
 
-/* Backward of Eq. 3 through the projection to the raw parameters.
- * The rasteriser pass recomputes compositing back to front from out_T and
- * out_last (no per-pixel lists are stored) and accumulates per-(view,
- * Gaussian) 2D gradients in accum_ws (device, accum_bytes; cleared by this
- * call); the per-Gaussian pass applies the chain rule through the 2D
- * covariance, projection, rotation/scale, opacity sigmoid and SH basis and
- * ADDS the result to grad (device, [59][n_cap]).  dL_drgb (device) has the
- * layout of out_rgb. */
+/* Backward of the rasteriser (reverse mode of Eq. 3 per pixel): recomputes
+ * compositing back to front from out_T and out_last (no per-pixel lists are
+ * stored) and accumulates, per (view, Gaussian), the gradients of the loss
+ * with respect to the 2D mean (level-0 pixels), the undilated 2D covariance
+ * (entries 00, 01, 11 of the symmetric matrix gradient), the opacity and the
+ * colour into accum_ws (device, accum_bytes; float32 [9][n_views * n_cap],
+ * rows in that order; cleared by this call).  dL_drgb (device) has the layout
+ * of out_rgb.  proj_ws, sort_ws, out_T, out_last as left by the forward. */
+gs_status gs_raster_bwd(const gs_settings *s, const void *proj_ws, int64_t n_cap,
+                        int32_t n_views, const void *sort_ws, int64_t pair_cap,
+                        const gs_target *targets, int32_t n_targets, int32_t total_tiles,
+                        const float *out_T, const int32_t *out_last, const float *dL_drgb,
+                        void *accum_ws, void *stream);
+
+/* Chain rule from the per-view 2D gradients in accum_ws to the raw parameters
+ * (through the 2D covariance, projection Jacobian with its field-of-view clamp,
+ * rotation/scale, opacity sigmoid and the SH basis including its view
+ * direction), summed over views and ADDED to grad (device, [59][n_cap]). */
+gs_status gs_project_bwd(const gs_settings *s, const float *params, int64_t n, int64_t n_cap,
+                         const gs_view *views, int32_t n_views, const void *accum_ws, float *grad,
+                         void *stream);
+
+/* gs_project_bwd fused with the Adam step of gs_adam_step: each parameter is
+ * updated in place (params, m, v: device [59][n_cap]) as soon as its gradient
+ * is known, so no gradient buffer is written, read or cleared.  Every column
+ * < n is stepped (Gaussians no view touched get a zero gradient); the result
+ * equals gs_project_bwd into a zeroed gradient followed by gs_adam_step. */
+gs_status gs_project_bwd_adam(const gs_settings *s, float *params, int64_t n, int64_t n_cap,
+                              const gs_view *views, int32_t n_views, const void *accum_ws,
+                              float *m, float *v, const float *lr_rows, double beta1,
+                              double beta2, double eps, int32_t step, void *stream);
+
+/* gs_raster_bwd followed by gs_project_bwd (the full backward to the raw
+ * parameters, ADDED to grad). */
 gs_status gs_render_bwd(const gs_settings *s, const float *params, int64_t n, int64_t n_cap,
                         const gs_view *views, int32_t n_views, const void *proj_ws,
                         const void *sort_ws, int64_t pair_cap, const gs_target *targets,
                         int32_t n_targets, int32_t total_tiles, const float *out_T,
                         const int32_t *out_last, const float *dL_drgb, void *accum_ws,
                         float *grad, void *stream);
+
+/* gs_raster_bwd followed by gs_project_bwd_adam (one optimiser step). */
+gs_status gs_render_bwd_adam(const gs_settings *s, float *params, int64_t n, int64_t n_cap,
+                             const gs_view *views, int32_t n_views, const void *proj_ws,
+                             const void *sort_ws, int64_t pair_cap, const gs_target *targets,
+                             int32_t n_targets, int32_t total_tiles, const float *out_T,
+                             const int32_t *out_last, const float *dL_drgb, void *accum_ws,
+                             float *m, float *v, const float *lr_rows, double beta1, double beta2,
+                             double eps, int32_t step, void *stream);
 
 /* Gaussian pyramid of one planar image (Section 3.4): level l+1 is level l
  * smoothed by the 5x5 binomial kernel (1 4 6 4 1)^2/256 with mirrored

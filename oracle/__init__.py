@@ -65,6 +65,8 @@ def _load():
         lib.orc_adam.argtypes = [dp, dp, dp, dp, C.c_int64, C.c_int64, dp, C.c_double,
                                  C.c_double, C.c_double, C.c_int]
         lib.orc_sh_basis.argtypes = [C.c_int, dp, dp, dp]
+        lib.orc_fd_gauss.argtypes = [dp, C.c_int64, C.c_int64, dp, dp, dp, i64p, C.c_int, i32p,
+                                     C.c_int, C.c_double, dp, i32p]
         lib.orc_num_threads.restype = C.c_int
         _lib = lib
     return _lib
@@ -224,3 +226,24 @@ def sh_basis(d, deg: int = 3):
     dY = np.zeros((16, 3), np.float64)
     lib.orc_sh_basis(deg, _ptr(dd, C.c_double), _ptr(Y, C.c_double), _ptr(dY, C.c_double))
     return Y, dY
+
+
+def fd_gauss(params, n: int, cam: dict, W, gid, rows, h: float = 1e-4, settings=None):
+    """Central differences of <W, I> w.r.t. rows of Gaussian(s) gid, re-rendering only
+    each perturbed Gaussian's footprint.  gid: int -> (fd [nrows], changed [nrows]);
+    sequence -> arrays [len(gid), nrows]."""
+    lib = _load()
+    P = _f64(params)
+    single = np.ndim(gid) == 0
+    gids = np.ascontiguousarray(np.atleast_1d(gid), dtype=np.int64)
+    rr = np.ascontiguousarray(rows, dtype=np.int32)
+    fd = np.zeros((len(gids), len(rr)), np.float64)
+    ch = np.zeros((len(gids), len(rr)), np.int32)
+    Wd = _f64(W)
+    lib.orc_fd_gauss(_ptr(P, C.c_double), n, P.shape[1], _ptr(cam_vec(cam), C.c_double),
+                     _ptr(set_vec(settings), C.c_double), _ptr(Wd, C.c_double),
+                     _ptr(gids, C.c_int64), len(gids), _ptr(rr, C.c_int32), len(rr), h,
+                     _ptr(fd, C.c_double), _ptr(ch, C.c_int32))
+    if single:
+        return fd[0], ch[0].astype(bool)
+    return fd, ch.astype(bool)

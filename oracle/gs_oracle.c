@@ -401,11 +401,33 @@ typedef struct {
     int bin, nbx, nby;
     int64_t *bin_start;
     int64_t *bin_list;
+    /* >= 0: this Gaussian is skipped in the bin lists and tested at every pixel
+     * (its record may have moved, as in a finite-difference perturbation) */
+    int64_t extra;
 } scene_t;
 
 #define AMB_IMAGE 1   /* a flip FP32 may take changes the pixel by > AMB_EFFECT */
 #define AMB_COUNT 2   /* a flip FP32 may take changes n_contrib / T_final */
 #define AMB_EFFECT 2e-5
+
+/* The candidate record of Gaussian g at pixel (px, py); returns 0 when it
+ * neither reaches the cutoff nor lies within FP32 reach of it. */
+static int make_cand(const scene_t *S, int64_t g, int px, int py, cand_t *c) {
+    const gauss_t *G = &S->gs[g];
+    if (!G->valid) return 0;
+    const double dx = G->m[0] - px, dy = G->m[1] - py;
+    const double power = -0.5 * (G->conic[0] * dx * dx + G->conic[2] * dy * dy) -
+                         G->conic[1] * dx * dy;
+    const double atil = G->o * exp(power);
+    const int contributes = atil >= S->st->alpha_min;
+    /* |ln(alpha_tilde / alpha_min)| */
+    const double margin = fabs(log(G->o / S->st->alpha_min) + power);
+    const int near = margin < power_err32(G, dx, dy, power);
+    if (!contributes && !near) return 0;
+    cand_t cc = {g, G->xc[2], atil, power, dx, dy, contributes, near};
+    *c = cc;
+    return 1;
+}
 
 /* Builds the candidate list of one pixel, sorted by (z, id). */
 static void gather(const scene_t *S, int px, int py, scratch_t *s, int64_t *evaluated) {
@@ -418,22 +440,19 @@ static void gather(const scene_t *S, int px, int py, scratch_t *s, int64_t *eval
         hi = S->bin_start[b + 1];
         list = S->bin_list;
     }
-    for (int64_t i = lo; i < hi; ++i) {
-        const int64_t g = list ? list[i] : i;
-        const gauss_t *G = &S->gs[g];
-        if (!G->valid) continue;
+    for (int64_t i = lo; i <= hi; ++i) {
+        int64_t g;
+        if (i == hi) {   /* the explicitly tested Gaussian, if any */
+            if (S->extra < 0) break;
+            g = S->extra;
+        } else {
+            g = list ? list[i] : i;
+            if (g == S->extra) continue;
+        }
+        if (!S->gs[g].valid) continue;
         ++*evaluated;
-        const double dx = G->m[0] - px, dy = G->m[1] - py;
-        const double power = -0.5 * (G->conic[0] * dx * dx + G->conic[2] * dy * dy) -
-                             G->conic[1] * dx * dy;
-        const double atil = G->o * exp(power);
-        const int contributes = atil >= S->st->alpha_min;
-        /* |ln(alpha_tilde / alpha_min)| */
-        const double margin = fabs(log(G->o / S->st->alpha_min) + power);
-        const int near = margin < power_err32(G, dx, dy, power);
-        if (!contributes && !near) continue;
-        cand_t c = {g, G->xc[2], atil, power, dx, dy, contributes, near};
-        push(s, &c);
+        cand_t c;
+        if (make_cand(S, g, px, py, &c)) push(s, &c);
     }
     qsort(s->c, s->n, sizeof(cand_t), cmp_cand);
 }
@@ -537,6 +556,7 @@ static void build_scene(scene_t *S, gauss_t *gs, int64_t n, const cam_t *cam, co
                         int prune) {
     memset(S, 0, sizeof *S);
     S->gs = gs; S->n = n; S->cam = cam; S->st = st;
+    S->extra = -1;
     if (!prune) return;
     S->bin = 16;
     S->nbx = (cam->W + S->bin - 1) / S->bin;
@@ -865,6 +885,137 @@ void orc_gauss_backward(const double *P, int64_t ncap, int64_t g, const double *
     gauss_t G;
     gauss_forward(P, ncap, g, &cam, &st, &G);
     gauss_backward(&G, &cam, &st, g2, out);
+}
+
+/*
+ * Central finite differences of L = <W, I> with respect to raw parameters of
+ * Gaussians gids[0..ngids) (output [ngids][nrows]): for each Gaussian and row,
+ * the parameter is moved by +-h and that Gaussian alone is re-projected; only
+ * pixels inside the union of its cutoff boxes can change, and there each
+ * pixel's sorted list of the other Gaussians is computed once and the moved
+ * Gaussian is merged into it for every evaluation.  fd receives
+ * (L+ - L-) / (2h); changed is 1 when the set of composited Gaussians or of
+ * cutoff-passing pairs differs between +h and -h at any of those pixels (a
+ * discrete event the derivative does not see).
+ */
+void orc_fd_gauss(const double *P, int64_t n, int64_t ncap, const double *camv,
+                  const double *setv, const double *W, const int64_t *gids, int ngids,
+                  const int32_t *rows, int nrows, double h, double *fd_all, int32_t *changed_all) {
+    const cam_t cam = read_cam(camv);
+    const set_t st = read_set(setv);
+    gauss_t *gs = forward_all(P, n, ncap, &cam, &st);
+    scene_t S;
+    build_scene(&S, gs, n, &cam, &st, 1);
+    const int64_t HW = (int64_t)cam.W * cam.H;
+    for (int gi = 0; gi < ngids; ++gi) {
+        const int64_t gid = gids[gi];
+        double *fd = fd_all + (size_t)gi * nrows;
+        int32_t *changed = changed_all + (size_t)gi * nrows;
+        const gauss_t G0 = gs[gid];
+        double col[NROWS];
+        for (int r = 0; r < NROWS; ++r) col[r] = P[r * ncap + gid];
+        gauss_t *Gp = (gauss_t *)malloc(sizeof(gauss_t) * 2 * (size_t)nrows);
+        double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+        for (int k = 0; k < 2 * nrows + 1; ++k) {
+            const gauss_t *G = &G0;
+            if (k < 2 * nrows) {
+                double c2[NROWS];
+                memcpy(c2, col, sizeof col);
+                c2[rows[k / 2]] += (k & 1) ? -h : h;
+                gauss_forward(c2, 1, 0, &cam, &st, &Gp[k]);
+                G = &Gp[k];
+            }
+            if (!G->valid || G->extx < 0) continue;
+            x0 = fmin(x0, G->m[0] - G->extx - 2); x1 = fmax(x1, G->m[0] + G->extx + 2);
+            y0 = fmin(y0, G->m[1] - G->exty - 2); y1 = fmax(y1, G->m[1] + G->exty + 2);
+        }
+        const int px0 = (int)fmax(0.0, floor(x0)), px1 = (int)fmin(cam.W - 1.0, ceil(x1));
+        const int py0 = (int)fmax(0.0, floor(y0)), py1 = (int)fmin(cam.H - 1.0, ceil(y1));
+        if (!(px0 <= px1 && py0 <= py1)) {
+            for (int k = 0; k < nrows; ++k) { fd[k] = 0; changed[k] = 0; }
+            free(Gp);
+            continue;
+        }
+        const int bw = px1 - px0 + 1, bh = py1 - py0 + 1;
+        const size_t npx = (size_t)bw * bh;
+        /* sorted candidate lists of the other Gaussians at every box pixel */
+        cand_t **lists = (cand_t **)calloc(npx, sizeof(cand_t *));
+        size_t *lens = (size_t *)calloc(npx, sizeof(size_t));
+        gs[gid].valid = 0;
+        S.extra = gid;
+#pragma omp parallel
+        {
+            scratch_t sc;
+            memset(&sc, 0, sizeof sc);
+#pragma omp for schedule(dynamic, 2)
+            for (int py = py0; py <= py1; ++py)
+                for (int px = px0; px <= px1; ++px) {
+                    int64_t ev = 0;
+                    gather(&S, px, py, &sc, &ev);
+                    const size_t q = (size_t)(py - py0) * bw + (px - px0);
+                    lens[q] = sc.n;
+                    lists[q] = (cand_t *)malloc(sizeof(cand_t) * (sc.n + 1));
+                    memcpy(lists[q], sc.c, sizeof(cand_t) * sc.n);
+                }
+            free(sc.c); free(sc.T); free(sc.rejT);
+        }
+        int *ncs = (int *)malloc(sizeof(int) * 2 * npx);
+        int64_t *ccs = (int64_t *)malloc(sizeof(int64_t) * 2 * npx);
+        for (int k = 0; k < nrows; ++k) {
+            double L[2] = {0, 0};
+            for (int sgn = 0; sgn < 2; ++sgn) {
+                gs[gid] = Gp[2 * k + sgn];
+                double acc = 0;
+#pragma omp parallel reduction(+ : acc)
+                {
+                    scratch_t sc;
+                    memset(&sc, 0, sizeof sc);
+#pragma omp for schedule(dynamic, 4)
+                    for (int py = py0; py <= py1; ++py)
+                        for (int px = px0; px <= px1; ++px) {
+                            const size_t q = (size_t)(py - py0) * bw + (px - px0);
+                            sc.n = 0;
+                            if (sc.cap < lens[q] + 1) {
+                                sc.cap = lens[q] + 1;
+                                sc.c = (cand_t *)realloc(sc.c, sc.cap * sizeof(cand_t));
+                            }
+                            cand_t c;
+                            const int have = make_cand(&S, gid, px, py, &c);
+                            size_t w = 0;
+                            int pending = have;   /* merge the moved Gaussian once */
+                            for (size_t i2 = 0; i2 < lens[q]; ++i2) {
+                                if (pending && cmp_cand(&c, &lists[q][i2]) < 0) {
+                                    sc.c[w++] = c;
+                                    pending = 0;
+                                }
+                                sc.c[w++] = lists[q][i2];
+                            }
+                            if (pending) sc.c[w++] = c;
+                            sc.n = w;
+                            pix_out_t o;
+                            composite(&S, &sc, &o);
+                            const int64_t pix = (int64_t)py * cam.W + px;
+                            for (int ch = 0; ch < 3; ++ch) acc += W[ch * HW + pix] * o.C[ch];
+                            ncs[sgn * npx + q] = o.ncontrib;
+                            ccs[sgn * npx + q] = o.contrib_pairs;
+                        }
+                    free(sc.c); free(sc.T); free(sc.rejT);
+                }
+                L[sgn] = acc;
+            }
+            int chg = 0;
+            for (size_t q = 0; q < npx; ++q)
+                if (ncs[q] != ncs[q + npx] || ccs[q] != ccs[q + npx]) chg = 1;
+            fd[k] = (L[0] - L[1]) / (2 * h);
+            changed[k] = chg;
+        }
+        gs[gid] = G0;
+        S.extra = -1;
+        for (size_t q = 0; q < npx; ++q) free(lists[q]);
+        free(lists); free(lens); free(ncs); free(ccs); free(Gp);
+    }
+    free_scene(&S);
+    free(gs);
 }
 
 /* ---------------------------------------------------------------------------

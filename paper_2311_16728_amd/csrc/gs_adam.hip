@@ -8,39 +8,32 @@
 
 namespace gs {
 
-struct LrRows {
-    float lr[kRows];
-};
-
+// grid.y = parameter row, grid.x * 256 threads = float4 columns of that row
 __global__ void __launch_bounds__(256) adam_kernel(float4 *__restrict__ p, const float4 *__restrict__ g,
                                                    float4 *__restrict__ m, float4 *__restrict__ v,
                                                    int64_t n, int64_t n_cap, LrRows lr, float b1,
                                                    float omb1, float b2, float omb2, float eps,
                                                    float ibc1, float isqbc2) {
-    const int64_t q = n_cap / 4;                  // float4s per row
-    const int64_t total = q * kRows;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
-         i += int64_t(gridDim.x) * blockDim.x) {
-        const int row = int(i / q);
-        const int64_t col = (i - int64_t(row) * q) * 4;
-        if (col >= n) continue;
-        const float rate = lr.lr[row];
-        float4 pp = p[i], gg = g[i], mm = m[i], vv = v[i];
-        auto step = [&](float &pv, float gv, float &mv, float &vvv, int64_t c) {
-            if (c >= n) return;
-            mv = b1 * mv + omb1 * gv;
-            vvv = b2 * vvv + omb2 * gv * gv;
-            const float denom = sqrtf(vvv) * isqbc2 + eps;
-            pv -= rate * (mv * ibc1) / denom;
-        };
-        step(pp.x, gg.x, mm.x, vv.x, col);
-        step(pp.y, gg.y, mm.y, vv.y, col + 1);
-        step(pp.z, gg.z, mm.z, vv.z, col + 2);
-        step(pp.w, gg.w, mm.w, vv.w, col + 3);
-        p[i] = pp;
-        m[i] = mm;
-        v[i] = vv;
-    }
+    const int row = blockIdx.y;
+    const int64_t c4 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;   // float4 column
+    const int64_t col = c4 * 4;
+    if (col >= n) return;
+    const int64_t i = int64_t(row) * (n_cap / 4) + c4;
+    const float rate = lr.lr[row] * ibc1;
+    float4 pp = p[i], gg = g[i], mm = m[i], vv = v[i];
+    auto step = [&](float &pv, float gv, float &mv, float &vvv, int64_t c) {
+        if (c >= n) return;
+        mv = b1 * mv + omb1 * gv;
+        vvv = b2 * vvv + omb2 * gv * gv;
+        pv -= rate * mv / (sqrtf(vvv) * isqbc2 + eps);
+    };
+    step(pp.x, gg.x, mm.x, vv.x, col);
+    step(pp.y, gg.y, mm.y, vv.y, col + 1);
+    step(pp.z, gg.z, mm.z, vv.z, col + 2);
+    step(pp.w, gg.w, mm.w, vv.w, col + 3);
+    p[i] = pp;
+    m[i] = mm;
+    v[i] = vv;
 }
 
 }  // namespace gs
@@ -59,10 +52,9 @@ extern "C" gs_status gs_adam_step(float *params, const float *grad, float *m, fl
     // decay factors and their complements are rounded once, from double
     const double bc1 = 1.0 - std::pow(beta1, step);
     const double bc2 = 1.0 - std::pow(beta2, step);
-    const int64_t total = (n_cap / 4) * kRows;
-    int64_t blocks = (total + 255) / 256;
-    if (blocks > 256 * 32) blocks = 256 * 32;
-    hipLaunchKernelGGL(adam_kernel, dim3(blocks), dim3(256), 0, static_cast<hipStream_t>(stream),
+    const int64_t cols4 = (n + 3) / 4;
+    const dim3 grid(unsigned((cols4 + 255) / 256), kRows);
+    hipLaunchKernelGGL(adam_kernel, grid, dim3(256), 0, static_cast<hipStream_t>(stream),
                        reinterpret_cast<float4 *>(params), reinterpret_cast<const float4 *>(grad),
                        reinterpret_cast<float4 *>(m), reinterpret_cast<float4 *>(v), n, n_cap, lr,
                        float(beta1), float(1.0 - beta1), float(beta2), float(1.0 - beta2), float(eps),

@@ -54,7 +54,7 @@ static inline Proj proj_at(void *ws, int64_t records) {
 enum Counter { kVisible = 0, kPairs = 1, kPairsClamped = 2, kNumCounters = 16 };
 
 struct SortLayout {
-    size_t counters, counts, vis_key0, vis_key1, vis_val0, vis_val1, vis_off, pair_key0,
+    size_t counters, counts, rects, vis_key0, vis_key1, vis_val0, vis_val1, vis_off, pair_key0,
         pair_key1, pair_val0, pair_val1, ranges, bsum, hist, digit, bytes;
     int64_t sources, pair_cap, max_blocks;
     static SortLayout make(int64_t sources, int64_t pair_cap, int64_t total_tiles) {
@@ -67,6 +67,7 @@ struct SortLayout {
         auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
         L.counters = take(sizeof(uint32_t) * kNumCounters);
         L.counts = take(sizeof(uint32_t) * sources);
+        L.rects = take(sizeof(uint32_t) * 2 * sources);
         L.vis_key0 = take(sizeof(uint32_t) * sources);
         L.vis_key1 = take(sizeof(uint32_t) * sources);
         L.vis_val0 = take(sizeof(uint32_t) * sources);
@@ -107,6 +108,11 @@ static inline Sorted sorted_at(const void *ws, int64_t sources, int64_t pair_cap
     return Sorted{reinterpret_cast<const uint32_t *>(b + val),
                   reinterpret_cast<const uint2 *>(b + L.ranges)};
 }
+
+// Per-row learning rates (kernel argument).
+struct LrRows {
+    float lr[kRows];
+};
 
 // Per-(view, Gaussian) accumulators of 2D gradients, 9 rows of `records`:
 // d mean x, d mean y (level-0 pixels), d cov00, d cov01, d cov11 (undilated

@@ -241,89 +241,75 @@ __global__ void __launch_bounds__(256) preprocess_kernel(gs_settings s, const fl
     }
 }
 
+// Gradient sinks of the projection backward: accumulate into a gradient
+// buffer, or apply the Adam update to the parameter right away (the gradient
+// then never leaves registers).
+struct GradSink {
+    float *grad;
+    __device__ __forceinline__ void operator()(int row, int64_t g, int64_t n_cap, float v) const {
+        grad[row * n_cap + g] += v;
+    }
+    __device__ __forceinline__ void untouched(int64_t, int64_t) const {}
+};
+
+struct AdamSink {
+    float *p, *m, *v;
+    LrRows lr;
+    float b1, omb1, b2, omb2, eps, ibc1, isqbc2;
+    __device__ __forceinline__ void operator()(int row, int64_t g, int64_t n_cap, float gv) const {
+        const int64_t i = row * n_cap + g;
+        const float mv = b1 * m[i] + omb1 * gv;
+        const float vv = b2 * v[i] + omb2 * gv * gv;
+        m[i] = mv;
+        v[i] = vv;
+        p[i] -= lr.lr[row] * ibc1 * mv / (sqrtf(vv) * isqbc2 + eps);
+    }
+    __device__ __forceinline__ void untouched(int64_t g, int64_t n_cap) const {
+        for (int r = 0; r < kRows; ++r) (*this)(r, g, n_cap, 0.f);
+    }
+};
+
 // Chain rule from the accumulated 2D gradients of every view to the 59 raw
-// parameter gradients (added to grad).
+// parameter gradients (added to grad).  Geometry is handled first, view by
+// view; the colour part then runs one channel at a time so that only that
+// channel's 16 SH coefficients and their gradients are live.
+template <class Sink>
 __global__ void __launch_bounds__(256) project_backward_kernel(
     gs_settings s, const float *__restrict__ P, int64_t n, int64_t n_cap,
     const gs_view *__restrict__ views, int32_t n_views, const float *__restrict__ acc,
-    int64_t records, float *__restrict__ grad) {
+    int64_t records, Sink sink) {
     const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (g >= n) return;
     Gauss G;
     load_gauss(P, n_cap, g, G);
     const int nk = (s.sh_degree + 1) * (s.sh_degree + 1);
-    float gmu[3] = {0, 0, 0}, gs_[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gop = 0.f;
-    float gsh[16][3];
-#pragma unroll
-    for (int k = 0; k < 16; ++k)
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) gsh[k][ch] = 0.f;
-    float dSig[6] = {0, 0, 0, 0, 0, 0};   // accumulated over views: 00 01 02 11 12 22 (matrix entries)
-    float sh[16][3];
-#pragma unroll
-    for (int k = 0; k < 16; ++k)
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) sh[k][ch] = (k < nk) ? P[(11 + 3 * k + ch) * n_cap + g] : 0.f;
+    float gmu[3] = {0, 0, 0}, gop = 0.f;
+    float dSig[6] = {0, 0, 0, 0, 0, 0};   // summed over views: 00 01 02 11 12 22 (matrix entries)
+    bool any_view = false;
 
     for (int v = 0; v < n_views; ++v) {
         const int64_t r = int64_t(v) * n_cap + g;
-        float a[kAccRows];
+        float a[6];
 #pragma unroll
-        for (int i = 0; i < kAccRows; ++i) a[i] = acc[i * records + r];
+        for (int i = 0; i < 6; ++i) a[i] = acc[i * records + r];
         bool any = false;
 #pragma unroll
-        for (int i = 0; i < kAccRows; ++i) any |= (a[i] != 0.f);
+        for (int i = 0; i < kAccRows; ++i) any |= (acc[i * records + r] != 0.f);
         if (!any) continue;
+        any_view = true;
         const Cam c = load_cam(views[v], s.fov_clamp);
         Proj2 p;
         if (!project(G, c, s.znear, p)) continue;
         const float z = p.xc[2], iz = 1.f / z, iz2 = iz * iz;
-
-        // colour: rgb = max(0, raw), raw = 0.5 + sum_k Y_k(d) sh_k
-        float d[3] = {G.mu[0] - c.C[0], G.mu[1] - c.C[1], G.mu[2] - c.C[2]};
-        const float dinv = rsqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-        const float dx = d[0] * dinv, dy = d[1] * dinv, dz = d[2] * dinv;
-        float Y[16];
-        sh_eval(s.sh_degree, dx, dy, dz, Y);
-        float draw[3];
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            float raw = 0.5f;
-#pragma unroll
-            for (int k = 0; k < 16; ++k) raw += Y[k] * sh[k][ch];
-            draw[ch] = raw < 0.f ? 0.f : a[6 + ch];
-        }
-        float wk[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            float w = 0.f;
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                gsh[k][ch] += Y[k] * draw[ch];
-                w += draw[ch] * sh[k][ch];
-            }
-            wk[k] = w;
-        }
-        float gd[3];
-        sh_grad(s.sh_degree, dx, dy, dz, wk, gd);
-        {   // unit-vector normalisation: (I - d d^T) / |mu - C|
-            const float dot = gd[0] * dx + gd[1] * dy + gd[2] * dz;
-            gmu[0] += (gd[0] - dx * dot) * dinv;
-            gmu[1] += (gd[1] - dy * dot) * dinv;
-            gmu[2] += (gd[2] - dz * dot) * dinv;
-        }
-
-        // 2D covariance cov = T Sigma T^T, T = J W.
         const float G00 = a[2], G01 = a[3], G11 = a[4];
-        // dL/dSigma = T^T G T
-        {
-            float GT[6];   // G T, 2x3
+        {   // dL/dSigma = T^T G T
+            float GT[6];
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                GT[j] = G00 * p.T[j] + G01 * p.T[3 + j];
-                GT[3 + j] = G01 * p.T[j] + G11 * p.T[3 + j];
+            for (int jj = 0; jj < 3; ++jj) {
+                GT[jj] = G00 * p.T[jj] + G01 * p.T[3 + jj];
+                GT[3 + jj] = G01 * p.T[jj] + G11 * p.T[3 + jj];
             }
-            auto e = [&](int i, int j) { return p.T[i] * GT[j] + p.T[3 + i] * GT[3 + j]; };
+            auto e = [&](int ii, int jj) { return p.T[ii] * GT[jj] + p.T[3 + ii] * GT[3 + jj]; };
             dSig[0] += e(0, 0); dSig[1] += e(0, 1); dSig[2] += e(0, 2);
             dSig[3] += e(1, 1); dSig[4] += e(1, 2); dSig[5] += e(2, 2);
         }
@@ -341,11 +327,10 @@ __global__ void __launch_bounds__(256) project_backward_kernel(
         }
         float dT[6];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            dT[j] = 2.f * (G00 * TS[j] + G01 * TS[3 + j]);
-            dT[3 + j] = 2.f * (G01 * TS[j] + G11 * TS[3 + j]);
+        for (int jj = 0; jj < 3; ++jj) {
+            dT[jj] = 2.f * (G00 * TS[jj] + G01 * TS[3 + jj]);
+            dT[3 + jj] = 2.f * (G01 * TS[jj] + G11 * TS[3 + jj]);
         }
-        // T0j = J00 W0j + J02 W2j, T1j = J11 W1j + J12 W2j
         const float dJ00 = dT[0] * c.R[0] + dT[1] * c.R[1] + dT[2] * c.R[2];
         const float dJ02 = dT[0] * c.R[6] + dT[1] * c.R[7] + dT[2] * c.R[8];
         const float dJ11 = dT[3] * c.R[3] + dT[4] * c.R[4] + dT[5] * c.R[5];
@@ -365,10 +350,52 @@ __global__ void __launch_bounds__(256) project_backward_kernel(
         gx[0] += a[0] * c.fx * iz;
         gx[1] += a[1] * c.fy * iz;
         gx[2] += -(a[0] * c.fx * p.xc[0] + a[1] * c.fy * p.xc[1]) * iz2;
-        // x_c = W mu + t
 #pragma unroll
-        for (int i = 0; i < 3; ++i) gmu[i] += c.R[i] * gx[0] + c.R[3 + i] * gx[1] + c.R[6 + i] * gx[2];
+        for (int ii = 0; ii < 3; ++ii) gmu[ii] += c.R[ii] * gx[0] + c.R[3 + ii] * gx[1] + c.R[6 + ii] * gx[2];
         gop += a[5];
+    }
+    if (!any_view) {   // no view touched this Gaussian: zero gradient
+        sink.untouched(g, n_cap);
+        return;
+    }
+
+    // colour, one channel at a time: rgb = max(0, raw), raw = 0.5 + sum_k Y_k(d) sh_k
+    for (int ch = 0; ch < 3; ++ch) {
+        float sh[16], gsh[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            sh[k] = (k < nk) ? P[(11 + 3 * k + ch) * n_cap + g] : 0.f;
+            gsh[k] = 0.f;
+        }
+        for (int v = 0; v < n_views; ++v) {
+            const int64_t r = int64_t(v) * n_cap + g;
+            const float drgb = acc[(6 + ch) * records + r];
+            if (drgb == 0.f) continue;
+            const Cam c = load_cam(views[v], s.fov_clamp);
+            float d[3] = {G.mu[0] - c.C[0], G.mu[1] - c.C[1], G.mu[2] - c.C[2]};
+            const float dinv = rsqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            const float dx = d[0] * dinv, dy = d[1] * dinv, dz = d[2] * dinv;
+            float Y[16];
+            sh_eval(s.sh_degree, dx, dy, dz, Y);
+            float raw = 0.5f;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) raw += Y[k] * sh[k];
+            if (raw < 0.f) continue;   // clamped colour passes no gradient
+#pragma unroll
+            for (int k = 0; k < 16; ++k) gsh[k] += Y[k] * drgb;
+            float wk[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) wk[k] = drgb * sh[k];
+            float gd[3];
+            sh_grad(s.sh_degree, dx, dy, dz, wk, gd);
+            // unit-vector normalisation: (I - d d^T) / |mu - C|
+            const float dot = gd[0] * dx + gd[1] * dy + gd[2] * dz;
+            gmu[0] += (gd[0] - dx * dot) * dinv;
+            gmu[1] += (gd[1] - dy * dot) * dinv;
+            gmu[2] += (gd[2] - dz * dot) * dinv;
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) sink(11 + 3 * k + ch, g, n_cap, gsh[k]);
     }
 
     // Sigma = M M^T, M = Rq diag(s): dM = 2 dSigma M (dSigma symmetric)
@@ -377,19 +404,20 @@ __global__ void __launch_bounds__(256) project_backward_kernel(
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
-            dM[3 * i + j] = 2.f * (D[3 * i] * G.M[j] + D[3 * i + 1] * G.M[3 + j] + D[3 * i + 2] * G.M[6 + j]);
-    float dR[9];
+        for (int jj = 0; jj < 3; ++jj)
+            dM[3 * i + jj] = 2.f * (D[3 * i] * G.M[jj] + D[3 * i + 1] * G.M[3 + jj] + D[3 * i + 2] * G.M[6 + jj]);
+    float dR[9], gls[3];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
+    for (int jj = 0; jj < 3; ++jj) {
         float acc_s = 0.f;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            acc_s += dM[3 * i + j] * G.Rq[3 * i + j];
-            dR[3 * i + j] = dM[3 * i + j] * G.s[j];
+            acc_s += dM[3 * i + jj] * G.Rq[3 * i + jj];
+            dR[3 * i + jj] = dM[3 * i + jj] * G.s[jj];
         }
-        gs_[j] = acc_s * G.s[j];   // d/d log-scale
+        gls[jj] = acc_s * G.s[jj];   // d/d log-scale
     }
+    float gq[4];
     {
         const float w = G.q[0], x = G.q[1], y = G.q[2], z = G.q[3];
         float dq[4];
@@ -404,20 +432,13 @@ __global__ void __launch_bounds__(256) project_backward_kernel(
 #pragma unroll
         for (int i = 0; i < 4; ++i) gq[i] = (dq[i] - G.q[i] * dot) * G.qinv;
     }
-    float out[kRows];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) out[i] = gmu[i];
+    for (int i = 0; i < 3; ++i) sink(i, g, n_cap, gmu[i]);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) out[3 + i] = gs_[i];
+    for (int i = 0; i < 3; ++i) sink(3 + i, g, n_cap, gls[i]);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) out[6 + i] = gq[i];
-    out[10] = gop * G.o * (1.f - G.o);
-#pragma unroll
-    for (int k = 0; k < 16; ++k)
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) out[11 + 3 * k + ch] = gsh[k][ch];
-#pragma unroll
-    for (int r = 0; r < kRows; ++r) grad[r * n_cap + g] += out[r];
+    for (int i = 0; i < 4; ++i) sink(6 + i, g, n_cap, gq[i]);
+    sink(10, g, n_cap, gop * G.o * (1.f - G.o));
 }
 
 gs_status launch_project_backward(const gs_settings &s, const float *params, int64_t n,
@@ -425,8 +446,32 @@ gs_status launch_project_backward(const gs_settings &s, const float *params, int
                                   const float *acc, float *grad, hipStream_t st) {
     if (n == 0) return GS_OK;
     const int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL(project_backward_kernel, dim3(blocks), dim3(256), 0, st, s, params, n, n_cap,
-                       views, n_views, acc, int64_t(n_views) * n_cap, grad);
+    hipLaunchKernelGGL(project_backward_kernel<GradSink>, dim3(blocks), dim3(256), 0, st, s, params, n,
+                       n_cap, views, n_views, acc, int64_t(n_views) * n_cap, GradSink{grad});
+    GS_CHECK_LAUNCH();
+    return GS_OK;
+}
+
+gs_status launch_project_backward_adam(const gs_settings &s, float *params, int64_t n, int64_t n_cap,
+                                       const gs_view *views, int32_t n_views, const float *acc,
+                                       float *m, float *v, const float *lr_rows, double beta1,
+                                       double beta2, double eps, int32_t step, hipStream_t st) {
+    if (n == 0) return GS_OK;
+    AdamSink a;
+    a.p = params;
+    a.m = m;
+    a.v = v;
+    for (int r = 0; r < kRows; ++r) a.lr.lr[r] = lr_rows[r];
+    a.b1 = float(beta1);
+    a.omb1 = float(1.0 - beta1);
+    a.b2 = float(beta2);
+    a.omb2 = float(1.0 - beta2);
+    a.eps = float(eps);
+    a.ibc1 = float(1.0 / (1.0 - std::pow(beta1, step)));
+    a.isqbc2 = float(1.0 / std::sqrt(1.0 - std::pow(beta2, step)));
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(project_backward_kernel<AdamSink>, dim3(blocks), dim3(256), 0, st, s, params, n,
+                       n_cap, views, n_views, acc, int64_t(n_views) * n_cap, a);
     GS_CHECK_LAUNCH();
     return GS_OK;
 }

@@ -31,10 +31,11 @@ __device__ __forceinline__ int find_target(const gs_target *__restrict__ targets
 // The record of source `src` as seen by a target at pyramid level `level`,
 // with its 2D mean relative to the tile origin (ox, oy): the FP64 mean is
 // reduced before rounding, so offsets inside the tile are accurate to a few
-// 1e-7 px.
+// 1e-7 px.  thr = ln(alpha_min / opacity): a pixel composites the Gaussian iff
+// its exponent reaches thr.
 __device__ __forceinline__ void stage_record(const gs_settings &s, const Proj &proj, int64_t n_cap,
                                              int view, int level, double ox, double oy, uint32_t src,
-                                             float4 &A, float4 &B, float &blue, int64_t &rec) {
+                                             float4 &A, float4 &B, float2 &C, int64_t &rec) {
     const int64_t g = int64_t(src % uint32_t(n_cap));
     const int64_t r = int64_t(view) * n_cap + g;
     rec = r;
@@ -50,7 +51,36 @@ __device__ __forceinline__ void stage_record(const gs_settings &s, const Proj &p
     const double dsc = double(sc);
     A = make_float4(float(m.x * dsc - ox), float(m.y * dsc - oy), c11 * idet, -c01 * idet);
     B = make_float4(c00 * idet, co.w, cz.x, cz.y);
-    blue = cz.z;
+    C = make_float2(cz.z, __logf(s.alpha_min / co.w));
+}
+
+// Minimum of the quadratic form q(d) = a dx^2 + 2 b dx dy + c dy^2, d = p - m,
+// over pixel centres p in [0, 15]^2 (tile-relative), relaxed to the square.
+__device__ __forceinline__ float qmin_tile(const float4 &A, const float4 &B) {
+    const float mx = A.x, my = A.y, a = A.z, b = A.w, c = B.x;
+    const float lo = 0.f, hi = float(kTile - 1);
+    if (mx >= lo && mx <= hi && my >= lo && my <= hi) return 0.f;
+    float best = 3.4e38f;
+    // edges x = const: minimise over dy
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const float dx = (e ? hi : lo) - mx;
+        const float dy = fminf(fmaxf(-b * dx / c, lo - my), hi - my);
+        best = fminf(best, a * dx * dx + 2.f * b * dx * dy + c * dy * dy);
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const float dy = (e ? hi : lo) - my;
+        const float dx = fminf(fmaxf(-b * dy / a, lo - mx), hi - mx);
+        best = fminf(best, a * dx * dx + 2.f * b * dx * dy + c * dy * dy);
+    }
+    return best;
+}
+
+// True when some pixel of the tile may reach the cutoff (conservative).
+__device__ __forceinline__ bool touches_tile(const float4 &A, const float4 &B, const float2 &C) {
+    const float tq = -2.f * C.y;   // q <= tq  <=>  exponent >= thr
+    return qmin_tile(A, B) <= tq * 1.0001f + 1e-3f;
 }
 
 // Opacity of a staged Gaussian at offset (dx, dy) = mean - pixel.  The same
@@ -67,7 +97,9 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(
     int32_t *__restrict__ out_last, int32_t *__restrict__ out_nc) {
     __shared__ float4 sA[kTilePix];
     __shared__ float4 sB[kTilePix];
-    __shared__ float sC[kTilePix];
+    __shared__ float2 sC[kTilePix];
+    __shared__ int32_t sPos[kTilePix];
+    __shared__ uint32_t scan_lds[8];
     const int tile = blockIdx.x;
     const int tid = threadIdx.x;
     const gs_target t = targets[find_target(targets, n_targets, tile)];
@@ -85,35 +117,43 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(
     const int batch = s.batch;
     for (uint32_t b0 = range.x; b0 < range.y; b0 += batch) {
         if (__syncthreads_count(done) == kTilePix) break;
+        // stage the batch, keeping only Gaussians whose cutoff ellipse meets the tile
         const uint32_t idx = b0 + tid;
+        float4 A, B;
+        float2 Cc;
+        int64_t rec;
+        bool keep = false;
         if (tid < batch && idx < range.y) {
-            float4 A, B;
-            float blue;
-            int64_t rec;
-            stage_record(s, proj, n_cap, t.view, t.level, ox, oy, srt.pair_val[idx], A, B, blue, rec);
-            sA[tid] = A;
-            sB[tid] = B;
-            sC[tid] = blue;
+            stage_record(s, proj, n_cap, t.view, t.level, ox, oy, srt.pair_val[idx], A, B, Cc, rec);
+            keep = touches_tile(A, B, Cc);
+        }
+        uint32_t cnt;
+        const uint32_t at_pos = block_exclusive_scan(keep ? 1u : 0u, scan_lds, &cnt);
+        if (keep) {
+            sA[at_pos] = A;
+            sB[at_pos] = B;
+            sC[at_pos] = Cc;
+            sPos[at_pos] = int32_t(idx - range.x);
         }
         __syncthreads();
-        const int cnt = min(uint32_t(batch), range.y - b0);
         if (!done) {
-            for (int j = 0; j < cnt; ++j) {
+            for (int j = 0; j < int(cnt); ++j) {
                 const float4 A = sA[j];
                 const float4 B = sB[j];
+                const float2 Cj = sC[j];
                 const float dx = A.x - fpx, dy = A.y - fpy;
-                const float at = B.y * __expf(eval_power(A, B, dx, dy));
-                if (at < s.alpha_min) continue;
-                const float alpha = fminf(s.alpha_max, at);
+                const float pw = eval_power(A, B, dx, dy);
+                if (pw < Cj.y) continue;
+                const float alpha = fminf(s.alpha_max, B.y * __expf(pw));
                 const float Tn = T * (1.f - alpha);
                 if (Tn < s.t_min) { done = true; break; }
                 const float w = alpha * T;
                 C0 = fmaf(w, B.z, C0);
                 C1 = fmaf(w, B.w, C1);
-                C2 = fmaf(w, sC[j], C2);
+                C2 = fmaf(w, Cj.x, C2);
                 T = Tn;
                 ++nc;
-                last = int32_t(b0 - range.x) + j + 1;
+                last = sPos[j] + 1;
             }
         }
     }
@@ -130,17 +170,39 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(
     }
 }
 
+// Cross-lane add through DPP (full-rate VALU; rows are 16 lanes).
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ float dpp_add(float v) {
+    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, kRowMask, 0xf, false));
+}
+
+// Sum over the 64 lanes; the total is valid in lane 63.
+__device__ __forceinline__ float wave_sum_to_last(float v) {
+    v = dpp_add<0xB1, 0xf>(v);    // quad_perm [1,0,3,2]
+    v = dpp_add<0x4E, 0xf>(v);    // quad_perm [2,3,0,1]
+    v = dpp_add<0x141, 0xf>(v);   // row_half_mirror: 8-lane sums
+    v = dpp_add<0x140, 0xf>(v);   // row_mirror: 16-lane sums
+    v = dpp_add<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v = dpp_add<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
 __global__ void __launch_bounds__(256) render_bwd_kernel(
     gs_settings s, Proj proj, int64_t n_cap, Sorted srt, const gs_target *__restrict__ targets,
     int n_targets, const float *__restrict__ in_T, const int32_t *__restrict__ in_last,
     const float *__restrict__ dL_drgb, float *__restrict__ acc, int64_t records) {
+    constexpr int kWaves = kTilePix / kWave;
     __shared__ float4 sA[kTilePix];
     __shared__ float4 sB[kTilePix];
-    __shared__ float sC[kTilePix];
-    __shared__ int64_t sR[kTilePix];
+    __shared__ float2 sC[kTilePix];
+    __shared__ int32_t sR[kTilePix];
+    __shared__ int32_t sPos[kTilePix];
+    __shared__ uint32_t scan_lds[8];
+    __shared__ float red[kWaves][kTilePix][kAccRows];   // per-wave partial sums of a batch
     __shared__ int sMaxLast;
     const int tile = blockIdx.x;
     const int tid = threadIdx.x;
+    const int wave = tid / kWave;
     const gs_target t = targets[find_target(targets, n_targets, tile)];
     const int local = tile - t.tile_offset;
     const int tx = local % t.tiles_x, ty = local / t.tiles_x;
@@ -176,32 +238,49 @@ __global__ void __launch_bounds__(256) render_bwd_kernel(
     for (int end = max_last; end > 0; end -= batch) {
         const int start = max(0, end - batch);
         __syncthreads();
+        float4 A, Bv;
+        float2 Cc;
+        int64_t rec;
+        bool keep = false;
         if (tid < end - start) {
-            float4 A, Bv;
-            float blue;
-            int64_t rec;
             stage_record(s, proj, n_cap, t.view, t.level, ox, oy, srt.pair_val[range.x + start + tid],
-                         A, Bv, blue, rec);
-            sA[tid] = A;
-            sB[tid] = Bv;
-            sC[tid] = blue;
-            sR[tid] = rec;
+                         A, Bv, Cc, rec);
+            keep = touches_tile(A, Bv, Cc);
+        }
+        uint32_t cnt;
+        const uint32_t at_pos = block_exclusive_scan(keep ? 1u : 0u, scan_lds, &cnt);
+        if (keep) {
+            sA[at_pos] = A;
+            sB[at_pos] = Bv;
+            sC[at_pos] = Cc;
+            sR[at_pos] = int32_t(rec);
+            sPos[at_pos] = start + tid;
         }
         __syncthreads();
-        for (int j = end - 1; j >= start; --j) {
-            const int k = j - start;
+        for (int k = int(cnt) - 1; k >= 0; --k) {
             const float4 A = sA[k];
             const float4 Bv = sB[k];
+            const float2 Ck = sC[k];
             const float dx = A.x - fpx, dy = A.y - fpy;
-            const float ep = __expf(eval_power(A, Bv, dx, dy));
-            const float at = Bv.y * ep;
-            const bool active = (j < last) && !(at < s.alpha_min);
+            const float pw = eval_power(A, Bv, dx, dy);
+            const bool active = (sPos[k] < last) && !(pw < Ck.y);
+            const uint64_t act = __ballot(active);
+            float *slot = red[wave][k];
+            if (act == 0) {
+                if (lane_id() == kWave - 1) {
+#pragma unroll
+                    for (int i = 0; i < kAccRows; ++i) slot[i] = 0.f;
+                }
+                continue;
+            }
             float v[kAccRows];
             if (active) {
+                const float ep = __expf(pw);
+                const float at = Bv.y * ep;
                 const float alpha = fminf(s.alpha_max, at);
                 const float oma = 1.f - alpha;
-                T = T / oma;                       // transmittance in front of this Gaussian
-                const float r = Bv.z, gg = Bv.w, bb = sC[k];
+                T = T * __builtin_amdgcn_rcpf(oma);   // transmittance in front of this Gaussian
+                const float r = Bv.z, gg = Bv.w, bb = Ck.x;
                 const float dal = T * ((r - B0) * g0 + (gg - B1) * g1 + (bb - B2) * g2);
                 const float w = alpha * T;
                 v[6] = w * g0;
@@ -222,31 +301,43 @@ __global__ void __launch_bounds__(256) render_bwd_kernel(
 #pragma unroll
                 for (int i = 0; i < kAccRows; ++i) v[i] = 0.f;
             }
-            if (__ballot(active) == 0) continue;
+            if (__popcll(act) == 1) {
+                // one pixel of this wave touches the Gaussian: read its values
+                const int src = __builtin_ctzll(act);
 #pragma unroll
-            for (int i = 0; i < kAccRows; ++i) v[i] = wave_sum(v[i]);
-            if (lane_id() == 0) {
+                for (int i = 0; i < kAccRows; ++i)
+                    v[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[i]), src));
+            } else {
+#pragma unroll
+                for (int i = 0; i < kAccRows; ++i) v[i] = wave_sum_to_last(v[i]);
+            }
+            if (lane_id() == kWave - 1) {
                 // conic gradient -> gradient of the dilated covariance, -K dK K,
-                // then back to level-0 units.
+                // and both back to level-0 units
                 const float a = A.z, b = A.w, c = Bv.x;
                 const float ga = v[2], gb = 0.5f * v[3], gc = v[4];
                 const float k00 = a * ga + b * gb, k01 = a * gb + b * gc;
                 const float k10 = b * ga + c * gb, k11 = b * gb + c * gc;
                 const float s2 = sc * sc;
-                const float d00 = -(k00 * a + k01 * b) * s2;
-                const float d01 = -(k00 * b + k01 * c) * s2;
-                const float d11 = -(k10 * b + k11 * c) * s2;
-                const int64_t rr = sR[k];
-                atomicAdd(&acc[0 * records + rr], v[0] * sc);
-                atomicAdd(&acc[1 * records + rr], v[1] * sc);
-                atomicAdd(&acc[2 * records + rr], d00);
-                atomicAdd(&acc[3 * records + rr], d01);
-                atomicAdd(&acc[4 * records + rr], d11);
-                atomicAdd(&acc[5 * records + rr], v[5]);
-                atomicAdd(&acc[6 * records + rr], v[6]);
-                atomicAdd(&acc[7 * records + rr], v[7]);
-                atomicAdd(&acc[8 * records + rr], v[8]);
+                slot[0] = v[0] * sc;
+                slot[1] = v[1] * sc;
+                slot[2] = -(k00 * a + k01 * b) * s2;
+                slot[3] = -(k00 * b + k01 * c) * s2;
+                slot[4] = -(k10 * b + k11 * c) * s2;
+                slot[5] = v[5];
+                slot[6] = v[6];
+                slot[7] = v[7];
+                slot[8] = v[8];
             }
+        }
+        __syncthreads();
+        // one atomic per (Gaussian, quantity) for the whole tile
+        for (int idx = tid; idx < int(cnt) * kAccRows; idx += kTilePix) {
+            const int k = idx / kAccRows, i = idx - k * kAccRows;
+            float sum = 0.f;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) sum += red[w][k][i];
+            if (sum != 0.f) atomicAdd(&acc[int64_t(i) * records + sR[k]], sum);
         }
     }
 }
@@ -259,6 +350,10 @@ __global__ void fill_f32_kernel(float *p, int64_t count, float v) {
 gs_status launch_project_backward(const gs_settings &s, const float *params, int64_t n,
                                   int64_t n_cap, const gs_view *views, int32_t n_views,
                                   const float *acc, float *grad, hipStream_t st);
+gs_status launch_project_backward_adam(const gs_settings &s, float *params, int64_t n, int64_t n_cap,
+                                       const gs_view *views, int32_t n_views, const float *acc,
+                                       float *m, float *v, const float *lr_rows, double beta1,
+                                       double beta2, double eps, int32_t step, hipStream_t st);
 
 static bool valid_settings(const gs_settings *s) {
     return s && s->sh_degree >= 0 && s->sh_degree <= 3 &&
@@ -289,17 +384,15 @@ extern "C" gs_status gs_render_fwd(const gs_settings *s, const void *proj_ws, in
     return GS_OK;
 }
 
-extern "C" gs_status gs_render_bwd(const gs_settings *s, const float *params, int64_t n,
-                                   int64_t n_cap, const gs_view *views, int32_t n_views,
-                                   const void *proj_ws, const void *sort_ws, int64_t pair_cap,
+extern "C" gs_status gs_raster_bwd(const gs_settings *s, const void *proj_ws, int64_t n_cap,
+                                   int32_t n_views, const void *sort_ws, int64_t pair_cap,
                                    const gs_target *targets, int32_t n_targets, int32_t total_tiles,
                                    const float *out_T, const int32_t *out_last,
-                                   const float *dL_drgb, void *accum_ws, float *grad,
-                                   void *stream) {
+                                   const float *dL_drgb, void *accum_ws, void *stream) {
     using namespace gs;
-    if (!valid_settings(s) || !params || !views || !proj_ws || !sort_ws || !targets || !out_T ||
-        !out_last || !dL_drgb || !accum_ws || !grad || n < 0 || n_cap <= 0 || n > n_cap ||
-        n_cap % 64 || n_views <= 0 || n_targets <= 0 || total_tiles <= 0 || pair_cap <= 0)
+    if (!valid_settings(s) || !proj_ws || !sort_ws || !targets || !out_T || !out_last || !dL_drgb ||
+        !accum_ws || n_cap <= 0 || n_cap % 64 || n_views <= 0 || n_targets <= 0 ||
+        total_tiles <= 0 || pair_cap <= 0)
         return GS_ERR_INVALID_ARGUMENT;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t records = int64_t(n_views) * n_cap;
@@ -312,7 +405,66 @@ extern "C" gs_status gs_render_bwd(const gs_settings *s, const float *params, in
     hipLaunchKernelGGL(render_bwd_kernel, dim3(total_tiles), dim3(kTilePix), 0, st, *s, proj, n_cap,
                        srt, targets, n_targets, out_T, out_last, dL_drgb, acc, records);
     GS_CHECK_LAUNCH();
-    return launch_project_backward(*s, params, n, n_cap, views, n_views, acc, grad, st);
+    return GS_OK;
+}
+
+extern "C" gs_status gs_project_bwd(const gs_settings *s, const float *params, int64_t n,
+                                    int64_t n_cap, const gs_view *views, int32_t n_views,
+                                    const void *accum_ws, float *grad, void *stream) {
+    using namespace gs;
+    if (!valid_settings(s) || !params || !views || !accum_ws || !grad || n < 0 || n_cap <= 0 ||
+        n > n_cap || n_cap % 64 || n_views <= 0)
+        return GS_ERR_INVALID_ARGUMENT;
+    return launch_project_backward(*s, params, n, n_cap, views, n_views,
+                                   static_cast<const float *>(accum_ws), grad,
+                                   static_cast<hipStream_t>(stream));
+}
+
+extern "C" gs_status gs_project_bwd_adam(const gs_settings *s, float *params, int64_t n,
+                                         int64_t n_cap, const gs_view *views, int32_t n_views,
+                                         const void *accum_ws, float *m, float *v,
+                                         const float *lr_rows, double beta1, double beta2,
+                                         double eps, int32_t step, void *stream) {
+    using namespace gs;
+    if (!valid_settings(s) || !params || !views || !accum_ws || !m || !v || !lr_rows || n < 0 ||
+        n_cap <= 0 || n > n_cap || n_cap % 64 || n_views <= 0 || step < 1 ||
+        !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) || !(eps >= 0.0))
+        return GS_ERR_INVALID_ARGUMENT;
+    return launch_project_backward_adam(*s, params, n, n_cap, views, n_views,
+                                        static_cast<const float *>(accum_ws), m, v, lr_rows, beta1,
+                                        beta2, eps, step, static_cast<hipStream_t>(stream));
+}
+
+extern "C" gs_status gs_render_bwd(const gs_settings *s, const float *params, int64_t n,
+                                   int64_t n_cap, const gs_view *views, int32_t n_views,
+                                   const void *proj_ws, const void *sort_ws, int64_t pair_cap,
+                                   const gs_target *targets, int32_t n_targets, int32_t total_tiles,
+                                   const float *out_T, const int32_t *out_last,
+                                   const float *dL_drgb, void *accum_ws, float *grad,
+                                   void *stream) {
+    if (!params || !grad || n < 0 || n > n_cap || !views) return GS_ERR_INVALID_ARGUMENT;
+    gs_status r = gs_raster_bwd(s, proj_ws, n_cap, n_views, sort_ws, pair_cap, targets, n_targets,
+                                total_tiles, out_T, out_last, dL_drgb, accum_ws, stream);
+    if (r != GS_OK) return r;
+    return gs_project_bwd(s, params, n, n_cap, views, n_views, accum_ws, grad, stream);
+}
+
+extern "C" gs_status gs_render_bwd_adam(const gs_settings *s, float *params, int64_t n,
+                                        int64_t n_cap, const gs_view *views, int32_t n_views,
+                                        const void *proj_ws, const void *sort_ws, int64_t pair_cap,
+                                        const gs_target *targets, int32_t n_targets,
+                                        int32_t total_tiles, const float *out_T,
+                                        const int32_t *out_last, const float *dL_drgb,
+                                        void *accum_ws, float *m, float *v, const float *lr_rows,
+                                        double beta1, double beta2, double eps, int32_t step,
+                                        void *stream) {
+    if (!params || !m || !v || !lr_rows || n < 0 || n > n_cap || !views || step < 1)
+        return GS_ERR_INVALID_ARGUMENT;
+    gs_status r = gs_raster_bwd(s, proj_ws, n_cap, n_views, sort_ws, pair_cap, targets, n_targets,
+                                total_tiles, out_T, out_last, dL_drgb, accum_ws, stream);
+    if (r != GS_OK) return r;
+    return gs_project_bwd_adam(s, params, n, n_cap, views, n_views, accum_ws, m, v, lr_rows, beta1,
+                               beta2, eps, step, stream);
 }
 
 extern "C" gs_status gs_fill(float *dst, int64_t count, float value, void *stream) {

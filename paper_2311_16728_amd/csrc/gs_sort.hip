@@ -46,22 +46,29 @@ __device__ __forceinline__ bool tile_rect(const gs_settings &s, double2 md, floa
     return true;
 }
 
-// counts[t * n_cap + g] = number of tiles of target t touched by Gaussian g.
+// counts[t * n_cap + g] = number of tiles of target t touched by Gaussian g;
+// rects[...] = its tile rectangle packed as (x0 | x1 << 16, y0 | y1 << 16).
 __global__ void __launch_bounds__(256) count_kernel(gs_settings s, Proj proj, int64_t n, int64_t n_cap,
                                                     const gs_target *__restrict__ targets,
-                                                    uint32_t *__restrict__ counts) {
+                                                    uint32_t *__restrict__ counts,
+                                                    uint2 *__restrict__ rects) {
     const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int ti = blockIdx.y;
     if (g >= n_cap) return;
     uint32_t c = 0;
+    uint2 packed = make_uint2(0u, 0u);
     if (g < n) {
         const gs_target t = targets[ti];
         const int64_t r = int64_t(t.view) * n_cap + g;
         Rect rc;
-        if (tile_rect(s, proj.mean[r], proj.cov_o[r], proj.rgb_z[r].w, t, rc))
+        if (tile_rect(s, proj.mean[r], proj.cov_o[r], proj.rgb_z[r].w, t, rc)) {
             c = uint32_t(rc.x1 - rc.x0 + 1) * uint32_t(rc.y1 - rc.y0 + 1);
+            packed = make_uint2(uint32_t(rc.x0) | (uint32_t(rc.x1) << 16),
+                                uint32_t(rc.y0) | (uint32_t(rc.y1) << 16));
+        }
     }
     counts[int64_t(ti) * n_cap + g] = c;
+    rects[int64_t(ti) * n_cap + g] = packed;
 }
 
 // ---------------------------------------------------------------------------
@@ -182,37 +189,65 @@ __global__ void __launch_bounds__(256) offsets_scatter_kernel(const uint32_t *__
     }
 }
 
-// One thread per sorted visible record writes its (tile, source) pairs.
-__global__ void __launch_bounds__(256) emit_kernel(gs_settings s, Proj proj, int64_t n_cap,
-                                                   const gs_target *__restrict__ targets,
+// Pair emission, one thread per output pair.  A block takes 256 consecutive
+// pair slots; the records covering them (at most 256, each has >= 1 pair) are
+// found with one binary search over the sorted records' offsets, staged in LDS,
+// and each thread locates its record by a second search there.  Near-camera
+// Gaussians that cover thousands of tiles are thus spread over many threads.
+__global__ void __launch_bounds__(256) emit_kernel(int64_t n_cap, const gs_target *__restrict__ targets,
                                                    uint32_t *__restrict__ counters,
                                                    const uint32_t *__restrict__ vis_val,
                                                    const uint32_t *__restrict__ vis_off,
-                                                   int64_t pair_cap, uint32_t *__restrict__ pkey,
+                                                   const uint2 *__restrict__ rects, int64_t pair_cap,
+                                                   uint32_t *__restrict__ pkey,
                                                    uint32_t *__restrict__ pval,
                                                    uint32_t *__restrict__ d_status) {
-    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    __shared__ uint32_t off[kScanThreads + 1];
+    __shared__ uint32_t first;
     const uint32_t V = counters[kVisible];
-    if (j == 0) {
-        const uint32_t P = counters[kPairs];
-        const bool over = int64_t(P) > pair_cap;
-        counters[kPairsClamped] = over ? uint32_t(pair_cap) : P;
-        if (over && d_status) atomicOr(d_status, GS_STATUS_PAIR_OVERFLOW);
+    const uint32_t P = counters[kPairs];
+    const uint32_t Pc = int64_t(P) > pair_cap ? uint32_t(pair_cap) : P;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        counters[kPairsClamped] = Pc;
+        if (Pc != P && d_status) atomicOr(d_status, GS_STATUS_PAIR_OVERFLOW);
     }
-    if (j >= V) return;
-    const uint32_t src = vis_val[j];
-    const int64_t ti = src / n_cap, g = src - ti * n_cap;
-    const gs_target t = targets[ti];
-    const int64_t r = int64_t(t.view) * n_cap + g;
-    Rect rc;
-    if (!tile_rect(s, proj.mean[r], proj.cov_o[r], proj.rgb_z[r].w, t, rc)) return;
-    int64_t o = vis_off[j];
-    for (int ty = rc.y0; ty <= rc.y1; ++ty)
-        for (int tx = rc.x0; tx <= rc.x1; ++tx, ++o) {
-            if (o >= pair_cap) return;
-            pkey[o] = uint32_t(t.tile_offset + ty * t.tiles_x + tx);
-            pval[o] = src;
+    if (V == 0) return;   // no visible record, no pair (Pc == 0)
+    for (int64_t chunk = blockIdx.x; chunk * kScanThreads < Pc; chunk += gridDim.x) {
+        const uint32_t o0 = uint32_t(chunk * kScanThreads);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            // last record j with vis_off[j] <= o0
+            uint32_t lo = 0, hi = V - 1;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi + 1) >> 1;
+                if (vis_off[mid] <= o0) lo = mid; else hi = mid - 1;
+            }
+            first = lo;
         }
+        __syncthreads();
+        const uint32_t j0 = first;
+        for (int i = threadIdx.x; i <= kScanThreads; i += blockDim.x) {
+            const uint32_t j = j0 + i;
+            off[i] = (j < V) ? vis_off[j] : 0xffffffffu;
+        }
+        __syncthreads();
+        const uint32_t o = o0 + threadIdx.x;
+        if (o >= Pc) continue;
+        int lo = 0, hi = kScanThreads;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (off[mid] <= o) lo = mid; else hi = mid - 1;
+        }
+        const uint32_t src = vis_val[j0 + lo];
+        const uint32_t k = o - off[lo];
+        const uint2 rc = rects[src];
+        const uint32_t x0 = rc.x & 0xffffu, x1 = rc.x >> 16, y0 = rc.y & 0xffffu;
+        const uint32_t w = x1 - x0 + 1;
+        const uint32_t ti = src / uint32_t(n_cap);
+        const gs_target &t = targets[ti];
+        pkey[o] = uint32_t(t.tile_offset) + (y0 + k / w) * uint32_t(t.tiles_x) + x0 + k % w;
+        pval[o] = src;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -315,7 +350,7 @@ __global__ void __launch_bounds__(256) radix_scatter_kernel(
 
 struct SortBufs {
     uint32_t *counters, *counts, *vk[2], *vv[2], *voff, *pk[2], *pv[2], *bsum, *hist, *digit;
-    uint2 *ranges;
+    uint2 *ranges, *rects;
     int64_t max_blocks;
 };
 
@@ -335,6 +370,7 @@ static SortBufs sort_bufs(void *ws, int64_t S, int64_t pair_cap, int32_t total_t
     B.hist = u(L.hist);
     B.digit = u(L.digit);
     B.ranges = reinterpret_cast<uint2 *>(b + L.ranges);
+    B.rects = reinterpret_cast<uint2 *>(b + L.rects);
     B.max_blocks = L.max_blocks;
     return B;
 }
@@ -366,12 +402,13 @@ __global__ void fill_u32_kernel(uint32_t *p, int64_t count, uint32_t v) {
 __global__ void __launch_bounds__(256) ranges_kernel(const uint32_t *__restrict__ counters,
                                                      const uint32_t *__restrict__ keys,
                                                      uint2 *__restrict__ ranges) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const uint32_t P = counters[kPairsClamped];
-    if (i >= P) return;
-    const uint32_t k = keys[i];
-    if (i == 0 || keys[i - 1] != k) ranges[k].x = uint32_t(i);
-    if (i == P - 1 || keys[i + 1] != k) ranges[k].y = uint32_t(i + 1);
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < P;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const uint32_t k = keys[i];
+        if (i == 0 || keys[i - 1] != k) ranges[k].x = uint32_t(i);
+        if (i == P - 1 || keys[i + 1] != k) ranges[k].y = uint32_t(i + 1);
+    }
 }
 
 }  // namespace gs
@@ -394,7 +431,7 @@ extern "C" gs_status gs_bin_sort(const gs_settings *s, const void *proj_ws, int6
     hipLaunchKernelGGL(fill_u32_kernel, dim3((2 * int64_t(total_tiles) + 255) / 256), dim3(256), 0, st,
                        reinterpret_cast<uint32_t *>(B.ranges), 2 * int64_t(total_tiles), 0u);
     hipLaunchKernelGGL(count_kernel, dim3((n_cap + 255) / 256, n_targets), dim3(256), 0, st, *s, proj,
-                       n, n_cap, targets, B.counts);
+                       n, n_cap, targets, B.counts, B.rects);
     // compact visible records
     const int64_t sblocks = (S + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(compact_reduce_kernel, dim3(sblocks), dim3(256), 0, st, B.counts, S, B.bsum);
@@ -411,14 +448,17 @@ extern "C" gs_status gs_bin_sort(const gs_settings *s, const void *proj_ws, int6
                        B.counters + kPairs, int64_t(0));
     hipLaunchKernelGGL(offsets_scatter_kernel, dim3(sblocks), dim3(256), 0, st, B.counters + kVisible,
                        B.counts, B.vv[cur], B.bsum, B.voff);
-    hipLaunchKernelGGL(emit_kernel, dim3(sblocks * (kScanTile / 256)), dim3(256), 0, st, *s, proj, n_cap,
-                       targets, B.counters, B.vv[cur], B.voff, pair_cap, B.pk[0], B.pv[0], d_status);
+    const int64_t pair_chunks = (pair_cap + kScanThreads - 1) / kScanThreads;
+    const int64_t persistent = 256 * 16;   // 16 workgroups per CU, grid-stride beyond
+    hipLaunchKernelGGL(emit_kernel, dim3(pair_chunks < persistent ? pair_chunks : persistent), dim3(256), 0,
+                       st, n_cap, targets, B.counters, B.vv[cur], B.voff, B.rects, pair_cap, B.pk[0],
+                       B.pv[0], d_status);
     // tile order
     const int64_t pblocks = (pair_cap + kScanTile - 1) / kScanTile;
     const int passes = tile_sort_passes(total_tiles);
     int pc = radix_sort(B.counters + kPairsClamped, B.pk, B.pv, 0, 0, passes, pblocks, B, st);
-    hipLaunchKernelGGL(ranges_kernel, dim3((pair_cap + 255) / 256), dim3(256), 0, st, B.counters,
-                       B.pk[pc], B.ranges);
+    hipLaunchKernelGGL(ranges_kernel, dim3(pair_chunks < persistent ? pair_chunks : persistent), dim3(256),
+                       0, st, B.counters, B.pk[pc], B.ranges);
     GS_CHECK_LAUNCH();
     return GS_OK;
 }

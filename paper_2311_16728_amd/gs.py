@@ -64,6 +64,13 @@ def _load():
         "gs_render_fwd": ([S, vp, i64, i32, vp, i64, vp, i32, i32, vp, vp, vp, vp, vp], C.c_int),
         "gs_render_bwd": ([S, vp, i64, i64, vp, i32, vp, vp, i64, vp, i32, i32, vp, vp, vp, vp,
                            vp, vp], C.c_int),
+        "gs_raster_bwd": ([S, vp, i64, i32, vp, i64, vp, i32, i32, vp, vp, vp, vp, vp], C.c_int),
+        "gs_project_bwd": ([S, vp, i64, i64, vp, i32, vp, vp, vp], C.c_int),
+        "gs_project_bwd_adam": ([S, vp, i64, i64, vp, i32, vp, vp, vp, C.POINTER(C.c_float), C.c_double,
+                                 C.c_double, C.c_double, i32, vp], C.c_int),
+        "gs_render_bwd_adam": ([S, vp, i64, i64, vp, i32, vp, vp, i64, vp, i32, i32, vp, vp, vp, vp,
+                                vp, vp, C.POINTER(C.c_float), C.c_double, C.c_double, C.c_double,
+                                i32, vp], C.c_int),
         "gs_pyramid_build": ([vp, i32, i32, i32, i32, vp, vp], C.c_int),
         "gs_pyramid_loss": ([vp, vp, vp, i32, i32, i64, f32, vp, vp, vp, vp, vp], C.c_int),
         "gs_adam_step": ([vp, vp, vp, vp, i64, i64, C.POINTER(C.c_float), C.c_double, C.c_double,
@@ -79,7 +86,9 @@ def _load():
 
 _lib = _load()
 EXPORTED = ["gs_status_string", "gs_default_settings", "gs_targets_layout", "gs_workspace_query",
-            "gs_preprocess", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd", "gs_pyramid_build",
+            "gs_preprocess", "gs_bin_sort", "gs_render_fwd", "gs_raster_bwd", "gs_project_bwd",
+            "gs_project_bwd_adam", "gs_render_bwd", "gs_render_bwd_adam",
+            "gs_pyramid_build",
             "gs_pyramid_loss", "gs_adam_step", "gs_fill"]
 
 
@@ -185,6 +194,37 @@ def gs_render_bwd(settings, params, n, views_dev, n_views, proj_ws, sort_ws, pai
                               n_views, _p(proj_ws), _p(sort_ws), pair_cap, _p(targets_dev),
                               n_targets, total_tiles, _p(out_T), _p(out_last), _p(dL_drgb),
                               _p(accum_ws), _p(grad), _stream(stream)), "gs_render_bwd")
+
+
+def gs_raster_bwd(settings, proj_ws, n_cap, n_views, sort_ws, pair_cap, targets_dev, n_targets,
+                  total_tiles, out_T, out_last, dL_drgb, accum_ws, stream=None):
+    _check(_lib.gs_raster_bwd(C.byref(settings), _p(proj_ws), n_cap, n_views, _p(sort_ws), pair_cap,
+                              _p(targets_dev), n_targets, total_tiles, _p(out_T), _p(out_last),
+                              _p(dL_drgb), _p(accum_ws), _stream(stream)), "gs_raster_bwd")
+
+
+def gs_project_bwd(settings, params, n, views_dev, n_views, accum_ws, grad, stream=None):
+    _check(_lib.gs_project_bwd(C.byref(settings), _p(params), n, params.shape[1], _p(views_dev),
+                               n_views, _p(accum_ws), _p(grad), _stream(stream)), "gs_project_bwd")
+
+
+def gs_project_bwd_adam(settings, params, n, views_dev, n_views, accum_ws, m, v, lr_rows, step,
+                        beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
+    lr = (C.c_float * NUM_ROWS)(*[float(x) for x in lr_rows])
+    _check(_lib.gs_project_bwd_adam(C.byref(settings), _p(params), n, params.shape[1], _p(views_dev),
+                                    n_views, _p(accum_ws), _p(m), _p(v), lr, beta1, beta2, eps, step,
+                                    _stream(stream)), "gs_project_bwd_adam")
+
+
+def gs_render_bwd_adam(settings, params, n, views_dev, n_views, proj_ws, sort_ws, pair_cap,
+                       targets_dev, n_targets, total_tiles, out_T, out_last, dL_drgb, accum_ws, m, v,
+                       lr_rows, step, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
+    lr = (C.c_float * NUM_ROWS)(*[float(x) for x in lr_rows])
+    _check(_lib.gs_render_bwd_adam(C.byref(settings), _p(params), n, params.shape[1], _p(views_dev),
+                                   n_views, _p(proj_ws), _p(sort_ws), pair_cap, _p(targets_dev),
+                                   n_targets, total_tiles, _p(out_T), _p(out_last), _p(dL_drgb),
+                                   _p(accum_ws), _p(m), _p(v), lr, beta1, beta2, eps, step,
+                                   _stream(stream)), "gs_render_bwd_adam")
 
 
 def gs_pyramid_build(img, levels, out, stream=None):

@@ -130,13 +130,25 @@ class Mapper:
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
 
-    def step(self, plan: RenderPlan, target_rgb: torch.Tensor, lam: float = LAMBDA, stream=None):
-        """One iteration: render every target, Eq. 4 loss, backward, Adam."""
+    def step(self, plan: RenderPlan, target_rgb: torch.Tensor, lam: float = LAMBDA, fused: bool = True,
+             stream=None):
+        """One iteration: render every target, Eq. 4 loss, backward, Adam.
+
+        fused=True applies Adam inside the backward's per-Gaussian pass
+        (gs_render_bwd_adam); fused=False runs gs_render_bwd into a zeroed
+        gradient and then gs_adam_step."""
         plan.render(self.params, self.n, stream=stream)
         plan.loss(target_rgb, lam, True, stream)
-        gs.gs_fill(self.grad, 0.0, stream)
-        plan.backward(self.params, self.n, plan.dL, self.grad, stream)
         self.step_count += 1
-        gs.gs_adam_step(self.params, self.grad, self.m, self.v, self.n, self.lr_rows, self.step_count,
-                        self.beta1, self.beta2, self.eps, stream)
+        if fused:
+            gs.gs_render_bwd_adam(plan.settings, self.params, self.n, plan.views_dev, plan.n_views,
+                                  plan.proj_ws, plan.sort_ws, plan.pair_cap, plan.targets_dev,
+                                  plan.n_targets, plan.total_tiles, plan.T, plan.last, plan.dL,
+                                  plan.accum_ws, self.m, self.v, self.lr_rows, self.step_count,
+                                  self.beta1, self.beta2, self.eps, stream)
+        else:
+            gs.gs_fill(self.grad, 0.0, stream)
+            plan.backward(self.params, self.n, plan.dL, self.grad, stream)
+            gs.gs_adam_step(self.params, self.grad, self.m, self.v, self.n, self.lr_rows,
+                            self.step_count, self.beta1, self.beta2, self.eps, stream)
         return plan.d_total

@@ -106,7 +106,7 @@ def test_tile_lists_sorted_and_complete(orc):
     up = lambda x: (x + 255) // 256 * 256
     offs = {}
     o = 0
-    for nm, nbytes in [("counters", 64), ("counts", 4 * S), ("vk0", 4 * S), ("vk1", 4 * S),
+    for nm, nbytes in [("counters", 64), ("counts", 4 * S), ("rects", 8 * S), ("vk0", 4 * S), ("vk1", 4 * S),
                        ("vv0", 4 * S), ("vv1", 4 * S), ("voff", 4 * (S + 1)),
                        ("pk0", 4 * plan.pair_cap), ("pk1", 4 * plan.pair_cap),
                        ("pv0", 4 * plan.pair_cap), ("pv1", 4 * plan.pair_cap),
@@ -286,3 +286,29 @@ def test_tiny_end_to_end_step(orc):
     frac_ok = (d[strong] <= 2e-6 + 1e-6 * np.abs(pp[:, :n][strong])).mean()
     print("fraction of resolved updates matching:", frac_ok)
     assert frac_ok >= 0.995
+
+
+def test_fused_backward_adam_matches_unfused(orc):
+    """gs_render_bwd_adam == gs_render_bwd into a zeroed gradient + gs_adam_step."""
+    from paper_2311_16728_amd.mapper import Mapper
+
+    p, tp, cam = scenes.tiny_scene(2)
+    n = 2000
+    target = orc.render(tp, n, cam)["img"].astype(np.float32)
+    tgt = _dev(target).reshape(-1).contiguous()
+    outs = []
+    for fused in (False, True):
+        plan = plan_for([cam], n_cap=p.shape[1])
+        mp = Mapper(_dev(p), n)
+        for _ in range(3):
+            mp.step(plan, tgt, lam=0.2, fused=fused)
+        torch.cuda.synchronize()
+        outs.append((mp.params.cpu().numpy(), mp.m.cpu().numpy(), mp.v.cpu().numpy()))
+    (p0, m0, v0), (p1, m1, v1) = outs
+    # atomics order differs between runs: compare to FP32 summation noise
+    assert np.abs(m1 - m0).max() <= 1e-5 * np.abs(m0).max()
+    assert np.abs(v1 - v0).max() <= 1e-4 * np.abs(v0).max()
+    moved = np.abs(p0 - p) > 0
+    frac = (np.abs(p1 - p0) <= 1e-6 + 1e-5 * np.abs(p0))[moved].mean()
+    assert frac >= 0.999, frac
+    assert np.all(p1[:, n:] == p[:, n:])

@@ -216,3 +216,19 @@ def test_gradient_2d_zero_for_invisible(orc):
     Wt = np.ones((3, cam["height"], cam["width"]))
     g = orc.render_backward(p, 40, cam, Wt)
     assert np.all(g[:, 0] == 0)
+
+
+def test_footprint_fd_equals_full_render_fd(orc):
+    """The footprint-local finite difference equals the one from full re-renders."""
+    p, cam = _tiny(5, n=30, W=24, H=24)
+    n = 30
+    Wt = np.random.default_rng(2).uniform(-1, 1, (3, 24, 24))
+    rows = np.array([0, 2, 4, 7, 10, 11, 20, 58], np.int32)
+    for gid in (3, 17):
+        fd, changed = orc.fd_gauss(p, n, cam, Wt, gid, rows, h=1e-4)
+        for k, r in enumerate(rows):
+            pp, pm = p.copy(), p.copy()
+            pp[r, gid] += 1e-4
+            pm[r, gid] -= 1e-4
+            ref = ((orc.render(pp, n, cam)["img"] - orc.render(pm, n, cam)["img"]) * Wt).sum() / 2e-4
+            assert fd[k] == pytest.approx(ref, rel=1e-7, abs=1e-9)
