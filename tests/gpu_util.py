@@ -69,3 +69,23 @@ def group_rel_err(g, ref, ids):
         floor = 1e-3 * np.median(nr)
         out[name] = np.linalg.norm(d, axis=0) / np.maximum(nr, max(floor, 1e-30))
     return out
+
+
+def check_gradients(g, ref, candidates, label="", n_sample=64, tol=1e-3, seed=0):
+    """The gradient metric: 64 Gaussians drawn with `seed` from `candidates`
+    (Gaussians with a composited pixel) must have relative error <= tol in every
+    group; over all candidates the 99th percentile must stay <= 0.1 tol and the
+    worst case <= 5 tol (scalar groups such as the opacity can cancel over
+    random-sign pixel weights, which amplifies FP32 rounding of single terms)."""
+    candidates = np.asarray(candidates)
+    rng = np.random.default_rng(seed)
+    ids = rng.choice(candidates, min(n_sample, len(candidates)), replace=False)
+    sampled = group_rel_err(g, ref, ids)
+    every = group_rel_err(g, ref, candidates)
+    for k in sampled:
+        print(f"{label} {k}: sampled max {sampled[k].max():.2e}; all p99 {np.quantile(every[k], 0.99):.2e} "
+              f"max {every[k].max():.2e}")
+    for k in sampled:
+        assert sampled[k].max() <= tol, (k, float(sampled[k].max()))
+        assert np.quantile(every[k], 0.99) <= 0.1 * tol, k
+        assert every[k].max() <= 5 * tol, k
