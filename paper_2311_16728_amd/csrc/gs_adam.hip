@@ -25,7 +25,7 @@ __global__ void __launch_bounds__(256) adam_kernel(float4 *__restrict__ p, const
         if (c >= n) return;
         mv = b1 * mv + omb1 * gv;
         vvv = b2 * vvv + omb2 * gv * gv;
-        pv -= rate * mv / (sqrtf(vvv) * isqbc2 + eps);
+        pv -= rate * mv * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(vvv) * isqbc2 + eps);
     };
     step(pp.x, gg.x, mm.x, vv.x, col);
     step(pp.y, gg.y, mm.y, vv.y, col + 1);

@@ -243,29 +243,55 @@ __global__ void __launch_bounds__(256) preprocess_kernel(gs_settings s, const fl
 
 // Gradient sinks of the projection backward: accumulate into a gradient
 // buffer, or apply the Adam update to the parameter right away (the gradient
-// then never leaves registers).
+// then never leaves registers).  Both take a group of rows (first, stride,
+// count) so every load of the group is issued before the first store.
 struct GradSink {
-    float *grad;
-    __device__ __forceinline__ void operator()(int row, int64_t g, int64_t n_cap, float v) const {
-        grad[row * n_cap + g] += v;
+    float *__restrict__ grad;
+    template <int N>
+    __device__ __forceinline__ void group(int first, int stride, int64_t g, int64_t n_cap,
+                                          const float (&val)[N]) const {
+        float cur[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) cur[j] = grad[int64_t(first + j * stride) * n_cap + g];
+#pragma unroll
+        for (int j = 0; j < N; ++j) grad[int64_t(first + j * stride) * n_cap + g] = cur[j] + val[j];
     }
     __device__ __forceinline__ void untouched(int64_t, int64_t) const {}
 };
 
 struct AdamSink {
-    float *p, *m, *v;
+    float *__restrict__ p;
+    float *__restrict__ m;
+    float *__restrict__ v;
     LrRows lr;
     float b1, omb1, b2, omb2, eps, ibc1, isqbc2;
-    __device__ __forceinline__ void operator()(int row, int64_t g, int64_t n_cap, float gv) const {
-        const int64_t i = row * n_cap + g;
-        const float mv = b1 * m[i] + omb1 * gv;
-        const float vv = b2 * v[i] + omb2 * gv * gv;
-        m[i] = mv;
-        v[i] = vv;
-        p[i] -= lr.lr[row] * ibc1 * mv / (sqrtf(vv) * isqbc2 + eps);
+    template <int N>
+    __device__ __forceinline__ void group(int first, int stride, int64_t g, int64_t n_cap,
+                                          const float (&gv)[N]) const {
+        float pp[N], mm[N], vv[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const int64_t i = int64_t(first + j * stride) * n_cap + g;
+            pp[j] = p[i];
+            mm[j] = m[i];
+            vv[j] = v[i];
+        }
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const int64_t i = int64_t(first + j * stride) * n_cap + g;
+            const float mv = b1 * mm[j] + omb1 * gv[j];
+            const float vq = b2 * vv[j] + omb2 * gv[j] * gv[j];
+            m[i] = mv;
+            v[i] = vq;
+            // hardware sqrt and reciprocal (1 ulp each) keep the unrolled group short
+            const float den = __builtin_amdgcn_sqrtf(vq) * isqbc2 + eps;
+            p[i] = pp[j] - lr.lr[first + j * stride] * ibc1 * mv * __builtin_amdgcn_rcpf(den);
+        }
     }
     __device__ __forceinline__ void untouched(int64_t g, int64_t n_cap) const {
-        for (int r = 0; r < kRows; ++r) (*this)(r, g, n_cap, 0.f);
+        const float z[1] = {0.f};
+#pragma unroll 1
+        for (int r = 0; r < kRows; ++r) group(r, 1, g, n_cap, z);
     }
 };
 
@@ -280,86 +306,92 @@ __global__ void __launch_bounds__(256) project_backward_kernel(
     int64_t records, Sink sink) {
     const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (g >= n) return;
-    Gauss G;
-    load_gauss(P, n_cap, g, G);
     const int nk = (s.sh_degree + 1) * (s.sh_degree + 1);
     float gmu[3] = {0, 0, 0}, gop = 0.f;
     float dSig[6] = {0, 0, 0, 0, 0, 0};   // summed over views: 00 01 02 11 12 22 (matrix entries)
+    float mu[3];
     bool any_view = false;
 
-    for (int v = 0; v < n_views; ++v) {
-        const int64_t r = int64_t(v) * n_cap + g;
-        float a[6];
+    {   // 1. geometry, view by view: 2D mean and covariance back to mean and Sigma
+        Gauss G;
+        load_gauss(P, n_cap, g, G);
+        mu[0] = G.mu[0]; mu[1] = G.mu[1]; mu[2] = G.mu[2];
+        for (int v = 0; v < n_views; ++v) {
+            const int64_t r = int64_t(v) * n_cap + g;
+            float a[kAccRows];
 #pragma unroll
-        for (int i = 0; i < 6; ++i) a[i] = acc[i * records + r];
-        bool any = false;
+            for (int i = 0; i < kAccRows; ++i) a[i] = acc[i * records + r];
+            bool any = false;
 #pragma unroll
-        for (int i = 0; i < kAccRows; ++i) any |= (acc[i * records + r] != 0.f);
-        if (!any) continue;
-        any_view = true;
-        const Cam c = load_cam(views[v], s.fov_clamp);
-        Proj2 p;
-        if (!project(G, c, s.znear, p)) continue;
-        const float z = p.xc[2], iz = 1.f / z, iz2 = iz * iz;
-        const float G00 = a[2], G01 = a[3], G11 = a[4];
-        {   // dL/dSigma = T^T G T
-            float GT[6];
+            for (int i = 0; i < kAccRows; ++i) any |= (a[i] != 0.f);
+            if (!any) continue;
+            any_view = true;
+            const Cam c = load_cam(views[v], s.fov_clamp);
+            Proj2 p;
+            if (!project(G, c, s.znear, p)) continue;
+            const float z = p.xc[2], iz = 1.f / z, iz2 = iz * iz;
+            const float G00 = a[2], G01 = a[3], G11 = a[4];
+            {   // dL/dSigma = T^T G T
+                float GT[6];
+#pragma unroll
+                for (int jj = 0; jj < 3; ++jj) {
+                    GT[jj] = G00 * p.T[jj] + G01 * p.T[3 + jj];
+                    GT[3 + jj] = G01 * p.T[jj] + G11 * p.T[3 + jj];
+                }
+                auto e = [&](int ii, int jj) { return p.T[ii] * GT[jj] + p.T[3 + ii] * GT[3 + jj]; };
+                dSig[0] += e(0, 0); dSig[1] += e(0, 1); dSig[2] += e(0, 2);
+                dSig[3] += e(1, 1); dSig[4] += e(1, 2); dSig[5] += e(2, 2);
+            }
+            // dL/dT = 2 G T Sigma; dL/dJ = dL/dT W^T
+            float TS[6];
+            {
+                const float *S = G.Sig;
+#pragma unroll
+                for (int r2 = 0; r2 < 2; ++r2) {
+                    const float a0 = p.T[3 * r2], b0 = p.T[3 * r2 + 1], d0 = p.T[3 * r2 + 2];
+                    TS[3 * r2 + 0] = a0 * S[0] + b0 * S[1] + d0 * S[2];
+                    TS[3 * r2 + 1] = a0 * S[1] + b0 * S[3] + d0 * S[4];
+                    TS[3 * r2 + 2] = a0 * S[2] + b0 * S[4] + d0 * S[5];
+                }
+            }
+            float dT[6];
 #pragma unroll
             for (int jj = 0; jj < 3; ++jj) {
-                GT[jj] = G00 * p.T[jj] + G01 * p.T[3 + jj];
-                GT[3 + jj] = G01 * p.T[jj] + G11 * p.T[3 + jj];
+                dT[jj] = 2.f * (G00 * TS[jj] + G01 * TS[3 + jj]);
+                dT[3 + jj] = 2.f * (G01 * TS[jj] + G11 * TS[3 + jj]);
             }
-            auto e = [&](int ii, int jj) { return p.T[ii] * GT[jj] + p.T[3 + ii] * GT[3 + jj]; };
-            dSig[0] += e(0, 0); dSig[1] += e(0, 1); dSig[2] += e(0, 2);
-            dSig[3] += e(1, 1); dSig[4] += e(1, 2); dSig[5] += e(2, 2);
-        }
-        // dL/dT = 2 G T Sigma; dL/dJ = dL/dT W^T
-        float TS[6];
-        {
-            const float *S = G.Sig;
-#pragma unroll
-            for (int r2 = 0; r2 < 2; ++r2) {
-                const float a0 = p.T[3 * r2], b0 = p.T[3 * r2 + 1], d0 = p.T[3 * r2 + 2];
-                TS[3 * r2 + 0] = a0 * S[0] + b0 * S[1] + d0 * S[2];
-                TS[3 * r2 + 1] = a0 * S[1] + b0 * S[3] + d0 * S[4];
-                TS[3 * r2 + 2] = a0 * S[2] + b0 * S[4] + d0 * S[5];
+            const float dJ00 = dT[0] * c.R[0] + dT[1] * c.R[1] + dT[2] * c.R[2];
+            const float dJ02 = dT[0] * c.R[6] + dT[1] * c.R[7] + dT[2] * c.R[8];
+            const float dJ11 = dT[3] * c.R[3] + dT[4] * c.R[4] + dT[5] * c.R[5];
+            const float dJ12 = dT[3] * c.R[6] + dT[4] * c.R[7] + dT[5] * c.R[8];
+            float gx[3] = {0.f, 0.f, 0.f};
+            // J00 = fx/z, J11 = fy/z, J02 = -fx ub/z, J12 = -fy vb/z
+            gx[2] += -(dJ00 * c.fx + dJ11 * c.fy) * iz2 + (dJ02 * c.fx * p.ub + dJ12 * c.fy * p.vb) * iz2;
+            if (!p.clampx) {
+                gx[0] += -dJ02 * c.fx * iz2;
+                gx[2] += dJ02 * c.fx * p.xc[0] * iz2 * iz;
             }
-        }
-        float dT[6];
+            if (!p.clampy) {
+                gx[1] += -dJ12 * c.fy * iz2;
+                gx[2] += dJ12 * c.fy * p.xc[1] * iz2 * iz;
+            }
+            // 2D mean (fx x/z + cx, fy y/z + cy)
+            gx[0] += a[0] * c.fx * iz;
+            gx[1] += a[1] * c.fy * iz;
+            gx[2] += -(a[0] * c.fx * p.xc[0] + a[1] * c.fy * p.xc[1]) * iz2;
 #pragma unroll
-        for (int jj = 0; jj < 3; ++jj) {
-            dT[jj] = 2.f * (G00 * TS[jj] + G01 * TS[3 + jj]);
-            dT[3 + jj] = 2.f * (G01 * TS[jj] + G11 * TS[3 + jj]);
+            for (int ii = 0; ii < 3; ++ii)
+                gmu[ii] += c.R[ii] * gx[0] + c.R[3 + ii] * gx[1] + c.R[6 + ii] * gx[2];
+            gop += a[5];
         }
-        const float dJ00 = dT[0] * c.R[0] + dT[1] * c.R[1] + dT[2] * c.R[2];
-        const float dJ02 = dT[0] * c.R[6] + dT[1] * c.R[7] + dT[2] * c.R[8];
-        const float dJ11 = dT[3] * c.R[3] + dT[4] * c.R[4] + dT[5] * c.R[5];
-        const float dJ12 = dT[3] * c.R[6] + dT[4] * c.R[7] + dT[5] * c.R[8];
-        float gx[3] = {0.f, 0.f, 0.f};
-        // J00 = fx/z, J11 = fy/z, J02 = -fx ub/z, J12 = -fy vb/z
-        gx[2] += -(dJ00 * c.fx + dJ11 * c.fy) * iz2 + (dJ02 * c.fx * p.ub + dJ12 * c.fy * p.vb) * iz2;
-        if (!p.clampx) {
-            gx[0] += -dJ02 * c.fx * iz2;
-            gx[2] += dJ02 * c.fx * p.xc[0] * iz2 * iz;
-        }
-        if (!p.clampy) {
-            gx[1] += -dJ12 * c.fy * iz2;
-            gx[2] += dJ12 * c.fy * p.xc[1] * iz2 * iz;
-        }
-        // 2D mean (fx x/z + cx, fy y/z + cy)
-        gx[0] += a[0] * c.fx * iz;
-        gx[1] += a[1] * c.fy * iz;
-        gx[2] += -(a[0] * c.fx * p.xc[0] + a[1] * c.fy * p.xc[1]) * iz2;
-#pragma unroll
-        for (int ii = 0; ii < 3; ++ii) gmu[ii] += c.R[ii] * gx[0] + c.R[3 + ii] * gx[1] + c.R[6 + ii] * gx[2];
-        gop += a[5];
     }
     if (!any_view) {   // no view touched this Gaussian: zero gradient
         sink.untouched(g, n_cap);
         return;
     }
 
-    // colour, one channel at a time: rgb = max(0, raw), raw = 0.5 + sum_k Y_k(d) sh_k
+    // 2. colour, one channel at a time: rgb = max(0, raw), raw = 0.5 + sum_k Y_k(d) sh_k
+#pragma unroll 1
     for (int ch = 0; ch < 3; ++ch) {
         float sh[16], gsh[16];
 #pragma unroll
@@ -372,7 +404,7 @@ __global__ void __launch_bounds__(256) project_backward_kernel(
             const float drgb = acc[(6 + ch) * records + r];
             if (drgb == 0.f) continue;
             const Cam c = load_cam(views[v], s.fov_clamp);
-            float d[3] = {G.mu[0] - c.C[0], G.mu[1] - c.C[1], G.mu[2] - c.C[2]};
+            float d[3] = {mu[0] - c.C[0], mu[1] - c.C[1], mu[2] - c.C[2]};
             const float dinv = rsqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
             const float dx = d[0] * dinv, dy = d[1] * dinv, dz = d[2] * dinv;
             float Y[16];
@@ -394,11 +426,19 @@ __global__ void __launch_bounds__(256) project_backward_kernel(
             gmu[1] += (gd[1] - dy * dot) * dinv;
             gmu[2] += (gd[2] - dz * dot) * dinv;
         }
+        // four groups of four rows: enough loads in flight, few registers
 #pragma unroll
-        for (int k = 0; k < 16; ++k) sink(11 + 3 * k + ch, g, n_cap, gsh[k]);
+        for (int q = 0; q < 4; ++q) {
+            const float part[4] = {gsh[4 * q], gsh[4 * q + 1], gsh[4 * q + 2], gsh[4 * q + 3]};
+            sink.group(11 + ch + 12 * q, 3, g, n_cap, part);
+        }
     }
 
-    // Sigma = M M^T, M = Rq diag(s): dM = 2 dSigma M (dSigma symmetric)
+    // 3. Sigma = M M^T, M = Rq diag(s): dM = 2 dSigma M (dSigma symmetric).
+    // The 11 geometric parameters are reloaded (SH rows may have been updated
+    // in place; these rows have not).
+    Gauss G;
+    load_gauss(P, n_cap, g, G);
     const float D[9] = {dSig[0], dSig[1], dSig[2], dSig[1], dSig[3], dSig[4], dSig[2], dSig[4], dSig[5]};
     float dM[9];
 #pragma unroll
@@ -432,13 +472,9 @@ __global__ void __launch_bounds__(256) project_backward_kernel(
 #pragma unroll
         for (int i = 0; i < 4; ++i) gq[i] = (dq[i] - G.q[i] * dot) * G.qinv;
     }
-#pragma unroll
-    for (int i = 0; i < 3; ++i) sink(i, g, n_cap, gmu[i]);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) sink(3 + i, g, n_cap, gls[i]);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) sink(6 + i, g, n_cap, gq[i]);
-    sink(10, g, n_cap, gop * G.o * (1.f - G.o));
+    const float geo[11] = {gmu[0], gmu[1], gmu[2], gls[0], gls[1], gls[2],
+                           gq[0], gq[1], gq[2], gq[3], gop * G.o * (1.f - G.o)};
+    sink.group(0, 1, g, n_cap, geo);
 }
 
 gs_status launch_project_backward(const gs_settings &s, const float *params, int64_t n,
