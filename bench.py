@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--pair-cap", type=int, default=1 << 26)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cpu-sample", type=float, default=0.05,
                     help="fraction of pixels the oracle baseline renders and differentiates")
     return ap.parse_args()
@@ -148,6 +149,13 @@ def main():
     p, tp, cams, plan, mapper, target = build_workload(args, torch)
     torch.cuda.synchronize()
     print(f"# workload ready: pairs={plan.pair_count()}", file=sys.stderr, flush=True)
+    tuned = None
+    if not args.no_autotune:
+        from paper_2311_16728_amd import autotune
+
+        tuned = autotune.tune(plan, mapper.params, mapper.n, target)
+        print(f"# autotuned: batch={tuned['batch']} bwd_waves={tuned['bwd_waves']} {tuned['ms']}",
+              file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
         mapper.step(plan, target)
@@ -235,6 +243,8 @@ def main():
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kernels.items()},
         "composited_pairs": composited,
+        "launch": {"batch": plan.settings.batch, "bwd_waves": plan.settings.bwd_waves,
+                   "autotune_ms": tuned["ms"] if tuned else None},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, n, cams, target.view(3, 680, 1200).cpu().numpy(),

@@ -60,14 +60,15 @@ typedef enum {
 
 /* Rasteriser settings.  Defaults (gs_default_settings): alpha_min 1/255,
  * alpha_max 0.99, t_min 1e-4, znear 0.2, dilation 0.3 px^2, fov_clamp 1.3,
- * sh_degree 3, batch 256.  A pixel composites a Gaussian iff its opacity
+ * sh_degree 3, batch 256, bwd_waves 2.  A pixel composites a Gaussian iff its opacity
  * there, o * exp(power), reaches alpha_min; the contribution uses
  * min(alpha_max, .); compositing stops before the Gaussian that would take
  * the transmittance below t_min (Eq. 3). */
 typedef struct {
     float alpha_min, alpha_max, t_min, znear, dilation, fov_clamp;
     int32_t sh_degree;   /* 0..3 */
-    int32_t batch;       /* Gaussians staged per LDS round: 64, 128 or 256 */
+    int32_t batch;       /* forward: Gaussians staged per LDS round: 64, 128 or 256 */
+    int32_t bwd_waves;   /* backward: waves per 16x16 tile, 1, 2 or 4 (4, 2 or 1 pixels per lane) */
 } gs_settings;
 
 /* A keyframe pose with its level-0 intrinsics and image size. */
@@ -162,8 +163,8 @@ gs_status gs_render_fwd(const gs_settings *s, const void *proj_ws, int64_t n_cap
  * stored) and accumulates, per (view, Gaussian), the gradients of the loss
  * with respect to the 2D mean (level-0 pixels), the undilated 2D covariance
  * (entries 00, 01, 11 of the symmetric matrix gradient), the opacity and the
- * colour into accum_ws (device, accum_bytes; float32 [9][n_views * n_cap],
- * rows in that order; cleared by this call).  dL_drgb (device) has the layout
+ * colour into accum_ws (device, accum_bytes; float32 [n_views * n_cap][9],
+ * the nine values of a record in that order; cleared by this call).  dL_drgb (device) has the layout
  * of out_rgb.  proj_ws, sort_ws, out_T, out_last as left by the forward. */
 gs_status gs_raster_bwd(const gs_settings *s, const void *proj_ws, int64_t n_cap,
                         int32_t n_views, const void *sort_ws, int64_t pair_cap,

@@ -23,6 +23,7 @@ extern "C" void gs_default_settings(gs_settings *s) {
     s->fov_clamp = 1.3f;
     s->sh_degree = 3;
     s->batch = 256;
+    s->bwd_waves = 2;
 }
 
 extern "C" gs_status gs_targets_layout(const gs_view *views, int32_t n_views, gs_target *targets,

@@ -61,8 +61,9 @@ struct SortLayout {
         SortLayout L;
         L.sources = sources;
         L.pair_cap = pair_cap;
-        int64_t big = sources > pair_cap ? sources : pair_cap;
-        L.max_blocks = (big + kScanTile - 1) / kScanTile + 1;
+        // radix blocks: 1024 keys per block for the record sort, 4096 for pairs
+        const int64_t rb = (sources + 1023) / 1024, pb = (pair_cap + kScanTile - 1) / kScanTile;
+        L.max_blocks = (rb > pb ? rb : pb) + 1;
         size_t o = 0;
         auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
         L.counters = take(sizeof(uint32_t) * kNumCounters);
@@ -114,9 +115,10 @@ struct LrRows {
     float lr[kRows];
 };
 
-// Per-(view, Gaussian) accumulators of 2D gradients, 9 rows of `records`:
-// d mean x, d mean y (level-0 pixels), d cov00, d cov01, d cov11 (undilated
-// level-0 covariance, symmetric-matrix entries), d opacity, d r, d g, d b.
+// Per-(view, Gaussian) accumulators of 2D gradients, [records][9] so that the
+// nine atomics of one record share a cache line: d mean x, d mean y (level-0
+// pixels), d cov00, d cov01, d cov11 (undilated level-0 covariance,
+// symmetric-matrix entries), d opacity, d r, d g, d b.
 constexpr int kAccRows = 9;
 static inline size_t accum_bytes(int64_t records) {
     return align_up(sizeof(float) * kAccRows * records, 256);

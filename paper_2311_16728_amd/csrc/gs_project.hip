@@ -320,7 +320,7 @@ __global__ void __launch_bounds__(256) project_backward_kernel(
             const int64_t r = int64_t(v) * n_cap + g;
             float a[kAccRows];
 #pragma unroll
-            for (int i = 0; i < kAccRows; ++i) a[i] = acc[i * records + r];
+            for (int i = 0; i < kAccRows; ++i) a[i] = acc[r * kAccRows + i];
             bool any = false;
 #pragma unroll
             for (int i = 0; i < kAccRows; ++i) any |= (a[i] != 0.f);
@@ -401,7 +401,7 @@ __global__ void __launch_bounds__(256) project_backward_kernel(
         }
         for (int v = 0; v < n_views; ++v) {
             const int64_t r = int64_t(v) * n_cap + g;
-            const float drgb = acc[(6 + ch) * records + r];
+            const float drgb = acc[r * kAccRows + 6 + ch];
             if (drgb == 0.f) continue;
             const Cam c = load_cam(views[v], s.fov_clamp);
             float d[3] = {mu[0] - c.C[0], mu[1] - c.C[1], mu[2] - c.C[2]};

@@ -187,18 +187,49 @@ __device__ __forceinline__ float wave_sum_to_last(float v) {
     return v;
 }
 
-__global__ void __launch_bounds__(256) render_bwd_kernel(
+// Block-wide exclusive scan for kThreads threads (a multiple of 64).
+template <int kThreads>
+__device__ __forceinline__ uint32_t block_scan_n(uint32_t v, uint32_t *lds, uint32_t *total) {
+    constexpr int kW = kThreads / kWave;
+    const int lane = lane_id();
+    const int wave = threadIdx.x / kWave;
+    const uint32_t inc = wave_inclusive_scan(v);
+    if (kW == 1) {
+        *total = __shfl(inc, kWave - 1, kWave);
+        return inc - v;
+    }
+    if (lane == kWave - 1) lds[wave] = inc;
+    __syncthreads();
+    uint32_t base = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < kW; ++w) {
+        const uint32_t s = lds[w];
+        base += (w < wave) ? s : 0u;
+        all += s;
+    }
+    __syncthreads();
+    *total = all;
+    return base + inc - v;
+}
+
+// Backward raster with kWaves waves per 16x16 tile; every lane owns
+// kPix = 4 / kWaves pixels (rows spaced by 4 * kWaves), so the per-Gaussian
+// wave reduction is shared by kPix pixels.  Entries are staged kThreads at a
+// time, back to front.
+template <int kWaves>
+__global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
     gs_settings s, Proj proj, int64_t n_cap, Sorted srt, const gs_target *__restrict__ targets,
     int n_targets, const float *__restrict__ in_T, const int32_t *__restrict__ in_last,
-    const float *__restrict__ dL_drgb, float *__restrict__ acc, int64_t records) {
-    constexpr int kWaves = kTilePix / kWave;
-    __shared__ float4 sA[kTilePix];
-    __shared__ float4 sB[kTilePix];
-    __shared__ float2 sC[kTilePix];
-    __shared__ int32_t sR[kTilePix];
-    __shared__ int32_t sPos[kTilePix];
+    const float *__restrict__ dL_drgb, float *__restrict__ acc) {
+    constexpr int kThreads = 64 * kWaves;
+    constexpr int kPix = kTilePix / kThreads;
+    __shared__ float4 sA[kThreads];
+    __shared__ float4 sB[kThreads];
+    __shared__ float2 sC[kThreads];
+    __shared__ int32_t sR[kThreads];
+    __shared__ int32_t sPos[kThreads];
     __shared__ uint32_t scan_lds[8];
-    __shared__ float red[kWaves][kTilePix][kAccRows];   // per-wave partial sums of a batch
+    __shared__ float red[kWaves][kThreads][kAccRows];
     __shared__ int sMaxLast;
     const int tile = blockIdx.x;
     const int tid = threadIdx.x;
@@ -206,37 +237,44 @@ __global__ void __launch_bounds__(256) render_bwd_kernel(
     const gs_target t = targets[find_target(targets, n_targets, tile)];
     const int local = tile - t.tile_offset;
     const int tx = local % t.tiles_x, ty = local / t.tiles_x;
-    const int px = tx * kTile + (tid % kTile), py = ty * kTile + tid / kTile;
-    const bool inside = px < t.width && py < t.height;
     const uint2 range = srt.ranges[tile];
     const double ox = double(tx * kTile), oy = double(ty * kTile);
-    const float fpx = float(tid % kTile), fpy = float(tid / kTile);   // relative to the tile origin
     const float sc = ldexpf(1.f, -t.level);
+    const int64_t HW = int64_t(t.width) * t.height;
+    const float *dLt = dL_drgb + 3 * t.pix_offset;
 
-    float T = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
-    int32_t last = 0;
-    if (inside) {
-        const int64_t HW = int64_t(t.width) * t.height;
-        const int64_t pix = int64_t(py) * t.width + px;
-        T = in_T[t.pix_offset + pix];
-        last = in_last[t.pix_offset + pix];
-        const float *d = dL_drgb + 3 * t.pix_offset;
-        g0 = d[pix];
-        g1 = d[HW + pix];
-        g2 = d[2 * HW + pix];
+    float T[kPix], g0[kPix], g1[kPix], g2[kPix], B0[kPix], B1[kPix], B2[kPix], fpy[kPix];
+    int32_t last[kPix];
+    const float fpx = float(tid % kTile);
+    int my_max = 0;
+#pragma unroll
+    for (int i = 0; i < kPix; ++i) {
+        const int lp = tid + i * kThreads;   // tile-local pixel index
+        const int ly = lp / kTile;
+        fpy[i] = float(ly);
+        const int px = tx * kTile + (lp % kTile), py = ty * kTile + ly;
+        T[i] = 0.f; g0[i] = g1[i] = g2[i] = 0.f; last[i] = 0;
+        if (px < t.width && py < t.height) {
+            const int64_t pix = int64_t(py) * t.width + px;
+            T[i] = in_T[t.pix_offset + pix];
+            last[i] = in_last[t.pix_offset + pix];
+            g0[i] = dLt[pix];
+            g1[i] = dLt[HW + pix];
+            g2[i] = dLt[2 * HW + pix];
+        }
+        // a restart position never exceeds the tile's list (guards stale input)
+        last[i] = min(last[i], int32_t(range.y - range.x));
+        my_max = max(my_max, last[i]);
+        B0[i] = t.bg[0]; B1[i] = t.bg[1]; B2[i] = t.bg[2];   // colour behind, unit transmittance
     }
-    // a pixel's restart position never exceeds its tile's list (guards stale input)
-    last = min(last, int32_t(range.y - range.x));
-    float B0 = t.bg[0], B1 = t.bg[1], B2 = t.bg[2];   // colour behind, unit transmittance
     if (tid == 0) sMaxLast = 0;
     __syncthreads();
-    if (last > 0) atomicMax(&sMaxLast, last);
+    if (my_max > 0) atomicMax(&sMaxLast, my_max);
     __syncthreads();
     const int max_last = sMaxLast;
-    const int batch = s.batch;
 
-    for (int end = max_last; end > 0; end -= batch) {
-        const int start = max(0, end - batch);
+    for (int end = max_last; end > 0; end -= kThreads) {
+        const int start = max(0, end - kThreads);
         __syncthreads();
         float4 A, Bv;
         float2 Cc;
@@ -248,7 +286,7 @@ __global__ void __launch_bounds__(256) render_bwd_kernel(
             keep = touches_tile(A, Bv, Cc);
         }
         uint32_t cnt;
-        const uint32_t at_pos = block_exclusive_scan(keep ? 1u : 0u, scan_lds, &cnt);
+        const uint32_t at_pos = block_scan_n<kThreads>(keep ? 1u : 0u, scan_lds, &cnt);
         if (keep) {
             sA[at_pos] = A;
             sB[at_pos] = Bv;
@@ -261,10 +299,42 @@ __global__ void __launch_bounds__(256) render_bwd_kernel(
             const float4 A = sA[k];
             const float4 Bv = sB[k];
             const float2 Ck = sC[k];
-            const float dx = A.x - fpx, dy = A.y - fpy;
-            const float pw = eval_power(A, Bv, dx, dy);
-            const bool active = (sPos[k] < last) && !(pw < Ck.y);
-            const uint64_t act = __ballot(active);
+            const int pos = sPos[k];
+            float v[kAccRows];
+#pragma unroll
+            for (int i = 0; i < kAccRows; ++i) v[i] = 0.f;
+            bool any = false;
+#pragma unroll
+            for (int i = 0; i < kPix; ++i) {
+                const float dx = A.x - fpx, dy = A.y - fpy[i];
+                const float pw = eval_power(A, Bv, dx, dy);
+                if (pos < last[i] && !(pw < Ck.y)) {
+                    any = true;
+                    const float ep = __expf(pw);
+                    const float at = Bv.y * ep;
+                    const float alpha = fminf(s.alpha_max, at);
+                    const float oma = 1.f - alpha;
+                    T[i] = T[i] * __builtin_amdgcn_rcpf(oma);   // transmittance in front of it
+                    const float r = Bv.z, gg = Bv.w, bb = Ck.x;
+                    const float dal = T[i] * ((r - B0[i]) * g0[i] + (gg - B1[i]) * g1[i] + (bb - B2[i]) * g2[i]);
+                    const float w = alpha * T[i];
+                    v[6] += w * g0[i];
+                    v[7] += w * g1[i];
+                    v[8] += w * g2[i];
+                    B0[i] = fmaf(alpha, r, oma * B0[i]);
+                    B1[i] = fmaf(alpha, gg, oma * B1[i]);
+                    B2[i] = fmaf(alpha, bb, oma * B2[i]);
+                    const float dat = (at < s.alpha_max) ? dal : 0.f;
+                    v[5] += ep * dat;
+                    const float dp = at * dat;
+                    v[0] -= dp * (A.z * dx + A.w * dy);
+                    v[1] -= dp * (A.w * dx + Bv.x * dy);
+                    v[2] -= 0.5f * dp * dx * dx;
+                    v[3] -= dp * dx * dy;
+                    v[4] -= 0.5f * dp * dy * dy;
+                }
+            }
+            const uint64_t act = __ballot(any);
             float *slot = red[wave][k];
             if (act == 0) {
                 if (lane_id() == kWave - 1) {
@@ -273,36 +343,8 @@ __global__ void __launch_bounds__(256) render_bwd_kernel(
                 }
                 continue;
             }
-            float v[kAccRows];
-            if (active) {
-                const float ep = __expf(pw);
-                const float at = Bv.y * ep;
-                const float alpha = fminf(s.alpha_max, at);
-                const float oma = 1.f - alpha;
-                T = T * __builtin_amdgcn_rcpf(oma);   // transmittance in front of this Gaussian
-                const float r = Bv.z, gg = Bv.w, bb = Ck.x;
-                const float dal = T * ((r - B0) * g0 + (gg - B1) * g1 + (bb - B2) * g2);
-                const float w = alpha * T;
-                v[6] = w * g0;
-                v[7] = w * g1;
-                v[8] = w * g2;
-                B0 = fmaf(alpha, r, oma * B0);
-                B1 = fmaf(alpha, gg, oma * B1);
-                B2 = fmaf(alpha, bb, oma * B2);
-                const float dat = (at < s.alpha_max) ? dal : 0.f;
-                v[5] = ep * dat;
-                const float dp = at * dat;
-                v[0] = -dp * (A.z * dx + A.w * dy);
-                v[1] = -dp * (A.w * dx + Bv.x * dy);
-                v[2] = -0.5f * dp * dx * dx;
-                v[3] = -dp * dx * dy;
-                v[4] = -0.5f * dp * dy * dy;
-            } else {
-#pragma unroll
-                for (int i = 0; i < kAccRows; ++i) v[i] = 0.f;
-            }
             if (__popcll(act) == 1) {
-                // one pixel of this wave touches the Gaussian: read its values
+                // one lane of this wave touches the Gaussian: read its values
                 const int src = __builtin_ctzll(act);
 #pragma unroll
                 for (int i = 0; i < kAccRows; ++i)
@@ -331,13 +373,14 @@ __global__ void __launch_bounds__(256) render_bwd_kernel(
             }
         }
         __syncthreads();
-        // one atomic per (Gaussian, quantity) for the whole tile
-        for (int idx = tid; idx < int(cnt) * kAccRows; idx += kTilePix) {
+        // one atomic per (Gaussian, quantity) for the whole tile; a record's nine
+        // accumulators are contiguous
+        for (int idx = tid; idx < int(cnt) * kAccRows; idx += kThreads) {
             const int k = idx / kAccRows, i = idx - k * kAccRows;
             float sum = 0.f;
 #pragma unroll
             for (int w = 0; w < kWaves; ++w) sum += red[w][k][i];
-            if (sum != 0.f) atomicAdd(&acc[int64_t(i) * records + sR[k]], sum);
+            if (sum != 0.f) atomicAdd(&acc[int64_t(sR[k]) * kAccRows + i], sum);
         }
     }
 }
@@ -357,7 +400,8 @@ gs_status launch_project_backward_adam(const gs_settings &s, float *params, int6
 
 static bool valid_settings(const gs_settings *s) {
     return s && s->sh_degree >= 0 && s->sh_degree <= 3 &&
-           (s->batch == 64 || s->batch == 128 || s->batch == 256) && s->alpha_min > 0.f &&
+           (s->batch == 64 || s->batch == 128 || s->batch == 256) &&
+           (s->bwd_waves == 1 || s->bwd_waves == 2 || s->bwd_waves == 4) && s->alpha_min > 0.f &&
            s->alpha_max <= 1.f && s->alpha_max >= s->alpha_min && s->t_min > 0.f &&
            s->dilation >= 0.f && s->fov_clamp > 0.f;
 }
@@ -402,8 +446,20 @@ extern "C" gs_status gs_raster_bwd(const gs_settings *s, const void *proj_ws, in
     float *acc = static_cast<float *>(accum_ws);
     const int64_t acc_n = int64_t(kAccRows) * records;
     hipLaunchKernelGGL(fill_f32_kernel, dim3((acc_n + 255) / 256), dim3(256), 0, st, acc, acc_n, 0.f);
-    hipLaunchKernelGGL(render_bwd_kernel, dim3(total_tiles), dim3(kTilePix), 0, st, *s, proj, n_cap,
-                       srt, targets, n_targets, out_T, out_last, dL_drgb, acc, records);
+    switch (s->bwd_waves) {
+        case 1:
+            hipLaunchKernelGGL(render_bwd_kernel<1>, dim3(total_tiles), dim3(64), 0, st, *s, proj, n_cap,
+                               srt, targets, n_targets, out_T, out_last, dL_drgb, acc);
+            break;
+        case 2:
+            hipLaunchKernelGGL(render_bwd_kernel<2>, dim3(total_tiles), dim3(128), 0, st, *s, proj, n_cap,
+                               srt, targets, n_targets, out_T, out_last, dL_drgb, acc);
+            break;
+        default:
+            hipLaunchKernelGGL(render_bwd_kernel<4>, dim3(total_tiles), dim3(256), 0, st, *s, proj, n_cap,
+                               srt, targets, n_targets, out_T, out_last, dL_drgb, acc);
+            break;
+    }
     GS_CHECK_LAUNCH();
     return GS_OK;
 }

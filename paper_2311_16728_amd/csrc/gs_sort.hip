@@ -252,19 +252,21 @@ __global__ void __launch_bounds__(256) emit_kernel(int64_t n_cap, const gs_targe
 
 // ---------------------------------------------------------------------------
 // Stable LSD radix sort pass (8-bit digit at `shift`) over n = *n_ptr pairs.
+// A block owns kItems * 256 consecutive elements.
 // ---------------------------------------------------------------------------
+template <int kItems>
 __global__ void __launch_bounds__(256) radix_hist_kernel(const uint32_t *__restrict__ n_ptr,
                                                          const uint32_t *__restrict__ keys, int shift,
                                                          uint32_t *__restrict__ hist,
                                                          int64_t max_blocks) {
     __shared__ uint32_t h[kRadixBins];
     const uint32_t n = *n_ptr;
-    const int64_t base = int64_t(blockIdx.x) * kScanTile;
+    const int64_t base = int64_t(blockIdx.x) * kItems * kScanThreads;
     if (base >= n) return;
     h[threadIdx.x] = 0;
     __syncthreads();
-#pragma unroll 4
-    for (int k = 0; k < kScanItems; ++k) {
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
         const int64_t e = base + k * kScanThreads + threadIdx.x;
         if (e < n) atomicAdd(&h[(keys[e] >> shift) & (kRadixBins - 1)], 1u);
     }
@@ -274,12 +276,13 @@ __global__ void __launch_bounds__(256) radix_hist_kernel(const uint32_t *__restr
 
 // Block d: exclusive scan of row d of hist over the active blocks; row total
 // to digit[d].
+template <int kItems>
 __global__ void __launch_bounds__(256) radix_rowscan_kernel(const uint32_t *__restrict__ n_ptr,
                                                             uint32_t *__restrict__ hist,
                                                             int64_t max_blocks,
                                                             uint32_t *__restrict__ digit) {
     __shared__ uint32_t lds[8];
-    const int64_t nb = active_blocks(*n_ptr);
+    const int64_t nb = (int64_t(*n_ptr) + kItems * kScanThreads - 1) / (kItems * kScanThreads);
     uint32_t *row = hist + int64_t(blockIdx.x) * max_blocks;
     uint32_t run = 0;
     for (int64_t c = 0; c < nb; c += 256) {
@@ -293,28 +296,46 @@ __global__ void __launch_bounds__(256) radix_rowscan_kernel(const uint32_t *__re
     if (threadIdx.x == 0) digit[blockIdx.x] = run;
 }
 
+// Scatter: stable in-block ranks (wave ballots on the 8 digit bits, per-wave
+// digit counters in LDS), the block's elements laid out in digit order in LDS,
+// then written out so that consecutive threads write consecutive addresses of
+// each digit's run.
+template <int kItems>
 __global__ void __launch_bounds__(256) radix_scatter_kernel(
     const uint32_t *__restrict__ n_ptr, const uint32_t *__restrict__ kin,
     const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
     int shift, const uint32_t *__restrict__ hist, int64_t max_blocks,
     const uint32_t *__restrict__ digit) {
     constexpr int kWaves = kScanThreads / kWave;
-    __shared__ uint32_t off[kRadixBins];
+    constexpr int kTileN = kItems * kScanThreads;
+    __shared__ uint32_t gbase[kRadixBins];    // global start of each digit's run of this block
+    __shared__ uint32_t lstart[kRadixBins];   // start of each digit inside the block
+    __shared__ uint32_t run[kRadixBins];      // elements of each digit placed so far
     __shared__ uint32_t wcnt[kWaves][kRadixBins];
+    __shared__ uint32_t skey[kTileN];
+    __shared__ uint32_t sval[kTileN];
     __shared__ uint32_t lds[8];
     const uint32_t n = *n_ptr;
-    const int64_t base = int64_t(blockIdx.x) * kScanTile;
+    const int64_t base = int64_t(blockIdx.x) * kTileN;
     if (base >= n) return;
     const int tid = threadIdx.x, wave = tid / kWave;
+    const int64_t nb = (int64_t(n) + kTileN - 1) / kTileN;
     {
+        // this block's count of digit tid, from the scanned histogram
+        const uint32_t pre = hist[int64_t(tid) * max_blocks + blockIdx.x];
+        const uint32_t nxt = (int64_t(blockIdx.x) + 1 < nb) ? hist[int64_t(tid) * max_blocks + blockIdx.x + 1]
+                                                            : digit[tid];
         uint32_t total;
         const uint32_t dbase = block_exclusive_scan(digit[tid], lds, &total);
-        off[tid] = dbase + hist[int64_t(tid) * max_blocks + blockIdx.x];
+        const uint32_t l = block_exclusive_scan(nxt - pre, lds, &total);
+        gbase[tid] = dbase + pre;
+        lstart[tid] = l;
+        run[tid] = 0;
     }
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0;
     __syncthreads();
-    for (int k = 0; k < kScanItems; ++k) {
+    for (int k = 0; k < kItems; ++k) {
         const int64_t e = base + k * kScanThreads + tid;
         const bool valid = e < n;
         uint32_t key = 0, val = 0, d = 0;
@@ -334,17 +355,25 @@ __global__ void __launch_bounds__(256) radix_scatter_kernel(
         if (valid && rank == 0) wcnt[wave][d] = uint32_t(__popcll(peers));
         __syncthreads();
         if (valid) {
-            uint32_t pos = off[d] + uint32_t(rank);
+            uint32_t pos = lstart[d] + run[d] + uint32_t(rank);
             for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-            kout[pos] = key;
-            vout[pos] = val;
+            skey[pos] = key;
+            sval[pos] = val;
         }
         __syncthreads();
         uint32_t add = 0;
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) { add += wcnt[w][tid]; wcnt[w][tid] = 0; }
-        off[tid] += add;
+        run[tid] += add;
         __syncthreads();
+    }
+    const int cnt = int(min(int64_t(kTileN), int64_t(n) - base));
+    for (int i = tid; i < cnt; i += kScanThreads) {
+        const uint32_t key = skey[i];
+        const uint32_t d = (key >> shift) & (kRadixBins - 1);
+        const uint32_t pos = gbase[d] + (uint32_t(i) - lstart[d]);
+        kout[pos] = key;
+        vout[pos] = sval[i];
     }
 }
 
@@ -375,18 +404,20 @@ static SortBufs sort_bufs(void *ws, int64_t S, int64_t pair_cap, int32_t total_t
     return B;
 }
 
-// Sorts (kbuf[cur], vbuf[cur]) in place of the two buffers over `passes`
-// 8-bit digits starting at bit 0; returns the buffer index holding the result.
+// Sorts (kbuf[cur], vbuf[cur]) through the two buffers over `passes` 8-bit
+// digits starting at bit first_bit; returns the buffer index holding the result.
+template <int kItems>
 static int radix_sort(const uint32_t *n_ptr, uint32_t *kbuf[2], uint32_t *vbuf[2], int cur,
-                      int first_bit, int passes, int64_t blocks, const SortBufs &B,
+                      int first_bit, int passes, int64_t capacity, const SortBufs &B,
                       hipStream_t st) {
+    const int64_t blocks = (capacity + kItems * kScanThreads - 1) / (kItems * kScanThreads);
     for (int p = 0; p < passes; ++p) {
         const int shift = first_bit + p * kRadixBits;
-        hipLaunchKernelGGL(radix_hist_kernel, dim3(blocks), dim3(256), 0, st, n_ptr, kbuf[cur],
+        hipLaunchKernelGGL(radix_hist_kernel<kItems>, dim3(blocks), dim3(256), 0, st, n_ptr, kbuf[cur],
                            shift, B.hist, B.max_blocks);
-        hipLaunchKernelGGL(radix_rowscan_kernel, dim3(kRadixBins), dim3(256), 0, st, n_ptr, B.hist,
+        hipLaunchKernelGGL(radix_rowscan_kernel<kItems>, dim3(kRadixBins), dim3(256), 0, st, n_ptr, B.hist,
                            B.max_blocks, B.digit);
-        hipLaunchKernelGGL(radix_scatter_kernel, dim3(blocks), dim3(256), 0, st, n_ptr, kbuf[cur],
+        hipLaunchKernelGGL(radix_scatter_kernel<kItems>, dim3(blocks), dim3(256), 0, st, n_ptr, kbuf[cur],
                            vbuf[cur], kbuf[cur ^ 1], vbuf[cur ^ 1], shift, B.hist, B.max_blocks,
                            B.digit);
         cur ^= 1;
@@ -440,7 +471,7 @@ extern "C" gs_status gs_bin_sort(const gs_settings *s, const void *proj_ws, int6
     hipLaunchKernelGGL(compact_scatter_kernel, dim3(sblocks), dim3(256), 0, st, B.counts, S, n_cap,
                        targets, proj, B.bsum, B.vk[0], B.vv[0]);
     // depth order (4 passes: result back in buffer 0)
-    int cur = radix_sort(B.counters + kVisible, B.vk, B.vv, 0, 0, 4, sblocks, B, st);
+    int cur = radix_sort<4>(B.counters + kVisible, B.vk, B.vv, 0, 0, 4, S, B, st);
     // pair offsets in depth order
     hipLaunchKernelGGL(offsets_reduce_kernel, dim3(sblocks), dim3(256), 0, st, B.counters + kVisible,
                        B.counts, B.vv[cur], B.bsum);
@@ -454,9 +485,8 @@ extern "C" gs_status gs_bin_sort(const gs_settings *s, const void *proj_ws, int6
                        st, n_cap, targets, B.counters, B.vv[cur], B.voff, B.rects, pair_cap, B.pk[0],
                        B.pv[0], d_status);
     // tile order
-    const int64_t pblocks = (pair_cap + kScanTile - 1) / kScanTile;
     const int passes = tile_sort_passes(total_tiles);
-    int pc = radix_sort(B.counters + kPairsClamped, B.pk, B.pv, 0, 0, passes, pblocks, B, st);
+    int pc = radix_sort<16>(B.counters + kPairsClamped, B.pk, B.pv, 0, 0, passes, pair_cap, B, st);
     hipLaunchKernelGGL(ranges_kernel, dim3(pair_chunks < persistent ? pair_chunks : persistent), dim3(256),
                        0, st, B.counters, B.pk[pc], B.ranges);
     GS_CHECK_LAUNCH();

@@ -309,3 +309,30 @@ def test_fused_backward_adam_matches_unfused(orc):
     frac = (np.abs(p1 - p0) <= 1e-6 + 1e-5 * np.abs(p0))[moved].mean()
     assert frac >= 0.999, frac
     assert np.all(p1[:, n:] == p[:, n:])
+
+
+def test_launch_shapes_do_not_change_results(orc):
+    """Forward bitwise identical for every LDS batch size; backward equal to
+    FP32 summation noise for 1, 2 and 4 waves per tile."""
+    from paper_2311_16728_amd import gs
+
+    p, _, cam = scenes.tiny_scene(8)
+    n = 2000
+    P = _dev(p)
+    Wt = _dev(np.random.default_rng(4).uniform(-1, 1, (3, 128, 128)).astype(np.float32)).reshape(-1)
+    imgs, grads = [], []
+    for batch in (64, 128, 256):
+        for waves in (1, 2, 4):
+            plan = plan_for([cam], n_cap=p.shape[1], settings=gs.default_settings(batch=batch, bwd_waves=waves))
+            plan.render(P, n)
+            grad = torch.zeros_like(P)
+            plan.backward(P, n, Wt.contiguous(), grad)
+            torch.cuda.synchronize()
+            imgs.append(plan.rgb.clone())
+            grads.append(grad.cpu().numpy())
+    for im in imgs[1:]:
+        assert torch.equal(im, imgs[0])
+    ref = grads[0]
+    scale = np.abs(ref).max(axis=1, keepdims=True) + 1e-30
+    for g in grads[1:]:
+        assert (np.abs(g - ref) / scale).max() <= 1e-4
