@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--batch", type=int, default=None, help="forward LDS batch (skips autotuning)")
+    ap.add_argument("--bwd-waves", type=int, default=None, help="backward waves per tile (skips autotuning)")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="after timing, copy a 256 MiB buffer once (HBM counter calibration)")
     ap.add_argument("--cpu-sample", type=float, default=0.05,
                     help="fraction of pixels the oracle baseline renders and differentiates")
     return ap.parse_args()
@@ -93,6 +97,31 @@ def step_with_events(plan, mapper, target, ev, torch):
 
 
 STAGES = ["preprocess", "bin_sort", "render_fwd", "loss", "raster_bwd", "project_bwd_adam"]
+
+
+KERNEL_SOURCES = {"project_bwd_adam": "paper_2311_16728_amd/csrc/gs_project.hip",
+                  "raster_bwd": "paper_2311_16728_amd/csrc/gs_raster.hip",
+                  "render_fwd": "paper_2311_16728_amd/csrc/gs_raster.hip"}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/traffic_<kernel>_1M_1200x680.json: FETCH_SIZE and WRITE_SIZE per
+    dispatch, scaled by the same counters' reading of a plain copy of known
+    size), or None when there is none or the kernel source has changed since."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_1M_1200x680.json")
+    src = KERNEL_SOURCES.get(kernel)
+    if not os.path.exists(path) or src is None:
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    with open(os.path.join(ROOT, src), "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    if rec.get("source_sha256") != digest:
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def cpu_baseline(p, n, cams, target_np, frac, seed=0):
@@ -150,7 +179,10 @@ def main():
     torch.cuda.synchronize()
     print(f"# workload ready: pairs={plan.pair_count()}", file=sys.stderr, flush=True)
     tuned = None
-    if not args.no_autotune:
+    if args.batch or args.bwd_waves:
+        plan.settings.batch = args.batch or plan.settings.batch
+        plan.settings.bwd_waves = args.bwd_waves or plan.settings.bwd_waves
+    elif not args.no_autotune:
         from paper_2311_16728_amd import autotune
 
         tuned = autotune.tune(plan, mapper.params, mapper.n, target)
@@ -195,6 +227,15 @@ def main():
     torch.cuda.synchronize()
     render_ms = r0.elapsed_time(r1) / args.steps
 
+    if args.calibrate:
+        # a plain device copy of known size: reads and writes 256 MiB
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     # algorithmic work of the two heaviest kernels (see the design notes):
     # raster backward: 55 FP32 operations (FMA = 2) per composited (pixel,
     # Gaussian) pair; chain rule + Adam: 1452 B of HBM traffic per Gaussian
@@ -218,7 +259,8 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k]["ms"])
     kd = kernels[dom]
     roofline = {"kernel": dom, "bound": kd["bound"], "achieved": round(kd["achieved"], 3),
-                "peak": kd["peak"], "unit": kd["unit"], "frac": round(kd["frac"], 4), "traffic": None}
+                "peak": kd["peak"], "unit": kd["unit"], "frac": round(kd["frac"], 4),
+                "traffic": measured_traffic(dom)}
 
     out = {
         "metric": "mapping iters/s (fwd+bwd+Adam) & render FPS, 1M Gaussians @1200x680",

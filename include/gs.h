@@ -188,7 +188,8 @@ gs_status gs_project_bwd(const gs_settings *s, const float *params, int64_t n, i
 gs_status gs_project_bwd_adam(const gs_settings *s, float *params, int64_t n, int64_t n_cap,
                               const gs_view *views, int32_t n_views, const void *accum_ws,
                               float *m, float *v, const float *lr_rows, double beta1,
-                              double beta2, double eps, int32_t step, void *stream);
+                              double beta2, double eps, int32_t step, const int32_t *d_step,
+                              void *stream);
 
 /* gs_raster_bwd followed by gs_project_bwd (the full backward to the raw
  * parameters, ADDED to grad). */
@@ -206,7 +207,7 @@ gs_status gs_render_bwd_adam(const gs_settings *s, float *params, int64_t n, int
                              int32_t n_targets, int32_t total_tiles, const float *out_T,
                              const int32_t *out_last, const float *dL_drgb, void *accum_ws,
                              float *m, float *v, const float *lr_rows, double beta1, double beta2,
-                             double eps, int32_t step, void *stream);
+                             double eps, int32_t step, const int32_t *d_step, void *stream);
 
 /* Gaussian pyramid of one planar image (Section 3.4): level l+1 is level l
  * smoothed by the 5x5 binomial kernel (1 4 6 4 1)^2/256 with mirrored
@@ -233,10 +234,87 @@ gs_status gs_pyramid_loss(const float *render, const float *target, const gs_tar
  * p -= lr[row] * (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
  * params, grad, m, v (device) [59][n_cap]; lr_rows (host) 59 floats;
  * beta1, beta2 in [0, 1), eps >= 0 (double so 1 - beta is formed before
- * rounding); step >= 1.  Only columns < n are updated. */
+ * rounding); step >= 1, or step = 0 with d_step (device int32) holding the
+ * step, read on the device (for graph replay; see gs_step_advance).  Only
+ * columns < n are updated. */
 gs_status gs_adam_step(float *params, const float *grad, float *m, float *v, int64_t n,
                        int64_t n_cap, const float *lr_rows, double beta1, double beta2, double eps,
-                       int32_t step, void *stream);
+                       int32_t step, const int32_t *d_step, void *stream);
+
+/* Adds 1 to the device step counter d_step (device int32) on the stream.  With
+ * step = 0 and d_step set, the Adam entry points read the step from d_step on
+ * the device, so a captured graph that advances it and then steps replays
+ * correctly. */
+gs_status gs_step_advance(int32_t *d_step, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Initialisation of newly densified primitives.  Section 3.3.1 creates
+ * temporary primitives at inactive keypoints of each new keyframe, placed with
+ * the keypoint's depth.  A small MLP proposes their scale, rotation, opacity
+ * and colour; the heuristic below is its fallback and its baseline.
+ * Keypoints kp (device float [B][4]): pixel u, v, depth (metres) and scale
+ * 1.2^octave.
+ * ------------------------------------------------------------------------- */
+
+/* Network input per keypoint (device BF16 [B][160]): the 7x7 RGB patch of img
+ * (device float [3][H][W], edge-clamped) around the rounded pixel, channel
+ * major, then depth, scale and a one-hot of the octave round(log_1.2 scale)
+ * clamped to 0..7 (157 values), zero-padded to 160. */
+gs_status gs_init_features(const float *img, int32_t H, int32_t W, const float *kp, int32_t B,
+                           void *x_bf16, void *stream);
+
+/* MLP 160 -> 128 -> 128 -> 16 with ReLU hidden layers, BF16 weights and
+ * activations on the matrix cores, FP32 accumulation.  w_bf16 (device, 38912
+ * BF16): W1 [128][160], W2 [128][128], W3 [16][128] row-major [out][in], in
+ * that order; bias (device, 272 floats): b1, b2, b3.  x_bf16 (device BF16
+ * [B][160]); y (device float [B][16]: log-scale in pixels (3), camera-frame
+ * quaternion (4), opacity logit, SH DC (3), 5 unused); act_ws (device,
+ * 2 * B * 128 BF16) keeps the hidden activations for the backward. */
+gs_status gs_init_mlp_fwd(const void *w_bf16, const float *bias, const void *x_bf16, int32_t B,
+                          float *y, void *act_ws, void *stream);
+
+/* Backward of sum over rows of <dy, y> (dy device float [B][16]): ADDS the
+ * weight gradient to dw (device float, layout of w_bf16) and the bias
+ * gradient to db (device float [272]).  BF16 operands (dy and the hidden
+ * gradients rounded where they enter a product), FP32 accumulation. */
+gs_status gs_init_mlp_bwd(const void *w_bf16, const void *x_bf16, const void *act_ws,
+                          const float *dy, int32_t B, float *dw, float *db, void *stream);
+
+/* Adam on the MLP's FP32 master weights (device, 38912) and biases (device,
+ * 272), moments m, v (device, 39184 each, weights then biases); refreshes the
+ * BF16 weight copy (round to nearest even). */
+gs_status gs_init_mlp_adam(float *w_master, float *b_master, void *w_bf16, const float *dw,
+                           const float *db, float *m, float *v, float lr, double beta1,
+                           double beta2, double eps, int32_t step, void *stream);
+
+/* FP32 to BF16 (round to nearest even), count values, device to device. */
+gs_status gs_to_bf16(const float *src, void *dst, int64_t count, void *stream);
+
+/* Heuristic initial parameters (device float [59][B]) for new means new_mu
+ * (device float [3][B], world) with pixel colours new_rgb (device [3][B]):
+ * log-scale = log(mean distance to the 3 nearest means among the n existing
+ * ones in params and the other new ones), isotropic; quaternion (1, 0, 0, 0);
+ * opacity logit ln(0.1/0.9); SH DC = (rgb - 0.5) / Y_0; other SH 0. */
+gs_status gs_init_heuristic(const float *new_mu, const float *new_rgb, int32_t B,
+                            const float *params, int64_t n, int64_t n_cap, float *out,
+                            void *stream);
+
+/* World-frame parameters (device float [59][B]) from MLP outputs y for
+ * keypoints kp seen by view (host struct, level 0): mean = back-projection of
+ * (u, v) at the depth; log-scale = y + log(depth / fx); quaternion = rotation
+ * of the camera-to-world transform composed with y's; opacity logit and DC
+ * from y; other SH 0.  Where sigmoid(opacity logit) < 0.01 the column of
+ * heuristic (device [59][B]) is used instead and used_fallback (device int32
+ * [B], optional) is set to 1. */
+gs_status gs_init_decode(const float *y, const float *kp, const gs_view *view, int32_t B,
+                         const float *heuristic, float *out, int32_t *used_fallback,
+                         void *stream);
+
+/* Appends B new columns (device float [59][B]) to params at column n
+ * (n + B <= n_cap); the Adam moments m, v (optional) of those columns are
+ * zeroed. */
+gs_status gs_append(float *params, float *m, float *v, int64_t n, int64_t n_cap,
+                    const float *new_params, int32_t B, void *stream);
 
 /* Fills dst (device, count floats) with value (a kernel, not a memset, so a
  * captured graph replays it faithfully). */

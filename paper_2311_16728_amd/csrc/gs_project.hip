@@ -247,6 +247,7 @@ __global__ void __launch_bounds__(256) preprocess_kernel(gs_settings s, const fl
 // count) so every load of the group is issued before the first store.
 struct GradSink {
     float *__restrict__ grad;
+    __device__ __forceinline__ void prepare() {}
     template <int N>
     __device__ __forceinline__ void group(int first, int stride, int64_t g, int64_t n_cap,
                                           const float (&val)[N]) const {
@@ -265,6 +266,17 @@ struct AdamSink {
     float *__restrict__ v;
     LrRows lr;
     float b1, omb1, b2, omb2, eps, ibc1, isqbc2;
+    // Device step counter (graph replay): when set, the bias corrections come
+    // from *d_step with ln(beta) given; 1 - beta^t = -expm1(t ln beta).
+    const int32_t *d_step;
+    float lnb1, lnb2;
+    __device__ __forceinline__ void prepare() {
+        if (d_step) {
+            const float t = float(*d_step);
+            ibc1 = 1.f / -expm1f(t * lnb1);
+            isqbc2 = rsqrtf(-expm1f(t * lnb2));
+        }
+    }
     template <int N>
     __device__ __forceinline__ void group(int first, int stride, int64_t g, int64_t n_cap,
                                           const float (&gv)[N]) const {
@@ -306,6 +318,7 @@ __global__ void __launch_bounds__(256) project_backward_kernel(
     int64_t records, Sink sink) {
     const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (g >= n) return;
+    sink.prepare();
     const int nk = (s.sh_degree + 1) * (s.sh_degree + 1);
     float gmu[3] = {0, 0, 0}, gop = 0.f;
     float dSig[6] = {0, 0, 0, 0, 0, 0};   // summed over views: 00 01 02 11 12 22 (matrix entries)
@@ -491,7 +504,8 @@ gs_status launch_project_backward(const gs_settings &s, const float *params, int
 gs_status launch_project_backward_adam(const gs_settings &s, float *params, int64_t n, int64_t n_cap,
                                        const gs_view *views, int32_t n_views, const float *acc,
                                        float *m, float *v, const float *lr_rows, double beta1,
-                                       double beta2, double eps, int32_t step, hipStream_t st) {
+                                       double beta2, double eps, int32_t step, const int32_t *d_step,
+                                       hipStream_t st) {
     if (n == 0) return GS_OK;
     AdamSink a;
     a.p = params;
@@ -503,8 +517,12 @@ gs_status launch_project_backward_adam(const gs_settings &s, float *params, int6
     a.b2 = float(beta2);
     a.omb2 = float(1.0 - beta2);
     a.eps = float(eps);
-    a.ibc1 = float(1.0 / (1.0 - std::pow(beta1, step)));
-    a.isqbc2 = float(1.0 / std::sqrt(1.0 - std::pow(beta2, step)));
+    a.d_step = d_step;
+    a.lnb1 = float(std::log(beta1));
+    a.lnb2 = float(std::log(beta2));
+    const int32_t t = step > 0 ? step : 1;
+    a.ibc1 = float(1.0 / (1.0 - std::pow(beta1, t)));
+    a.isqbc2 = float(1.0 / std::sqrt(1.0 - std::pow(beta2, t)));
     const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(project_backward_kernel<AdamSink>, dim3(blocks), dim3(256), 0, st, s, params, n,
                        n_cap, views, n_views, acc, int64_t(n_views) * n_cap, a);

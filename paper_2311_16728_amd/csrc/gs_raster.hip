@@ -396,7 +396,8 @@ gs_status launch_project_backward(const gs_settings &s, const float *params, int
 gs_status launch_project_backward_adam(const gs_settings &s, float *params, int64_t n, int64_t n_cap,
                                        const gs_view *views, int32_t n_views, const float *acc,
                                        float *m, float *v, const float *lr_rows, double beta1,
-                                       double beta2, double eps, int32_t step, hipStream_t st);
+                                       double beta2, double eps, int32_t step, const int32_t *d_step,
+                                       hipStream_t st);
 
 static bool valid_settings(const gs_settings *s) {
     return s && s->sh_degree >= 0 && s->sh_degree <= 3 &&
@@ -480,15 +481,17 @@ extern "C" gs_status gs_project_bwd_adam(const gs_settings *s, float *params, in
                                          int64_t n_cap, const gs_view *views, int32_t n_views,
                                          const void *accum_ws, float *m, float *v,
                                          const float *lr_rows, double beta1, double beta2,
-                                         double eps, int32_t step, void *stream) {
+                                         double eps, int32_t step, const int32_t *d_step,
+                                         void *stream) {
     using namespace gs;
     if (!valid_settings(s) || !params || !views || !accum_ws || !m || !v || !lr_rows || n < 0 ||
-        n_cap <= 0 || n > n_cap || n_cap % 64 || n_views <= 0 || step < 1 ||
+        n_cap <= 0 || n > n_cap || n_cap % 64 || n_views <= 0 || (step < 1 && !d_step) ||
         !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) || !(eps >= 0.0))
         return GS_ERR_INVALID_ARGUMENT;
     return launch_project_backward_adam(*s, params, n, n_cap, views, n_views,
                                         static_cast<const float *>(accum_ws), m, v, lr_rows, beta1,
-                                        beta2, eps, step, static_cast<hipStream_t>(stream));
+                                        beta2, eps, step, step < 1 ? d_step : nullptr,
+                                        static_cast<hipStream_t>(stream));
 }
 
 extern "C" gs_status gs_render_bwd(const gs_settings *s, const float *params, int64_t n,
@@ -513,14 +516,28 @@ extern "C" gs_status gs_render_bwd_adam(const gs_settings *s, float *params, int
                                         const int32_t *out_last, const float *dL_drgb,
                                         void *accum_ws, float *m, float *v, const float *lr_rows,
                                         double beta1, double beta2, double eps, int32_t step,
-                                        void *stream) {
-    if (!params || !m || !v || !lr_rows || n < 0 || n > n_cap || !views || step < 1)
+                                        const int32_t *d_step, void *stream) {
+    if (!params || !m || !v || !lr_rows || n < 0 || n > n_cap || !views || (step < 1 && !d_step))
         return GS_ERR_INVALID_ARGUMENT;
     gs_status r = gs_raster_bwd(s, proj_ws, n_cap, n_views, sort_ws, pair_cap, targets, n_targets,
                                 total_tiles, out_T, out_last, dL_drgb, accum_ws, stream);
     if (r != GS_OK) return r;
     return gs_project_bwd_adam(s, params, n, n_cap, views, n_views, accum_ws, m, v, lr_rows, beta1,
-                               beta2, eps, step, stream);
+                               beta2, eps, step, d_step, stream);
+}
+
+namespace gs {
+__global__ void step_advance_kernel(int32_t *d_step) {
+    if (threadIdx.x == 0) *d_step += 1;
+}
+}  // namespace gs
+
+extern "C" gs_status gs_step_advance(int32_t *d_step, void *stream) {
+    if (!d_step) return GS_ERR_INVALID_ARGUMENT;
+    hipLaunchKernelGGL(gs::step_advance_kernel, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream),
+                       d_step);
+    GS_CHECK_LAUNCH();
+    return GS_OK;
 }
 
 extern "C" gs_status gs_fill(float *dst, int64_t count, float value, void *stream) {

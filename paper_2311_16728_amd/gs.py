@@ -67,14 +67,24 @@ def _load():
         "gs_raster_bwd": ([S, vp, i64, i32, vp, i64, vp, i32, i32, vp, vp, vp, vp, vp], C.c_int),
         "gs_project_bwd": ([S, vp, i64, i64, vp, i32, vp, vp, vp], C.c_int),
         "gs_project_bwd_adam": ([S, vp, i64, i64, vp, i32, vp, vp, vp, C.POINTER(C.c_float), C.c_double,
-                                 C.c_double, C.c_double, i32, vp], C.c_int),
+                                 C.c_double, C.c_double, i32, vp, vp], C.c_int),
         "gs_render_bwd_adam": ([S, vp, i64, i64, vp, i32, vp, vp, i64, vp, i32, i32, vp, vp, vp, vp,
                                 vp, vp, C.POINTER(C.c_float), C.c_double, C.c_double, C.c_double,
-                                i32, vp], C.c_int),
+                                i32, vp, vp], C.c_int),
         "gs_pyramid_build": ([vp, i32, i32, i32, i32, vp, vp], C.c_int),
         "gs_pyramid_loss": ([vp, vp, vp, i32, i32, i64, f32, vp, vp, vp, vp, vp], C.c_int),
         "gs_adam_step": ([vp, vp, vp, vp, i64, i64, C.POINTER(C.c_float), C.c_double, C.c_double,
-                          C.c_double, i32, vp], C.c_int),
+                          C.c_double, i32, vp, vp], C.c_int),
+        "gs_step_advance": ([vp, vp], C.c_int),
+        "gs_init_features": ([vp, i32, i32, vp, i32, vp, vp], C.c_int),
+        "gs_init_mlp_fwd": ([vp, vp, vp, i32, vp, vp, vp], C.c_int),
+        "gs_init_mlp_bwd": ([vp, vp, vp, vp, i32, vp, vp, vp], C.c_int),
+        "gs_init_mlp_adam": ([vp, vp, vp, vp, vp, vp, vp, f32, C.c_double, C.c_double, C.c_double, i32,
+                              vp], C.c_int),
+        "gs_to_bf16": ([vp, vp, i64, vp], C.c_int),
+        "gs_init_heuristic": ([vp, vp, i32, vp, i64, i64, vp, vp], C.c_int),
+        "gs_init_decode": ([vp, vp, V, i32, vp, vp, vp, vp], C.c_int),
+        "gs_append": ([vp, vp, vp, i64, i64, vp, i32, vp], C.c_int),
         "gs_fill": ([vp, i64, f32, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
@@ -89,7 +99,9 @@ EXPORTED = ["gs_status_string", "gs_default_settings", "gs_targets_layout", "gs_
             "gs_preprocess", "gs_bin_sort", "gs_render_fwd", "gs_raster_bwd", "gs_project_bwd",
             "gs_project_bwd_adam", "gs_render_bwd", "gs_render_bwd_adam",
             "gs_pyramid_build",
-            "gs_pyramid_loss", "gs_adam_step", "gs_fill"]
+            "gs_pyramid_loss", "gs_adam_step", "gs_step_advance", "gs_fill", "gs_init_features",
+            "gs_init_mlp_fwd", "gs_init_mlp_bwd", "gs_init_mlp_adam", "gs_to_bf16", "gs_init_heuristic",
+            "gs_init_decode", "gs_append"]
 
 
 def _check(status: int, what: str):
@@ -208,11 +220,19 @@ def gs_project_bwd(settings, params, n, views_dev, n_views, accum_ws, grad, stre
                                n_views, _p(accum_ws), _p(grad), _stream(stream)), "gs_project_bwd")
 
 
+def _step_args(step):
+    """An int step, or a device int32 tensor holding it (graph replay)."""
+    if isinstance(step, torch.Tensor):
+        return 0, _p(step)
+    return int(step), None
+
+
 def gs_project_bwd_adam(settings, params, n, views_dev, n_views, accum_ws, m, v, lr_rows, step,
                         beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
     lr = (C.c_float * NUM_ROWS)(*[float(x) for x in lr_rows])
+    st, dst = _step_args(step)
     _check(_lib.gs_project_bwd_adam(C.byref(settings), _p(params), n, params.shape[1], _p(views_dev),
-                                    n_views, _p(accum_ws), _p(m), _p(v), lr, beta1, beta2, eps, step,
+                                    n_views, _p(accum_ws), _p(m), _p(v), lr, beta1, beta2, eps, st, dst,
                                     _stream(stream)), "gs_project_bwd_adam")
 
 
@@ -220,10 +240,11 @@ def gs_render_bwd_adam(settings, params, n, views_dev, n_views, proj_ws, sort_ws
                        targets_dev, n_targets, total_tiles, out_T, out_last, dL_drgb, accum_ws, m, v,
                        lr_rows, step, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
     lr = (C.c_float * NUM_ROWS)(*[float(x) for x in lr_rows])
+    st, dst = _step_args(step)
     _check(_lib.gs_render_bwd_adam(C.byref(settings), _p(params), n, params.shape[1], _p(views_dev),
                                    n_views, _p(proj_ws), _p(sort_ws), pair_cap, _p(targets_dev),
                                    n_targets, total_tiles, _p(out_T), _p(out_last), _p(dL_drgb),
-                                   _p(accum_ws), _p(m), _p(v), lr, beta1, beta2, eps, step,
+                                   _p(accum_ws), _p(m), _p(v), lr, beta1, beta2, eps, st, dst,
                                    _stream(stream)), "gs_render_bwd_adam")
 
 
@@ -243,9 +264,57 @@ def gs_pyramid_loss(render, target, targets_dev, n_targets, total_tiles, total_p
 def gs_adam_step(params, grad, m, v, n, lr_rows, step, beta1=0.9, beta2=0.999, eps=1e-15,
                  stream=None):
     lr = (C.c_float * NUM_ROWS)(*[float(x) for x in lr_rows])
+    st, dst = _step_args(step)
     _check(_lib.gs_adam_step(_p(params), _p(grad), _p(m), _p(v), n, params.shape[1], lr, beta1,
-                             beta2, eps, step, _stream(stream)), "gs_adam_step")
+                             beta2, eps, st, dst, _stream(stream)), "gs_adam_step")
+
+
+def gs_step_advance(d_step, stream=None):
+    _check(_lib.gs_step_advance(_p(d_step), _stream(stream)), "gs_step_advance")
 
 
 def gs_fill(dst, value, stream=None):
     _check(_lib.gs_fill(_p(dst), dst.numel(), float(value), _stream(stream)), "gs_fill")
+
+
+# ---- initialiser -----------------------------------------------------------
+def gs_init_features(img, kp, x_bf16, stream=None):
+    _, H, W = img.shape
+    _check(_lib.gs_init_features(_p(img), H, W, _p(kp), kp.shape[0], _p(x_bf16), _stream(stream)),
+           "gs_init_features")
+
+
+def gs_init_mlp_fwd(w_bf16, bias, x_bf16, y, act_ws, stream=None):
+    _check(_lib.gs_init_mlp_fwd(_p(w_bf16), _p(bias), _p(x_bf16), x_bf16.shape[0], _p(y), _p(act_ws),
+                                _stream(stream)), "gs_init_mlp_fwd")
+
+
+def gs_init_mlp_bwd(w_bf16, x_bf16, act_ws, dy, dw, db, stream=None):
+    _check(_lib.gs_init_mlp_bwd(_p(w_bf16), _p(x_bf16), _p(act_ws), _p(dy), dy.shape[0], _p(dw), _p(db),
+                                _stream(stream)), "gs_init_mlp_bwd")
+
+
+def gs_init_mlp_adam(w_master, b_master, w_bf16, dw, db, m, v, lr, step, beta1=0.9, beta2=0.999,
+                     eps=1e-8, stream=None):
+    _check(_lib.gs_init_mlp_adam(_p(w_master), _p(b_master), _p(w_bf16), _p(dw), _p(db), _p(m), _p(v),
+                                 float(lr), beta1, beta2, eps, int(step), _stream(stream)),
+           "gs_init_mlp_adam")
+
+
+def gs_to_bf16(src, dst, stream=None):
+    _check(_lib.gs_to_bf16(_p(src), _p(dst), src.numel(), _stream(stream)), "gs_to_bf16")
+
+
+def gs_init_heuristic(new_mu, new_rgb, params, n, out, stream=None):
+    _check(_lib.gs_init_heuristic(_p(new_mu), _p(new_rgb), new_mu.shape[1], _p(params), n,
+                                  params.shape[1], _p(out), _stream(stream)), "gs_init_heuristic")
+
+
+def gs_init_decode(y, kp, view, heuristic, out, used_fallback=None, stream=None):
+    _check(_lib.gs_init_decode(_p(y), _p(kp), C.byref(view), y.shape[0], _p(heuristic), _p(out),
+                               _p(used_fallback), _stream(stream)), "gs_init_decode")
+
+
+def gs_append(params, m, v, n, new_params, stream=None):
+    _check(_lib.gs_append(_p(params), _p(m), _p(v), n, params.shape[1], _p(new_params),
+                          new_params.shape[1], _stream(stream)), "gs_append")

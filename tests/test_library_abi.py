@@ -86,7 +86,7 @@ def test_invalid_arguments_rejected():
     # null device pointers fail validation on the host without touching a GPU
     lib = gs._lib
     assert lib.gs_preprocess(C.byref(s), None, 10, 256, None, 1, None, None) == 1
-    assert lib.gs_adam_step(None, None, None, None, 10, 256, None, 0.9, 0.999, 1e-15, 1, None) == 1
+    assert lib.gs_adam_step(None, None, None, None, 10, 256, None, 0.9, 0.999, 1e-15, 1, None, None) == 1
     assert lib.gs_pyramid_build(None, 3, 10, 10, 3, None, None) == 1
     bad = gs.default_settings(batch=100)
     assert lib.gs_render_fwd(C.byref(bad), C.c_void_p(1), 256, 1, C.c_void_p(1), 1024, C.c_void_p(1),
