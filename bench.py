@@ -50,6 +50,12 @@ def parse():
                     help="after timing, copy a 256 MiB buffer once (HBM counter calibration)")
     ap.add_argument("--cpu-sample", type=float, default=0.05,
                     help="fraction of pixels the oracle baseline renders and differentiates")
+    ap.add_argument("--workload", choices=("single", "batched"), default="single",
+                    help="single: one 1200x680 keyframe; batched: 32 mixed keyframes x 3 pyramid "
+                         "levels in one graph-captured iteration")
+    ap.add_argument("--psnr-compare", type=int, default=0, metavar="ROUNDS",
+                    help="batched workload: also compare with the per-frame mapper at equal final "
+                         "PSNR after ROUNDS visits of every keyframe")
     return ap.parse_args()
 
 
@@ -165,6 +171,174 @@ def cpu_baseline(p, n, cams, target_np, frac, seed=0):
                         f"{sampled:.1f} s of CPU work"))
 
 
+def level0_psnr(plan, rgb, target, levels):
+    vals = []
+    for v in range(plan.n_views):
+        a = plan.image(rgb, v * levels).clamp(0, 1)
+        b = plan.image(target, v * levels).clamp(0, 1)
+        vals.append(10.0 * np.log10(1.0 / max(float(((a - b) ** 2).mean()), 1e-12)))
+    return float(np.mean(vals))
+
+
+def psnr_compare(p, n, cams, gt, rounds, torch):
+    """Per-frame mapper (one keyframe's 3 levels per Adam step, keyframes in
+    turn) against the batched mapper (all keyframes and levels per step) from
+    the same start: the per-frame mapper runs `rounds` visits of every
+    keyframe; the batched mapper runs until its level-0 PSNR reaches the
+    per-frame one minus 0.1 dB.  GPU time of the mapping work only."""
+    from paper_2311_16728_amd.batching import BatchedMapper
+    from paper_2311_16728_amd.mapper import Mapper, RenderPlan, mapping_lr_rows
+
+    lr = mapping_lr_rows()
+    levels = 3
+    bm = BatchedMapper(torch.as_tensor(p).cuda(), n, cams, gt, levels, lr_rows=lr)
+    bm.plan.settings.batch, bm.plan.settings.bwd_waves = 128, 1
+    start_psnr = None
+    # per-frame: a plan (3 levels) per keyframe, targets sliced from the batched layout
+    mp = Mapper(torch.as_tensor(p).cuda(), n, lr_rows=lr)
+    plans, targets = [], []
+    for v, cam in enumerate(cams):
+        pl = RenderPlan([cam], [(0, l, (0.0, 0.0, 0.0), 1.0) for l in range(levels)], p.shape[1], 1 << 24)
+        pl.settings.batch, pl.settings.bwd_waves = 128, 1
+        t = torch.empty(3 * pl.total_pixels, dtype=torch.float32, device="cuda")
+        for l in range(levels):
+            pl.image(t, l).copy_(bm.plan.image(bm.target, v * levels + l))
+        plans.append(pl)
+        targets.append(t)
+    bm.plan.render(mp.params, n)
+    start_psnr = level0_psnr(bm.plan, bm.plan.rgb, bm.target, levels)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(rounds):
+        for v in range(len(cams)):
+            mp.step(plans[v], targets[v])
+    e1.record()
+    torch.cuda.synchronize()
+    pf_ms = e0.elapsed_time(e1)
+    if any(pl.overflowed() for pl in plans):
+        raise SystemExit("pair buffer overflow in the per-frame plans")
+    bm.plan.render(mp.params, n)
+    pf_psnr = level0_psnr(bm.plan, bm.plan.rgb, bm.target, levels)
+    print(f"# per-frame: {rounds} rounds, PSNR {start_psnr:.2f} -> {pf_psnr:.2f} dB in {pf_ms:.0f} ms",
+          file=sys.stderr, flush=True)
+    del plans, targets, mp
+    # batched: check the PSNR every `chunk` iterations (outside the timed work)
+    goal = pf_psnr - 0.1
+    b_ms, iters, chunk, b_psnr = 0.0, 0, 5, start_psnr
+    max_iters = rounds * len(cams)
+    while iters < max_iters:
+        e0.record()
+        for _ in range(chunk):
+            bm.iteration()
+        e1.record()
+        torch.cuda.synchronize()
+        b_ms += e0.elapsed_time(e1)
+        iters += chunk
+        bm.plan.render(bm.params, n)
+        b_psnr = level0_psnr(bm.plan, bm.plan.rgb, bm.target, levels)
+        if b_psnr >= goal:
+            break
+    print(f"# batched: {iters} iterations, PSNR {b_psnr:.2f} dB in {b_ms:.0f} ms", file=sys.stderr, flush=True)
+    return {"start_psnr_db": round(start_psnr, 3),
+            "per_frame": {"rounds": rounds, "adam_steps": rounds * len(cams), "psnr_db": round(pf_psnr, 3),
+                          "gpu_ms": round(pf_ms, 1)},
+            "batched": {"iterations": iters, "psnr_db": round(b_psnr, 3), "gpu_ms": round(b_ms, 1),
+                        "reached": bool(b_psnr >= goal)},
+            "speedup_at_equal_psnr": round(pf_ms / b_ms, 3) if b_psnr >= goal else None}
+
+
+def main_batched(args, torch):
+    """32 keyframes of mixed resolution x 3 pyramid levels (96 render targets)
+    over one shared map; one iteration = every stage once over all targets,
+    replayed from a captured HIP graph."""
+    import scenes
+    from paper_2311_16728_amd import autotune
+    from paper_2311_16728_amd.batching import BatchedMapper
+    from paper_2311_16728_amd.mapper import RenderPlan
+
+    n = args.n
+    rng = np.random.default_rng(args.seed)
+    p = scenes.draw_gaussians(rng, n, scenes.ROOM_LO, scenes.ROOM_HI)
+    tp = scenes.perturb(rng, p, n)
+    cams = scenes.mixed_keyframes(args.seed, 32)
+    ref = RenderPlan(cams, [(v, 0, (0.0, 0.0, 0.0), 1.0) for v in range(len(cams))], p.shape[1], 1 << 28)
+    ref.render(torch.as_tensor(tp).cuda(), n)
+    gt = [ref.image(ref.rgb, v).clone() for v in range(len(cams))]
+    del ref
+    bm = BatchedMapper(torch.as_tensor(p).cuda(), n, cams, gt, 3)
+    plan = bm.plan
+    torch.cuda.synchronize()
+    tuned = None
+    if args.batch or args.bwd_waves:
+        plan.settings.batch = args.batch or plan.settings.batch
+        plan.settings.bwd_waves = args.bwd_waves or plan.settings.bwd_waves
+    elif not args.no_autotune:
+        tuned = autotune.tune(plan, bm.params, n, bm.target)
+        print(f"# autotuned: batch={tuned['batch']} bwd_waves={tuned['bwd_waves']} {tuned['ms']}",
+              file=sys.stderr, flush=True)
+    bm.capture(warmup=max(1, args.warmup))
+    torch.cuda.synchronize()
+    if plan.overflowed():
+        raise SystemExit("pair buffer overflow")
+    pairs = plan.pair_count()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(args.steps):
+        bm.step()
+    stop.record()
+    torch.cuda.synchronize()
+    ms_step = start.elapsed_time(stop) / args.steps
+    print(f"# graph replays done: {args.steps}", file=sys.stderr, flush=True)
+    # eager iteration with an event between stages (stage breakdown)
+    from paper_2311_16728_amd import gs
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(STAGES) + 1)]
+    ev[0].record()
+    plan.preprocess(bm.params, n)
+    ev[1].record()
+    plan.bin_sort(n)
+    ev[2].record()
+    plan.render_fwd()
+    ev[3].record()
+    plan.loss(bm.target, bm.lam, True)
+    ev[4].record()
+    gs.gs_raster_bwd(plan.settings, plan.proj_ws, plan.n_cap, plan.n_views, plan.sort_ws, plan.pair_cap,
+                     plan.targets_dev, plan.n_targets, plan.total_tiles, plan.T, plan.last, plan.dL,
+                     plan.accum_ws)
+    gs.gs_step_advance(bm.d_step)
+    ev[5].record()
+    gs.gs_project_bwd_adam(plan.settings, bm.params, n, plan.views_dev, plan.n_views, plan.accum_ws, bm.m,
+                           bm.v, bm.lr_rows, bm.d_step, bm.beta1, bm.beta2, bm.eps)
+    ev[6].record()
+    torch.cuda.synchronize()
+    stage_ms = {s: round(ev[i].elapsed_time(ev[i + 1]), 4) for i, s in enumerate(STAGES)}
+    out = {
+        "metric": "batched mapping iters/s (fwd+bwd+Adam over 96 targets), 1M Gaussians",
+        "value": round(1000.0 / ms_step, 3),
+        "unit": "iters/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "1M Gaussians in a 10x4x10 m room; 32 keyframes (12 at 640x480 f=320, "
+                               "10 at 752x480 f=376, 10 at 1200x680 f=600) x 3 pyramid levels = 96 "
+                               "targets per iteration, Eq. 4 on every target, one HIP graph",
+                   "gaussians": n, "targets": plan.n_targets, "pixels": plan.total_pixels,
+                   "pairs": pairs},
+        "targets_per_s": round(plan.n_targets * 1000.0 / ms_step, 1),
+        "megapixels_per_s": round(plan.total_pixels * 1e-3 / ms_step, 1),
+        "stage_ms_eager": stage_ms,
+        "launch": {"batch": plan.settings.batch, "bwd_waves": plan.settings.bwd_waves,
+                   "autotune_ms": tuned["ms"] if tuned else None},
+    }
+    if args.psnr_compare:
+        del bm
+        torch.cuda.empty_cache()
+        out["equal_psnr"] = psnr_compare(p, n, cams, gt, args.psnr_compare, torch)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -175,6 +349,8 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a ROCm GPU")
+    if args.workload == "batched":
+        return main_batched(args, torch)
     p, tp, cams, plan, mapper, target = build_workload(args, torch)
     torch.cuda.synchronize()
     print(f"# workload ready: pairs={plan.pair_count()}", file=sys.stderr, flush=True)

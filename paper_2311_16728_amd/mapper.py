@@ -21,6 +21,21 @@ LAMBDA = 0.2          # weight of the D-SSIM term (Section 4.1)
 PYRAMID_LEVELS = 3    # n = 2 (Section 4.1, Eq. 5)
 
 
+def mapping_lr_rows(extent: float = 5.0) -> np.ndarray:
+    """Per-row Adam learning rates for mapping runs that must converge.  The
+    paper gives none; these follow common 3D Gaussian splatting practice:
+    means 1.6e-4 x scene extent, log-scales 5e-3, quaternions 1e-3, opacity
+    logit 5e-2, SH DC 2.5e-3, higher SH 1.25e-4."""
+    lr = np.empty(59, np.float32)
+    lr[0:3] = 1.6e-4 * extent
+    lr[3:6] = 5e-3
+    lr[6:10] = 1e-3
+    lr[10] = 5e-2
+    lr[11:14] = 2.5e-3
+    lr[14:] = 1.25e-4
+    return lr
+
+
 def _bytes(n: int, device) -> torch.Tensor:
     return torch.empty(max(int(n), 256), dtype=torch.uint8, device=device)
 

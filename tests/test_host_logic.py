@@ -1,0 +1,72 @@
+"""Host-side logic that needs no GPU: the benchmark's single-GPU contract, the
+batched workload's target layout, and the initialiser pipeline's quaternion
+helpers."""
+
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+import torch
+from scipy.spatial.transform import Rotation
+
+import scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
+
+
+def test_batched_workload_layout():
+    from paper_2311_16728_amd import gs
+
+    cams = scenes.mixed_keyframes(0, 32)
+    sizes = sorted({(c["width"], c["height"]) for c in cams})
+    assert sizes == [(640, 480), (752, 480), (1200, 680)]
+    counts = {s: sum((c["width"], c["height"]) == s for c in cams) for s in sizes}
+    assert counts == {(640, 480): 12, (752, 480): 10, (1200, 680): 10}
+    views = [gs.make_view(c) for c in cams]
+    specs = [(v, l, (0, 0, 0), 1.0) for v in range(32) for l in range(3)]
+    targets, pixels, tiles = gs.gs_targets_layout(views, specs)
+    assert len(targets) == 96
+    expect_px, expect_tiles = 0, 0
+    for c in cams:
+        w, h = c["width"], c["height"]
+        for _ in range(3):
+            expect_px += w * h
+            expect_tiles += ((w + 15) // 16) * ((h + 15) // 16)
+            w, h = (w + 1) // 2, (h + 1) // 2
+    assert pixels == expect_px and tiles == expect_tiles
+
+
+def test_quaternion_helpers_match_scipy():
+    from paper_2311_16728_amd.init_pipeline import _mat_to_quat, _quat_mul
+
+    rng = np.random.default_rng(0)
+    a = Rotation.random(50, random_state=1)
+    b = Rotation.random(50, random_state=2)
+    qa = torch.as_tensor(a.as_quat()[:, [3, 0, 1, 2]])
+    qb = torch.as_tensor(b.as_quat()[:, [3, 0, 1, 2]])
+    qc = _quat_mul(qa, qb).numpy()
+    got = Rotation.from_quat(qc[:, [1, 2, 3, 0]]).as_matrix()
+    np.testing.assert_allclose(got, (a * b).as_matrix(), atol=1e-12)
+    R = Rotation.from_rotvec(rng.normal(size=3)).as_matrix()
+    q = _mat_to_quat(R)
+    np.testing.assert_allclose(Rotation.from_quat(q[[1, 2, 3, 0]]).as_matrix(), R, atol=1e-12)
+
+
+def test_mapping_learning_rates():
+    from paper_2311_16728_amd.mapper import mapping_lr_rows
+
+    lr = mapping_lr_rows(5.0)
+    assert lr.shape == (59,) and lr.dtype == np.float32
+    assert np.all(lr > 0)
+    assert lr[10] > lr[3] > lr[11] > lr[14]
