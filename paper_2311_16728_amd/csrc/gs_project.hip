@@ -247,17 +247,18 @@ __global__ void __launch_bounds__(256) preprocess_kernel(gs_settings s, const fl
 // count) so every load of the group is issued before the first store.
 struct GradSink {
     float *__restrict__ grad;
-    __device__ __forceinline__ void prepare() {}
+    struct Scale {};
+    __device__ __forceinline__ Scale prepare() const { return {}; }
     template <int N>
     __device__ __forceinline__ void group(int first, int stride, int64_t g, int64_t n_cap,
-                                          const float (&val)[N]) const {
+                                          const float (&val)[N], Scale) const {
         float cur[N];
 #pragma unroll
         for (int j = 0; j < N; ++j) cur[j] = grad[int64_t(first + j * stride) * n_cap + g];
 #pragma unroll
         for (int j = 0; j < N; ++j) grad[int64_t(first + j * stride) * n_cap + g] = cur[j] + val[j];
     }
-    __device__ __forceinline__ void untouched(int64_t, int64_t) const {}
+    __device__ __forceinline__ void untouched(int64_t, int64_t, Scale) const {}
 };
 
 struct AdamSink {
@@ -270,16 +271,22 @@ struct AdamSink {
     // from *d_step with ln(beta) given; 1 - beta^t = -expm1(t ln beta).
     const int32_t *d_step;
     float lnb1, lnb2;
-    __device__ __forceinline__ void prepare() {
+    // Bias corrections of this step.  Returned rather than stored: the sink
+    // stays a read-only kernel argument, so the per-row learning rates are
+    // read from the argument segment instead of a private copy in scratch.
+    struct Scale {
+        float ibc1, isqbc2;
+    };
+    __device__ __forceinline__ Scale prepare() const {
         if (d_step) {
             const float t = float(*d_step);
-            ibc1 = 1.f / -expm1f(t * lnb1);
-            isqbc2 = rsqrtf(-expm1f(t * lnb2));
+            return {1.f / -expm1f(t * lnb1), rsqrtf(-expm1f(t * lnb2))};
         }
+        return {ibc1, isqbc2};
     }
     template <int N>
     __device__ __forceinline__ void group(int first, int stride, int64_t g, int64_t n_cap,
-                                          const float (&gv)[N]) const {
+                                          const float (&gv)[N], Scale sc) const {
         float pp[N], mm[N], vv[N];
 #pragma unroll
         for (int j = 0; j < N; ++j) {
@@ -296,14 +303,14 @@ struct AdamSink {
             m[i] = mv;
             v[i] = vq;
             // hardware sqrt and reciprocal (1 ulp each) keep the unrolled group short
-            const float den = __builtin_amdgcn_sqrtf(vq) * isqbc2 + eps;
-            p[i] = pp[j] - lr.lr[first + j * stride] * ibc1 * mv * __builtin_amdgcn_rcpf(den);
+            const float den = __builtin_amdgcn_sqrtf(vq) * sc.isqbc2 + eps;
+            p[i] = pp[j] - lr.lr[first + j * stride] * sc.ibc1 * mv * __builtin_amdgcn_rcpf(den);
         }
     }
-    __device__ __forceinline__ void untouched(int64_t g, int64_t n_cap) const {
+    __device__ __forceinline__ void untouched(int64_t g, int64_t n_cap, Scale sc) const {
         const float z[1] = {0.f};
 #pragma unroll 1
-        for (int r = 0; r < kRows; ++r) group(r, 1, g, n_cap, z);
+        for (int r = 0; r < kRows; ++r) group(r, 1, g, n_cap, z, sc);
     }
 };
 
@@ -318,7 +325,7 @@ __global__ void __launch_bounds__(256) project_backward_kernel(
     int64_t records, Sink sink) {
     const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (g >= n) return;
-    sink.prepare();
+    const typename Sink::Scale sc = sink.prepare();
     const int nk = (s.sh_degree + 1) * (s.sh_degree + 1);
     float gmu[3] = {0, 0, 0}, gop = 0.f;
     float dSig[6] = {0, 0, 0, 0, 0, 0};   // summed over views: 00 01 02 11 12 22 (matrix entries)
@@ -399,7 +406,7 @@ __global__ void __launch_bounds__(256) project_backward_kernel(
         }
     }
     if (!any_view) {   // no view touched this Gaussian: zero gradient
-        sink.untouched(g, n_cap);
+        sink.untouched(g, n_cap, sc);
         return;
     }
 
@@ -443,7 +450,7 @@ __global__ void __launch_bounds__(256) project_backward_kernel(
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const float part[4] = {gsh[4 * q], gsh[4 * q + 1], gsh[4 * q + 2], gsh[4 * q + 3]};
-            sink.group(11 + ch + 12 * q, 3, g, n_cap, part);
+            sink.group(11 + ch + 12 * q, 3, g, n_cap, part, sc);
         }
     }
 
@@ -487,7 +494,7 @@ __global__ void __launch_bounds__(256) project_backward_kernel(
     }
     const float geo[11] = {gmu[0], gmu[1], gmu[2], gls[0], gls[1], gls[2],
                            gq[0], gq[1], gq[2], gq[3], gop * G.o * (1.f - G.o)};
-    sink.group(0, 1, g, n_cap, geo);
+    sink.group(0, 1, g, n_cap, geo, sc);
 }
 
 gs_status launch_project_backward(const gs_settings &s, const float *params, int64_t n,

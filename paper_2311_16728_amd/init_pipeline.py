@@ -4,8 +4,8 @@ Section 3.3.1 adds temporary primitives at inactive keypoints of a new
 keyframe, placed at the keypoint's depth.  Here a keypoint is synthetic: a
 visible Gaussian of a seeded room scene is held out of the map, and its
 projected centre, camera depth and footprint octave form the keypoint.  The
-map without the held-out Gaussians (perturbed like the other workloads)
-plus the new primitives is optimised for a fixed number of batched mapping
+map without the held-out Gaussians (the converged map a new keyframe meets;
+optionally perturbed) plus the new primitives is optimised for a fixed number of batched mapping
 iterations over every keyframe and pyramid level; the converged parameters of
 the new primitives, expressed in the keyframe's camera frame, are the labels
 and the keyframe's 7x7 patch around the keypoint is the input.
@@ -55,26 +55,31 @@ class Case:
     """One seeded scene with held-out keypoints in each keyframe."""
 
     def __init__(self, seed: int, n: int = 500_000, n_kf: int = 8, per_kf: int = 1280,
-                 width: int = 1200, height: int = 680, f: float = 600.0, device="cuda"):
+                 width: int = 1200, height: int = 680, f: float = 600.0, perturb_map: bool = False,
+                 device="cuda"):
         self.seed, self.device = seed, device
         gt, pert, cams = scenes.room_scene(seed, n, n_kf, width, height, f)
         self.cams = cams
         rng = np.random.default_rng(seed + 104729)
         Pgt = torch.as_tensor(gt).to(device)
         # ground-truth images and per-Gaussian visible weight sum_pixels alpha*T in each keyframe
-        plan = RenderPlan(cams, [(v, 0, (0, 0, 0), 1.0) for v in range(n_kf)], gt.shape[1], 1 << 28)
+        plan = RenderPlan(cams, [(v, 0, (0, 0, 0), 1.0) for v in range(n_kf)], gt.shape[1], 1 << 27)
         plan.render(Pgt, n)
+        if plan.overflowed():
+            raise RuntimeError("pair buffer overflow while rendering the ground truth")
         self.gt_images = [plan.image(plan.rgb, v).clone() for v in range(n_kf)]
         taken = np.zeros(n, bool)
         self.held = []            # per keyframe: GT column indices
         self.kp = []              # per keyframe: [B][4] float32 (u, v, depth, scale)
         for v, cam in enumerate(cams):
-            one = RenderPlan([cam], [(0, 0, (0, 0, 0), 1.0)], gt.shape[1], 1 << 28)
+            one = RenderPlan([cam], [(0, 0, (0, 0, 0), 1.0)], gt.shape[1], 1 << 25)
             one.render(Pgt, n)
             dL = torch.zeros(3 * one.total_pixels, dtype=torch.float32, device=device)
             dL[:one.total_pixels] = 1.0
             grad = torch.zeros_like(Pgt)
             one.backward(Pgt, n, dL, grad)
+            if one.overflowed():
+                raise RuntimeError("pair buffer overflow while scoring visibility")
             weight = (grad[11, :n] / C0).cpu().numpy()
             R = np.asarray(cam["R"], np.float64)
             xc = gt[0:3, :n].T.astype(np.float64) @ R.T + np.asarray(cam["t"], np.float64)
@@ -98,7 +103,8 @@ class Case:
         self.n_total = self.n_exist + self.n_new
         self.n_cap = scenes.pad_cap(self.n_total)
         base = np.zeros((59, self.n_cap), np.float32)
-        base[:, :self.n_exist] = pert[:, :n][:, keep]
+        # the map the new keyframe meets: converged (the ground truth) or perturbed
+        base[:, :self.n_exist] = (pert if perturb_map else gt)[:, :n][:, keep]
         self.base = base
         self.gt_new = [gt[:, h] for h in self.held]
 
@@ -200,11 +206,14 @@ def psnr_level0(bm: BatchedMapper) -> float:
 
 
 def generate(seeds, iters=100, log=print, **case_kw):
-    X, Y = [], []
+    """(features, labels, heuristic start) for every held-out keypoint of the
+    seeds' scenes; labels and heuristic start in the keyframe's camera frame."""
+    X, Y, H = [], [], []
     for s in seeds:
         t0 = time.time()
         c = Case(s, **case_kw)
         P, _ = c.initial_params(None)
+        H += [h.to(c.device) for h in c.labels(P)]
         bm = c.mapper(P)
         loss, _ = run(bm, iters)
         for v, lab in enumerate(c.labels(bm.params)):
@@ -212,7 +221,15 @@ def generate(seeds, iters=100, log=print, **case_kw):
             Y.append(lab.to(c.device))
         log(f"scene {s}: {c.n_new} pairs, loss after {iters} iterations {loss:.4f} ({time.time() - t0:.1f}s)")
         del c, bm, P
-    return torch.cat(X), torch.cat(Y)
+    return torch.cat(X), torch.cat(Y), torch.cat(H)
+
+
+GROUPS = {"log_scale": slice(0, 3), "quat": slice(3, 7), "opacity_logit": slice(7, 8), "sh_dc": slice(8, 11)}
+
+
+def param_errors(pred: torch.Tensor, label: torch.Tensor) -> dict:
+    """Mean squared error per parameter group (camera frame)."""
+    return {k: float(((pred[:, sl] - label[:, sl]) ** 2).mean()) for k, sl in GROUPS.items()}
 
 
 def train(X, Y, steps=3000, batch=4096, lr=1e-3, seed=0, log=print):
@@ -277,12 +294,18 @@ def main(argv=None):
         kw = dict(n=200_000, n_kf=4, per_kf=1024)
         a.train_seeds, a.eval_seeds, a.steps = 6, 3, 1500
     t0 = time.time()
-    X, Y = generate(range(a.train_seeds), a.iters, **kw)
+    X, Y, H = generate(range(a.train_seeds), a.iters, **kw)
     print(f"{X.shape[0]} pairs in {time.time() - t0:.1f}s", flush=True)
-    net, first, last = train(X, Y, a.steps)
+    # hold out every tenth pair to compare predictions with the heuristic in parameter space
+    val = torch.arange(X.shape[0], device=X.device) % 10 == 0
+    net, first, last = train(X[~val].contiguous(), Y[~val].contiguous(), a.steps)
     print(f"training mse {first:.4f} -> {last:.4f}", flush=True)
+    pred = net.forward(X[val].contiguous())[:, :N_TARGET]
+    perr = {"learned": param_errors(pred, Y[val]), "heuristic": param_errors(H[val], Y[val])}
+    print("validation parameter mse " + json.dumps(perr), flush=True)
     res = evaluate(net, range(1000, 1000 + a.eval_seeds), a.iters, **kw)
     res["pairs"] = int(X.shape[0])
+    res["validation_param_mse"] = perr
     res["train_mse"] = [first, last]
     summary = {k: v for k, v in res.items() if k != "rows"}
     print(json.dumps(summary, default=float), flush=True)

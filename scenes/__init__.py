@@ -37,4 +37,6 @@ from .gen import (  # noqa: F401
     level_camera,
     smooth_image,
     mixed_keyframes,
+    ROOM_LO,
+    ROOM_HI,
 )
