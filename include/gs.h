@@ -258,17 +258,19 @@ gs_status gs_step_advance(int32_t *d_step, void *stream);
 
 /* Network input per keypoint (device BF16 [B][160]): the 7x7 RGB patch of img
  * (device float [3][H][W], edge-clamped) around the rounded pixel, channel
- * major, then depth, scale and a one-hot of the octave round(log_1.2 scale)
- * clamped to 0..7 (157 values), zero-padded to 160. */
+ * major, then depth, scale, a one-hot of the octave round(log_1.2 scale)
+ * clamped to 0..7, the heuristic log-scale (row 3 of heuristic, device float
+ * [59][B], optional: 0 when NULL) and log depth (159 values), zero-padded to
+ * 160. */
 gs_status gs_init_features(const float *img, int32_t H, int32_t W, const float *kp, int32_t B,
-                           void *x_bf16, void *stream);
+                           const float *heuristic, void *x_bf16, void *stream);
 
 /* MLP 160 -> 128 -> 128 -> 16 with ReLU hidden layers, BF16 weights and
  * activations on the matrix cores, FP32 accumulation.  w_bf16 (device, 38912
  * BF16): W1 [128][160], W2 [128][128], W3 [16][128] row-major [out][in], in
  * that order; bias (device, 272 floats): b1, b2, b3.  x_bf16 (device BF16
- * [B][160]); y (device float [B][16]: log-scale in pixels (3), camera-frame
- * quaternion (4), opacity logit, SH DC (3), 5 unused); act_ws (device,
+ * [B][160]); y (device float [B][16]: log-scale correction (3), camera-frame
+ * quaternion (4), opacity logit, SH DC correction (3), 5 unused); act_ws (device,
  * 2 * B * 128 BF16) keeps the hidden activations for the backward. */
 gs_status gs_init_mlp_fwd(const void *w_bf16, const float *bias, const void *x_bf16, int32_t B,
                           float *y, void *act_ws, void *stream);
@@ -300,11 +302,12 @@ gs_status gs_init_heuristic(const float *new_mu, const float *new_rgb, int32_t B
                             void *stream);
 
 /* World-frame parameters (device float [59][B]) from MLP outputs y for
- * keypoints kp seen by view (host struct, level 0): mean = back-projection of
- * (u, v) at the depth; log-scale = y + log(depth / fx); quaternion = rotation
- * of the camera-to-world transform composed with y's; opacity logit and DC
- * from y; other SH 0.  Where sigmoid(opacity logit) < 0.01 the column of
- * heuristic (device [59][B]) is used instead and used_fallback (device int32
+ * keypoints kp seen by view (host struct, level 0), relative to the heuristic
+ * columns (device [59][B]): mean = back-projection of (u, v) at the depth;
+ * log-scale = heuristic log-scale + y[0..2]; quaternion = rotation of the
+ * camera-to-world transform composed with y[3..6]; opacity logit = y[7];
+ * SH DC = heuristic DC + y[8..10]; other SH 0.  Where sigmoid(y[7]) < 0.01
+ * the heuristic column is used unchanged and used_fallback (device int32
  * [B], optional) is set to 1. */
 gs_status gs_init_decode(const float *y, const float *kp, const gs_view *view, int32_t B,
                          const float *heuristic, float *out, int32_t *used_fallback,

@@ -2,14 +2,16 @@
 // primitives are created at inactive 2D keypoints of a new keyframe, placed in
 // 3D with the keypoint's depth).  Kernels:
 //   features  - network input per keypoint: 7x7 RGB patch of the keyframe image
-//               (edge-clamped), depth, keypoint scale and a one-hot of its
-//               octave (8), zero-padded to 160, BF16;
+//               (edge-clamped), depth, keypoint scale, a one-hot of its
+//               octave (8), the heuristic's log-scale and log depth,
+//               zero-padded to 160, BF16;
 //   heuristic - scale = mean distance to the 3 nearest means (existing and
 //               new), isotropic, identity rotation, opacity 0.1, colour from
 //               the pixel, higher SH zero;
-//   decode    - network outputs (camera frame: log-scale in pixels, quaternion,
-//               opacity logit, SH DC) to world-frame parameters, falling back
-//               to the heuristic when the predicted opacity is below 0.01;
+//   decode    - network outputs (corrections to the heuristic's log-scale and
+//               SH DC, a camera-frame quaternion, the opacity logit) to
+//               world-frame parameters, falling back to the heuristic when the
+//               predicted opacity is below 0.01;
 //   append    - copy new columns into the parameter store, Adam moments zeroed.
 // Keypoints are float4 (u, v, depth, scale) in pixels / metres; scale is
 // 1.2^octave.
@@ -27,6 +29,7 @@ __device__ __forceinline__ uint16_t f2bf_init(float f) {
 
 __global__ void __launch_bounds__(256) features_kernel(const float *__restrict__ img, int H, int W,
                                                        const float4 *__restrict__ kp, int B,
+                                                       const float *__restrict__ heur,
                                                        uint16_t *__restrict__ x) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= B) return;
@@ -44,6 +47,8 @@ __global__ void __launch_bounds__(256) features_kernel(const float *__restrict__
     row[f++] = f2bf_init(k.w);                                  // scale
     const int oct = min(max(int(rintf(__logf(fmaxf(k.w, 1.f)) / __logf(1.2f))), 0), 7);
     for (int o = 0; o < 8; ++o) row[f++] = f2bf_init(o == oct ? 1.f : 0.f);
+    row[f++] = f2bf_init(heur ? heur[int64_t(3) * B + i] : 0.f);   // heuristic log-scale (metres)
+    row[f++] = f2bf_init(logf(k.z));                                 // log depth
     for (; f < kFeat; ++f) row[f] = 0;
 }
 
@@ -140,8 +145,8 @@ __global__ void __launch_bounds__(256) decode_kernel(const float *__restrict__ y
     float col[kRows];
     for (int r = 0; r < kRows; ++r) col[r] = 0.f;
     for (int a = 0; a < 3; ++a) col[a] = R[a] * d[0] + R[3 + a] * d[1] + R[6 + a] * d[2];
-    const float lpx = logf(k.z / view.fx);   // pixel size at the keypoint's depth
-    for (int a = 0; a < 3; ++a) col[3 + a] = yi[a] + lpx;
+    // log-scale: the heuristic's plus the predicted correction
+    for (int a = 0; a < 3; ++a) col[3 + a] = heur[int64_t(3 + a) * B + i] + yi[a];
     // camera-frame rotation to world: q_w = q(R^T) * q_c
     float Rt[9] = {R[0], R[3], R[6], R[1], R[4], R[7], R[2], R[5], R[8]};
     float qa[4];
@@ -152,7 +157,8 @@ __global__ void __launch_bounds__(256) decode_kernel(const float *__restrict__ y
     col[8] = qa[0] * qb[2] - qa[1] * qb[3] + qa[2] * qb[0] + qa[3] * qb[1];
     col[9] = qa[0] * qb[3] + qa[1] * qb[2] - qa[2] * qb[1] + qa[3] * qb[0];
     col[10] = yi[7];
-    for (int c = 0; c < 3; ++c) col[11 + c] = yi[8 + c];
+    // SH DC: the heuristic's (pixel colour) plus the predicted correction
+    for (int c = 0; c < 3; ++c) col[11 + c] = heur[int64_t(11 + c) * B + i] + yi[8 + c];
     for (int r = 0; r < kRows; ++r) out[int64_t(r) * B + i] = col[r];
 }
 
@@ -172,11 +178,11 @@ __global__ void __launch_bounds__(256) append_kernel(float *__restrict__ P, floa
 }  // namespace gs
 
 extern "C" gs_status gs_init_features(const float *img, int32_t H, int32_t W, const float *kp,
-                                      int32_t B, void *x_bf16, void *stream) {
+                                      int32_t B, const float *heuristic, void *x_bf16, void *stream) {
     if (!img || !kp || !x_bf16 || H <= 0 || W <= 0 || B <= 0) return GS_ERR_INVALID_ARGUMENT;
     hipLaunchKernelGGL(gs::features_kernel, dim3((B + 255) / 256), dim3(256), 0,
                        static_cast<hipStream_t>(stream), img, H, W, reinterpret_cast<const float4 *>(kp), B,
-                       static_cast<uint16_t *>(x_bf16));
+                       heuristic, static_cast<uint16_t *>(x_bf16));
     GS_CHECK_LAUNCH();
     return GS_OK;
 }

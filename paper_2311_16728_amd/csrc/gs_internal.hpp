@@ -15,8 +15,10 @@ constexpr int kTilePix = kTile * kTile;          // 256 pixels, one thread each
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;   // 4096 elements per block
-constexpr int kRadixBits = 8;
-constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kRadixBits = 8;                 // digit width of the depth sort
+constexpr int kRadixBitsMax = 9;              // widest digit (tile sort)
+constexpr int kRadixBinsMax = 1 << kRadixBitsMax;
+constexpr int kRadixPersist = 2048;           // workgroups of the grid-stride radix kernels
 
 static inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -53,9 +55,12 @@ static inline Proj proj_at(void *ws, int64_t records) {
 // Counters at the head of the sort workspace.
 enum Counter { kVisible = 0, kPairs = 1, kPairsClamped = 2, kNumCounters = 16 };
 
+// Pair emission works in chunks of 256 consecutive pair slots.
+static inline int64_t pair_chunks(int64_t pair_cap) { return (pair_cap + 255) / 256; }
+
 struct SortLayout {
     size_t counters, counts, rects, vis_key0, vis_key1, vis_val0, vis_val1, vis_off, pair_key0,
-        pair_key1, pair_val0, pair_val1, ranges, bsum, hist, digit, bytes;
+        pair_key1, pair_val0, pair_val1, ranges, bsum, hist, digit, chunk_first, bytes;
     int64_t sources, pair_cap, max_blocks;
     static SortLayout make(int64_t sources, int64_t pair_cap, int64_t total_tiles) {
         SortLayout L;
@@ -80,18 +85,26 @@ struct SortLayout {
         L.pair_val1 = take(sizeof(uint32_t) * pair_cap);
         L.ranges = take(sizeof(uint32_t) * 2 * (total_tiles > 0 ? total_tiles : 1));
         L.bsum = take(sizeof(uint32_t) * (L.max_blocks + 1));
-        L.hist = take(sizeof(uint32_t) * kRadixBins * L.max_blocks);
-        L.digit = take(sizeof(uint32_t) * (kRadixBins + 1));
+        L.hist = take(sizeof(uint32_t) * kRadixBinsMax * L.max_blocks);
+        L.digit = take(sizeof(uint32_t) * (kRadixBinsMax + 1));
+        // first sorted record of every 256-pair emission chunk
+        L.chunk_first = take(sizeof(uint32_t) * (pair_chunks(pair_cap) + 1));
         L.bytes = o;
         return L;
     }
 };
 
-// Number of 8-bit radix passes that order global tile indices < total_tiles.
-static inline int tile_sort_passes(int32_t total_tiles) {
+// Digit width and number of stable radix passes that order global tile
+// indices < total_tiles: 8-bit digits, or 9-bit ones where they save a pass
+// (17 or 18 bits: two passes instead of three).
+struct TileSortPlan {
+    int bits, passes;
+};
+static inline TileSortPlan tile_sort_plan(int32_t total_tiles) {
     int bits = 1;
     while ((int64_t(1) << bits) < total_tiles) ++bits;
-    return (bits + kRadixBits - 1) / kRadixBits;
+    const int p8 = (bits + 7) / 8, p9 = (bits + 8) / 9;
+    return p9 < p8 ? TileSortPlan{9, p9} : TileSortPlan{8, p8};
 }
 
 // Sorted pair buffers after binning: the tile sort ends in buffer (passes & 1).
@@ -104,7 +117,7 @@ static inline Sorted sorted_at(const void *ws, int64_t sources, int64_t pair_cap
                                int32_t total_tiles) {
     SortLayout L = SortLayout::make(sources, pair_cap, total_tiles);
     const char *b = static_cast<const char *>(ws);
-    int passes = tile_sort_passes(total_tiles);
+    const int passes = tile_sort_plan(total_tiles).passes;
     size_t val = (passes & 1) ? L.pair_val1 : L.pair_val0;
     return Sorted{reinterpret_cast<const uint32_t *>(b + val),
                   reinterpret_cast<const uint2 *>(b + L.ranges)};
@@ -166,6 +179,17 @@ __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
     return v;
+}
+
+// Workgroups of a launch are handed to the chip's 8 XCDs in turn, and each
+// XCD has its own L2.  A grid of xcd_grid(T) workgroups with tile xcd_tile(b)
+// gives every XCD one contiguous eighth of the T tiles, so neighbouring tiles
+// that read the same lines (image halos) share an L2.  Workgroups with
+// xcd_tile(b) >= T have nothing to do.
+constexpr int kXcds = 8;
+static inline int64_t xcd_grid(int64_t T) { return kXcds * ((T + kXcds - 1) / kXcds); }
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t T) {
+    return (b % kXcds) * ((T + kXcds - 1) / kXcds) + b / kXcds;
 }
 
 // Exclusive scan over a 256-thread block; returns the prefix of this thread

@@ -54,7 +54,7 @@ __device__ __forceinline__ void load_halo(const float *__restrict__ plane, int W
 __global__ void __launch_bounds__(256) ssim_fwd_kernel(const float *__restrict__ render,
                                                        const float *__restrict__ target,
                                                        const gs_target *__restrict__ targets,
-                                                       int n_targets, Window win,
+                                                       int n_targets, int total_tiles, Window win,
                                                        float *__restrict__ maps,
                                                        float *__restrict__ partial) {
     __shared__ float sx[kHalo][kHalo];
@@ -62,7 +62,8 @@ __global__ void __launch_bounds__(256) ssim_fwd_kernel(const float *__restrict__
     __shared__ float h[5][kHalo][kTile];
     __shared__ float red[2][kTilePix / kWave];
     const float C1 = 0.01f * 0.01f, C2 = 0.03f * 0.03f;
-    const int tile = blockIdx.x, tid = threadIdx.x;
+    const int tile = int(xcd_tile(blockIdx.x, total_tiles)), tid = threadIdx.x;
+    if (tile >= total_tiles) return;
     const gs_target t = targets[find_target_loss(targets, n_targets, tile)];
     const int local = tile - t.tile_offset;
     const int x0 = (local % t.tiles_x) * kTile, y0 = (local / t.tiles_x) * kTile;
@@ -133,12 +134,14 @@ __global__ void __launch_bounds__(256) ssim_fwd_kernel(const float *__restrict__
 __global__ void __launch_bounds__(256) ssim_bwd_kernel(const float *__restrict__ render,
                                                        const float *__restrict__ target,
                                                        const gs_target *__restrict__ targets,
-                                                       int n_targets, Window win, float lambda,
+                                                       int n_targets, int total_tiles, Window win,
+                                                       float lambda,
                                                        const float *__restrict__ maps,
                                                        float *__restrict__ dL) {
     __shared__ float sm[3][kHalo][kHalo];
     __shared__ float h[3][kHalo][kTile];
-    const int tile = blockIdx.x, tid = threadIdx.x;
+    const int tile = int(xcd_tile(blockIdx.x, total_tiles)), tid = threadIdx.x;
+    if (tile >= total_tiles) return;
     const gs_target t = targets[find_target_loss(targets, n_targets, tile)];
     const int local = tile - t.tile_offset;
     const int x0 = (local % t.tiles_x) * kTile, y0 = (local / t.tiles_x) * kTile;
@@ -301,11 +304,12 @@ extern "C" gs_status gs_pyramid_loss(const float *render, const float *target,
     float *partial = reinterpret_cast<float *>(b + L.partial);
     float *maps = reinterpret_cast<float *>(b + L.maps);
     const Window win = ssim_window();
-    hipLaunchKernelGGL(ssim_fwd_kernel, dim3(total_tiles), dim3(kTilePix), 0, st, render, target,
-                       targets, n_targets, win, maps, partial);
+    const int64_t grid = xcd_grid(total_tiles);
+    hipLaunchKernelGGL(ssim_fwd_kernel, dim3(grid), dim3(kTilePix), 0, st, render, target, targets,
+                       n_targets, total_tiles, win, maps, partial);
     if (dL_drender)
-        hipLaunchKernelGGL(ssim_bwd_kernel, dim3(total_tiles), dim3(kTilePix), 0, st, render, target,
-                           targets, n_targets, win, lambda, maps, dL_drender);
+        hipLaunchKernelGGL(ssim_bwd_kernel, dim3(grid), dim3(kTilePix), 0, st, render, target, targets,
+                           n_targets, total_tiles, win, lambda, maps, dL_drender);
     hipLaunchKernelGGL(loss_finalize_kernel, dim3(1), dim3(256), 0, st, targets, n_targets, lambda,
                        partial, d_loss, d_total);
     GS_CHECK_LAUNCH();

@@ -173,7 +173,9 @@ __global__ void __launch_bounds__(256) offsets_scatter_kernel(const uint32_t *__
                                                               const uint32_t *__restrict__ counts,
                                                               const uint32_t *__restrict__ vis_val,
                                                               const uint32_t *__restrict__ bsum,
-                                                              uint32_t *__restrict__ vis_off) {
+                                                              uint32_t *__restrict__ vis_off,
+                                                              uint32_t *__restrict__ chunk_first,
+                                                              int64_t n_chunks) {
     __shared__ uint32_t lds[8];
     const uint32_t n = *n_ptr;
     const int64_t base = int64_t(blockIdx.x) * kScanTile;
@@ -184,26 +186,34 @@ __global__ void __launch_bounds__(256) offsets_scatter_kernel(const uint32_t *__
         const uint32_t c = (e < n) ? counts[vis_val[e]] : 0u;
         uint32_t total;
         const uint32_t pre = block_exclusive_scan(c, lds, &total);
-        if (e < n) vis_off[e] = run + pre;
+        if (e < n) {
+            const uint32_t o = run + pre;
+            vis_off[e] = o;
+            // this record holds the first slot of every chunk starting in [o, o + c)
+            const uint64_t end = uint64_t(o) + c;
+            for (uint64_t q = (uint64_t(o) + 255) / 256; q * 256 < end && int64_t(q) < n_chunks; ++q)
+                chunk_first[q] = uint32_t(e);
+        }
         run += total;
     }
 }
 
 // Pair emission, one thread per output pair.  A block takes 256 consecutive
-// pair slots; the records covering them (at most 256, each has >= 1 pair) are
-// found with one binary search over the sorted records' offsets, staged in LDS,
-// and each thread locates its record by a second search there.  Near-camera
-// Gaussians that cover thousands of tiles are thus spread over many threads.
+// pair slots; the records covering them (at most 256, each has >= 1 pair)
+// start at chunk_first[chunk] (written by the offsets scan), their offsets are
+// staged in LDS, and each thread locates its record by a binary search there.
+// Near-camera Gaussians that cover thousands of tiles are thus spread over many
+// threads.
 __global__ void __launch_bounds__(256) emit_kernel(int64_t n_cap, const gs_target *__restrict__ targets,
                                                    uint32_t *__restrict__ counters,
                                                    const uint32_t *__restrict__ vis_val,
                                                    const uint32_t *__restrict__ vis_off,
-                                                   const uint2 *__restrict__ rects, int64_t pair_cap,
-                                                   uint32_t *__restrict__ pkey,
+                                                   const uint2 *__restrict__ rects,
+                                                   const uint32_t *__restrict__ chunk_first,
+                                                   int64_t pair_cap, uint32_t *__restrict__ pkey,
                                                    uint32_t *__restrict__ pval,
                                                    uint32_t *__restrict__ d_status) {
     __shared__ uint32_t off[kScanThreads + 1];
-    __shared__ uint32_t first;
     const uint32_t V = counters[kVisible];
     const uint32_t P = counters[kPairs];
     const uint32_t Pc = int64_t(P) > pair_cap ? uint32_t(pair_cap) : P;
@@ -214,18 +224,8 @@ __global__ void __launch_bounds__(256) emit_kernel(int64_t n_cap, const gs_targe
     if (V == 0) return;   // no visible record, no pair (Pc == 0)
     for (int64_t chunk = blockIdx.x; chunk * kScanThreads < Pc; chunk += gridDim.x) {
         const uint32_t o0 = uint32_t(chunk * kScanThreads);
+        const uint32_t j0 = chunk_first[chunk];   // last record j with vis_off[j] <= o0
         __syncthreads();
-        if (threadIdx.x == 0) {
-            // last record j with vis_off[j] <= o0
-            uint32_t lo = 0, hi = V - 1;
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi + 1) >> 1;
-                if (vis_off[mid] <= o0) lo = mid; else hi = mid - 1;
-            }
-            first = lo;
-        }
-        __syncthreads();
-        const uint32_t j0 = first;
         for (int i = threadIdx.x; i <= kScanThreads; i += blockDim.x) {
             const uint32_t j = j0 + i;
             off[i] = (j < V) ? vis_off[j] : 0xffffffffu;
@@ -251,27 +251,34 @@ __global__ void __launch_bounds__(256) emit_kernel(int64_t n_cap, const gs_targe
 }
 
 // ---------------------------------------------------------------------------
-// Stable LSD radix sort pass (8-bit digit at `shift`) over n = *n_ptr pairs.
-// A block owns kItems * 256 consecutive elements.
+// Stable LSD radix sort pass (kBits-bit digit at `shift`) over n = *n_ptr
+// elements.  A sort block owns kItems * 256 consecutive elements; wave w of
+// it owns the contiguous quarter [w * kItems * 64, (w + 1) * kItems * 64).
+// The grids are grid-stride over the sort blocks, so a capacity-sized launch
+// does not start thousands of idle workgroups.
 // ---------------------------------------------------------------------------
-template <int kItems>
+template <int kItems, int kBits>
 __global__ void __launch_bounds__(256) radix_hist_kernel(const uint32_t *__restrict__ n_ptr,
                                                          const uint32_t *__restrict__ keys, int shift,
                                                          uint32_t *__restrict__ hist,
                                                          int64_t max_blocks) {
-    __shared__ uint32_t h[kRadixBins];
+    constexpr int kBins = 1 << kBits, kTileN = kItems * kScanThreads;
+    __shared__ uint32_t h[kBins];
     const uint32_t n = *n_ptr;
-    const int64_t base = int64_t(blockIdx.x) * kItems * kScanThreads;
-    if (base >= n) return;
-    h[threadIdx.x] = 0;
-    __syncthreads();
+    const int64_t nb = (int64_t(n) + kTileN - 1) / kTileN;
+    for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < kBins; i += kScanThreads) h[i] = 0;
+        __syncthreads();
+        const int64_t base = b * kTileN;
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        const int64_t e = base + k * kScanThreads + threadIdx.x;
-        if (e < n) atomicAdd(&h[(keys[e] >> shift) & (kRadixBins - 1)], 1u);
+        for (int k = 0; k < kItems; ++k) {
+            const int64_t e = base + k * kScanThreads + threadIdx.x;
+            if (e < n) atomicAdd(&h[(keys[e] >> shift) & (kBins - 1)], 1u);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < kBins; i += kScanThreads) hist[int64_t(i) * max_blocks + b] = h[i];
     }
-    __syncthreads();
-    hist[int64_t(threadIdx.x) * max_blocks + blockIdx.x] = h[threadIdx.x];
 }
 
 // Block d: exclusive scan of row d of hist over the active blocks; row total
@@ -296,89 +303,124 @@ __global__ void __launch_bounds__(256) radix_rowscan_kernel(const uint32_t *__re
     if (threadIdx.x == 0) digit[blockIdx.x] = run;
 }
 
-// Scatter: stable in-block ranks (wave ballots on the 8 digit bits, per-wave
-// digit counters in LDS), the block's elements laid out in digit order in LDS,
-// then written out so that consecutive threads write consecutive addresses of
-// each digit's run.
-template <int kItems>
+// Scatter.  Ranks are found per wave with no workgroup barrier per element:
+// a wave walks its quarter in order, groups equal digits with kBits ballots,
+// and keeps a running count per digit in its own LDS row.  One barrier later
+// the rows are turned into per-wave offsets, the block's elements are laid out
+// in digit order in LDS and written so that consecutive threads write
+// consecutive addresses of each digit's run.  Order inside a digit is the
+// input order (stable).
+template <int kItems, int kBits>
 __global__ void __launch_bounds__(256) radix_scatter_kernel(
     const uint32_t *__restrict__ n_ptr, const uint32_t *__restrict__ kin,
     const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
     int shift, const uint32_t *__restrict__ hist, int64_t max_blocks,
     const uint32_t *__restrict__ digit) {
+    constexpr int kBins = 1 << kBits, kPer = kBins / kScanThreads;
     constexpr int kWaves = kScanThreads / kWave;
-    constexpr int kTileN = kItems * kScanThreads;
-    __shared__ uint32_t gbase[kRadixBins];    // global start of each digit's run of this block
-    __shared__ uint32_t lstart[kRadixBins];   // start of each digit inside the block
-    __shared__ uint32_t run[kRadixBins];      // elements of each digit placed so far
-    __shared__ uint32_t wcnt[kWaves][kRadixBins];
+    constexpr int kTileN = kItems * kScanThreads, kWaveN = kItems * kWave;
+    static_assert(kPer >= 1 && kBins % kScanThreads == 0, "digit bins per thread");
+    __shared__ uint32_t dbase[kBins];         // start of each digit over all blocks
+    __shared__ uint32_t gbase[kBins];         // global start of each digit's run of this block
+    __shared__ uint32_t lstart[kBins];        // start of each digit inside the block
+    __shared__ uint32_t wcnt[kWaves][kBins];  // per-wave digit counts, then per-wave offsets
     __shared__ uint32_t skey[kTileN];
     __shared__ uint32_t sval[kTileN];
     __shared__ uint32_t lds[8];
     const uint32_t n = *n_ptr;
-    const int64_t base = int64_t(blockIdx.x) * kTileN;
-    if (base >= n) return;
-    const int tid = threadIdx.x, wave = tid / kWave;
     const int64_t nb = (int64_t(n) + kTileN - 1) / kTileN;
+    if (int64_t(blockIdx.x) >= nb) return;   // uniform over the workgroup
+    const int tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
     {
-        // this block's count of digit tid, from the scanned histogram
-        const uint32_t pre = hist[int64_t(tid) * max_blocks + blockIdx.x];
-        const uint32_t nxt = (int64_t(blockIdx.x) + 1 < nb) ? hist[int64_t(tid) * max_blocks + blockIdx.x + 1]
-                                                            : digit[tid];
-        uint32_t total;
-        const uint32_t dbase = block_exclusive_scan(digit[tid], lds, &total);
-        const uint32_t l = block_exclusive_scan(nxt - pre, lds, &total);
-        gbase[tid] = dbase + pre;
-        lstart[tid] = l;
-        run[tid] = 0;
+        uint32_t v[kPer], sum = 0, total;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) { v[j] = digit[tid * kPer + j]; sum += v[j]; }
+        uint32_t pre = block_exclusive_scan(sum, lds, &total);
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) { dbase[tid * kPer + j] = pre; pre += v[j]; }
     }
+    for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        const int64_t base = b * kTileN;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0;
-    __syncthreads();
-    for (int k = 0; k < kItems; ++k) {
-        const int64_t e = base + k * kScanThreads + tid;
-        const bool valid = e < n;
-        uint32_t key = 0, val = 0, d = 0;
-        if (valid) {
-            key = kin[e];
-            val = vin[e];
-            d = (key >> shift) & (kRadixBins - 1);
-        }
-        uint64_t peers = __ballot(valid);
+        for (int j = 0; j < kPer; ++j)
 #pragma unroll
-        for (int b = 0; b < kRadixBits; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
-        }
-        const int rank = mask_rank(peers);
-        if (valid && rank == 0) wcnt[wave][d] = uint32_t(__popcll(peers));
+            for (int w = 0; w < kWaves; ++w) wcnt[w][tid * kPer + j] = 0;
         __syncthreads();
-        if (valid) {
-            uint32_t pos = lstart[d] + run[d] + uint32_t(rank);
-            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-            skey[pos] = key;
-            sval[pos] = val;
-        }
-        __syncthreads();
-        uint32_t add = 0;
+        uint32_t key[kItems], val[kItems], pos[kItems];
+        const int64_t wbase = base + int64_t(wave) * kWaveN;
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) { add += wcnt[w][tid]; wcnt[w][tid] = 0; }
-        run[tid] += add;
+        for (int k = 0; k < kItems; ++k) {
+            const int64_t e = wbase + k * kWave + lane;
+            const bool valid = e < n;
+            key[k] = valid ? kin[e] : 0u;
+            val[k] = valid ? vin[e] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const bool valid = wbase + k * kWave + lane < n;
+            const uint32_t d = (key[k] >> shift) & (kBins - 1);
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int bit = 0; bit < kBits; ++bit) {
+                const bool set = (d >> bit) & 1u;
+                const uint64_t m = __ballot(set);
+                peers &= set ? m : ~m;
+            }
+            const int rank = mask_rank(peers);
+            const uint32_t prior = valid ? wcnt[wave][d] : 0u;
+            pos[k] = prior + uint32_t(rank);
+            if (valid && rank == 0) wcnt[wave][d] = prior + uint32_t(__popcll(peers));
+        }
         __syncthreads();
-    }
-    const int cnt = int(min(int64_t(kTileN), int64_t(n) - base));
-    for (int i = tid; i < cnt; i += kScanThreads) {
-        const uint32_t key = skey[i];
-        const uint32_t d = (key >> shift) & (kRadixBins - 1);
-        const uint32_t pos = gbase[d] + (uint32_t(i) - lstart[d]);
-        kout[pos] = key;
-        vout[pos] = sval[i];
+        {
+            uint32_t cnt[kPer], sum = 0, total;
+#pragma unroll
+            for (int j = 0; j < kPer; ++j) {
+                const int d = tid * kPer + j;
+                uint32_t r = 0;
+#pragma unroll
+                for (int w = 0; w < kWaves; ++w) {
+                    const uint32_t c = wcnt[w][d];
+                    wcnt[w][d] = r;
+                    r += c;
+                }
+                cnt[j] = r;
+                sum += r;
+            }
+            uint32_t pre = block_exclusive_scan(sum, lds, &total);
+#pragma unroll
+            for (int j = 0; j < kPer; ++j) {
+                const int d = tid * kPer + j;
+                lstart[d] = pre;
+                gbase[d] = dbase[d] + hist[int64_t(d) * max_blocks + b];
+                pre += cnt[j];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            if (wbase + k * kWave + lane < n) {
+                const uint32_t d = (key[k] >> shift) & (kBins - 1);
+                const uint32_t p = lstart[d] + wcnt[wave][d] + pos[k];
+                skey[p] = key[k];
+                sval[p] = val[k];
+            }
+        }
+        __syncthreads();
+        const int cnt = int(min(int64_t(kTileN), int64_t(n) - base));
+        for (int i = tid; i < cnt; i += kScanThreads) {
+            const uint32_t k2 = skey[i];
+            const uint32_t d = (k2 >> shift) & (kBins - 1);
+            const uint32_t p = gbase[d] + (uint32_t(i) - lstart[d]);
+            kout[p] = k2;
+            vout[p] = sval[i];
+        }
+        __syncthreads();
     }
 }
 
 struct SortBufs {
-    uint32_t *counters, *counts, *vk[2], *vv[2], *voff, *pk[2], *pv[2], *bsum, *hist, *digit;
+    uint32_t *counters, *counts, *vk[2], *vv[2], *voff, *pk[2], *pv[2], *bsum, *hist, *digit, *chunk_first;
     uint2 *ranges, *rects;
     int64_t max_blocks;
 };
@@ -398,27 +440,29 @@ static SortBufs sort_bufs(void *ws, int64_t S, int64_t pair_cap, int32_t total_t
     B.bsum = u(L.bsum);
     B.hist = u(L.hist);
     B.digit = u(L.digit);
+    B.chunk_first = u(L.chunk_first);
     B.ranges = reinterpret_cast<uint2 *>(b + L.ranges);
     B.rects = reinterpret_cast<uint2 *>(b + L.rects);
     B.max_blocks = L.max_blocks;
     return B;
 }
 
-// Sorts (kbuf[cur], vbuf[cur]) through the two buffers over `passes` 8-bit
+// Sorts (kbuf[cur], vbuf[cur]) through the two buffers over `passes` kBits
 // digits starting at bit first_bit; returns the buffer index holding the result.
-template <int kItems>
+template <int kItems, int kBits>
 static int radix_sort(const uint32_t *n_ptr, uint32_t *kbuf[2], uint32_t *vbuf[2], int cur,
                       int first_bit, int passes, int64_t capacity, const SortBufs &B,
                       hipStream_t st) {
     const int64_t blocks = (capacity + kItems * kScanThreads - 1) / (kItems * kScanThreads);
+    const int64_t grid = blocks < kRadixPersist ? blocks : kRadixPersist;
     for (int p = 0; p < passes; ++p) {
-        const int shift = first_bit + p * kRadixBits;
-        hipLaunchKernelGGL(radix_hist_kernel<kItems>, dim3(blocks), dim3(256), 0, st, n_ptr, kbuf[cur],
-                           shift, B.hist, B.max_blocks);
-        hipLaunchKernelGGL(radix_rowscan_kernel<kItems>, dim3(kRadixBins), dim3(256), 0, st, n_ptr, B.hist,
+        const int shift = first_bit + p * kBits;
+        hipLaunchKernelGGL((radix_hist_kernel<kItems, kBits>), dim3(grid), dim3(256), 0, st, n_ptr,
+                           kbuf[cur], shift, B.hist, B.max_blocks);
+        hipLaunchKernelGGL(radix_rowscan_kernel<kItems>, dim3(1 << kBits), dim3(256), 0, st, n_ptr, B.hist,
                            B.max_blocks, B.digit);
-        hipLaunchKernelGGL(radix_scatter_kernel<kItems>, dim3(blocks), dim3(256), 0, st, n_ptr, kbuf[cur],
-                           vbuf[cur], kbuf[cur ^ 1], vbuf[cur ^ 1], shift, B.hist, B.max_blocks,
+        hipLaunchKernelGGL((radix_scatter_kernel<kItems, kBits>), dim3(grid), dim3(256), 0, st, n_ptr,
+                           kbuf[cur], vbuf[cur], kbuf[cur ^ 1], vbuf[cur ^ 1], shift, B.hist, B.max_blocks,
                            B.digit);
         cur ^= 1;
     }
@@ -471,24 +515,26 @@ extern "C" gs_status gs_bin_sort(const gs_settings *s, const void *proj_ws, int6
     hipLaunchKernelGGL(compact_scatter_kernel, dim3(sblocks), dim3(256), 0, st, B.counts, S, n_cap,
                        targets, proj, B.bsum, B.vk[0], B.vv[0]);
     // depth order (4 passes: result back in buffer 0)
-    int cur = radix_sort<4>(B.counters + kVisible, B.vk, B.vv, 0, 0, 4, S, B, st);
+    int cur = radix_sort<4, kRadixBits>(B.counters + kVisible, B.vk, B.vv, 0, 0, 32 / kRadixBits, S, B, st);
     // pair offsets in depth order
     hipLaunchKernelGGL(offsets_reduce_kernel, dim3(sblocks), dim3(256), 0, st, B.counters + kVisible,
                        B.counts, B.vv[cur], B.bsum);
     hipLaunchKernelGGL(scan_bsums_kernel, dim3(1), dim3(1024), 0, st, B.counters + kVisible, B.bsum,
                        B.counters + kPairs, int64_t(0));
+    const int64_t n_chunks = pair_chunks(pair_cap);
     hipLaunchKernelGGL(offsets_scatter_kernel, dim3(sblocks), dim3(256), 0, st, B.counters + kVisible,
-                       B.counts, B.vv[cur], B.bsum, B.voff);
-    const int64_t pair_chunks = (pair_cap + kScanThreads - 1) / kScanThreads;
+                       B.counts, B.vv[cur], B.bsum, B.voff, B.chunk_first, n_chunks);
     const int64_t persistent = 256 * 16;   // 16 workgroups per CU, grid-stride beyond
-    hipLaunchKernelGGL(emit_kernel, dim3(pair_chunks < persistent ? pair_chunks : persistent), dim3(256), 0,
-                       st, n_cap, targets, B.counters, B.vv[cur], B.voff, B.rects, pair_cap, B.pk[0],
-                       B.pv[0], d_status);
+    hipLaunchKernelGGL(emit_kernel, dim3(n_chunks < persistent ? n_chunks : persistent), dim3(256), 0, st,
+                       n_cap, targets, B.counters, B.vv[cur], B.voff, B.rects, B.chunk_first, pair_cap,
+                       B.pk[0], B.pv[0], d_status);
     // tile order
-    const int passes = tile_sort_passes(total_tiles);
-    int pc = radix_sort<16>(B.counters + kPairsClamped, B.pk, B.pv, 0, 0, passes, pair_cap, B, st);
-    hipLaunchKernelGGL(ranges_kernel, dim3(pair_chunks < persistent ? pair_chunks : persistent), dim3(256),
-                       0, st, B.counters, B.pk[pc], B.ranges);
+    const TileSortPlan plan = tile_sort_plan(total_tiles);
+    const int pc = plan.bits == 9
+                       ? radix_sort<16, 9>(B.counters + kPairsClamped, B.pk, B.pv, 0, 0, plan.passes, pair_cap, B, st)
+                       : radix_sort<16, 8>(B.counters + kPairsClamped, B.pk, B.pv, 0, 0, plan.passes, pair_cap, B, st);
+    hipLaunchKernelGGL(ranges_kernel, dim3(n_chunks < persistent ? n_chunks : persistent), dim3(256), 0, st,
+                       B.counters, B.pk[pc], B.ranges);
     GS_CHECK_LAUNCH();
     return GS_OK;
 }

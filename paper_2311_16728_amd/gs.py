@@ -76,7 +76,7 @@ def _load():
         "gs_adam_step": ([vp, vp, vp, vp, i64, i64, C.POINTER(C.c_float), C.c_double, C.c_double,
                           C.c_double, i32, vp, vp], C.c_int),
         "gs_step_advance": ([vp, vp], C.c_int),
-        "gs_init_features": ([vp, i32, i32, vp, i32, vp, vp], C.c_int),
+        "gs_init_features": ([vp, i32, i32, vp, i32, vp, vp, vp], C.c_int),
         "gs_init_mlp_fwd": ([vp, vp, vp, i32, vp, vp, vp], C.c_int),
         "gs_init_mlp_bwd": ([vp, vp, vp, vp, i32, vp, vp, vp], C.c_int),
         "gs_init_mlp_adam": ([vp, vp, vp, vp, vp, vp, vp, f32, C.c_double, C.c_double, C.c_double, i32,
@@ -278,10 +278,10 @@ def gs_fill(dst, value, stream=None):
 
 
 # ---- initialiser -----------------------------------------------------------
-def gs_init_features(img, kp, x_bf16, stream=None):
+def gs_init_features(img, kp, x_bf16, heuristic=None, stream=None):
     _, H, W = img.shape
-    _check(_lib.gs_init_features(_p(img), H, W, _p(kp), kp.shape[0], _p(x_bf16), _stream(stream)),
-           "gs_init_features")
+    _check(_lib.gs_init_features(_p(img), H, W, _p(kp), kp.shape[0], _p(heuristic), _p(x_bf16),
+                                 _stream(stream)), "gs_init_features")
 
 
 def gs_init_mlp_fwd(w_bf16, bias, x_bf16, y, act_ws, stream=None):

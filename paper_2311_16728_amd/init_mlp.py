@@ -15,11 +15,12 @@ import torch
 
 from . import gs
 
-N_IN, N_IN_PAD, N_HID, N_OUT = 157, 160, 128, 16
+N_IN, N_IN_PAD, N_HID, N_OUT = 159, 160, 128, 16
 N_W = N_HID * N_IN_PAD + N_HID * N_HID + N_OUT * N_HID
 N_B = 2 * N_HID + N_OUT
-# output columns: log-scale (3, log pixels), quaternion in the camera frame (4),
-# opacity logit (1), SH DC (3)
+# output columns: log-scale correction (3), quaternion in the camera frame (4),
+# opacity logit (1), SH DC correction (3); corrections are relative to the
+# heuristic initialiser
 N_TARGET = 11
 
 
@@ -30,9 +31,15 @@ class InitMLP:
                               np.full(N_OUT * N_HID, N_HID)])
         w = rng.normal(size=N_W) * np.sqrt(2.0 / fan)        # He initialisation for ReLU
         w[:N_HID * N_IN_PAD].reshape(N_HID, N_IN_PAD)[:, N_IN:] = 0.0
+        # small last layer and biases at the heuristic (zero corrections, identity
+        # rotation, opacity 0.1): the untrained network reproduces the heuristic
+        w[N_HID * N_IN_PAD + N_HID * N_HID:] *= 0.01
+        b = np.zeros(N_B)
+        b[2 * N_HID + 3] = 1.0
+        b[2 * N_HID + 7] = np.log(0.1 / 0.9)
         self.device = device
         self.w = torch.as_tensor(w, dtype=torch.float32, device=device)
-        self.b = torch.zeros(N_B, dtype=torch.float32, device=device)
+        self.b = torch.as_tensor(b, dtype=torch.float32, device=device)
         self.w_bf16 = torch.empty(N_W, dtype=torch.int16, device=device)
         gs.gs_to_bf16(self.w, self.w_bf16)
         self.dw = torch.zeros(N_W, dtype=torch.float32, device=device)
@@ -49,7 +56,7 @@ class InitMLP:
         return self._ws[B]
 
     def pack_inputs(self, x: torch.Tensor) -> torch.Tensor:
-        """Float [B][157] features (device) to the zero-padded BF16 [B][160] layout."""
+        """Float [B][k <= 160] features (device) to the zero-padded BF16 [B][160] layout."""
         B = x.shape[0]
         pad = torch.zeros(B, N_IN_PAD, dtype=torch.float32, device=x.device)
         pad[:, :x.shape[1]] = x

@@ -7,8 +7,10 @@ projected centre, camera depth and footprint octave form the keypoint.  The
 map without the held-out Gaussians (the converged map a new keyframe meets;
 optionally perturbed) plus the new primitives is optimised for a fixed number of batched mapping
 iterations over every keyframe and pyramid level; the converged parameters of
-the new primitives, expressed in the keyframe's camera frame, are the labels
-and the keyframe's 7x7 patch around the keypoint is the input.
+the new primitives, relative to the heuristic start (log-scale and colour as
+corrections, rotation in the keyframe's camera frame), are the labels and the
+keyframe's 7x7 patch around the keypoint (with the keypoint's depth, scale and
+the heuristic's log-scale) is the input.
 
 Evaluation repeats the construction on held-out seeds and compares the
 photometric loss (Eq. 4 summed over the pyramid, Eq. 5) after the same number
@@ -86,7 +88,7 @@ class Case:
             z = xc[:, 2]
             u = cam["fx"] * xc[:, 0] / np.maximum(z, 1e-9) + cam["cx"]
             vv = cam["fy"] * xc[:, 1] / np.maximum(z, 1e-9) + cam["cy"]
-            ok = (weight >= 4.0) & (z > 0.3) & (u >= 4) & (u < width - 4) & (vv >= 4) & (vv < height - 4) & ~taken
+            ok = (weight >= 1.0) & (z > 0.3) & (u >= 4) & (u < width - 4) & (vv >= 4) & (vv < height - 4) & ~taken
             cand = np.nonzero(ok)[0]
             pick = np.sort(rng.choice(cand, size=min(per_kf, cand.size), replace=False))
             taken[pick] = True
@@ -126,21 +128,23 @@ class Case:
                              P, n_exist, out)
         return out
 
-    def features(self, v) -> torch.Tensor:
+    def features(self, v, heur=None) -> torch.Tensor:
         kp = torch.as_tensor(self.kp[v]).to(self.device)
         x = torch.empty(kp.shape[0], N_IN_PAD, dtype=torch.int16, device=self.device)
-        gs.gs_init_features(self.gt_images[v], kp, x)
+        gs.gs_init_features(self.gt_images[v], kp, x, heur)
         return x
 
     def initial_params(self, net: InitMLP | None = None):
-        """Parameter store with the new primitives appended; returns (P, fallback fraction)."""
+        """Parameter store with the new primitives appended.  Returns (P,
+        fallback fraction, heuristic columns per keyframe)."""
         P = torch.as_tensor(self.base).to(self.device)
-        n_cur, fallback, count = self.n_exist, 0, 0
+        n_cur, fallback, count, heurs = self.n_exist, 0, 0, []
         for v in range(len(self.cams)):
             heur = self._heuristic(P, self.n_exist, v)
+            heurs.append(heur)
             new = heur
             if net is not None:
-                y = net.forward(self.features(v))
+                y = net.forward(self.features(v, heur))
                 new = torch.empty_like(heur)
                 used = torch.zeros(heur.shape[1], dtype=torch.int32, device=self.device)
                 gs.gs_init_decode(y, torch.as_tensor(self.kp[v]).to(self.device), gs.make_view(self.cams[v]),
@@ -150,31 +154,32 @@ class Case:
             gs.gs_append(P, None, None, n_cur, new)
             n_cur += heur.shape[1]
         assert n_cur == self.n_total
-        return P, fallback / max(count, 1)
+        return P, fallback / max(count, 1), heurs
 
     def mapper(self, P, lr_rows=None):
         return BatchedMapper(P, self.n_total, self.cams, self.gt_images, PYRAMID_LEVELS,
                              lr_rows=mapping_lr_rows() if lr_rows is None else lr_rows)
 
     # -- labels ----------------------------------------------------------------
-    def labels(self, P) -> list[torch.Tensor]:
-        """Camera-frame targets of the new primitives per keyframe ([B][11] float32):
-        log-scale - log(depth / fx), unit quaternion relative to the camera
-        (w >= 0), opacity logit, SH DC."""
+    def labels(self, P, heurs) -> list[torch.Tensor]:
+        """Targets of the network for the new primitives per keyframe ([B][11]
+        float32): log-scale minus the heuristic's, unit quaternion relative to
+        the keyframe's camera (w >= 0), opacity logit, SH DC minus the
+        heuristic's."""
         out, at = [], self.n_exist
         Pc = P.double().cpu()
         for v, cam in enumerate(self.cams):
             B = self.kp[v].shape[0]
             cols = Pc[:, at:at + B]
+            h = heurs[v].double().cpu()
             at += B
-            z = torch.as_tensor(self.kp[v][:, 2], dtype=torch.float64)
-            ls = cols[3:6].T - torch.log(z / cam["fx"])[:, None]
+            ls = (cols[3:6] - h[3:6]).T
             qw = cols[6:10].T
             qw = qw / qw.norm(dim=1, keepdim=True).clamp_min(1e-12)
             qr = torch.as_tensor(_mat_to_quat(cam["R"]))[None].expand_as(qw)
             qc = _quat_mul(qr, qw)
             qc = torch.where(qc[:, :1] < 0, -qc, qc)
-            out.append(torch.cat([ls, qc, cols[10:11].T, cols[11:14].T], 1).float())
+            out.append(torch.cat([ls, qc, cols[10:11].T, (cols[11:14] - h[11:14]).T], 1).float())
         return out
 
 
@@ -212,14 +217,15 @@ def generate(seeds, iters=100, log=print, **case_kw):
     for s in seeds:
         t0 = time.time()
         c = Case(s, **case_kw)
-        P, _ = c.initial_params(None)
-        H += [h.to(c.device) for h in c.labels(P)]
+        P, _, heurs = c.initial_params(None)
+        H += [h.to(c.device) for h in c.labels(P, heurs)]
         bm = c.mapper(P)
         loss, _ = run(bm, iters)
-        for v, lab in enumerate(c.labels(bm.params)):
-            X.append(c.features(v))
+        for v, lab in enumerate(c.labels(bm.params, heurs)):
+            X.append(c.features(v, heurs[v]))
             Y.append(lab.to(c.device))
-        log(f"scene {s}: {c.n_new} pairs, loss after {iters} iterations {loss:.4f} ({time.time() - t0:.1f}s)")
+        if log:
+                log(f"scene {s}: {c.n_new} pairs, loss after {iters} iterations {loss:.4f} ({time.time() - t0:.1f}s)")
         del c, bm, P
     return torch.cat(X), torch.cat(Y), torch.cat(H)
 
@@ -253,7 +259,7 @@ def evaluate(net, seeds, iters=100, log=print, **case_kw):
         c = Case(s, **case_kw)
         res = {"seed": s}
         for name, model in (("heuristic", None), ("learned", net)):
-            P, fb = c.initial_params(model)
+            P, fb, _ = c.initial_params(model)
             bm = c.mapper(P)
             l0 = final_loss(bm)
             lf, hist = run(bm, iters, record=True)
@@ -266,7 +272,8 @@ def evaluate(net, seeds, iters=100, log=print, **case_kw):
         res["learned_iters_to_heuristic_final"] = int(hit[0]) if hit.size else None
         for name in ("heuristic", "learned"):
             res[name].pop("hist")
-        log(json.dumps(res))
+        if log:
+            log(json.dumps(res))
         rows.append(res)
     hf = np.array([r["heuristic"]["loss_final"] for r in rows])
     lf = np.array([r["learned"]["loss_final"] for r in rows])

@@ -123,3 +123,23 @@ def test_graph_replay_matches_eager():
         assert diff <= 1e-5, (r, diff)
         assert torch.equal(graphed.plan.rgb, eager.plan.rgb) or \
             (graphed.plan.rgb - eager.plan.rgb).abs().max().item() <= 1e-5
+
+
+def test_wide_tile_sort_equals_per_target():
+    """22 keyframes at 1200x680 hold 70,950 tiles (17-bit tile keys, sorted with
+    two 9-bit passes); every target equals its own single-target render (12-bit
+    keys, two 8-bit passes) bitwise."""
+    p, _, cams = scenes.room_scene(5, 50_000, n_keyframes=22)
+    n = 50_000
+    P = _dev(p)
+    big = plan_for(cams, levels=(0,), n_cap=p.shape[1], pair_cap=1 << 24)
+    assert big.total_tiles > 1 << 16
+    big.render(P, n)
+    torch.cuda.synchronize()
+    assert not big.overflowed()
+    for v in (0, 7, 21):
+        one = plan_for([cams[v]], levels=(0,), n_cap=p.shape[1], pair_cap=1 << 22)
+        one.render(P, n)
+        torch.cuda.synchronize()
+        assert torch.equal(one.image(one.rgb, 0), big.image(big.rgb, v)), v
+        assert torch.equal(one.plane(one.T, 0), big.plane(big.T, v)), v
