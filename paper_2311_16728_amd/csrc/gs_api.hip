@@ -71,7 +71,7 @@ extern "C" gs_status gs_workspace_query(const gs_settings *s, int64_t n_cap, int
     }
     const int64_t records = int64_t(n_views) * n_cap;
     out->proj_bytes = gs::ProjLayout::make(records).bytes;
-    out->sort_bytes = gs::SortLayout::make(int64_t(n_targets) * n_cap, pair_cap, tiles).bytes;
+    out->sort_bytes = gs::SortLayout::make(n_views, n_targets, n_cap, pair_cap, tiles).bytes;
     out->accum_bytes = gs::accum_bytes(records);
     out->loss_bytes = gs::LossLayout::make(pix, tiles).bytes;
     return GS_OK;

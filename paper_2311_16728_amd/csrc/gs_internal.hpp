@@ -60,10 +60,15 @@ static inline int64_t pair_chunks(int64_t pair_cap) { return (pair_cap + 255) / 
 
 struct SortLayout {
     size_t counters, counts, rects, vis_key0, vis_key1, vis_val0, vis_val1, vis_off, pair_key0,
-        pair_key1, pair_val0, pair_val1, ranges, bsum, hist, digit, chunk_first, bytes;
+        pair_key1, pair_val0, pair_val1, ranges, bsum, hist, digit, chunk_first, view_off, view_list,
+        bytes;
     int64_t sources, pair_cap, max_blocks;
-    static SortLayout make(int64_t sources, int64_t pair_cap, int64_t total_tiles) {
+    // sources: (view, Gaussian) records, n_views * n_cap; rects: one per
+    // (target, Gaussian), n_targets * n_cap
+    static SortLayout make(int64_t n_views, int64_t n_targets, int64_t n_cap, int64_t pair_cap,
+                           int64_t total_tiles) {
         SortLayout L;
+        const int64_t sources = n_views * n_cap;
         L.sources = sources;
         L.pair_cap = pair_cap;
         // radix blocks: 1024 keys per block for the record sort, 4096 for pairs
@@ -73,7 +78,7 @@ struct SortLayout {
         auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
         L.counters = take(sizeof(uint32_t) * kNumCounters);
         L.counts = take(sizeof(uint32_t) * sources);
-        L.rects = take(sizeof(uint32_t) * 2 * sources);
+        L.rects = take(sizeof(uint32_t) * 2 * n_targets * n_cap);
         L.vis_key0 = take(sizeof(uint32_t) * sources);
         L.vis_key1 = take(sizeof(uint32_t) * sources);
         L.vis_val0 = take(sizeof(uint32_t) * sources);
@@ -89,6 +94,9 @@ struct SortLayout {
         L.digit = take(sizeof(uint32_t) * (kRadixBinsMax + 1));
         // first sorted record of every 256-pair emission chunk
         L.chunk_first = take(sizeof(uint32_t) * (pair_chunks(pair_cap) + 1));
+        // targets of each view (CSR)
+        L.view_off = take(sizeof(uint32_t) * (n_views + 1));
+        L.view_list = take(sizeof(uint32_t) * n_targets);
         L.bytes = o;
         return L;
     }
@@ -109,13 +117,13 @@ static inline TileSortPlan tile_sort_plan(int32_t total_tiles) {
 
 // Sorted pair buffers after binning: the tile sort ends in buffer (passes & 1).
 struct Sorted {
-    const uint32_t *pair_val;   // source index t * n_cap + g, per pair
+    const uint32_t *pair_val;   // record index view * n_cap + g, per pair
     const uint2 *ranges;        // [start, end) of each global tile
 };
 
-static inline Sorted sorted_at(const void *ws, int64_t sources, int64_t pair_cap,
-                               int32_t total_tiles) {
-    SortLayout L = SortLayout::make(sources, pair_cap, total_tiles);
+static inline Sorted sorted_at(const void *ws, int64_t n_views, int64_t n_targets, int64_t n_cap,
+                               int64_t pair_cap, int32_t total_tiles) {
+    SortLayout L = SortLayout::make(n_views, n_targets, n_cap, pair_cap, total_tiles);
     const char *b = static_cast<const char *>(ws);
     const int passes = tile_sort_plan(total_tiles).passes;
     size_t val = (passes & 1) ? L.pair_val1 : L.pair_val0;
@@ -139,13 +147,16 @@ static inline size_t accum_bytes(int64_t records) {
 
 // Loss workspace: per-tile partial sums (L1, SSIM) and three SSIM partial maps
 // per pixel and channel.
+// per-target losses in double (a target has at least one tile)
 struct LossLayout {
-    size_t partial, maps, bytes;
+    size_t partial, maps, tloss, bytes;
     static LossLayout make(int64_t total_pixels, int64_t total_tiles) {
         LossLayout L;
         size_t o = 0;
-        L.partial = o; o = align_up(o + sizeof(float) * 2 * (total_tiles > 0 ? total_tiles : 1), 256);
+        const int64_t tiles = total_tiles > 0 ? total_tiles : 1;
+        L.partial = o; o = align_up(o + sizeof(float) * 2 * tiles, 256);
         L.maps = o;    o = align_up(o + sizeof(float) * 9 * total_pixels, 256);
+        L.tloss = o;   o = align_up(o + sizeof(double) * tiles, 256);
         L.bytes = o;
         return L;
     }

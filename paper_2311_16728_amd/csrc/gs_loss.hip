@@ -191,38 +191,42 @@ __global__ void __launch_bounds__(256) ssim_bwd_kernel(const float *__restrict__
 
 // One block: per-target means from the tile partials (fixed order), then the
 // weighted total.
-__global__ void __launch_bounds__(256) loss_finalize_kernel(const gs_target *__restrict__ targets,
-                                                            int n_targets, float lambda,
-                                                            const float *__restrict__ partial,
-                                                            float *__restrict__ d_loss,
-                                                            float *__restrict__ d_total) {
+// Eq. 4 per target (one workgroup each, tile partials summed in double in a
+// fixed order), then the weighted sum over targets in target order.
+__global__ void __launch_bounds__(256) loss_target_kernel(const gs_target *__restrict__ targets,
+                                                          float lambda,
+                                                          const float *__restrict__ partial,
+                                                          double *__restrict__ tloss,
+                                                          float *__restrict__ d_loss) {
     __shared__ double red[2][kTilePix / kWave];
-    __shared__ double total;
-    if (threadIdx.x == 0) total = 0.0;
-    for (int ti = 0; ti < n_targets; ++ti) {
-        const gs_target t = targets[ti];
-        const int nt = t.tiles_x * t.tiles_y;
-        double a = 0, b = 0;
-        for (int i = threadIdx.x; i < nt; i += blockDim.x) {
-            a += partial[2 * int64_t(t.tile_offset + i)];
-            b += partial[2 * int64_t(t.tile_offset + i) + 1];
-        }
-        a = wave_sum(a);
-        b = wave_sum(b);
-        __syncthreads();
-        if (lane_id() == 0) { red[0][threadIdx.x / kWave] = a; red[1][threadIdx.x / kWave] = b; }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double sa = 0, sb = 0;
-            for (int w = 0; w < kTilePix / kWave; ++w) { sa += red[0][w]; sb += red[1][w]; }
-            const double n = 3.0 * double(t.width) * double(t.height);
-            const double L = (1.0 - lambda) * sa / n + lambda * (1.0 - sb / n);
-            if (d_loss) d_loss[ti] = float(L);
-            total += double(t.weight) * L;
-        }
+    const int ti = blockIdx.x;
+    const gs_target t = targets[ti];
+    const int nt = t.tiles_x * t.tiles_y;
+    double a = 0, b = 0;
+    for (int i = threadIdx.x; i < nt; i += blockDim.x) {
+        a += partial[2 * int64_t(t.tile_offset + i)];
+        b += partial[2 * int64_t(t.tile_offset + i) + 1];
     }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (lane_id() == 0) { red[0][threadIdx.x / kWave] = a; red[1][threadIdx.x / kWave] = b; }
     __syncthreads();
-    if (threadIdx.x == 0 && d_total) *d_total = float(total);
+    if (threadIdx.x == 0) {
+        double sa = 0, sb = 0;
+        for (int w = 0; w < kTilePix / kWave; ++w) { sa += red[0][w]; sb += red[1][w]; }
+        const double n = 3.0 * double(t.width) * double(t.height);
+        const double L = (1.0 - lambda) * sa / n + lambda * (1.0 - sb / n);
+        tloss[ti] = double(t.weight) * L;
+        if (d_loss) d_loss[ti] = float(L);
+    }
+}
+
+__global__ void __launch_bounds__(64) loss_total_kernel(int n_targets, const double *__restrict__ tloss,
+                                                        float *__restrict__ d_total) {
+    if (threadIdx.x != 0) return;
+    double total = 0.0;
+    for (int ti = 0; ti < n_targets; ++ti) total += tloss[ti];
+    if (d_total) *d_total = float(total);
 }
 
 // One pyramid level down: 5x5 binomial, reflected borders (edge not repeated),
@@ -295,7 +299,7 @@ extern "C" gs_status gs_pyramid_loss(const float *render, const float *target,
                                      void *loss_ws, float *d_loss, float *d_total,
                                      float *dL_drender, void *stream) {
     using namespace gs;
-    if (!render || !target || !targets || !loss_ws || n_targets <= 0 || total_tiles <= 0 ||
+    if (!render || !target || !targets || !loss_ws || n_targets <= 0 || total_tiles <= 0 || n_targets > total_tiles ||
         total_pixels <= 0 || !(lambda >= 0.f && lambda <= 1.f))
         return GS_ERR_INVALID_ARGUMENT;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -310,8 +314,10 @@ extern "C" gs_status gs_pyramid_loss(const float *render, const float *target,
     if (dL_drender)
         hipLaunchKernelGGL(ssim_bwd_kernel, dim3(grid), dim3(kTilePix), 0, st, render, target, targets,
                            n_targets, total_tiles, win, lambda, maps, dL_drender);
-    hipLaunchKernelGGL(loss_finalize_kernel, dim3(1), dim3(256), 0, st, targets, n_targets, lambda,
-                       partial, d_loss, d_total);
+    double *tloss = reinterpret_cast<double *>(b + L.tloss);
+    hipLaunchKernelGGL(loss_target_kernel, dim3(n_targets), dim3(256), 0, st, targets, lambda, partial, tloss,
+                       d_loss);
+    hipLaunchKernelGGL(loss_total_kernel, dim3(1), dim3(64), 0, st, n_targets, tloss, d_total);
     GS_CHECK_LAUNCH();
     return GS_OK;
 }

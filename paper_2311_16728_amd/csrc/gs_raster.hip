@@ -420,8 +420,7 @@ extern "C" gs_status gs_render_fwd(const gs_settings *s, const void *proj_ws, in
         !out_T || !out_last)
         return GS_ERR_INVALID_ARGUMENT;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int64_t S = int64_t(n_targets) * n_cap;
-    const Sorted srt = sorted_at(sort_ws, S, pair_cap, total_tiles);
+    const Sorted srt = sorted_at(sort_ws, n_views, n_targets, n_cap, pair_cap, total_tiles);
     const Proj proj = proj_at(const_cast<void *>(proj_ws), int64_t(n_views) * n_cap);
     hipLaunchKernelGGL(render_fwd_kernel, dim3(total_tiles), dim3(kTilePix), 0, st, *s, proj, n_cap,
                        srt, targets, n_targets, out_rgb, out_T, out_last, out_ncontrib);
@@ -441,8 +440,7 @@ extern "C" gs_status gs_raster_bwd(const gs_settings *s, const void *proj_ws, in
         return GS_ERR_INVALID_ARGUMENT;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t records = int64_t(n_views) * n_cap;
-    const int64_t S = int64_t(n_targets) * n_cap;
-    const Sorted srt = sorted_at(sort_ws, S, pair_cap, total_tiles);
+    const Sorted srt = sorted_at(sort_ws, n_views, n_targets, n_cap, pair_cap, total_tiles);
     const Proj proj = proj_at(const_cast<void *>(proj_ws), records);
     float *acc = static_cast<float *>(accum_ws);
     const int64_t acc_n = int64_t(kAccRows) * records;

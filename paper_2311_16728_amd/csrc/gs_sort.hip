@@ -3,12 +3,14 @@
 // Gaussian) pair, and each tile's pairs are put in front-to-back order.
 //
 // The order is built in two stable LSD radix sorts instead of one wide-key
-// sort: (1) the visible (target, Gaussian) records are compacted and sorted by
-// their camera depth (32-bit keys, four 8-bit passes over V records); (2) the
-// records emit their pairs in that depth order and the pairs are sorted by
+// sort: (1) the visible (view, Gaussian) records (visible in any target of
+// the view: the pyramid levels of a keyframe share one record and one depth)
+// are compacted and sorted by their camera depth (32-bit keys, four 8-bit
+// passes over V records); (2) the records emit their pairs, for every target
+// of their view, in that depth order and the pairs are sorted by
 // global tile index alone (ceil(log2(tiles)/8) passes, two at 1200x680).
-// Because both sorts are stable and records are compacted in (target,
-// Gaussian) order, each tile's list is ordered by (depth, Gaussian index).
+// Because both sorts are stable and records are compacted in (view, Gaussian)
+// order, each tile's list is ordered by (depth, Gaussian index).
 // Pair counts are data dependent; every kernel reads them from device
 // counters so the whole sequence is launch-shape static and graph-capturable.
 #include "gs_internal.hpp"
@@ -46,29 +48,74 @@ __device__ __forceinline__ bool tile_rect(const gs_settings &s, double2 md, floa
     return true;
 }
 
-// counts[t * n_cap + g] = number of tiles of target t touched by Gaussian g;
-// rects[...] = its tile rectangle packed as (x0 | x1 << 16, y0 | y1 << 16).
+// Set-up of a binning call: counters to zero, tile ranges to empty, and
+// (block 0) the targets of each view as a CSR list in target order.
+__global__ void __launch_bounds__(256) sort_setup_kernel(const gs_target *__restrict__ targets,
+                                                         int32_t n_targets, int32_t n_views,
+                                                         uint32_t *__restrict__ counters,
+                                                         uint32_t *__restrict__ view_off,
+                                                         uint32_t *__restrict__ view_list,
+                                                         uint2 *__restrict__ ranges, int64_t total_tiles) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < total_tiles) ranges[i] = make_uint2(0u, 0u);
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    for (int c = 0; c < kNumCounters; ++c) counters[c] = 0u;
+    for (int v = 0; v <= n_views; ++v) view_off[v] = 0u;
+    for (int t = 0; t < n_targets; ++t) {
+        const int v = targets[t].view;
+        if (v >= 0 && v < n_views) ++view_off[v + 1];
+    }
+    for (int v = 0; v < n_views; ++v) view_off[v + 1] += view_off[v];
+    // place each target at its view's cursor (view_off[v] runs to view_off[v + 1])
+    for (int t = 0; t < n_targets; ++t) {
+        const int v = targets[t].view;
+        if (v >= 0 && v < n_views) view_list[view_off[v]++] = uint32_t(t);
+    }
+    for (int v = n_views; v > 0; --v) view_off[v] = view_off[v - 1];
+    view_off[0] = 0u;
+}
+
+// A tile rectangle that holds no tile (x0 = 1 > x1 = 0): count 0.
+constexpr uint32_t kEmptyRectX = 1u;
+
+__device__ __forceinline__ uint32_t rect_count(uint2 rc) {
+    const uint32_t w = (rc.x >> 16) - (rc.x & 0xffffu) + 1u;
+    const uint32_t h = (rc.y >> 16) - (rc.y & 0xffffu) + 1u;
+    return w * h;
+}
+
+// For record (v, g): rects[t * n_cap + g] = its tile rectangle in each target t
+// of view v, packed as (x0 | x1 << 16, y0 | y1 << 16) (empty when it touches
+// none), and counts[v * n_cap + g] = its number of tiles over those targets.
 __global__ void __launch_bounds__(256) count_kernel(gs_settings s, Proj proj, int64_t n, int64_t n_cap,
                                                     const gs_target *__restrict__ targets,
+                                                    const uint32_t *__restrict__ view_off,
+                                                    const uint32_t *__restrict__ view_list,
                                                     uint32_t *__restrict__ counts,
                                                     uint2 *__restrict__ rects) {
     const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int ti = blockIdx.y;
+    const int v = blockIdx.y;
     if (g >= n_cap) return;
-    uint32_t c = 0;
-    uint2 packed = make_uint2(0u, 0u);
+    const int64_t r = int64_t(v) * n_cap + g;
+    uint32_t total = 0;
     if (g < n) {
-        const gs_target t = targets[ti];
-        const int64_t r = int64_t(t.view) * n_cap + g;
-        Rect rc;
-        if (tile_rect(s, proj.mean[r], proj.cov_o[r], proj.rgb_z[r].w, t, rc)) {
-            c = uint32_t(rc.x1 - rc.x0 + 1) * uint32_t(rc.y1 - rc.y0 + 1);
-            packed = make_uint2(uint32_t(rc.x0) | (uint32_t(rc.x1) << 16),
-                                uint32_t(rc.y0) | (uint32_t(rc.y1) << 16));
+        const double2 md = proj.mean[r];
+        const float4 co = proj.cov_o[r];
+        const float z = proj.rgb_z[r].w;
+        for (uint32_t q = view_off[v]; q < view_off[v + 1]; ++q) {
+            const uint32_t ti = view_list[q];
+            const gs_target t = targets[ti];
+            Rect rc;
+            uint2 packed = make_uint2(kEmptyRectX, 0u);
+            if (tile_rect(s, md, co, z, t, rc)) {
+                total += uint32_t(rc.x1 - rc.x0 + 1) * uint32_t(rc.y1 - rc.y0 + 1);
+                packed = make_uint2(uint32_t(rc.x0) | (uint32_t(rc.x1) << 16),
+                                    uint32_t(rc.y0) | (uint32_t(rc.y1) << 16));
+            }
+            rects[int64_t(ti) * n_cap + g] = packed;
         }
     }
-    counts[int64_t(ti) * n_cap + g] = c;
-    rects[int64_t(ti) * n_cap + g] = packed;
+    counts[r] = total;
 }
 
 // ---------------------------------------------------------------------------
@@ -137,9 +184,8 @@ __global__ void __launch_bounds__(256) compact_reduce_kernel(const uint32_t *__r
 }
 
 __global__ void __launch_bounds__(256) compact_scatter_kernel(const uint32_t *__restrict__ counts,
-                                                              int64_t S, int64_t n_cap,
-                                                              const gs_target *__restrict__ targets,
-                                                              Proj proj, const uint32_t *__restrict__ bsum,
+                                                              int64_t S, Proj proj,
+                                                              const uint32_t *__restrict__ bsum,
                                                               uint32_t *__restrict__ vis_key,
                                                               uint32_t *__restrict__ vis_val) {
     __shared__ uint32_t lds[8];
@@ -152,9 +198,7 @@ __global__ void __launch_bounds__(256) compact_scatter_kernel(const uint32_t *__
         uint32_t total;
         const uint32_t pre = block_exclusive_scan(f, lds, &total);
         if (f) {
-            const int64_t ti = e / n_cap, g = e - ti * n_cap;
-            const int64_t r = int64_t(targets[ti].view) * n_cap + g;
-            vis_key[run + pre] = __float_as_uint(proj.rgb_z[r].w);
+            vis_key[run + pre] = __float_as_uint(proj.rgb_z[e].w);
             vis_val[run + pre] = uint32_t(e);
         }
         run += total;
@@ -209,6 +253,8 @@ __global__ void __launch_bounds__(256) emit_kernel(int64_t n_cap, const gs_targe
                                                    const uint32_t *__restrict__ vis_val,
                                                    const uint32_t *__restrict__ vis_off,
                                                    const uint2 *__restrict__ rects,
+                                                   const uint32_t *__restrict__ view_off,
+                                                   const uint32_t *__restrict__ view_list,
                                                    const uint32_t *__restrict__ chunk_first,
                                                    int64_t pair_cap, uint32_t *__restrict__ pkey,
                                                    uint32_t *__restrict__ pval,
@@ -238,14 +284,25 @@ __global__ void __launch_bounds__(256) emit_kernel(int64_t n_cap, const gs_targe
             const int mid = (lo + hi + 1) >> 1;
             if (off[mid] <= o) lo = mid; else hi = mid - 1;
         }
-        const uint32_t src = vis_val[j0 + lo];
-        const uint32_t k = o - off[lo];
-        const uint2 rc = rects[src];
-        const uint32_t x0 = rc.x & 0xffffu, x1 = rc.x >> 16, y0 = rc.y & 0xffffu;
-        const uint32_t w = x1 - x0 + 1;
-        const uint32_t ti = src / uint32_t(n_cap);
-        const gs_target &t = targets[ti];
-        pkey[o] = uint32_t(t.tile_offset) + (y0 + k / w) * uint32_t(t.tiles_x) + x0 + k % w;
+        const uint32_t src = vis_val[j0 + lo];          // record v * n_cap + g
+        uint32_t k = o - off[lo];
+        const uint32_t v = src / uint32_t(n_cap), g = src - v * uint32_t(n_cap);
+        // the k-th pair of the record: targets of its view in order, tiles row-major
+        uint32_t key = 0u;
+        for (uint32_t q = view_off[v]; q < view_off[v + 1]; ++q) {
+            const uint32_t ti = view_list[q];
+            const uint2 rc = rects[int64_t(ti) * n_cap + g];
+            const uint32_t c = rect_count(rc);
+            if (k < c) {
+                const uint32_t x0 = rc.x & 0xffffu, x1 = rc.x >> 16, y0 = rc.y & 0xffffu;
+                const uint32_t w = x1 - x0 + 1;
+                const gs_target &t = targets[ti];
+                key = uint32_t(t.tile_offset) + (y0 + k / w) * uint32_t(t.tiles_x) + x0 + k % w;
+                break;
+            }
+            k -= c;
+        }
+        pkey[o] = key;
         pval[o] = src;
     }
 }
@@ -420,13 +477,15 @@ __global__ void __launch_bounds__(256) radix_scatter_kernel(
 }
 
 struct SortBufs {
-    uint32_t *counters, *counts, *vk[2], *vv[2], *voff, *pk[2], *pv[2], *bsum, *hist, *digit, *chunk_first;
+    uint32_t *counters, *counts, *vk[2], *vv[2], *voff, *pk[2], *pv[2], *bsum, *hist, *digit, *chunk_first,
+        *view_off, *view_list;
     uint2 *ranges, *rects;
     int64_t max_blocks;
 };
 
-static SortBufs sort_bufs(void *ws, int64_t S, int64_t pair_cap, int32_t total_tiles) {
-    SortLayout L = SortLayout::make(S, pair_cap, total_tiles);
+static SortBufs sort_bufs(void *ws, int32_t n_views, int32_t n_targets, int64_t n_cap, int64_t pair_cap,
+                          int32_t total_tiles) {
+    SortLayout L = SortLayout::make(n_views, n_targets, n_cap, pair_cap, total_tiles);
     char *b = static_cast<char *>(ws);
     auto u = [&](size_t o) { return reinterpret_cast<uint32_t *>(b + o); };
     SortBufs B;
@@ -441,6 +500,8 @@ static SortBufs sort_bufs(void *ws, int64_t S, int64_t pair_cap, int32_t total_t
     B.hist = u(L.hist);
     B.digit = u(L.digit);
     B.chunk_first = u(L.chunk_first);
+    B.view_off = u(L.view_off);
+    B.view_list = u(L.view_list);
     B.ranges = reinterpret_cast<uint2 *>(b + L.ranges);
     B.rects = reinterpret_cast<uint2 *>(b + L.rects);
     B.max_blocks = L.max_blocks;
@@ -469,11 +530,6 @@ static int radix_sort(const uint32_t *n_ptr, uint32_t *kbuf[2], uint32_t *vbuf[2
     return cur;
 }
 
-__global__ void fill_u32_kernel(uint32_t *p, int64_t count, uint32_t v) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < count) p[i] = v;
-}
-
 __global__ void __launch_bounds__(256) ranges_kernel(const uint32_t *__restrict__ counters,
                                                      const uint32_t *__restrict__ keys,
                                                      uint2 *__restrict__ ranges) {
@@ -495,25 +551,24 @@ extern "C" gs_status gs_bin_sort(const gs_settings *s, const void *proj_ws, int6
     using namespace gs;
     if (!s || !proj_ws || !targets || !sort_ws || n < 0 || n_cap <= 0 || n > n_cap || n_cap % 64 ||
         n_views <= 0 || n_targets <= 0 || total_tiles <= 0 || pair_cap <= 0 ||
-        pair_cap > 0x7fffffffLL || int64_t(n_targets) * n_cap > 0xffffffffLL)
+        pair_cap > 0x7fffffffLL || int64_t(n_views) * n_cap > 0xffffffffLL)
         return GS_ERR_INVALID_ARGUMENT;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int64_t S = int64_t(n_targets) * n_cap;
-    SortBufs B = sort_bufs(sort_ws, S, pair_cap, total_tiles);
-    Proj proj = proj_at(const_cast<void *>(proj_ws), int64_t(n_views) * n_cap);
+    const int64_t S = int64_t(n_views) * n_cap;   // (view, Gaussian) records
+    SortBufs B = sort_bufs(sort_ws, n_views, n_targets, n_cap, pair_cap, total_tiles);
+    Proj proj = proj_at(const_cast<void *>(proj_ws), S);
 
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, B.counters, int64_t(kNumCounters), 0u);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3((2 * int64_t(total_tiles) + 255) / 256), dim3(256), 0, st,
-                       reinterpret_cast<uint32_t *>(B.ranges), 2 * int64_t(total_tiles), 0u);
-    hipLaunchKernelGGL(count_kernel, dim3((n_cap + 255) / 256, n_targets), dim3(256), 0, st, *s, proj,
-                       n, n_cap, targets, B.counts, B.rects);
+    hipLaunchKernelGGL(sort_setup_kernel, dim3((int64_t(total_tiles) + 255) / 256), dim3(256), 0, st, targets,
+                       n_targets, n_views, B.counters, B.view_off, B.view_list, B.ranges, int64_t(total_tiles));
+    hipLaunchKernelGGL(count_kernel, dim3((n_cap + 255) / 256, n_views), dim3(256), 0, st, *s, proj, n, n_cap,
+                       targets, B.view_off, B.view_list, B.counts, B.rects);
     // compact visible records
     const int64_t sblocks = (S + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(compact_reduce_kernel, dim3(sblocks), dim3(256), 0, st, B.counts, S, B.bsum);
     hipLaunchKernelGGL(scan_bsums_kernel, dim3(1), dim3(1024), 0, st, nullptr, B.bsum,
                        B.counters + kVisible, S);
-    hipLaunchKernelGGL(compact_scatter_kernel, dim3(sblocks), dim3(256), 0, st, B.counts, S, n_cap,
-                       targets, proj, B.bsum, B.vk[0], B.vv[0]);
+    hipLaunchKernelGGL(compact_scatter_kernel, dim3(sblocks), dim3(256), 0, st, B.counts, S, proj, B.bsum,
+                       B.vk[0], B.vv[0]);
     // depth order (4 passes: result back in buffer 0)
     int cur = radix_sort<4, kRadixBits>(B.counters + kVisible, B.vk, B.vv, 0, 0, 32 / kRadixBits, S, B, st);
     // pair offsets in depth order
@@ -526,8 +581,8 @@ extern "C" gs_status gs_bin_sort(const gs_settings *s, const void *proj_ws, int6
                        B.counts, B.vv[cur], B.bsum, B.voff, B.chunk_first, n_chunks);
     const int64_t persistent = 256 * 16;   // 16 workgroups per CU, grid-stride beyond
     hipLaunchKernelGGL(emit_kernel, dim3(n_chunks < persistent ? n_chunks : persistent), dim3(256), 0, st,
-                       n_cap, targets, B.counters, B.vv[cur], B.voff, B.rects, B.chunk_first, pair_cap,
-                       B.pk[0], B.pv[0], d_status);
+                       n_cap, targets, B.counters, B.vv[cur], B.voff, B.rects, B.view_off, B.view_list,
+                       B.chunk_first, pair_cap, B.pk[0], B.pv[0], d_status);
     // tile order
     const TileSortPlan plan = tile_sort_plan(total_tiles);
     const int pc = plan.bits == 9

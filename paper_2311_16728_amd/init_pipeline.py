@@ -225,7 +225,7 @@ def generate(seeds, iters=100, log=print, **case_kw):
             X.append(c.features(v, heurs[v]))
             Y.append(lab.to(c.device))
         if log:
-                log(f"scene {s}: {c.n_new} pairs, loss after {iters} iterations {loss:.4f} ({time.time() - t0:.1f}s)")
+            log(f"scene {s}: {c.n_new} pairs, loss after {iters} iterations {loss:.4f} ({time.time() - t0:.1f}s)")
         del c, bm, P
     return torch.cat(X), torch.cat(Y), torch.cat(H)
 
