@@ -84,9 +84,11 @@ __device__ __forceinline__ uint32_t rect_count(uint2 rc) {
     return w * h;
 }
 
-// For record (v, g): rects[t * n_cap + g] = its tile rectangle in each target t
-// of view v, packed as (x0 | x1 << 16, y0 | y1 << 16) (empty when it touches
-// none), and counts[v * n_cap + g] = its number of tiles over those targets.
+// For record (v, g): its tile rectangle in the q-th target of view v, packed
+// as (x0 | x1 << 16, y0 | y1 << 16) (empty when it touches none), at
+// rects[view_off[v] * n_cap + g * m_v + q] (m_v targets in view v: a record's
+// rectangles are adjacent), and counts[v * n_cap + g] = its number of tiles
+// over those targets.
 __global__ void __launch_bounds__(256) count_kernel(gs_settings s, Proj proj, int64_t n, int64_t n_cap,
                                                     const gs_target *__restrict__ targets,
                                                     const uint32_t *__restrict__ view_off,
@@ -102,9 +104,10 @@ __global__ void __launch_bounds__(256) count_kernel(gs_settings s, Proj proj, in
         const double2 md = proj.mean[r];
         const float4 co = proj.cov_o[r];
         const float z = proj.rgb_z[r].w;
-        for (uint32_t q = view_off[v]; q < view_off[v + 1]; ++q) {
-            const uint32_t ti = view_list[q];
-            const gs_target t = targets[ti];
+        const uint32_t q0 = view_off[v], m = view_off[v + 1] - q0;
+        uint2 *out = rects + int64_t(q0) * n_cap + g * m;
+        for (uint32_t q = 0; q < m; ++q) {
+            const gs_target t = targets[view_list[q0 + q]];
             Rect rc;
             uint2 packed = make_uint2(kEmptyRectX, 0u);
             if (tile_rect(s, md, co, z, t, rc)) {
@@ -112,7 +115,7 @@ __global__ void __launch_bounds__(256) count_kernel(gs_settings s, Proj proj, in
                 packed = make_uint2(uint32_t(rc.x0) | (uint32_t(rc.x1) << 16),
                                     uint32_t(rc.y0) | (uint32_t(rc.y1) << 16));
             }
-            rects[int64_t(ti) * n_cap + g] = packed;
+            out[q] = packed;
         }
     }
     counts[r] = total;
@@ -289,14 +292,15 @@ __global__ void __launch_bounds__(256) emit_kernel(int64_t n_cap, const gs_targe
         const uint32_t v = src / uint32_t(n_cap), g = src - v * uint32_t(n_cap);
         // the k-th pair of the record: targets of its view in order, tiles row-major
         uint32_t key = 0u;
-        for (uint32_t q = view_off[v]; q < view_off[v + 1]; ++q) {
-            const uint32_t ti = view_list[q];
-            const uint2 rc = rects[int64_t(ti) * n_cap + g];
+        const uint32_t q0 = view_off[v], m = view_off[v + 1] - q0;
+        const uint2 *rc_v = rects + int64_t(q0) * n_cap + int64_t(g) * m;
+        for (uint32_t q = 0; q < m; ++q) {
+            const uint2 rc = rc_v[q];
             const uint32_t c = rect_count(rc);
             if (k < c) {
                 const uint32_t x0 = rc.x & 0xffffu, x1 = rc.x >> 16, y0 = rc.y & 0xffffu;
                 const uint32_t w = x1 - x0 + 1;
-                const gs_target &t = targets[ti];
+                const gs_target &t = targets[view_list[q0 + q]];
                 key = uint32_t(t.tile_offset) + (y0 + k / w) * uint32_t(t.tiles_x) + x0 + k % w;
                 break;
             }
