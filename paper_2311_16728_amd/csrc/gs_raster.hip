@@ -11,8 +11,8 @@
 // last composited Gaussian; the backward restarts from those, divides the
 // transmittance back out Gaussian by Gaussian, and keeps a running colour of
 // what lies behind, so no per-pixel list is stored.  Gradients of the nine 2D
-// quantities are summed over the wave with cross-lane shuffles and committed
-// with one atomic per quantity per wave.
+// quantities are summed over the tile in registers, DPP and LDS and committed
+// with one atomic per quantity per tile.
 #include "gs_internal.hpp"
 
 namespace gs {
@@ -91,6 +91,7 @@ __device__ __forceinline__ float eval_power(const float4 &A, const float4 &B, fl
     return fmaf(-0.5f, q, -(A.w * dx * dy));
 }
 
+template <bool kCount>
 __global__ void __launch_bounds__(256) render_fwd_kernel(
     gs_settings s, Proj proj, int64_t n_cap, Sorted srt, const gs_target *__restrict__ targets,
     int n_targets, float *__restrict__ out_rgb, float *__restrict__ out_T,
@@ -137,6 +138,7 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(
         }
         __syncthreads();
         if (!done) {
+            int lj = -1;   // staged index of this batch's last composited Gaussian
             for (int j = 0; j < int(cnt); ++j) {
                 const float4 A = sA[j];
                 const float4 B = sB[j];
@@ -152,9 +154,11 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(
                 C1 = fmaf(w, B.w, C1);
                 C2 = fmaf(w, Cj.x, C2);
                 T = Tn;
-                ++nc;
-                last = sPos[j] + 1;
+                if (kCount) ++nc;
+                lj = j;
             }
+            // one past the list position of the last composited Gaussian
+            if (lj >= 0) last = sPos[lj] + 1;
         }
     }
     if (inside) {
@@ -166,7 +170,7 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(
         rgb[2 * HW + pix] = fmaf(T, t.bg[2], C2);
         out_T[t.pix_offset + pix] = T;
         out_last[t.pix_offset + pix] = last;
-        if (out_nc) out_nc[t.pix_offset + pix] = nc;
+        if (kCount) out_nc[t.pix_offset + pix] = nc;
     }
 }
 
@@ -478,8 +482,12 @@ extern "C" gs_status gs_render_fwd(const gs_settings *s, const void *proj_ws, in
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Sorted srt = sorted_at(sort_ws, n_views, n_targets, n_cap, pair_cap, total_tiles);
     const Proj proj = proj_at(const_cast<void *>(proj_ws), int64_t(n_views) * n_cap);
-    hipLaunchKernelGGL(render_fwd_kernel, dim3(total_tiles), dim3(kTilePix), 0, st, *s, proj, n_cap,
-                       srt, targets, n_targets, out_rgb, out_T, out_last, out_ncontrib);
+    if (out_ncontrib)
+        hipLaunchKernelGGL(render_fwd_kernel<true>, dim3(total_tiles), dim3(kTilePix), 0, st, *s, proj, n_cap,
+                           srt, targets, n_targets, out_rgb, out_T, out_last, out_ncontrib);
+    else
+        hipLaunchKernelGGL(render_fwd_kernel<false>, dim3(total_tiles), dim3(kTilePix), 0, st, *s, proj, n_cap,
+                           srt, targets, n_targets, out_rgb, out_T, out_last, out_ncontrib);
     GS_CHECK_LAUNCH();
     return GS_OK;
 }
