@@ -184,12 +184,17 @@ gs_status gs_project_bwd(const gs_settings *s, const float *params, int64_t n, i
  * updated in place (params, m, v: device [59][n_cap]) as soon as its gradient
  * is known, so no gradient buffer is written, read or cleared.  Every column
  * < n is stepped (Gaussians no view touched get a zero gradient); the result
- * equals gs_project_bwd into a zeroed gradient followed by gs_adam_step. */
+ * equals gs_project_bwd into a zeroed gradient followed by gs_adam_step.
+ * proj_out (device, proj_bytes, optional): when non-NULL, the projection
+ * records of the updated parameters for the same views are also written there,
+ * equal to what gs_preprocess of the updated parameters writes, so the next
+ * iteration can skip gs_preprocess; it may be the proj_ws of the iteration
+ * (this call does not read projection records). */
 gs_status gs_project_bwd_adam(const gs_settings *s, float *params, int64_t n, int64_t n_cap,
                               const gs_view *views, int32_t n_views, const void *accum_ws,
                               float *m, float *v, const float *lr_rows, double beta1,
                               double beta2, double eps, int32_t step, const int32_t *d_step,
-                              void *stream);
+                              void *proj_out, void *stream);
 
 /* gs_raster_bwd followed by gs_project_bwd (the full backward to the raw
  * parameters, ADDED to grad). */
@@ -200,14 +205,15 @@ gs_status gs_render_bwd(const gs_settings *s, const float *params, int64_t n, in
                         const int32_t *out_last, const float *dL_drgb, void *accum_ws,
                         float *grad, void *stream);
 
-/* gs_raster_bwd followed by gs_project_bwd_adam (one optimiser step). */
+/* gs_raster_bwd followed by gs_project_bwd_adam (one optimiser step); proj_out
+ * as there (it may be proj_ws: the raster backward has read it by then). */
 gs_status gs_render_bwd_adam(const gs_settings *s, float *params, int64_t n, int64_t n_cap,
                              const gs_view *views, int32_t n_views, const void *proj_ws,
                              const void *sort_ws, int64_t pair_cap, const gs_target *targets,
                              int32_t n_targets, int32_t total_tiles, const float *out_T,
                              const int32_t *out_last, const float *dL_drgb, void *accum_ws,
                              float *m, float *v, const float *lr_rows, double beta1, double beta2,
-                             double eps, int32_t step, const int32_t *d_step, void *stream);
+                             double eps, int32_t step, const int32_t *d_step, void *proj_out, void *stream);
 
 /* Gaussian pyramid of one planar image (Section 3.4): level l+1 is level l
  * smoothed by the 5x5 binomial kernel (1 4 6 4 1)^2/256 with mirrored

@@ -56,18 +56,29 @@ class BatchedMapper:
                 self.plan.image(self.target, v * self.levels + l).copy_(pyr[at:at + 3 * h * w].view(3, h, w))
                 at += 3 * h * w
 
+    def invalidate(self):
+        """Call after changing the parameters outside iteration() (the next
+        iteration then projects again)."""
+        self.plan.records_of = None
+
     def iteration(self, stream=None):
         """One batched iteration: render all targets, Eq. 4 over all targets,
-        backward, Adam (step counter advanced on the device)."""
+        backward, Adam (step counter advanced on the device).  The optimiser
+        step also writes the projection records of the updated parameters, so
+        only the first iteration runs gs_preprocess."""
         p = self.plan
-        p.render(self.params, self.n, stream=stream)
+        if p.records_of != id(self):
+            p.preprocess(self.params, self.n, stream)
+        p.bin_sort(self.n, stream)
+        p.render_fwd(stream=stream)
         p.loss(self.target, self.lam, True, stream)
         gs.gs_raster_bwd(p.settings, p.proj_ws, p.n_cap, p.n_views, p.sort_ws, p.pair_cap, p.targets_dev,
                          p.n_targets, p.total_tiles, p.T, p.last, p.dL, p.accum_ws, stream)
         gs.gs_step_advance(self.d_step, stream)
         gs.gs_project_bwd_adam(p.settings, self.params, self.n, p.views_dev, p.n_views, p.accum_ws,
                                self.m, self.v, self.lr_rows, self.d_step, self.beta1, self.beta2,
-                               self.eps, stream)
+                               self.eps, p.proj_ws, stream)
+        p.records_of = id(self)
 
     def capture(self, warmup: int = 1):
         """Capture one iteration into a HIP graph (after `warmup` eager iterations

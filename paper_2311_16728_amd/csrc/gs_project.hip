@@ -199,12 +199,10 @@ __device__ __forceinline__ bool project(const Gauss &G, const Cam &c, float znea
     return true;
 }
 
-__global__ void __launch_bounds__(256) preprocess_kernel(gs_settings s, const float *__restrict__ P,
-                                                         int64_t n, int64_t n_cap,
-                                                         const gs_view *__restrict__ views,
-                                                         int32_t n_views, Proj out) {
-    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (g >= n) return;
+// Projection records of Gaussian g for every view (see gs_preprocess).
+__device__ __forceinline__ void preprocess_one(const gs_settings &s, const float *P, int64_t n_cap,
+                                               int64_t g, const gs_view *__restrict__ views,
+                                               int32_t n_views, const Proj &out) {
     Gauss G;
     load_gauss(P, n_cap, g, G);
     float sh[16][3];
@@ -241,6 +239,53 @@ __global__ void __launch_bounds__(256) preprocess_kernel(gs_settings s, const fl
     }
 }
 
+// The same records with one colour channel's coefficients live at a time (each
+// channel's SH rows are read per view), for the end of the fused optimiser
+// kernel, whose occupancy is bounded by its registers.  Same arithmetic in the
+// same order as preprocess_one, so the records are identical.
+__device__ __forceinline__ void preprocess_one_lean(const gs_settings &s, const float *P, int64_t n_cap,
+                                                    int64_t g, const gs_view *__restrict__ views,
+                                                    int32_t n_views, const Proj &out) {
+    Gauss G;
+    load_gauss(P, n_cap, g, G);
+    const int nk = (s.sh_degree + 1) * (s.sh_degree + 1);
+    for (int v = 0; v < n_views; ++v) {
+        const int64_t r = int64_t(v) * n_cap + g;
+        const Cam c = load_cam(views[v], s.fov_clamp);
+        Proj2 p;
+        if (!project(G, c, s.znear, p)) {
+            out.mean[r] = make_double2(0.0, 0.0);
+            out.cov_o[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+            out.rgb_z[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+            continue;
+        }
+        float d[3] = {G.mu[0] - c.C[0], G.mu[1] - c.C[1], G.mu[2] - c.C[2]};
+        const float dinv = rsqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        float Y[16];
+        sh_eval(s.sh_degree, d[0] * dinv, d[1] * dinv, d[2] * dinv, Y);
+        float rgb[3];
+#pragma unroll 1
+        for (int ch = 0; ch < 3; ++ch) {
+            float acc = 0.5f;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) acc += Y[k] * ((k < nk) ? P[(11 + 3 * k + ch) * n_cap + g] : 0.f);
+            rgb[ch] = fmaxf(acc, 0.f);
+        }
+        out.mean[r] = make_double2(p.md[0], p.md[1]);
+        out.cov_o[r] = make_float4(p.cov[0], p.cov[1], p.cov[2], G.o);
+        out.rgb_z[r] = make_float4(rgb[0], rgb[1], rgb[2], p.xc[2]);
+    }
+}
+
+__global__ void __launch_bounds__(256) preprocess_kernel(gs_settings s, const float *__restrict__ P,
+                                                         int64_t n, int64_t n_cap,
+                                                         const gs_view *__restrict__ views,
+                                                         int32_t n_views, Proj out) {
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    preprocess_one(s, P, n_cap, g, views, n_views, out);
+}
+
 // Gradient sinks of the projection backward: accumulate into a gradient
 // buffer, or apply the Adam update to the parameter right away (the gradient
 // then never leaves registers).  Both take a group of rows (first, stride,
@@ -259,6 +304,8 @@ struct GradSink {
         for (int j = 0; j < N; ++j) grad[int64_t(first + j * stride) * n_cap + g] = cur[j] + val[j];
     }
     __device__ __forceinline__ void untouched(int64_t, int64_t, Scale) const {}
+    __device__ __forceinline__ void finish(const gs_settings &, int64_t, int64_t, const gs_view *,
+                                           int32_t) const {}
 };
 
 struct AdamSink {
@@ -312,6 +359,14 @@ struct AdamSink {
 #pragma unroll 1
         for (int r = 0; r < kRows; ++r) group(r, 1, g, n_cap, z, sc);
     }
+    // Optionally the projection records of the updated Gaussian for the same
+    // views (the next iteration's preprocess).  The rows are read back through
+    // the pointer they were written with, so the reads follow the writes.
+    Proj next;
+    __device__ __forceinline__ void finish(const gs_settings &s, int64_t g, int64_t n_cap,
+                                           const gs_view *views, int32_t n_views) const {
+        if (next.mean) preprocess_one_lean(s, p, n_cap, g, views, n_views, next);
+    }
 };
 
 // Chain rule from the accumulated 2D gradients of every view to the 59 raw
@@ -319,7 +374,7 @@ struct AdamSink {
 // view; the colour part then runs one channel at a time so that only that
 // channel's 16 SH coefficients and their gradients are live.
 template <class Sink>
-__global__ void __launch_bounds__(256) project_backward_kernel(
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) project_backward_kernel(
     gs_settings s, const float *__restrict__ P, int64_t n, int64_t n_cap,
     const gs_view *__restrict__ views, int32_t n_views, const float *__restrict__ acc,
     int64_t records, Sink sink) {
@@ -407,6 +462,7 @@ __global__ void __launch_bounds__(256) project_backward_kernel(
     }
     if (!any_view) {   // no view touched this Gaussian: zero gradient
         sink.untouched(g, n_cap, sc);
+        sink.finish(s, g, n_cap, views, n_views);
         return;
     }
 
@@ -495,6 +551,7 @@ __global__ void __launch_bounds__(256) project_backward_kernel(
     const float geo[11] = {gmu[0], gmu[1], gmu[2], gls[0], gls[1], gls[2],
                            gq[0], gq[1], gq[2], gq[3], gop * G.o * (1.f - G.o)};
     sink.group(0, 1, g, n_cap, geo, sc);
+    sink.finish(s, g, n_cap, views, n_views);
 }
 
 gs_status launch_project_backward(const gs_settings &s, const float *params, int64_t n,
@@ -512,9 +569,10 @@ gs_status launch_project_backward_adam(const gs_settings &s, float *params, int6
                                        const gs_view *views, int32_t n_views, const float *acc,
                                        float *m, float *v, const float *lr_rows, double beta1,
                                        double beta2, double eps, int32_t step, const int32_t *d_step,
-                                       hipStream_t st) {
+                                       void *proj_out, hipStream_t st) {
     if (n == 0) return GS_OK;
     AdamSink a;
+    a.next = proj_out ? proj_at(proj_out, int64_t(n_views) * n_cap) : Proj{nullptr, nullptr, nullptr};
     a.p = params;
     a.m = m;
     a.v = v;

@@ -457,7 +457,7 @@ gs_status launch_project_backward_adam(const gs_settings &s, float *params, int6
                                        const gs_view *views, int32_t n_views, const float *acc,
                                        float *m, float *v, const float *lr_rows, double beta1,
                                        double beta2, double eps, int32_t step, const int32_t *d_step,
-                                       hipStream_t st);
+                                       void *proj_out, hipStream_t st);
 
 static bool valid_settings(const gs_settings *s) {
     return s && s->sh_degree >= 0 && s->sh_degree <= 3 &&
@@ -544,7 +544,7 @@ extern "C" gs_status gs_project_bwd_adam(const gs_settings *s, float *params, in
                                          const void *accum_ws, float *m, float *v,
                                          const float *lr_rows, double beta1, double beta2,
                                          double eps, int32_t step, const int32_t *d_step,
-                                         void *stream) {
+                                         void *proj_out, void *stream) {
     using namespace gs;
     if (!valid_settings(s) || !params || !views || !accum_ws || !m || !v || !lr_rows || n < 0 ||
         n_cap <= 0 || n > n_cap || n_cap % 64 || n_views <= 0 || (step < 1 && !d_step) ||
@@ -552,7 +552,7 @@ extern "C" gs_status gs_project_bwd_adam(const gs_settings *s, float *params, in
         return GS_ERR_INVALID_ARGUMENT;
     return launch_project_backward_adam(*s, params, n, n_cap, views, n_views,
                                         static_cast<const float *>(accum_ws), m, v, lr_rows, beta1,
-                                        beta2, eps, step, step < 1 ? d_step : nullptr,
+                                        beta2, eps, step, step < 1 ? d_step : nullptr, proj_out,
                                         static_cast<hipStream_t>(stream));
 }
 
@@ -578,14 +578,14 @@ extern "C" gs_status gs_render_bwd_adam(const gs_settings *s, float *params, int
                                         const int32_t *out_last, const float *dL_drgb,
                                         void *accum_ws, float *m, float *v, const float *lr_rows,
                                         double beta1, double beta2, double eps, int32_t step,
-                                        const int32_t *d_step, void *stream) {
+                                        const int32_t *d_step, void *proj_out, void *stream) {
     if (!params || !m || !v || !lr_rows || n < 0 || n > n_cap || !views || (step < 1 && !d_step))
         return GS_ERR_INVALID_ARGUMENT;
     gs_status r = gs_raster_bwd(s, proj_ws, n_cap, n_views, sort_ws, pair_cap, targets, n_targets,
                                 total_tiles, out_T, out_last, dL_drgb, accum_ws, stream);
     if (r != GS_OK) return r;
     return gs_project_bwd_adam(s, params, n, n_cap, views, n_views, accum_ws, m, v, lr_rows, beta1,
-                               beta2, eps, step, d_step, stream);
+                               beta2, eps, step, d_step, proj_out, stream);
 }
 
 namespace gs {

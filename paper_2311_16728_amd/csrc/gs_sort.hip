@@ -589,8 +589,10 @@ extern "C" gs_status gs_bin_sort(const gs_settings *s, const void *proj_ws, int6
                        B.chunk_first, pair_cap, B.pk[0], B.pv[0], d_status);
     // tile order
     const TileSortPlan plan = tile_sort_plan(total_tiles);
+    // 9-bit digits come with many tiles and pairs: 8192-element sort blocks keep
+    // each digit's run per block long enough for full write segments
     const int pc = plan.bits == 9
-                       ? radix_sort<16, 9>(B.counters + kPairsClamped, B.pk, B.pv, 0, 0, plan.passes, pair_cap, B, st)
+                       ? radix_sort<32, 9>(B.counters + kPairsClamped, B.pk, B.pv, 0, 0, plan.passes, pair_cap, B, st)
                        : radix_sort<16, 8>(B.counters + kPairsClamped, B.pk, B.pv, 0, 0, plan.passes, pair_cap, B, st);
     hipLaunchKernelGGL(ranges_kernel, dim3(n_chunks < persistent ? n_chunks : persistent), dim3(256), 0, st,
                        B.counters, B.pk[pc], B.ranges);

@@ -67,10 +67,10 @@ def _load():
         "gs_raster_bwd": ([S, vp, i64, i32, vp, i64, vp, i32, i32, vp, vp, vp, vp, vp], C.c_int),
         "gs_project_bwd": ([S, vp, i64, i64, vp, i32, vp, vp, vp], C.c_int),
         "gs_project_bwd_adam": ([S, vp, i64, i64, vp, i32, vp, vp, vp, C.POINTER(C.c_float), C.c_double,
-                                 C.c_double, C.c_double, i32, vp, vp], C.c_int),
+                                 C.c_double, C.c_double, i32, vp, vp, vp], C.c_int),
         "gs_render_bwd_adam": ([S, vp, i64, i64, vp, i32, vp, vp, i64, vp, i32, i32, vp, vp, vp, vp,
                                 vp, vp, C.POINTER(C.c_float), C.c_double, C.c_double, C.c_double,
-                                i32, vp, vp], C.c_int),
+                                i32, vp, vp, vp], C.c_int),
         "gs_pyramid_build": ([vp, i32, i32, i32, i32, vp, vp], C.c_int),
         "gs_pyramid_loss": ([vp, vp, vp, i32, i32, i64, f32, vp, vp, vp, vp, vp], C.c_int),
         "gs_adam_step": ([vp, vp, vp, vp, i64, i64, C.POINTER(C.c_float), C.c_double, C.c_double,
@@ -228,24 +228,24 @@ def _step_args(step):
 
 
 def gs_project_bwd_adam(settings, params, n, views_dev, n_views, accum_ws, m, v, lr_rows, step,
-                        beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
+                        beta1=0.9, beta2=0.999, eps=1e-15, proj_out=None, stream=None):
     lr = (C.c_float * NUM_ROWS)(*[float(x) for x in lr_rows])
     st, dst = _step_args(step)
     _check(_lib.gs_project_bwd_adam(C.byref(settings), _p(params), n, params.shape[1], _p(views_dev),
                                     n_views, _p(accum_ws), _p(m), _p(v), lr, beta1, beta2, eps, st, dst,
-                                    _stream(stream)), "gs_project_bwd_adam")
+                                    _p(proj_out), _stream(stream)), "gs_project_bwd_adam")
 
 
 def gs_render_bwd_adam(settings, params, n, views_dev, n_views, proj_ws, sort_ws, pair_cap,
                        targets_dev, n_targets, total_tiles, out_T, out_last, dL_drgb, accum_ws, m, v,
-                       lr_rows, step, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
+                       lr_rows, step, beta1=0.9, beta2=0.999, eps=1e-15, proj_out=None, stream=None):
     lr = (C.c_float * NUM_ROWS)(*[float(x) for x in lr_rows])
     st, dst = _step_args(step)
     _check(_lib.gs_render_bwd_adam(C.byref(settings), _p(params), n, params.shape[1], _p(views_dev),
                                    n_views, _p(proj_ws), _p(sort_ws), pair_cap, _p(targets_dev),
                                    n_targets, total_tiles, _p(out_T), _p(out_last), _p(dL_drgb),
                                    _p(accum_ws), _p(m), _p(v), lr, beta1, beta2, eps, st, dst,
-                                   _stream(stream)), "gs_render_bwd_adam")
+                                   _p(proj_out), _stream(stream)), "gs_render_bwd_adam")
 
 
 def gs_pyramid_build(img, levels, out, stream=None):

@@ -73,6 +73,9 @@ class RenderPlan:
         self.d_loss = torch.zeros(self.n_targets, dtype=torch.float32, device=d)
         self.d_total = torch.zeros(1, dtype=torch.float32, device=d)
         self.dL = torch.zeros(3 * P, dtype=torch.float32, device=d)
+        # (owner, parameter version) whose projection records proj_ws holds,
+        # when written by a fused optimiser step; None otherwise
+        self.records_of = None
 
     # -- layout helpers ---------------------------------------------------
     def target_slice(self, i: int):
@@ -91,6 +94,7 @@ class RenderPlan:
     # -- steps ----------------------------------------------------------------
     def preprocess(self, params: torch.Tensor, n: int, stream=None):
         gs.gs_preprocess(self.settings, params, n, self.views_dev, self.n_views, self.proj_ws, stream)
+        self.records_of = None
 
     def bin_sort(self, n: int, stream=None):
         gs.gs_bin_sort(self.settings, self.proj_ws, n, self.n_cap, self.n_views, self.targets_dev,
@@ -144,23 +148,35 @@ class Mapper:
         self.grad = torch.zeros_like(self.params)
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
+        self.version = 0   # bumped by every change of the parameters
+
+    def invalidate(self):
+        """Call after changing the parameters outside step() (e.g. appending)."""
+        self.version += 1
 
     def step(self, plan: RenderPlan, target_rgb: torch.Tensor, lam: float = LAMBDA, fused: bool = True,
              stream=None):
         """One iteration: render every target, Eq. 4 loss, backward, Adam.
 
         fused=True applies Adam inside the backward's per-Gaussian pass
-        (gs_render_bwd_adam); fused=False runs gs_render_bwd into a zeroed
+        (gs_render_bwd_adam), which also writes the projection records of the
+        updated parameters into the plan, so the next step on the same plan
+        skips gs_preprocess; fused=False runs gs_render_bwd into a zeroed
         gradient and then gs_adam_step."""
-        plan.render(self.params, self.n, stream=stream)
+        if not (fused and plan.records_of == (id(self), self.version)):
+            plan.preprocess(self.params, self.n, stream)
+        plan.bin_sort(self.n, stream)
+        plan.render_fwd(stream=stream)
         plan.loss(target_rgb, lam, True, stream)
         self.step_count += 1
+        self.version += 1
         if fused:
             gs.gs_render_bwd_adam(plan.settings, self.params, self.n, plan.views_dev, plan.n_views,
                                   plan.proj_ws, plan.sort_ws, plan.pair_cap, plan.targets_dev,
                                   plan.n_targets, plan.total_tiles, plan.T, plan.last, plan.dL,
                                   plan.accum_ws, self.m, self.v, self.lr_rows, self.step_count,
-                                  self.beta1, self.beta2, self.eps, stream)
+                                  self.beta1, self.beta2, self.eps, plan.proj_ws, stream)
+            plan.records_of = (id(self), self.version)
         else:
             gs.gs_fill(self.grad, 0.0, stream)
             plan.backward(self.params, self.n, plan.dL, self.grad, stream)
