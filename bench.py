@@ -174,6 +174,30 @@ def cpu_baseline(p, n, cams, target_np, frac, seed=0):
                         f"{sampled:.1f} s of CPU work"))
 
 
+def iteration_roofline(n, plan, composited, ms_step):
+    """Lower bound of one iteration from its algorithmic work, stage by stage
+    (each stage at the better of its bounds): HBM bytes at 8 TB/s, FP32 lane
+    operations at the unpacked vector rate (256 CUs x 64 lanes x 2.4 GHz =
+    39.3 T lane-op/s).  Bytes: chain rule + Adam + next records 1500 B per
+    Gaussian; ground truth 12 B per pixel; pairs 8 B written at emission plus
+    two radix passes of 4 B (histogram) + 16 B (scatter).  Lane operations:
+    18 per composited pair forward, 55 backward, ~330 per pixel for the loss
+    (five moments with two 11-tap passes per channel, forward and backward)."""
+    lane_rate = 256 * 64 * 2.4e9
+    bw = HBM_PEAK_GBS * 1e9
+    pairs = plan.pair_count()
+    terms = {
+        "bin_sort": (8.0 + 2 * 20.0) * pairs / bw,
+        "render_fwd": 18.0 * composited / lane_rate,
+        "loss": max(12.0 * plan.total_pixels / bw, 330.0 * 3 * plan.total_pixels / lane_rate),
+        "raster_bwd": 55.0 * composited / lane_rate,
+        "project_bwd_adam": (1452.0 + 48.0 * plan.n_views) * n / bw,
+    }
+    t_roof = sum(terms.values()) * 1e3
+    return {"t_roof_ms": round(t_roof, 4), "t_measured_ms": round(ms_step, 4),
+            "frac": round(t_roof / ms_step, 4), "terms_ms": {k: round(v * 1e3, 4) for k, v in terms.items()}}
+
+
 def level0_psnr(plan, rgb, target, levels):
     vals = []
     for v in range(plan.n_views):
@@ -477,6 +501,7 @@ def main():
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kernels.items()},
         "composited_pairs": composited,
+        "iteration_roofline": iteration_roofline(n, plan, composited, ms_step),
         "launch": {"batch": plan.settings.batch, "bwd_waves": plan.settings.bwd_waves,
                    "autotune_ms": tuned["ms"] if tuned else None},
     }

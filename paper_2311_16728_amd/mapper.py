@@ -36,6 +36,31 @@ def mapping_lr_rows(extent: float = 5.0) -> np.ndarray:
     return lr
 
 
+class PyramidSchedule:
+    """Eq. 5 coarse-to-fine supervision per keyframe (Section 3.4): a keyframe
+    is first supervised at the top level n of its Gaussian pyramid and moves
+    one level finer every `tau` times it is used, down to level 0.  The paper
+    does not give the number of uses per level; tau = 4 is this build's
+    choice."""
+
+    def __init__(self, levels: int = PYRAMID_LEVELS, tau: int = 4):
+        if levels < 1 or tau < 1:
+            raise ValueError("levels and tau must be positive")
+        self.top = levels - 1
+        self.tau = tau
+        self.uses: dict = {}
+
+    def level(self, keyframe) -> int:
+        """Pyramid level the next use of `keyframe` is supervised at."""
+        return max(0, self.top - self.uses.get(keyframe, 0) // self.tau)
+
+    def use(self, keyframe) -> int:
+        """Level for this use of `keyframe`; counts the use."""
+        lv = self.level(keyframe)
+        self.uses[keyframe] = self.uses.get(keyframe, 0) + 1
+        return lv
+
+
 def _bytes(n: int, device) -> torch.Tensor:
     return torch.empty(max(int(n), 256), dtype=torch.uint8, device=device)
 

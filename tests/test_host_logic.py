@@ -70,3 +70,18 @@ def test_mapping_learning_rates():
     assert lr.shape == (59,) and lr.dtype == np.float32
     assert np.all(lr > 0)
     assert lr[10] > lr[3] > lr[11] > lr[14]
+
+
+def test_pyramid_schedule_coarse_to_fine():
+    """Eq. 5: level n first, one level finer every tau uses, then level 0 for good;
+    keyframes are counted separately."""
+    from paper_2311_16728_amd.mapper import PyramidSchedule
+
+    sch = PyramidSchedule(levels=3, tau=4)
+    seq = [sch.use("a") for _ in range(14)]
+    assert seq == [2] * 4 + [1] * 4 + [0] * 6
+    assert sch.use("b") == 2 and sch.level("a") == 0
+    one = PyramidSchedule(levels=1, tau=2)
+    assert [one.use(0) for _ in range(3)] == [0, 0, 0]
+    with pytest.raises(ValueError):
+        PyramidSchedule(levels=0)
