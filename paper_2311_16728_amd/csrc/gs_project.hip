@@ -199,6 +199,9 @@ __device__ __forceinline__ bool project(const Gauss &G, const Cam &c, float znea
     return true;
 }
 
+// Views up to which the optimiser kernel also computes the next records.
+constexpr int kFuseProjectionViews = 2;
+
 // Projection records of Gaussian g for every view (see gs_preprocess).
 __device__ __forceinline__ void preprocess_one(const gs_settings &s, const float *P, int64_t n_cap,
                                                int64_t g, const gs_view *__restrict__ views,
@@ -571,8 +574,13 @@ gs_status launch_project_backward_adam(const gs_settings &s, float *params, int6
                                        double beta2, double eps, int32_t step, const int32_t *d_step,
                                        void *proj_out, hipStream_t st) {
     if (n == 0) return GS_OK;
+    // The next records are computed inside the optimiser kernel for few views;
+    // with many views the separate projection kernel (parameters read once,
+    // colour coefficients kept in registers across views) is faster.
+    const Proj next = proj_out ? proj_at(proj_out, int64_t(n_views) * n_cap) : Proj{nullptr, nullptr, nullptr};
+    const bool fuse_next = proj_out && n_views <= kFuseProjectionViews;
     AdamSink a;
-    a.next = proj_out ? proj_at(proj_out, int64_t(n_views) * n_cap) : Proj{nullptr, nullptr, nullptr};
+    a.next = fuse_next ? next : Proj{nullptr, nullptr, nullptr};
     a.p = params;
     a.m = m;
     a.v = v;
@@ -591,6 +599,9 @@ gs_status launch_project_backward_adam(const gs_settings &s, float *params, int6
     const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(project_backward_kernel<AdamSink>, dim3(blocks), dim3(256), 0, st, s, params, n,
                        n_cap, views, n_views, acc, int64_t(n_views) * n_cap, a);
+    if (proj_out && !fuse_next)
+        hipLaunchKernelGGL(preprocess_kernel, dim3(blocks), dim3(256), 0, st, s, params, n, n_cap, views,
+                           n_views, next);
     GS_CHECK_LAUNCH();
     return GS_OK;
 }

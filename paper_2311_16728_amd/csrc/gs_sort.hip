@@ -77,6 +77,7 @@ __global__ void __launch_bounds__(256) sort_setup_kernel(const gs_target *__rest
 
 // A tile rectangle that holds no tile (x0 = 1 > x1 = 0): count 0.
 constexpr uint32_t kEmptyRectX = 1u;
+constexpr uint32_t kRectKeep = 4;   // rectangles per record kept in registers while counting
 
 __device__ __forceinline__ uint32_t rect_count(uint2 rc) {
     const uint32_t w = (rc.x >> 16) - (rc.x & 0xffffu) + 1u;
@@ -84,11 +85,12 @@ __device__ __forceinline__ uint32_t rect_count(uint2 rc) {
     return w * h;
 }
 
-// For record (v, g): its tile rectangle in the q-th target of view v, packed
-// as (x0 | x1 << 16, y0 | y1 << 16) (empty when it touches none), at
-// rects[view_off[v] * n_cap + g * m_v + q] (m_v targets in view v: a record's
-// rectangles are adjacent), and counts[v * n_cap + g] = its number of tiles
-// over those targets.
+// For record (v, g): counts[v * n_cap + g] = its number of tiles over the
+// targets of view v, and, when that is not zero, its tile rectangle in the
+// q-th target packed as (x0 | x1 << 16, y0 | y1 << 16) (empty when it touches
+// none) at rects[view_off[v] * n_cap + g * m_v + q] (m_v targets in view v: a
+// record's rectangles are adjacent).  Rectangles of records with no tile are
+// not written.
 __global__ void __launch_bounds__(256) count_kernel(gs_settings s, Proj proj, int64_t n, int64_t n_cap,
                                                     const gs_target *__restrict__ targets,
                                                     const uint32_t *__restrict__ view_off,
@@ -105,17 +107,38 @@ __global__ void __launch_bounds__(256) count_kernel(gs_settings s, Proj proj, in
         const float4 co = proj.cov_o[r];
         const float z = proj.rgb_z[r].w;
         const uint32_t q0 = view_off[v], m = view_off[v + 1] - q0;
-        uint2 *out = rects + int64_t(q0) * n_cap + g * m;
-        for (uint32_t q = 0; q < m; ++q) {
+        auto rect_of = [&](uint32_t q, uint32_t &c) {
             const gs_target t = targets[view_list[q0 + q]];
             Rect rc;
-            uint2 packed = make_uint2(kEmptyRectX, 0u);
-            if (tile_rect(s, md, co, z, t, rc)) {
-                total += uint32_t(rc.x1 - rc.x0 + 1) * uint32_t(rc.y1 - rc.y0 + 1);
-                packed = make_uint2(uint32_t(rc.x0) | (uint32_t(rc.x1) << 16),
-                                    uint32_t(rc.y0) | (uint32_t(rc.y1) << 16));
+            c = 0u;
+            if (!tile_rect(s, md, co, z, t, rc)) return make_uint2(kEmptyRectX, 0u);
+            c = uint32_t(rc.x1 - rc.x0 + 1) * uint32_t(rc.y1 - rc.y0 + 1);
+            return make_uint2(uint32_t(rc.x0) | (uint32_t(rc.x1) << 16), uint32_t(rc.y0) | (uint32_t(rc.y1) << 16));
+        };
+        // the first kRectKeep rectangles stay in registers; only records that
+        // touch some tile store them (most records are culled in every target)
+        uint2 keep[kRectKeep];
+#pragma unroll
+        for (uint32_t q = 0; q < kRectKeep; ++q) {
+            uint32_t c = 0u;
+            keep[q] = make_uint2(kEmptyRectX, 0u);
+            if (q < m) keep[q] = rect_of(q, c);
+            total += c;
+        }
+        for (uint32_t q = kRectKeep; q < m; ++q) {
+            uint32_t c;
+            rect_of(q, c);
+            total += c;
+        }
+        if (total > 0) {
+            uint2 *out = rects + int64_t(q0) * n_cap + g * m;
+#pragma unroll
+            for (uint32_t q = 0; q < kRectKeep; ++q)
+                if (q < m) out[q] = keep[q];
+            for (uint32_t q = kRectKeep; q < m; ++q) {
+                uint32_t c;
+                out[q] = rect_of(q, c);
             }
-            out[q] = packed;
         }
     }
     counts[r] = total;

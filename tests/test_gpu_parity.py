@@ -338,29 +338,32 @@ def test_launch_shapes_do_not_change_results(orc):
         assert (np.abs(g - ref) / scale).max() <= 1e-4
 
 
-def test_fused_step_writes_next_records():
+@pytest.mark.parametrize("n_views", [2, 3])
+def test_fused_step_writes_next_records(n_views):
     """The records gs_project_bwd_adam writes for the updated parameters equal
-    gs_preprocess of those parameters bitwise (two views, ragged sizes)."""
-    from paper_2311_16728_amd import gs
+    gs_preprocess of those parameters bitwise (ragged sizes; two views take the
+    fused path, three the separate projection kernel)."""
     from paper_2311_16728_amd.mapper import Mapper
 
     p, tp, cam = scenes.tiny_scene(4)
     n = 1900
     c2 = scenes.pinhole(150, 110, 130.0, 125.0, 71.3, 52.6, R=[[0.995, 0, 0.0998], [0, 1, 0], [-0.0998, 0, 0.995]],
                         t=[0.1, 0.0, 0.1])
-    plan = plan_for([cam, c2], levels=(0, 1), n_cap=p.shape[1])
-    tplan = plan_for([cam, c2], levels=(0, 1), n_cap=p.shape[1])
+    c3 = scenes.pinhole(96, 80, 90.0, R=[[1, 0, 0], [0, 0.995, 0.0998], [0, -0.0998, 0.995]], t=[0.0, 0.05, 0.2])
+    cams = [cam, c2, c3][:n_views]
+    plan = plan_for(cams, levels=(0, 1), n_cap=p.shape[1])
+    tplan = plan_for(cams, levels=(0, 1), n_cap=p.shape[1])
     tplan.render(_dev(tp), n)
     tgt = tplan.rgb.clone()
     mp = Mapper(_dev(p), n)
     mp.step(plan, tgt, lam=0.2)          # fused: plan.proj_ws now holds the next records
     torch.cuda.synchronize()
     got = proj_records(plan, n)
-    ref = plan_for([cam, c2], levels=(0, 1), n_cap=p.shape[1])
+    ref = plan_for(cams, levels=(0, 1), n_cap=p.shape[1])
     ref.preprocess(mp.params, n)
     torch.cuda.synchronize()
     want = proj_records(ref, n)
-    for v in range(2):
+    for v in range(n_views):
         rows = slice(v * p.shape[1], v * p.shape[1] + n)   # records of Gaussians < n
         for a, b in zip(got, want):
             np.testing.assert_array_equal(a[rows], b[rows])
