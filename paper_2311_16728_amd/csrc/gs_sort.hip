@@ -268,12 +268,22 @@ __global__ void __launch_bounds__(256) offsets_scatter_kernel(const uint32_t *__
     }
 }
 
+// q = k / w, r = k % w for k < 2^24, w >= 1: a float reciprocal estimate
+// corrected by one step (exact: the estimate is off by at most one).
+__device__ __forceinline__ void divmod_small(uint32_t k, uint32_t w, uint32_t &q, uint32_t &r) {
+    q = uint32_t(float(k) * __builtin_amdgcn_rcpf(float(w)));
+    int32_t rr = int32_t(k) - int32_t(q * w);
+    if (rr < 0) { --q; rr += int32_t(w); }
+    else if (rr >= int32_t(w)) { ++q; rr -= int32_t(w); }
+    r = uint32_t(rr);
+}
+
 // Pair emission, one thread per output pair.  A block takes 256 consecutive
 // pair slots; the records covering them (at most 256, each has >= 1 pair)
-// start at chunk_first[chunk] (written by the offsets scan), their offsets are
-// staged in LDS, and each thread locates its record by a binary search there.
-// Near-camera Gaussians that cover thousands of tiles are thus spread over many
-// threads.
+// start at chunk_first[chunk] (written by the offsets scan).  Every record
+// after the first marks the slot where it starts, and a block scan of the
+// marks gives each slot its record, so near-camera Gaussians that cover
+// thousands of tiles are spread over many threads.
 __global__ void __launch_bounds__(256) emit_kernel(int64_t n_cap, const gs_target *__restrict__ targets,
                                                    uint32_t *__restrict__ counters,
                                                    const uint32_t *__restrict__ vis_val,
@@ -285,7 +295,9 @@ __global__ void __launch_bounds__(256) emit_kernel(int64_t n_cap, const gs_targe
                                                    int64_t pair_cap, uint32_t *__restrict__ pkey,
                                                    uint32_t *__restrict__ pval,
                                                    uint32_t *__restrict__ d_status) {
-    __shared__ uint32_t off[kScanThreads + 1];
+    __shared__ uint32_t off[kScanThreads];
+    __shared__ uint32_t mark[kScanThreads];
+    __shared__ uint32_t lds[8];
     const uint32_t V = counters[kVisible];
     const uint32_t P = counters[kPairs];
     const uint32_t Pc = int64_t(P) > pair_cap ? uint32_t(pair_cap) : P;
@@ -294,37 +306,40 @@ __global__ void __launch_bounds__(256) emit_kernel(int64_t n_cap, const gs_targe
         if (Pc != P && d_status) atomicOr(d_status, GS_STATUS_PAIR_OVERFLOW);
     }
     if (V == 0) return;   // no visible record, no pair (Pc == 0)
+    const int tid = threadIdx.x;
     for (int64_t chunk = blockIdx.x; chunk * kScanThreads < Pc; chunk += gridDim.x) {
         const uint32_t o0 = uint32_t(chunk * kScanThreads);
         const uint32_t j0 = chunk_first[chunk];   // last record j with vis_off[j] <= o0
         __syncthreads();
-        for (int i = threadIdx.x; i <= kScanThreads; i += blockDim.x) {
-            const uint32_t j = j0 + i;
-            off[i] = (j < V) ? vis_off[j] : 0xffffffffu;
-        }
+        mark[tid] = 0u;
+        const uint32_t jt = j0 + uint32_t(tid);
+        const uint32_t ot = jt < V ? vis_off[jt] : 0xffffffffu;
+        off[tid] = ot;
         __syncthreads();
-        const uint32_t o = o0 + threadIdx.x;
+        // records after the first start strictly after o0
+        if (tid > 0 && jt < V && ot - o0 < uint32_t(kScanThreads)) mark[ot - o0] = 1u;
+        __syncthreads();
+        uint32_t total;
+        const uint32_t m = mark[tid];
+        const uint32_t rec = block_exclusive_scan(m, lds, &total) + m;   // record of slot tid
+        const uint32_t o = o0 + uint32_t(tid);
         if (o >= Pc) continue;
-        int lo = 0, hi = kScanThreads;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (off[mid] <= o) lo = mid; else hi = mid - 1;
-        }
-        const uint32_t src = vis_val[j0 + lo];          // record v * n_cap + g
-        uint32_t k = o - off[lo];
+        const uint32_t src = vis_val[j0 + rec];          // record v * n_cap + g
+        uint32_t k = o - off[rec];
         const uint32_t v = src / uint32_t(n_cap), g = src - v * uint32_t(n_cap);
         // the k-th pair of the record: targets of its view in order, tiles row-major
         uint32_t key = 0u;
-        const uint32_t q0 = view_off[v], m = view_off[v + 1] - q0;
-        const uint2 *rc_v = rects + int64_t(q0) * n_cap + int64_t(g) * m;
-        for (uint32_t q = 0; q < m; ++q) {
+        const uint32_t q0 = view_off[v], mv = view_off[v + 1] - q0;
+        const uint2 *rc_v = rects + int64_t(q0) * n_cap + int64_t(g) * mv;
+        for (uint32_t q = 0; q < mv; ++q) {
             const uint2 rc = rc_v[q];
             const uint32_t c = rect_count(rc);
             if (k < c) {
                 const uint32_t x0 = rc.x & 0xffffu, x1 = rc.x >> 16, y0 = rc.y & 0xffffu;
-                const uint32_t w = x1 - x0 + 1;
+                uint32_t dy, dx;
+                divmod_small(k, x1 - x0 + 1, dy, dx);
                 const gs_target &t = targets[view_list[q0 + q]];
-                key = uint32_t(t.tile_offset) + (y0 + k / w) * uint32_t(t.tiles_x) + x0 + k % w;
+                key = uint32_t(t.tile_offset) + (y0 + dy) * uint32_t(t.tiles_x) + x0 + dx;
                 break;
             }
             k -= c;
