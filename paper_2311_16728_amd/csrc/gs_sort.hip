@@ -77,7 +77,6 @@ __global__ void __launch_bounds__(256) sort_setup_kernel(const gs_target *__rest
 
 // A tile rectangle that holds no tile (x0 = 1 > x1 = 0): count 0.
 constexpr uint32_t kEmptyRectX = 1u;
-constexpr uint32_t kRectKeep = 4;   // rectangles per record kept in registers while counting
 
 __device__ __forceinline__ uint32_t rect_count(uint2 rc) {
     const uint32_t w = (rc.x >> 16) - (rc.x & 0xffffu) + 1u;
@@ -115,27 +114,16 @@ __global__ void __launch_bounds__(256) count_kernel(gs_settings s, Proj proj, in
             c = uint32_t(rc.x1 - rc.x0 + 1) * uint32_t(rc.y1 - rc.y0 + 1);
             return make_uint2(uint32_t(rc.x0) | (uint32_t(rc.x1) << 16), uint32_t(rc.y0) | (uint32_t(rc.y1) << 16));
         };
-        // the first kRectKeep rectangles stay in registers; only records that
-        // touch some tile store them (most records are culled in every target)
-        uint2 keep[kRectKeep];
-#pragma unroll
-        for (uint32_t q = 0; q < kRectKeep; ++q) {
-            uint32_t c = 0u;
-            keep[q] = make_uint2(kEmptyRectX, 0u);
-            if (q < m) keep[q] = rect_of(q, c);
-            total += c;
-        }
-        for (uint32_t q = kRectKeep; q < m; ++q) {
+        // count first; only records that touch some tile store their
+        // rectangles (most records are culled in every target)
+        for (uint32_t q = 0; q < m; ++q) {
             uint32_t c;
             rect_of(q, c);
             total += c;
         }
         if (total > 0) {
             uint2 *out = rects + int64_t(q0) * n_cap + g * m;
-#pragma unroll
-            for (uint32_t q = 0; q < kRectKeep; ++q)
-                if (q < m) out[q] = keep[q];
-            for (uint32_t q = kRectKeep; q < m; ++q) {
+            for (uint32_t q = 0; q < m; ++q) {
                 uint32_t c;
                 out[q] = rect_of(q, c);
             }
