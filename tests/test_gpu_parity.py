@@ -367,3 +367,26 @@ def test_fused_step_writes_next_records(n_views):
         rows = slice(v * p.shape[1], v * p.shape[1] + n)   # records of Gaussians < n
         for a, b in zip(got, want):
             np.testing.assert_array_equal(a[rows], b[rows])
+
+
+def test_pair_overflow_is_reported():
+    """With a pair buffer far smaller than the scene needs, binning keeps the
+    first pair_cap pairs, raises the overflow flag, and every later stage still
+    runs on the clamped lists (finite images, transmittance in [1e-4, 1])."""
+    p, _, cam = scenes.tiny_scene(1)
+    n = 2000
+    full = plan_for([cam], n_cap=p.shape[1])
+    full.render(_dev(p), n)
+    torch.cuda.synchronize()
+    need = full.pair_count()
+    assert not full.overflowed() and need > 4096
+    small = plan_for([cam], n_cap=p.shape[1], pair_cap=need // 3)
+    small.render(_dev(p), n)
+    torch.cuda.synchronize()
+    assert small.overflowed()
+    counters = small.sort_ws[:64].view(torch.int32).cpu().numpy()
+    assert counters[1] == need and counters[2] == need // 3   # pairs wanted, pairs kept
+    img = small.image(small.rgb, 0)
+    T = small.plane(small.T, 0)
+    assert torch.isfinite(img).all()
+    assert bool(((T >= 1e-4) & (T <= 1.0)).all())
