@@ -118,19 +118,20 @@ struct Gauss {
     float Rq[9], M[9], Sig[6];   // Sig: 00 01 02 11 12 22
 };
 
-__device__ __forceinline__ void load_gauss(const float *__restrict__ P, int64_t n_cap, int64_t g,
-                                           Gauss &G) {
+// Activations of the 11 geometric raw parameters (mean, log-scale, quaternion,
+// opacity logit) and the derived rotation, M = R S and Sigma = M M^T.
+__device__ __forceinline__ void gauss_from_raw(const float (&raw)[11], Gauss &G) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i) G.mu[i] = P[(0 + i) * n_cap + g];
+    for (int i = 0; i < 3; ++i) G.mu[i] = raw[i];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) G.s[i] = __expf(P[(3 + i) * n_cap + g]);
+    for (int i = 0; i < 3; ++i) G.s[i] = __expf(raw[3 + i]);
     float q[4], qq = 0.f;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) { q[i] = P[(6 + i) * n_cap + g]; qq += q[i] * q[i]; }
+    for (int i = 0; i < 4; ++i) { q[i] = raw[6 + i]; qq += q[i] * q[i]; }
     G.qinv = rsqrtf(qq);
 #pragma unroll
     for (int i = 0; i < 4; ++i) G.q[i] = q[i] * G.qinv;
-    G.o = 1.f / (1.f + __expf(-P[10 * n_cap + g]));
+    G.o = 1.f / (1.f + __expf(-raw[10]));
     const float w = G.q[0], x = G.q[1], y = G.q[2], z = G.q[3];
     G.Rq[0] = 1.f - 2.f * (y * y + z * z); G.Rq[1] = 2.f * (x * y - w * z); G.Rq[2] = 2.f * (x * z + w * y);
     G.Rq[3] = 2.f * (x * y + w * z); G.Rq[4] = 1.f - 2.f * (x * x + z * z); G.Rq[5] = 2.f * (y * z - w * x);
@@ -144,6 +145,14 @@ __device__ __forceinline__ void load_gauss(const float *__restrict__ P, int64_t 
     };
     G.Sig[0] = dot3(0, 0); G.Sig[1] = dot3(0, 1); G.Sig[2] = dot3(0, 2);
     G.Sig[3] = dot3(1, 1); G.Sig[4] = dot3(1, 2); G.Sig[5] = dot3(2, 2);
+}
+
+__device__ __forceinline__ void load_gauss(const float *__restrict__ P, int64_t n_cap, int64_t g,
+                                           Gauss &G) {
+    float raw[11];
+#pragma unroll
+    for (int i = 0; i < 11; ++i) raw[i] = P[int64_t(i) * n_cap + g];
+    gauss_from_raw(raw, G);
 }
 
 // View-dependent projection of one Gaussian.
@@ -242,15 +251,15 @@ __device__ __forceinline__ void preprocess_one(const gs_settings &s, const float
     }
 }
 
-// The same records with one colour channel's coefficients live at a time (each
-// channel's SH rows are read per view), for the end of the fused optimiser
-// kernel, whose occupancy is bounded by its registers.  Same arithmetic in the
-// same order as preprocess_one, so the records are identical.
-__device__ __forceinline__ void preprocess_one_lean(const gs_settings &s, const float *P, int64_t n_cap,
-                                                    int64_t g, const gs_view *__restrict__ views,
-                                                    int32_t n_views, const Proj &out) {
-    Gauss G;
-    load_gauss(P, n_cap, g, G);
+// Records of Gaussian g (activated geometry G) for every view, one colour
+// channel's coefficients live at a time: channels are read from P, except
+// channel 2 when keep2 is given (keep2[k * kTilePix], coefficient k).  Same
+// arithmetic in the same order as preprocess_one, so the records are
+// identical.
+__device__ __forceinline__ void project_records(const gs_settings &s, const float *P, int64_t n_cap,
+                                                int64_t g, const Gauss &G, const float *keep2,
+                                                const gs_view *__restrict__ views, int32_t n_views,
+                                                const Proj &out) {
     const int nk = (s.sh_degree + 1) * (s.sh_degree + 1);
     for (int v = 0; v < n_views; ++v) {
         const int64_t r = int64_t(v) * n_cap + g;
@@ -270,14 +279,27 @@ __device__ __forceinline__ void preprocess_one_lean(const gs_settings &s, const 
 #pragma unroll 1
         for (int ch = 0; ch < 3; ++ch) {
             float acc = 0.5f;
+            if (keep2 && ch == 2) {
 #pragma unroll
-            for (int k = 0; k < 16; ++k) acc += Y[k] * ((k < nk) ? P[(11 + 3 * k + ch) * n_cap + g] : 0.f);
+                for (int k = 0; k < 16; ++k) acc += Y[k] * ((k < nk) ? keep2[k * kTilePix] : 0.f);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 16; ++k) acc += Y[k] * ((k < nk) ? P[(11 + 3 * k + ch) * n_cap + g] : 0.f);
+            }
             rgb[ch] = fmaxf(acc, 0.f);
         }
         out.mean[r] = make_double2(p.md[0], p.md[1]);
         out.cov_o[r] = make_float4(p.cov[0], p.cov[1], p.cov[2], G.o);
         out.rgb_z[r] = make_float4(rgb[0], rgb[1], rgb[2], p.xc[2]);
     }
+}
+
+__device__ __forceinline__ void preprocess_one_lean(const gs_settings &s, const float *P, int64_t n_cap,
+                                                    int64_t g, const gs_view *__restrict__ views,
+                                                    int32_t n_views, const Proj &out) {
+    Gauss G;
+    load_gauss(P, n_cap, g, G);
+    project_records(s, P, n_cap, g, G, nullptr, views, n_views, out);
 }
 
 __global__ void __launch_bounds__(256) preprocess_kernel(gs_settings s, const float *__restrict__ P,
@@ -297,9 +319,10 @@ struct GradSink {
     float *__restrict__ grad;
     struct Scale {};
     __device__ __forceinline__ Scale prepare() const { return {}; }
+    static constexpr int kKeepRows = 1;   // no colour rows kept (see AdamSink)
     template <int N>
     __device__ __forceinline__ void group(int first, int stride, int64_t g, int64_t n_cap,
-                                          const float (&val)[N], Scale) const {
+                                          float (&val)[N], Scale) const {
         float cur[N];
 #pragma unroll
         for (int j = 0; j < N; ++j) cur[j] = grad[int64_t(first + j * stride) * n_cap + g];
@@ -309,6 +332,9 @@ struct GradSink {
     __device__ __forceinline__ void untouched(int64_t, int64_t, Scale) const {}
     __device__ __forceinline__ void finish(const gs_settings &, int64_t, int64_t, const gs_view *,
                                            int32_t) const {}
+    __device__ __forceinline__ void finish_updated(const gs_settings &, int64_t, int64_t,
+                                                   const gs_view *, int32_t, const float (&)[11],
+                                                   const float *) const {}
 };
 
 struct AdamSink {
@@ -334,9 +360,11 @@ struct AdamSink {
         }
         return {ibc1, isqbc2};
     }
+    // The updated parameters replace the gradients in gv.
+    static constexpr int kKeepRows = 16;   // one colour channel's coefficients kept in LDS
     template <int N>
     __device__ __forceinline__ void group(int first, int stride, int64_t g, int64_t n_cap,
-                                          const float (&gv)[N], Scale sc) const {
+                                          float (&gv)[N], Scale sc) const {
         float pp[N], mm[N], vv[N];
 #pragma unroll
         for (int j = 0; j < N; ++j) {
@@ -354,13 +382,17 @@ struct AdamSink {
             v[i] = vq;
             // hardware sqrt and reciprocal (1 ulp each) keep the unrolled group short
             const float den = __builtin_amdgcn_sqrtf(vq) * sc.isqbc2 + eps;
-            p[i] = pp[j] - lr.lr[first + j * stride] * sc.ibc1 * mv * __builtin_amdgcn_rcpf(den);
+            const float np = pp[j] - lr.lr[first + j * stride] * sc.ibc1 * mv * __builtin_amdgcn_rcpf(den);
+            p[i] = np;
+            gv[j] = np;
         }
     }
     __device__ __forceinline__ void untouched(int64_t g, int64_t n_cap, Scale sc) const {
-        const float z[1] = {0.f};
 #pragma unroll 1
-        for (int r = 0; r < kRows; ++r) group(r, 1, g, n_cap, z, sc);
+        for (int r = 0; r < kRows; ++r) {
+            float z[1] = {0.f};
+            group(r, 1, g, n_cap, z, sc);
+        }
     }
     // Optionally the projection records of the updated Gaussian for the same
     // views (the next iteration's preprocess).  The rows are read back through
@@ -369,6 +401,17 @@ struct AdamSink {
     __device__ __forceinline__ void finish(const gs_settings &s, int64_t g, int64_t n_cap,
                                            const gs_view *views, int32_t n_views) const {
         if (next.mean) preprocess_one_lean(s, p, n_cap, g, views, n_views, next);
+    }
+    // The same records with the updated geometry taken from registers and the
+    // last colour channel's coefficients from LDS (keep2[k * 256]); only the
+    // other two channels are read back.
+    __device__ __forceinline__ void finish_updated(const gs_settings &s, int64_t g, int64_t n_cap,
+                                                   const gs_view *views, int32_t n_views,
+                                                   const float (&raw)[11], const float *keep2) const {
+        if (!next.mean) return;
+        Gauss G;
+        gauss_from_raw(raw, G);
+        project_records(s, p, n_cap, g, G, keep2, views, n_views, next);
     }
 };
 
@@ -381,6 +424,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
     gs_settings s, const float *__restrict__ P, int64_t n, int64_t n_cap,
     const gs_view *__restrict__ views, int32_t n_views, const float *__restrict__ acc,
     int64_t records, Sink sink) {
+    __shared__ float keep2[Sink::kKeepRows][256];   // updated coefficients of colour channel 2
     const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (g >= n) return;
     const typename Sink::Scale sc = sink.prepare();
@@ -508,8 +552,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
         // four groups of four rows: enough loads in flight, few registers
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const float part[4] = {gsh[4 * q], gsh[4 * q + 1], gsh[4 * q + 2], gsh[4 * q + 3]};
+            float part[4] = {gsh[4 * q], gsh[4 * q + 1], gsh[4 * q + 2], gsh[4 * q + 3]};
             sink.group(11 + ch + 12 * q, 3, g, n_cap, part, sc);
+            if (Sink::kKeepRows == 16 && ch == 2) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) keep2[(4 * q + j) % Sink::kKeepRows][threadIdx.x] = part[j];
+            }
         }
     }
 
@@ -551,10 +599,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
 #pragma unroll
         for (int i = 0; i < 4; ++i) gq[i] = (dq[i] - G.q[i] * dot) * G.qinv;
     }
-    const float geo[11] = {gmu[0], gmu[1], gmu[2], gls[0], gls[1], gls[2],
-                           gq[0], gq[1], gq[2], gq[3], gop * G.o * (1.f - G.o)};
+    float geo[11] = {gmu[0], gmu[1], gmu[2], gls[0], gls[1], gls[2],
+                     gq[0], gq[1], gq[2], gq[3], gop * G.o * (1.f - G.o)};
     sink.group(0, 1, g, n_cap, geo, sc);
-    sink.finish(s, g, n_cap, views, n_views);
+    sink.finish_updated(s, g, n_cap, views, n_views, geo, &keep2[0][threadIdx.x]);
 }
 
 gs_status launch_project_backward(const gs_settings &s, const float *params, int64_t n,
