@@ -180,17 +180,6 @@ __device__ __forceinline__ float dpp_add(float v) {
     return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, kRowMask, 0xf, false));
 }
 
-// Sum over the 64 lanes; the total is valid in lane 63.
-__device__ __forceinline__ float wave_sum_to_last(float v) {
-    v = dpp_add<0xB1, 0xf>(v);    // quad_perm [1,0,3,2]
-    v = dpp_add<0x4E, 0xf>(v);    // quad_perm [2,3,0,1]
-    v = dpp_add<0x141, 0xf>(v);   // row_half_mirror: 8-lane sums
-    v = dpp_add<0x140, 0xf>(v);   // row_mirror: 16-lane sums
-    v = dpp_add<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
-    v = dpp_add<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
-    return v;
-}
-
 // Block-wide exclusive scan for kThreads threads (a multiple of 64).
 template <int kThreads>
 __device__ __forceinline__ uint32_t block_scan_n(uint32_t v, uint32_t *lds, uint32_t *total) {
