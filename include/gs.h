@@ -125,8 +125,9 @@ gs_status gs_workspace_query(const gs_settings *s, int64_t n_cap, int32_t n_view
  * g < n, the camera-frame depth, the level-0 2D mean, the undilated 2D
  * covariance J W Sigma W^T J^T, the opacity sigmoid(raw) and the SH colour
  * seen from the view's centre (max(0, 0.5 + sum_k Y_k c_k)).  Gaussians with
- * depth <= znear are marked invalid.  params (device) as above; views
- * (device) n_views entries; proj_ws (device) proj_bytes. */
+ * depth <= znear are marked invalid (zero record: opacity 0, depth 0).
+ * params (device) as above; views (device) n_views entries; proj_ws (device)
+ * proj_bytes. */
 gs_status gs_preprocess(const gs_settings *s, const float *params, int64_t n, int64_t n_cap,
                         const gs_view *views, int32_t n_views, void *proj_ws, void *stream);
 

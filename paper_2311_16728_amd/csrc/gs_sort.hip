@@ -18,14 +18,14 @@
 namespace gs {
 
 // Conservative pixel bounding box of {alpha >= alpha_min} for a record at a
-// pyramid level.  Returns false when the record cannot reach any pixel.
+// pyramid level.  Returns false when the record cannot reach any pixel; records
+// behind the near plane carry opacity 0 and are rejected by the opacity test.
 struct Rect {
     int x0, x1, y0, y1;   // inclusive tile ranges
 };
 
-__device__ __forceinline__ bool tile_rect(const gs_settings &s, double2 md, float4 cov_o, float z,
+__device__ __forceinline__ bool tile_rect(const gs_settings &s, double2 md, float4 cov_o,
                                           const gs_target &t, Rect &r) {
-    if (!(z > 0.f)) return false;
     const float o = cov_o.w;
     if (!(o >= s.alpha_min)) return false;
     const float sc = ldexpf(1.f, -t.level);
@@ -85,11 +85,10 @@ __device__ __forceinline__ uint32_t rect_count(uint2 rc) {
 }
 
 // For record (v, g): counts[v * n_cap + g] = its number of tiles over the
-// targets of view v, and, when that is not zero, its tile rectangle in the
-// q-th target packed as (x0 | x1 << 16, y0 | y1 << 16) (empty when it touches
-// none) at rects[view_off[v] * n_cap + g * m_v + q] (m_v targets in view v: a
-// record's rectangles are adjacent).  Rectangles of records with no tile are
-// not written.
+// targets of view v, and its tile rectangle in the q-th target packed as
+// (x0 | x1 << 16, y0 | y1 << 16) (empty when it touches none) at
+// rects[view_off[v] * n_cap + g * m_v + q] (m_v targets in view v: a record's
+// rectangles are adjacent).
 __global__ void __launch_bounds__(256) count_kernel(gs_settings s, Proj proj, int64_t n, int64_t n_cap,
                                                     const gs_target *__restrict__ targets,
                                                     const uint32_t *__restrict__ view_off,
@@ -104,29 +103,18 @@ __global__ void __launch_bounds__(256) count_kernel(gs_settings s, Proj proj, in
     if (g < n) {
         const double2 md = proj.mean[r];
         const float4 co = proj.cov_o[r];
-        const float z = proj.rgb_z[r].w;
         const uint32_t q0 = view_off[v], m = view_off[v + 1] - q0;
-        auto rect_of = [&](uint32_t q, uint32_t &c) {
+        uint2 *out = rects + int64_t(q0) * n_cap + g * m;
+        for (uint32_t q = 0; q < m; ++q) {
             const gs_target t = targets[view_list[q0 + q]];
             Rect rc;
-            c = 0u;
-            if (!tile_rect(s, md, co, z, t, rc)) return make_uint2(kEmptyRectX, 0u);
-            c = uint32_t(rc.x1 - rc.x0 + 1) * uint32_t(rc.y1 - rc.y0 + 1);
-            return make_uint2(uint32_t(rc.x0) | (uint32_t(rc.x1) << 16), uint32_t(rc.y0) | (uint32_t(rc.y1) << 16));
-        };
-        // count first; only records that touch some tile store their
-        // rectangles (most records are culled in every target)
-        for (uint32_t q = 0; q < m; ++q) {
-            uint32_t c;
-            rect_of(q, c);
-            total += c;
-        }
-        if (total > 0) {
-            uint2 *out = rects + int64_t(q0) * n_cap + g * m;
-            for (uint32_t q = 0; q < m; ++q) {
-                uint32_t c;
-                out[q] = rect_of(q, c);
+            uint2 packed = make_uint2(kEmptyRectX, 0u);
+            if (tile_rect(s, md, co, t, rc)) {
+                total += uint32_t(rc.x1 - rc.x0 + 1) * uint32_t(rc.y1 - rc.y0 + 1);
+                packed = make_uint2(uint32_t(rc.x0) | (uint32_t(rc.x1) << 16),
+                                    uint32_t(rc.y0) | (uint32_t(rc.y1) << 16));
             }
+            out[q] = packed;   // streamed for every record: cheaper than sparse writes
         }
     }
     counts[r] = total;
@@ -266,12 +254,17 @@ __device__ __forceinline__ void divmod_small(uint32_t k, uint32_t w, uint32_t &q
     r = uint32_t(rr);
 }
 
-// Pair emission, one thread per output pair.  A block takes 256 consecutive
-// pair slots; the records covering them (at most 256, each has >= 1 pair)
-// start at chunk_first[chunk] (written by the offsets scan).  Every record
-// after the first marks the slot where it starts, and a block scan of the
-// marks gives each slot its record, so near-camera Gaussians that cover
-// thousands of tiles are spread over many threads.
+// Pair emission over chunks of kEmitChunk consecutive pair slots, kEmitPer
+// consecutive slots per thread.  The records covering a chunk (at most one per
+// slot, each has >= 1 pair) start at chunk_first[] (one entry per 256 slots,
+// written by the offsets scan).  Every record after the first marks the slot
+// where it starts, and a block scan of the marks gives each slot its record,
+// so near-camera Gaussians that cover thousands of tiles are spread over many
+// threads; a thread reuses its record's data across its slots and stores its
+// keys and values as one vector each.
+constexpr int kEmitPer = 4;
+constexpr int kEmitChunk = kScanThreads * kEmitPer;
+
 __global__ void __launch_bounds__(256) emit_kernel(int64_t n_cap, const gs_target *__restrict__ targets,
                                                    uint32_t *__restrict__ counters,
                                                    const uint32_t *__restrict__ vis_val,
@@ -283,8 +276,8 @@ __global__ void __launch_bounds__(256) emit_kernel(int64_t n_cap, const gs_targe
                                                    int64_t pair_cap, uint32_t *__restrict__ pkey,
                                                    uint32_t *__restrict__ pval,
                                                    uint32_t *__restrict__ d_status) {
-    __shared__ uint32_t off[kScanThreads];
-    __shared__ uint32_t mark[kScanThreads];
+    __shared__ uint32_t off[kEmitChunk];
+    __shared__ uint32_t mark[kEmitChunk];
     __shared__ uint32_t lds[8];
     const uint32_t V = counters[kVisible];
     const uint32_t P = counters[kPairs];
@@ -295,45 +288,77 @@ __global__ void __launch_bounds__(256) emit_kernel(int64_t n_cap, const gs_targe
     }
     if (V == 0) return;   // no visible record, no pair (Pc == 0)
     const int tid = threadIdx.x;
-    for (int64_t chunk = blockIdx.x; chunk * kScanThreads < Pc; chunk += gridDim.x) {
-        const uint32_t o0 = uint32_t(chunk * kScanThreads);
-        const uint32_t j0 = chunk_first[chunk];   // last record j with vis_off[j] <= o0
+    for (int64_t chunk = blockIdx.x; chunk * kEmitChunk < Pc; chunk += gridDim.x) {
+        const uint32_t o0 = uint32_t(chunk * kEmitChunk);
+        const uint32_t j0 = chunk_first[chunk * (kEmitChunk / kScanThreads)];   // record holding slot o0
         __syncthreads();
-        mark[tid] = 0u;
-        const uint32_t jt = j0 + uint32_t(tid);
-        const uint32_t ot = jt < V ? vis_off[jt] : 0xffffffffu;
-        off[tid] = ot;
+#pragma unroll
+        for (int r = 0; r < kEmitPer; ++r) {
+            const int i = tid + r * kScanThreads;
+            mark[i] = 0u;
+            const uint32_t j = j0 + uint32_t(i);
+            off[i] = j < V ? vis_off[j] : 0xffffffffu;
+        }
         __syncthreads();
         // records after the first start strictly after o0
-        if (tid > 0 && jt < V && ot - o0 < uint32_t(kScanThreads)) mark[ot - o0] = 1u;
-        __syncthreads();
-        uint32_t total;
-        const uint32_t m = mark[tid];
-        const uint32_t rec = block_exclusive_scan(m, lds, &total) + m;   // record of slot tid
-        const uint32_t o = o0 + uint32_t(tid);
-        if (o >= Pc) continue;
-        const uint32_t src = vis_val[j0 + rec];          // record v * n_cap + g
-        uint32_t k = o - off[rec];
-        const uint32_t v = src / uint32_t(n_cap), g = src - v * uint32_t(n_cap);
-        // the k-th pair of the record: targets of its view in order, tiles row-major
-        uint32_t key = 0u;
-        const uint32_t q0 = view_off[v], mv = view_off[v + 1] - q0;
-        const uint2 *rc_v = rects + int64_t(q0) * n_cap + int64_t(g) * mv;
-        for (uint32_t q = 0; q < mv; ++q) {
-            const uint2 rc = rc_v[q];
-            const uint32_t c = rect_count(rc);
-            if (k < c) {
-                const uint32_t x0 = rc.x & 0xffffu, x1 = rc.x >> 16, y0 = rc.y & 0xffffu;
-                uint32_t dy, dx;
-                divmod_small(k, x1 - x0 + 1, dy, dx);
-                const gs_target &t = targets[view_list[q0 + q]];
-                key = uint32_t(t.tile_offset) + (y0 + dy) * uint32_t(t.tiles_x) + x0 + dx;
-                break;
-            }
-            k -= c;
+#pragma unroll
+        for (int r = 0; r < kEmitPer; ++r) {
+            const int i = tid + r * kScanThreads;
+            const uint32_t rel = off[i] - o0;
+            if (i > 0 && j0 + uint32_t(i) < V && rel < uint32_t(kEmitChunk)) mark[rel] = 1u;
         }
-        pkey[o] = key;
-        pval[o] = src;
+        __syncthreads();
+        uint32_t mk[kEmitPer], msum = 0;
+#pragma unroll
+        for (int i = 0; i < kEmitPer; ++i) { mk[i] = mark[tid * kEmitPer + i]; msum += mk[i]; }
+        uint32_t total;
+        uint32_t rec = block_exclusive_scan(msum, lds, &total);   // records started before my slots
+        uint32_t key[kEmitPer], val[kEmitPer];
+        uint32_t cur = 0xffffffffu, src = 0, base = 0, v = 0, g = 0, q0 = 0, mv = 0;
+        const uint2 *rc_v = rects;
+#pragma unroll
+        for (int i = 0; i < kEmitPer; ++i) {
+            rec += mk[i];
+            const uint32_t o = o0 + uint32_t(tid * kEmitPer + i);
+            key[i] = 0u;
+            val[i] = 0u;
+            if (o >= Pc) continue;
+            if (rec != cur) {   // first slot of this thread in a record
+                cur = rec;
+                src = vis_val[j0 + rec];   // record v * n_cap + g
+                base = off[rec];
+                v = src / uint32_t(n_cap);
+                g = src - v * uint32_t(n_cap);
+                q0 = view_off[v];
+                mv = view_off[v + 1] - q0;
+                rc_v = rects + int64_t(q0) * n_cap + int64_t(g) * mv;
+            }
+            // the k-th pair of the record: targets of its view in order, tiles row-major
+            uint32_t k = o - base;
+            for (uint32_t q = 0; q < mv; ++q) {
+                const uint2 rc = rc_v[q];
+                const uint32_t c = rect_count(rc);
+                if (k < c) {
+                    const uint32_t x0 = rc.x & 0xffffu, x1 = rc.x >> 16, y0 = rc.y & 0xffffu;
+                    uint32_t dy, dx;
+                    divmod_small(k, x1 - x0 + 1, dy, dx);
+                    const gs_target &t = targets[view_list[q0 + q]];
+                    key[i] = uint32_t(t.tile_offset) + (y0 + dy) * uint32_t(t.tiles_x) + x0 + dx;
+                    break;
+                }
+                k -= c;
+            }
+            val[i] = src;
+        }
+        const uint32_t o_first = o0 + uint32_t(tid * kEmitPer);
+        if (o_first + kEmitPer <= Pc) {
+            *reinterpret_cast<uint4 *>(pkey + o_first) = make_uint4(key[0], key[1], key[2], key[3]);
+            *reinterpret_cast<uint4 *>(pval + o_first) = make_uint4(val[0], val[1], val[2], val[3]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < kEmitPer; ++i)
+                if (o_first + uint32_t(i) < Pc) { pkey[o_first + i] = key[i]; pval[o_first + i] = val[i]; }
+        }
     }
 }
 
@@ -610,7 +635,8 @@ extern "C" gs_status gs_bin_sort(const gs_settings *s, const void *proj_ws, int6
     hipLaunchKernelGGL(offsets_scatter_kernel, dim3(sblocks), dim3(256), 0, st, B.counters + kVisible,
                        B.counts, B.vv[cur], B.bsum, B.voff, B.chunk_first, n_chunks);
     const int64_t persistent = 256 * 16;   // 16 workgroups per CU, grid-stride beyond
-    hipLaunchKernelGGL(emit_kernel, dim3(n_chunks < persistent ? n_chunks : persistent), dim3(256), 0, st,
+    const int64_t emit_chunks = (pair_cap + kEmitChunk - 1) / kEmitChunk;
+    hipLaunchKernelGGL(emit_kernel, dim3(emit_chunks < persistent ? emit_chunks : persistent), dim3(256), 0, st,
                        n_cap, targets, B.counters, B.vv[cur], B.voff, B.rects, B.view_off, B.view_list,
                        B.chunk_first, pair_cap, B.pk[0], B.pv[0], d_status);
     // tile order
