@@ -322,7 +322,7 @@ struct GradSink {
     static constexpr int kKeepRows = 1;   // no colour rows kept (see AdamSink)
     template <int N>
     __device__ __forceinline__ void group(int first, int stride, int64_t g, int64_t n_cap,
-                                          float (&val)[N], Scale) const {
+                                          float (&val)[N], const float (&)[N], Scale) const {
         float cur[N];
 #pragma unroll
         for (int j = 0; j < N; ++j) cur[j] = grad[int64_t(first + j * stride) * n_cap + g];
@@ -360,16 +360,17 @@ struct AdamSink {
         }
         return {ibc1, isqbc2};
     }
-    // The updated parameters replace the gradients in gv.
+    // pcur holds the rows' current values (already loaded by the caller); the
+    // updated parameters replace the gradients in gv.
     static constexpr int kKeepRows = 16;   // one colour channel's coefficients kept in LDS
     template <int N>
     __device__ __forceinline__ void group(int first, int stride, int64_t g, int64_t n_cap,
-                                          float (&gv)[N], Scale sc) const {
+                                          float (&gv)[N], const float (&pcur)[N], Scale sc) const {
         float pp[N], mm[N], vv[N];
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             const int64_t i = int64_t(first + j * stride) * n_cap + g;
-            pp[j] = p[i];
+            pp[j] = pcur[j];
             mm[j] = m[i];
             vv[j] = v[i];
         }
@@ -391,7 +392,8 @@ struct AdamSink {
 #pragma unroll 1
         for (int r = 0; r < kRows; ++r) {
             float z[1] = {0.f};
-            group(r, 1, g, n_cap, z, sc);
+            const float cur[1] = {p[int64_t(r) * n_cap + g]};
+            group(r, 1, g, n_cap, z, cur, sc);
         }
     }
     // Optionally the projection records of the updated Gaussian for the same
@@ -516,10 +518,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
     // 2. colour, one channel at a time: rgb = max(0, raw), raw = 0.5 + sum_k Y_k(d) sh_k
 #pragma unroll 1
     for (int ch = 0; ch < 3; ++ch) {
-        float sh[16], gsh[16];
+        // the rows' stored values (the optimiser step needs them for every k);
+        // the colour uses the first nk
+        float shv[16], sh[16], gsh[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            sh[k] = (k < nk) ? P[(11 + 3 * k + ch) * n_cap + g] : 0.f;
+            shv[k] = P[(11 + 3 * k + ch) * n_cap + g];
+            sh[k] = (k < nk) ? shv[k] : 0.f;
             gsh[k] = 0.f;
         }
         for (int v = 0; v < n_views; ++v) {
@@ -553,7 +558,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             float part[4] = {gsh[4 * q], gsh[4 * q + 1], gsh[4 * q + 2], gsh[4 * q + 3]};
-            sink.group(11 + ch + 12 * q, 3, g, n_cap, part, sc);
+            const float cur[4] = {shv[4 * q], shv[4 * q + 1], shv[4 * q + 2], shv[4 * q + 3]};
+            sink.group(11 + ch + 12 * q, 3, g, n_cap, part, cur, sc);
             if (Sink::kKeepRows == 16 && ch == 2) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) keep2[(4 * q + j) % Sink::kKeepRows][threadIdx.x] = part[j];
@@ -564,8 +570,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
     // 3. Sigma = M M^T, M = Rq diag(s): dM = 2 dSigma M (dSigma symmetric).
     // The 11 geometric parameters are reloaded (SH rows may have been updated
     // in place; these rows have not).
+    float raw[11];
+#pragma unroll
+    for (int i = 0; i < 11; ++i) raw[i] = P[int64_t(i) * n_cap + g];
     Gauss G;
-    load_gauss(P, n_cap, g, G);
+    gauss_from_raw(raw, G);
     const float D[9] = {dSig[0], dSig[1], dSig[2], dSig[1], dSig[3], dSig[4], dSig[2], dSig[4], dSig[5]};
     float dM[9];
 #pragma unroll
@@ -601,7 +610,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
     }
     float geo[11] = {gmu[0], gmu[1], gmu[2], gls[0], gls[1], gls[2],
                      gq[0], gq[1], gq[2], gq[3], gop * G.o * (1.f - G.o)};
-    sink.group(0, 1, g, n_cap, geo, sc);
+    sink.group(0, 1, g, n_cap, geo, raw, sc);
     sink.finish_updated(s, g, n_cap, views, n_views, geo, &keep2[0][threadIdx.x]);
 }
 
