@@ -117,6 +117,37 @@ def _p(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _typed(t, dtype, what, ndim=None, rows=None):
+    """Device pointer of a contiguous tensor of the given dtype (and shape)."""
+    if t is None:
+        return None
+    if t.dtype != dtype:
+        raise GsError(f"{what}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise GsError(f"{what}: expected a contiguous tensor")
+    if ndim is not None and t.dim() != ndim:
+        raise GsError(f"{what}: expected {ndim} dimensions, got {t.dim()}")
+    if rows is not None and t.shape[0] != rows:
+        raise GsError(f"{what}: expected {rows} rows, got {t.shape[0]}")
+    return _p(t)
+
+
+def _store(t, what, like=None):
+    """A [59][n_cap] float32 parameter-layout tensor (params, grad, m, v)."""
+    ptr = _typed(t, torch.float32, what, 2, NUM_ROWS)
+    if like is not None and t is not None and t.shape != like.shape:
+        raise GsError(f"{what}: shape {tuple(t.shape)} differs from the parameters' {tuple(like.shape)}")
+    return ptr
+
+
+def _f32(t, what):
+    return _typed(t, torch.float32, what)
+
+
+def _i32(t, what):
+    return _typed(t, torch.int32, what)
+
+
 def _stream(stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     return C.c_void_p(s.cuda_stream)
@@ -182,7 +213,7 @@ def to_device_struct_array(arr, device="cuda") -> torch.Tensor:
 
 
 def gs_preprocess(settings, params, n, views_dev, n_views, proj_ws, stream=None):
-    _check(_lib.gs_preprocess(C.byref(settings), _p(params), n, params.shape[1], _p(views_dev),
+    _check(_lib.gs_preprocess(C.byref(settings), _store(params, "params"), n, params.shape[1], _p(views_dev),
                               n_views, _p(proj_ws), _stream(stream)), "gs_preprocess")
 
 
@@ -196,28 +227,32 @@ def gs_bin_sort(settings, proj_ws, n, n_cap, n_views, targets_dev, n_targets, to
 def gs_render_fwd(settings, proj_ws, n_cap, n_views, sort_ws, pair_cap, targets_dev, n_targets,
                   total_tiles, out_rgb, out_T, out_last, out_ncontrib=None, stream=None):
     _check(_lib.gs_render_fwd(C.byref(settings), _p(proj_ws), n_cap, n_views, _p(sort_ws), pair_cap,
-                              _p(targets_dev), n_targets, total_tiles, _p(out_rgb), _p(out_T),
-                              _p(out_last), _p(out_ncontrib), _stream(stream)), "gs_render_fwd")
+                              _p(targets_dev), n_targets, total_tiles, _f32(out_rgb, "out_rgb"),
+                              _f32(out_T, "out_T"), _i32(out_last, "out_last"),
+                              _i32(out_ncontrib, "out_ncontrib"), _stream(stream)), "gs_render_fwd")
 
 
 def gs_render_bwd(settings, params, n, views_dev, n_views, proj_ws, sort_ws, pair_cap, targets_dev,
                   n_targets, total_tiles, out_T, out_last, dL_drgb, accum_ws, grad, stream=None):
-    _check(_lib.gs_render_bwd(C.byref(settings), _p(params), n, params.shape[1], _p(views_dev),
+    _check(_lib.gs_render_bwd(C.byref(settings), _store(params, "params"), n, params.shape[1], _p(views_dev),
                               n_views, _p(proj_ws), _p(sort_ws), pair_cap, _p(targets_dev),
-                              n_targets, total_tiles, _p(out_T), _p(out_last), _p(dL_drgb),
-                              _p(accum_ws), _p(grad), _stream(stream)), "gs_render_bwd")
+                              n_targets, total_tiles, _f32(out_T, "out_T"), _i32(out_last, "out_last"),
+                              _f32(dL_drgb, "dL_drgb"), _p(accum_ws), _store(grad, "grad", params),
+                              _stream(stream)), "gs_render_bwd")
 
 
 def gs_raster_bwd(settings, proj_ws, n_cap, n_views, sort_ws, pair_cap, targets_dev, n_targets,
                   total_tiles, out_T, out_last, dL_drgb, accum_ws, stream=None):
     _check(_lib.gs_raster_bwd(C.byref(settings), _p(proj_ws), n_cap, n_views, _p(sort_ws), pair_cap,
-                              _p(targets_dev), n_targets, total_tiles, _p(out_T), _p(out_last),
-                              _p(dL_drgb), _p(accum_ws), _stream(stream)), "gs_raster_bwd")
+                              _p(targets_dev), n_targets, total_tiles, _f32(out_T, "out_T"),
+                              _i32(out_last, "out_last"), _f32(dL_drgb, "dL_drgb"), _p(accum_ws),
+                              _stream(stream)), "gs_raster_bwd")
 
 
 def gs_project_bwd(settings, params, n, views_dev, n_views, accum_ws, grad, stream=None):
-    _check(_lib.gs_project_bwd(C.byref(settings), _p(params), n, params.shape[1], _p(views_dev),
-                               n_views, _p(accum_ws), _p(grad), _stream(stream)), "gs_project_bwd")
+    _check(_lib.gs_project_bwd(C.byref(settings), _store(params, "params"), n, params.shape[1], _p(views_dev),
+                               n_views, _p(accum_ws), _store(grad, "grad", params), _stream(stream)),
+           "gs_project_bwd")
 
 
 def _step_args(step):
@@ -231,8 +266,9 @@ def gs_project_bwd_adam(settings, params, n, views_dev, n_views, accum_ws, m, v,
                         beta1=0.9, beta2=0.999, eps=1e-15, proj_out=None, stream=None):
     lr = (C.c_float * NUM_ROWS)(*[float(x) for x in lr_rows])
     st, dst = _step_args(step)
-    _check(_lib.gs_project_bwd_adam(C.byref(settings), _p(params), n, params.shape[1], _p(views_dev),
-                                    n_views, _p(accum_ws), _p(m), _p(v), lr, beta1, beta2, eps, st, dst,
+    _check(_lib.gs_project_bwd_adam(C.byref(settings), _store(params, "params"), n, params.shape[1],
+                                    _p(views_dev), n_views, _p(accum_ws), _store(m, "m", params),
+                                    _store(v, "v", params), lr, beta1, beta2, eps, st, dst,
                                     _p(proj_out), _stream(stream)), "gs_project_bwd_adam")
 
 
@@ -241,31 +277,36 @@ def gs_render_bwd_adam(settings, params, n, views_dev, n_views, proj_ws, sort_ws
                        lr_rows, step, beta1=0.9, beta2=0.999, eps=1e-15, proj_out=None, stream=None):
     lr = (C.c_float * NUM_ROWS)(*[float(x) for x in lr_rows])
     st, dst = _step_args(step)
-    _check(_lib.gs_render_bwd_adam(C.byref(settings), _p(params), n, params.shape[1], _p(views_dev),
-                                   n_views, _p(proj_ws), _p(sort_ws), pair_cap, _p(targets_dev),
-                                   n_targets, total_tiles, _p(out_T), _p(out_last), _p(dL_drgb),
-                                   _p(accum_ws), _p(m), _p(v), lr, beta1, beta2, eps, st, dst,
+    _check(_lib.gs_render_bwd_adam(C.byref(settings), _store(params, "params"), n, params.shape[1],
+                                   _p(views_dev), n_views, _p(proj_ws), _p(sort_ws), pair_cap,
+                                   _p(targets_dev), n_targets, total_tiles, _f32(out_T, "out_T"),
+                                   _i32(out_last, "out_last"), _f32(dL_drgb, "dL_drgb"), _p(accum_ws),
+                                   _store(m, "m", params), _store(v, "v", params), lr, beta1, beta2,
+                                   eps, st, dst,
                                    _p(proj_out), _stream(stream)), "gs_render_bwd_adam")
 
 
 def gs_pyramid_build(img, levels, out, stream=None):
     Cc, H, W = img.shape
-    _check(_lib.gs_pyramid_build(_p(img), Cc, H, W, levels, _p(out), _stream(stream)),
+    _check(_lib.gs_pyramid_build(_typed(img, torch.float32, "img", 3), Cc, H, W, levels, _f32(out, "out"),
+                                 _stream(stream)),
            "gs_pyramid_build")
 
 
 def gs_pyramid_loss(render, target, targets_dev, n_targets, total_tiles, total_pixels, lam, loss_ws,
                     d_loss, d_total, dL_drender, stream=None):
-    _check(_lib.gs_pyramid_loss(_p(render), _p(target), _p(targets_dev), n_targets, total_tiles,
-                                total_pixels, lam, _p(loss_ws), _p(d_loss), _p(d_total),
-                                _p(dL_drender), _stream(stream)), "gs_pyramid_loss")
+    _check(_lib.gs_pyramid_loss(_f32(render, "render"), _f32(target, "target"), _p(targets_dev), n_targets,
+                                total_tiles, total_pixels, lam, _p(loss_ws), _f32(d_loss, "d_loss"),
+                                _f32(d_total, "d_total"), _f32(dL_drender, "dL_drender"),
+                                _stream(stream)), "gs_pyramid_loss")
 
 
 def gs_adam_step(params, grad, m, v, n, lr_rows, step, beta1=0.9, beta2=0.999, eps=1e-15,
                  stream=None):
     lr = (C.c_float * NUM_ROWS)(*[float(x) for x in lr_rows])
     st, dst = _step_args(step)
-    _check(_lib.gs_adam_step(_p(params), _p(grad), _p(m), _p(v), n, params.shape[1], lr, beta1,
+    _check(_lib.gs_adam_step(_store(params, "params"), _store(grad, "grad", params), _store(m, "m", params),
+                             _store(v, "v", params), n, params.shape[1], lr, beta1,
                              beta2, eps, st, dst, _stream(stream)), "gs_adam_step")
 
 

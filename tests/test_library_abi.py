@@ -91,3 +91,24 @@ def test_invalid_arguments_rejected():
     bad = gs.default_settings(batch=100)
     assert lib.gs_render_fwd(C.byref(bad), C.c_void_p(1), 256, 1, C.c_void_p(1), 1024, C.c_void_p(1),
                              1, 16, C.c_void_p(1), C.c_void_p(1), C.c_void_p(1), None, None) == 1
+
+
+def test_binding_rejects_wrong_tensors():
+    """The Python layer checks dtype, layout and shape before any device call."""
+    import torch
+
+    from paper_2311_16728_amd import gs
+
+    s = gs.default_settings()
+    bad_dtype = torch.zeros(59, 64, dtype=torch.float64)
+    with pytest.raises(gs.GsError, match="float32"):
+        gs.gs_preprocess(s, bad_dtype, 1, None, 1, None)
+    bad_rows = torch.zeros(58, 64, dtype=torch.float32)
+    with pytest.raises(gs.GsError, match="59 rows"):
+        gs.gs_preprocess(s, bad_rows, 1, None, 1, None)
+    not_contig = torch.zeros(64, 59, dtype=torch.float32).t()
+    with pytest.raises(gs.GsError, match="contiguous"):
+        gs.gs_preprocess(s, not_contig, 1, None, 1, None)
+    on_host = torch.zeros(59, 64, dtype=torch.float32)
+    with pytest.raises(gs.GsError, match="device"):
+        gs.gs_preprocess(s, on_host, 1, None, 1, None)
