@@ -185,6 +185,9 @@ __global__ void __launch_bounds__(256) compact_reduce_kernel(const uint32_t *__r
     block_reduce_to(uint32_t(S), bsum, [&](int64_t e) { return counts[e] ? 1u : 0u; });
 }
 
+// Thread t of a block takes the kScanItems consecutive elements
+// [base + t * kScanItems, ...): one block scan of the per-thread totals places
+// them, in element order.
 __global__ void __launch_bounds__(256) compact_scatter_kernel(const uint32_t *__restrict__ counts,
                                                               int64_t S, Proj proj,
                                                               const uint32_t *__restrict__ bsum,
@@ -193,17 +196,23 @@ __global__ void __launch_bounds__(256) compact_scatter_kernel(const uint32_t *__
     __shared__ uint32_t lds[8];
     const int64_t base = int64_t(blockIdx.x) * kScanTile;
     if (base >= S) return;
-    uint32_t run = bsum[blockIdx.x];
+    const int64_t e0 = base + int64_t(threadIdx.x) * kScanItems;
+    uint32_t flags = 0, mine = 0;
+#pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        const int64_t e = base + k * kScanThreads + threadIdx.x;
-        const uint32_t f = (e < S && counts[e]) ? 1u : 0u;
-        uint32_t total;
-        const uint32_t pre = block_exclusive_scan(f, lds, &total);
-        if (f) {
-            vis_key[run + pre] = __float_as_uint(proj.rgb_z[e].w);
-            vis_val[run + pre] = uint32_t(e);
+        const int64_t e = e0 + k;
+        if (e < S && counts[e]) { flags |= 1u << k; ++mine; }
+    }
+    uint32_t total;
+    uint32_t at = bsum[blockIdx.x] + block_exclusive_scan(mine, lds, &total);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (flags & (1u << k)) {
+            const int64_t e = e0 + k;
+            vis_key[at] = __float_as_uint(proj.rgb_z[e].w);
+            vis_val[at] = uint32_t(e);
+            ++at;
         }
-        run += total;
     }
 }
 
@@ -226,21 +235,26 @@ __global__ void __launch_bounds__(256) offsets_scatter_kernel(const uint32_t *__
     const uint32_t n = *n_ptr;
     const int64_t base = int64_t(blockIdx.x) * kScanTile;
     if (base >= n) return;
-    uint32_t run = bsum[blockIdx.x];
+    const int64_t e0 = base + int64_t(threadIdx.x) * kScanItems;   // consecutive elements per thread
+    uint32_t c[kScanItems], mine = 0;
+#pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        const int64_t e = base + k * kScanThreads + threadIdx.x;
-        const uint32_t c = (e < n) ? counts[vis_val[e]] : 0u;
-        uint32_t total;
-        const uint32_t pre = block_exclusive_scan(c, lds, &total);
-        if (e < n) {
-            const uint32_t o = run + pre;
+        c[k] = (e0 + k < int64_t(n)) ? counts[vis_val[e0 + k]] : 0u;
+        mine += c[k];
+    }
+    uint32_t total;
+    uint32_t o = bsum[blockIdx.x] + block_exclusive_scan(mine, lds, &total);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t e = e0 + k;
+        if (e < int64_t(n)) {
             vis_off[e] = o;
             // this record holds the first slot of every chunk starting in [o, o + c)
-            const uint64_t end = uint64_t(o) + c;
+            const uint64_t end = uint64_t(o) + c[k];
             for (uint64_t q = (uint64_t(o) + 255) / 256; q * 256 < end && int64_t(q) < n_chunks; ++q)
                 chunk_first[q] = uint32_t(e);
         }
-        run += total;
+        o += c[k];
     }
 }
 
