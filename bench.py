@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--bwd-waves", type=int, default=None, help="backward waves per tile (skips autotuning)")
     ap.add_argument("--calibrate", action="store_true",
                     help="after timing, copy a 256 MiB buffer once (HBM counter calibration)")
-    ap.add_argument("--cpu-sample", type=float, default=0.3,
+    ap.add_argument("--cpu-sample", type=float, default=1.0,
                     help="fraction of pixels the oracle baseline renders and differentiates")
     ap.add_argument("--workload", choices=("single", "batched"), default="single",
                     help="single: one 1200x680 keyframe; batched: 32 mixed keyframes x 3 pyramid "
