@@ -168,10 +168,11 @@ def cpu_baseline(p, n, cams, target_np, frac, seed=0):
     sampled = t_setup * 3 + t_render + t_bwd + t_loss + t_adam
     return dict(value=1.0 / t_iter, unit="iters/s", cores=oracle.num_threads(), kind="oracle",
                 render_fps=1.0 / t_render_full,
-                sample=(f"FP64 oracle, one iteration at the same workload: render and backward on a "
-                        f"random {100 * f:.1f}% pixel sample scaled to the full image, loss and Adam "
-                        f"in full, projection/binning set-up {t_setup:.2f} s per call counted once; "
-                        f"{sampled:.1f} s of CPU work"))
+                sample=("FP64 oracle, one iteration at the same workload: render and backward "
+                        + ("over the whole image" if f >= 1.0 else
+                           f"on a random {100 * f:.1f}% pixel sample scaled to the full image")
+                        + f", loss and Adam in full, projection/binning set-up {t_setup:.2f} s per call "
+                          f"counted once; {sampled:.1f} s of CPU work"))
 
 
 def iteration_roofline(n, plan, composited, ms_step):
