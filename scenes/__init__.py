@@ -39,4 +39,5 @@ from .gen import (  # noqa: F401
     mixed_keyframes,
     ROOM_LO,
     ROOM_HI,
+    densify_case,
 )

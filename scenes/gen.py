@@ -174,3 +174,43 @@ def smooth_image(rng: np.random.Generator, height: int, width: int, channels: in
             acc += rng.uniform(0.02, 0.12) * np.cos(kx * xx + ky * yy + ph)
         img[c] = np.clip(acc, 0.0, 1.0)
     return img.astype(np.float32)
+
+
+def densify_case(seed: int, n: int, n_views: int = 2, extent: float = 10.0, n_cap: int | None = None):
+    """Inputs of the densification rule for a map of ``n`` Gaussians.
+
+    The laws straddle the rule's thresholds for a scene of the given extent:
+    log-scales ~ N(ln(0.01 extent), 1) per axis (so both clones and splits
+    occur, and a few primitives exceed 0.1 extent), opacity logits ~ N(-1, 2.5)
+    (a few percent below logit(0.005)), visit counts uniform on 0..8 and mean
+    gradient norms log-normal around 2e-4.  Also per-view 2D-gradient
+    accumulators ``[n_views, n_cap, 9]`` with about a third of the records
+    zero and a tenth carrying colour gradients only, the views' level-0 sizes,
+    Adam moments and the split noise ``[6, n_cap]``.  Returns a dict.
+    """
+    rng = np.random.default_rng(seed + 104729)
+    n_cap = pad_cap(n) if n_cap is None else n_cap
+    p = draw_gaussians(rng, n, ROOM_LO, ROOM_HI, n_cap)
+    p[3:6, :n] = rng.normal(math.log(0.01 * extent), 1.0, size=(3, n))
+    p[10, :n] = rng.normal(-1.0, 2.5, size=n)
+    m = np.zeros((NROWS, n_cap), np.float32)
+    v = np.zeros((NROWS, n_cap), np.float32)
+    m[:, :n] = rng.normal(0.0, 1e-3, size=(NROWS, n))
+    v[:, :n] = rng.uniform(0.0, 1e-6, size=(NROWS, n))
+    stats = np.zeros((2, n_cap), np.float32)
+    visits = rng.integers(0, 9, size=n).astype(np.float32)
+    mean = np.exp(rng.normal(math.log(2e-4), 0.7, size=n))
+    stats[0, :n] = (visits * mean).astype(np.float32)
+    stats[1, :n] = visits
+    noise = np.zeros((6, n_cap), np.float32)
+    noise[:, :n] = rng.normal(size=(6, n))
+    acc = np.zeros((n_views, n_cap, 9), np.float32)
+    vals = rng.normal(0.0, 1e-6, size=(n_views, n, 9))
+    kind = rng.uniform(size=(n_views, n))
+    vals[kind < 0.33] = 0.0
+    colour_only = (kind >= 0.33) & (kind < 0.43)
+    vals[..., :6][colour_only] = 0.0
+    acc[:, :n] = vals
+    sizes = [((1200, 680), (640, 480), (752, 480))[i % 3] for i in range(n_views)]
+    return dict(params=p, m=m, v=v, stats=stats, noise=noise, acc=acc, sizes=sizes, n=n, n_cap=n_cap,
+                extent=extent)
