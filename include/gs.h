@@ -330,6 +330,78 @@ gs_status gs_append(float *params, float *m, float *v, int64_t n, int64_t n_cap,
  * captured graph replays it faithfully). */
 gs_status gs_fill(float *dst, int64_t count, float value, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Gradient-driven densification (Section 3.3.1: split or clone primitives
+ * with large loss gradients, as in 3D Gaussian splatting, Kerbl et al. 2023,
+ * Sec. 5.2), plus the pruning and the opacity reset of the same rule.
+ * ------------------------------------------------------------------------- */
+
+/* Thresholds of the rule, in the float32 form the kernels compare against. */
+typedef struct {
+    float grad_threshold; /* mean NDC gradient norm at or above which a primitive is densified */
+    float log_dense;      /* clone if the largest log-scale is <= this, else split */
+    float log_big;        /* prune if the largest log-scale is > this (+inf: never) */
+    float logit_min;      /* prune if the opacity logit is < this */
+    float log_shrink;     /* subtracted from the log-scales of a split's children */
+} gs_densify_rule;
+
+/* (host) Rule for a scene of the given extent (e.g. the radius of the
+ * keyframe centres): grad_threshold; log_dense = ln(percent_dense * extent);
+ * log_big = ln(big_fraction * extent), or +inf when big_fraction <= 0;
+ * logit_min = ln(min_opacity / (1 - min_opacity)); log_shrink = ln(shrink);
+ * each computed in double and rounded to float.  The usual values are
+ * 2e-4, 0.01, 0.005, 0.1 and 1.6.  Invalid arguments (extent, percent_dense
+ * or shrink <= 0, min_opacity outside (0, 1)) return GS_ERR_INVALID_ARGUMENT. */
+gs_status gs_densify_rule_make(double extent, double grad_threshold, double percent_dense,
+                               double min_opacity, double big_fraction, double shrink,
+                               gs_densify_rule *out);
+
+/* Adds one backward pass to the densification statistic stats (device float
+ * [2][n_cap]): for every view v and primitive g < n whose accumulator record
+ * in accum_ws (as left by gs_raster_bwd; [n_views * n_cap][9]) holds any
+ * nonzero value, row 0 gains the norm of its 2D-mean gradient in normalised
+ * device coordinates, |(dx * W_v / 2, dy * H_v / 2)| with W_v, H_v the view's
+ * level-0 size, and row 1 gains 1.  views: device gs_view[n_views]. */
+gs_status gs_densify_stats(const void *accum_ws, int64_t n, int64_t n_cap, const gs_view *views,
+                           int32_t n_views, float *stats, void *stream);
+
+/* Bytes of device workspace gs_densify needs for n primitives. */
+size_t gs_densify_workspace_bytes(int64_t n);
+
+/* Applies the rule to primitives 0..n-1 of params, m, v (device [59][n_cap])
+ * with the statistic stats (device [2][n_cap]; mean = row 0 / row 1, 0 where
+ * row 1 is 0) and writes the result to out_params, out_m, out_v (device
+ * [59][out_cap], not overlapping the inputs):
+ *   - densified (mean >= grad_threshold) and largest log-scale <= log_dense:
+ *     cloned (the original and an identical copy);
+ *   - densified and larger: split into two children with the parent's
+ *     values except mean + Rq (exp(log-scale) * z_c) and log-scale -
+ *     log_shrink (Rq the rotation of the normalised quaternion, z_0 = noise
+ *     rows 0-2, z_1 = rows 3-5 of the parent's column; noise: device float
+ *     [6][n_cap] standard normals); the parent is dropped;
+ *   - any primitive, original or new, with opacity logit < logit_min or
+ *     largest log-scale > log_big is dropped.
+ * Output order: the surviving originals in order, then for each original in
+ * order its surviving copy or children.  Survivors keep their moments, new
+ * primitives get zero moments.  d_counts (device int64[4]) receives the
+ * output count, the copies made, the primitives split and the originals
+ * pruned.  If the output count exceeds out_cap nothing is written to the
+ * outputs (d_counts[0] still tells the count required).  ws: device,
+ * gs_densify_workspace_bytes(n).  The statistic is not cleared (the caller
+ * restarts it for the new layout).  Columns >= the output count are not
+ * written. */
+gs_status gs_densify(const gs_densify_rule *rule, const float *params, const float *m,
+                     const float *v, const float *stats, const float *noise, int64_t n,
+                     int64_t n_cap, float *out_params, float *out_m, float *out_v,
+                     int64_t out_cap, void *ws, int64_t *d_counts, void *stream);
+
+/* Opacity reset of the same rule: the opacity logit of every primitive < n is
+ * lowered to ln(max_opacity / (1 - max_opacity)) (computed in double, rounded
+ * to float) where it is above, and the opacity row of m and v (optional) is
+ * zeroed. */
+gs_status gs_reset_opacity(float *params, float *m, float *v, int64_t n, int64_t n_cap,
+                           double max_opacity, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

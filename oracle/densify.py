@@ -93,31 +93,57 @@ def quat_rotation(q) -> np.ndarray:
 
 def decide(P, stats, n: int, rule: dict):
     """Per original: its action (KEEP / CLONE / SPLIT), whether the original
-    survives, and how many new primitives it contributes, decided in float32."""
-    P32 = np.asarray(P, F32)
-    s = np.asarray(stats, F32)
-    action = np.zeros(n, np.int32)
-    keep = np.zeros(n, bool)
-    new = np.zeros(n, np.int32)
-    for g in range(n):
-        visits = s[1, g]
-        avg = s[0, g] / visits if visits > F32(0) else F32(0)
-        maxls = max(P32[3, g], P32[4, g], P32[5, g])
-        logit = P32[10, g]
-        faint = logit < rule["logit_min"]
-        prune = faint or maxls > rule["log_big"]
-        if avg >= rule["grad_threshold"]:
-            if maxls <= rule["log_dense"]:
-                action[g] = CLONE
-                keep[g] = not prune
-                new[g] = 0 if prune else 1
-            else:
-                action[g] = SPLIT
-                child_big = F32(maxls - rule["log_shrink"]) > rule["log_big"]
-                new[g] = 0 if (faint or child_big) else 2
-        else:
-            keep[g] = not prune
-    return action, keep, new
+    survives, and how many new primitives it contributes.  Elementwise
+    float32 arithmetic and comparisons (IEEE, as on the device)."""
+    P32 = np.asarray(P, F32)[:, :n]
+    s = np.asarray(stats, F32)[:, :n]
+    visits = s[1]
+    avg = np.zeros(n, F32)
+    seen = visits > F32(0)
+    avg[seen] = s[0][seen] / visits[seen]
+    maxls = np.maximum(np.maximum(P32[3], P32[4]), P32[5])
+    faint = P32[10] < rule["logit_min"]
+    prune = faint | (maxls > rule["log_big"])
+    hot = avg >= rule["grad_threshold"]
+    clone = hot & (maxls <= rule["log_dense"])
+    split = hot & ~clone
+    child_big = (maxls - rule["log_shrink"]).astype(F32) > rule["log_big"]
+    action = np.where(clone, CLONE, np.where(split, SPLIT, KEEP)).astype(np.int32)
+    keep = ~split & ~prune
+    new = np.where(clone & ~prune, 1, 0) + np.where(split & ~(faint | child_big), 2, 0)
+    return action, keep, new.astype(np.int32)
+
+
+# kind of an output column
+SURVIVOR, COPY, CHILD0, CHILD1 = 0, 1, 2, 3
+
+
+def layout(action, keep, new):
+    """Source original and kind of every output column: the surviving
+    originals in order, then each original's copy or two children."""
+    n = len(new)
+    kept = np.nonzero(keep)[0]
+    src_new = np.repeat(np.arange(n), new)
+    first = np.ones(len(src_new), bool)
+    first[1:] = src_new[1:] != src_new[:-1]
+    kind_new = np.where(action[src_new] == CLONE, COPY, np.where(first, CHILD0, CHILD1))
+    src = np.concatenate([kept, src_new]).astype(np.int64)
+    kind = np.concatenate([np.full(len(kept), SURVIVOR), kind_new]).astype(np.int32)
+    return src, kind
+
+
+def column(P, m, v, noise, g: int, kind: int, rule: dict):
+    """One output column (parameters, m, v) in FP64."""
+    p = np.asarray(P[:, g], np.float64).copy()
+    if kind == SURVIVOR:
+        return p, np.asarray(m[:, g], np.float64), np.asarray(v[:, g], np.float64)
+    if kind in (CHILD0, CHILD1):
+        c = kind - CHILD0
+        R = quat_rotation(p[6:10])
+        z = np.asarray(noise[3 * c:3 * c + 3, g], np.float64)
+        p[0:3] = p[0:3] + R @ (np.exp(p[3:6]) * z)
+        p[3:6] = p[3:6] - math.log(rule["shrink"])
+    return p, np.zeros(NROWS), np.zeros(NROWS)
 
 
 def densify(P, m, v, stats, n: int, noise, rule: dict):
@@ -125,33 +151,17 @@ def densify(P, m, v, stats, n: int, noise, rule: dict):
     ``[6, >=n]`` standard normals (child 0 rows 0-2, child 1 rows 3-5).
     Returns (P_out, m_out, v_out) ``[59, n_out]`` float64 and the counts
     (n_out, cloned, split, pruned originals)."""
-    P = np.asarray(P, np.float64)
     action, keep, new = decide(P, stats, n, rule)
-    kept = np.nonzero(keep)[0]
-    cols, mcols, vcols = [P[:, kept]], [np.asarray(m, np.float64)[:, kept]], \
-        [np.asarray(v, np.float64)[:, kept]]
-    for g in range(n):
-        if new[g] == 0:
-            continue
-        if action[g] == CLONE:
-            cols.append(P[:, g:g + 1].copy())
-        else:
-            R = quat_rotation(P[6:10, g])
-            s = np.exp(P[3:6, g])
-            for c in range(2):
-                z = np.asarray(noise[3 * c:3 * c + 3, g], np.float64)
-                child = P[:, g].copy()
-                child[0:3] = P[0:3, g] + R @ (s * z)
-                child[3:6] = P[3:6, g] - math.log(rule["shrink"])
-                cols.append(child[:, None])
-        zeros = np.zeros((NROWS, int(new[g])))
-        mcols.append(zeros)
-        vcols.append(zeros)
-    P_out = np.concatenate(cols, axis=1)
-    counts = dict(n_out=P_out.shape[1], cloned=int(np.sum((action == CLONE) & (new > 0))),
+    src, kind = layout(action, keep, new)
+    P_out = np.zeros((NROWS, len(src)))
+    m_out = np.zeros((NROWS, len(src)))
+    v_out = np.zeros((NROWS, len(src)))
+    for j in range(len(src)):
+        P_out[:, j], m_out[:, j], v_out[:, j] = column(P, m, v, noise, int(src[j]), int(kind[j]), rule)
+    counts = dict(n_out=len(src), cloned=int(np.sum((action == CLONE) & (new > 0))),
                   split=int(np.sum(action == SPLIT)),
                   pruned=int(np.sum((action != SPLIT) & ~keep)))
-    return P_out, np.concatenate(mcols, axis=1), np.concatenate(vcols, axis=1), counts
+    return P_out, m_out, v_out, counts
 
 
 def reset_opacity(P, m, v, n: int, max_opacity: float = 0.01):

@@ -43,6 +43,11 @@ class gs_target(C.Structure):
                 ("bg", C.c_float * 3), ("weight", C.c_float)]
 
 
+class gs_densify_rule(C.Structure):
+    _fields_ = [("grad_threshold", C.c_float), ("log_dense", C.c_float), ("log_big", C.c_float),
+                ("logit_min", C.c_float), ("log_shrink", C.c_float)]
+
+
 class gs_sizes(C.Structure):
     _fields_ = [("proj_bytes", C.c_size_t), ("sort_bytes", C.c_size_t),
                 ("accum_bytes", C.c_size_t), ("loss_bytes", C.c_size_t)]
@@ -86,6 +91,12 @@ def _load():
         "gs_init_decode": ([vp, vp, V, i32, vp, vp, vp, vp], C.c_int),
         "gs_append": ([vp, vp, vp, i64, i64, vp, i32, vp], C.c_int),
         "gs_fill": ([vp, i64, f32, vp], C.c_int),
+        "gs_densify_rule_make": ([C.c_double] * 6 + [C.POINTER(gs_densify_rule)], C.c_int),
+        "gs_densify_stats": ([vp, i64, i64, vp, i32, vp, vp], C.c_int),
+        "gs_densify_workspace_bytes": ([i64], C.c_size_t),
+        "gs_densify": ([C.POINTER(gs_densify_rule), vp, vp, vp, vp, vp, i64, i64, vp, vp, vp, i64, vp,
+                        vp, vp], C.c_int),
+        "gs_reset_opacity": ([vp, vp, vp, i64, i64, C.c_double, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -101,7 +112,8 @@ EXPORTED = ["gs_status_string", "gs_default_settings", "gs_targets_layout", "gs_
             "gs_pyramid_build",
             "gs_pyramid_loss", "gs_adam_step", "gs_step_advance", "gs_fill", "gs_init_features",
             "gs_init_mlp_fwd", "gs_init_mlp_bwd", "gs_init_mlp_adam", "gs_to_bf16", "gs_init_heuristic",
-            "gs_init_decode", "gs_append"]
+            "gs_init_decode", "gs_append", "gs_densify_rule_make", "gs_densify_stats",
+            "gs_densify_workspace_bytes", "gs_densify", "gs_reset_opacity"]
 
 
 def _check(status: int, what: str):
@@ -359,3 +371,40 @@ def gs_init_decode(y, kp, view, heuristic, out, used_fallback=None, stream=None)
 def gs_append(params, m, v, n, new_params, stream=None):
     _check(_lib.gs_append(_p(params), _p(m), _p(v), n, params.shape[1], _p(new_params),
                           new_params.shape[1], _stream(stream)), "gs_append")
+
+
+def densify_rule(extent, grad_threshold=2e-4, percent_dense=0.01, min_opacity=0.005, big_fraction=0.1,
+                 shrink=1.6) -> gs_densify_rule:
+    """Thresholds of the densification rule (big_fraction None: no size pruning)."""
+    r = gs_densify_rule()
+    _check(_lib.gs_densify_rule_make(float(extent), float(grad_threshold), float(percent_dense),
+                                     float(min_opacity), 0.0 if big_fraction is None else float(big_fraction),
+                                     float(shrink), C.byref(r)), "gs_densify_rule_make")
+    return r
+
+
+def gs_densify_stats(accum_ws, n, n_cap, views_dev, n_views, stats, stream=None):
+    _check(_lib.gs_densify_stats(_p(accum_ws), n, n_cap, _p(views_dev), n_views,
+                                 _typed(stats, torch.float32, "stats", 2, 2), _stream(stream)),
+           "gs_densify_stats")
+
+
+def gs_densify_workspace_bytes(n) -> int:
+    return int(_lib.gs_densify_workspace_bytes(n))
+
+
+def gs_densify(rule, params, m, v, stats, noise, n, out_params, out_m, out_v, ws, d_counts, stream=None):
+    if stats.shape[1] != params.shape[1] or noise.shape[1] != params.shape[1]:
+        raise GsError("stats and noise need the parameters' column capacity")
+    _check(_lib.gs_densify(C.byref(rule), _store(params, "params"), _store(m, "m", params),
+                           _store(v, "v", params), _typed(stats, torch.float32, "stats", 2, 2),
+                           _typed(noise, torch.float32, "noise", 2, 6), n, params.shape[1],
+                           _store(out_params, "out_params"), _store(out_m, "out_m", out_params),
+                           _store(out_v, "out_v", out_params), out_params.shape[1], _p(ws),
+                           _typed(d_counts, torch.int64, "d_counts"), _stream(stream)), "gs_densify")
+
+
+def gs_reset_opacity(params, m, v, n, max_opacity=0.01, stream=None):
+    _check(_lib.gs_reset_opacity(_store(params, "params"), _store(m, "m", params), _store(v, "v", params),
+                                 n, params.shape[1], float(max_opacity), _stream(stream)),
+           "gs_reset_opacity")

@@ -1,0 +1,234 @@
+"""GPU parity of the densification calls (gs_densify_stats, gs_densify,
+gs_reset_opacity) against the FP64 oracle on seeded inputs.
+
+Bars: the decisions, counts and every copied value (survivors, copies, the
+rows a child shares with its parent, the moments) are bit-exact; a child's
+log-scale is within 1e-6 and its centre within 1e-5 (float32 rotation of the
+scaled noise); the statistic within a relative 1e-5 of the FP64 sum (2e-3
+when it is fed by a full backward pass, whose own bar is 1e-3).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import scenes
+from oracle import densify as od
+from tests.gpu_util import plan_for, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+SENTINEL = -7.25
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a)).cuda()
+
+
+def _run(c, n=None, out_cap=None, **rule_kw):
+    from paper_2311_16728_amd import gs
+
+    n = c["n"] if n is None else n
+    n_cap = c["n_cap"]
+    out_cap = out_cap if out_cap is not None else 2 * n_cap
+    rule = gs.densify_rule(c["extent"], **rule_kw)
+    P, M, V = _dev(c["params"]), _dev(c["m"]), _dev(c["v"])
+    S, Z = _dev(c["stats"]), _dev(c["noise"])
+    outs = [torch.full((59, out_cap), SENTINEL, dtype=torch.float32, device="cuda") for _ in range(3)]
+    ws = torch.empty(gs.gs_densify_workspace_bytes(n), dtype=torch.uint8, device="cuda")
+    counts = torch.zeros(4, dtype=torch.int64, device="cuda")
+    gs.gs_densify(rule, P, M, V, S, Z, n, *outs, ws, counts)
+    torch.cuda.synchronize()
+    # inputs are read only
+    assert torch.equal(P.cpu(), torch.as_tensor(c["params"]))
+    return [o.cpu().numpy() for o in outs], counts.cpu().numpy()
+
+
+def _expect_counts(c, n, **rule_kw):
+    rule = od.densify_rule(c["extent"], **rule_kw)
+    action, keep, new = od.decide(c["params"], c["stats"], n, rule)
+    return rule, action, keep, new, [int(keep.sum() + new.sum()),
+                                     int(np.sum((action == od.CLONE) & (new > 0))),
+                                     int(np.sum(action == od.SPLIT)),
+                                     int(np.sum((action != od.SPLIT) & ~keep))]
+
+
+def _check_columns(c, outs, rule, action, keep, new, cols=None):
+    src, kind = od.layout(action, keep, new)
+    n_out = len(src)
+    cols = range(n_out) if cols is None else cols
+    oP, oM, oV = outs
+    for j in cols:
+        p, m, v = od.column(c["params"], c["m"], c["v"], c["noise"], int(src[j]), int(kind[j]), rule)
+        k = kind[j]
+        if k in (od.SURVIVOR, od.COPY):
+            assert np.array_equal(oP[:, j], p.astype(np.float32)), (j, k)
+        else:
+            assert np.array_equal(oP[6:, j], p[6:].astype(np.float32)), (j, k)
+            assert np.abs(oP[3:6, j] - p[3:6]).max() <= 1e-6, (j, k)
+            assert np.abs(oP[0:3, j] - p[0:3]).max() <= 1e-5, (j, k)
+        assert np.array_equal(oM[:, j], m.astype(np.float32)) and np.array_equal(oV[:, j], v.astype(np.float32))
+
+
+@pytest.mark.parametrize("seed,n", [(0, 5000), (1, 1), (2, 1024), (3, 3001)])
+def test_densify_matches_oracle(seed, n):
+    c = scenes.densify_case(seed, n)
+    outs, counts = _run(c)
+    rule, action, keep, new, expect = _expect_counts(c, n)
+    assert list(counts) == expect
+    _check_columns(c, outs, rule, action, keep, new)
+    # columns past the output count are not written
+    n_out = expect[0]
+    for o in outs:
+        assert np.all(o[:, n_out:] == SENTINEL)
+
+
+def test_densify_rule_variants():
+    c = scenes.densify_case(4, 4000)
+    for kw in [dict(big_fraction=None), dict(grad_threshold=1e9), dict(grad_threshold=0.0, min_opacity=0.5),
+               dict(percent_dense=10.0)]:
+        outs, counts = _run(c, **kw)
+        rule, action, keep, new, expect = _expect_counts(c, c["n"], **kw)
+        assert list(counts) == expect, kw
+        _check_columns(c, outs, rule, action, keep, new)
+
+
+def test_densify_empty_and_capacity():
+    c = scenes.densify_case(5, 3000)
+    outs, counts = _run(c, n=0)
+    assert list(counts) == [0, 0, 0, 0]
+    assert all(np.all(o == SENTINEL) for o in outs)
+    _, _, _, _, expect = _expect_counts(c, 3000)
+    need = expect[0]
+    cap_small = (need - 1) // 64 * 64          # one column short, rounded to the alignment
+    outs, counts = _run(c, out_cap=cap_small)
+    assert list(counts) == expect and counts[0] > cap_small
+    assert all(np.all(o == SENTINEL) for o in outs)   # nothing written
+    exact = (need + 63) // 64 * 64
+    outs, counts = _run(c, out_cap=exact)
+    assert list(counts) == expect
+
+
+def test_densify_full_size_sampled():
+    """One million primitives (the mapping workload's map size), checked on
+    all counts and on 3000 sampled output columns."""
+    c = scenes.densify_case(6, 1_000_000, grad_median=8e-5)
+    outs, counts = _run(c, out_cap=c["n_cap"] + 262144)
+    rule, action, keep, new, expect = _expect_counts(c, c["n"])
+    assert list(counts) == expect
+    rng = np.random.default_rng(0)
+    cols = np.unique(np.r_[rng.integers(0, expect[0], 3000), 0, expect[0] - 1,
+                           int(keep.sum()) - 1, int(keep.sum())])
+    _check_columns(c, outs, rule, action, keep, new, cols)
+
+
+def test_stats_matches_oracle():
+    from paper_2311_16728_amd import gs
+
+    c = scenes.densify_case(7, 2500, n_views=3)
+    n, n_cap = c["n"], c["n_cap"]
+    cams = [scenes.pinhole(w, h, 300.0) for (w, h) in c["sizes"]]
+    views = gs.to_device_struct_array((gs.gs_view * 3)(*[gs.make_view(cm) for cm in cams]))
+    acc = _dev(c["acc"].reshape(-1))
+    st0 = np.zeros((2, n_cap), np.float32)
+    r0 = np.random.default_rng(1)
+    st0[0, :n] = np.abs(r0.normal(size=n)) * 1e-3
+    st0[1, :n] = r0.integers(0, 6, size=n)        # visit counts are whole numbers
+    S = _dev(st0)
+    gs.gs_densify_stats(acc, n, n_cap, views, 3, S)
+    gs.gs_densify_stats(acc, n, n_cap, views, 3, S)
+    torch.cuda.synchronize()
+    got = S.cpu().numpy()
+    once = od.densify_stats(c["acc"][:, :n], c["sizes"])
+    ref = st0[:, :n].astype(np.float64) + 2 * once
+    np.testing.assert_allclose(got[:, :n], ref, rtol=1e-5, atol=0)
+    assert np.array_equal(got[1, :n], ref[1])
+    assert np.all(got[:, n:] == 0)
+
+
+def test_stats_after_backward(orc):
+    """The statistic fed by a full backward pass equals the oracle's, built
+    from its own FP64 2D gradients (pixels with FP32-ambiguous compositing
+    decisions carry no loss gradient on either side)."""
+    from paper_2311_16728_amd import gs
+    from paper_2311_16728_amd.densify import Densifier
+    from paper_2311_16728_amd.mapper import Mapper
+
+    p, _, cam = scenes.tiny_scene(0)
+    n = 2000
+    plan = plan_for([cam], n_cap=p.shape[1])
+    P = _dev(p)
+    plan.render(P, n, with_ncontrib=True)
+    o = orc.render(p, n, cam)
+    rng = np.random.default_rng(12)
+    Wt = rng.uniform(-1, 1, (3, cam["height"], cam["width"])).astype(np.float32)
+    Wt[:, o["amb"] != 0] = 0.0
+    grad = torch.zeros_like(P)
+    plan.backward(P, n, _dev(Wt).reshape(-1).contiguous(), grad)
+    mp = Mapper(P, n)
+    d = Densifier(mp, extent=3.0)
+    d.accumulate(plan)
+    torch.cuda.synchronize()
+    got = d.stats.cpu().numpy()[:, :n].astype(np.float64)
+    _, g2 = orc.render_backward(p, n, cam, Wt, with_2d=True)
+    ref = od.densify_stats(g2[None], [(cam["width"], cam["height"])])
+    assert np.array_equal(got[1], ref[1])
+    scale = ref[0].max()
+    assert np.abs(got[0] - ref[0]).max() <= 2e-3 * scale
+    big = ref[0] > 1e-2 * scale
+    assert big.sum() > 200
+    assert (np.abs(got[0] - ref[0])[big] / ref[0][big]).max() <= 2e-3
+
+
+def test_reset_opacity():
+    from paper_2311_16728_amd import gs
+
+    c = scenes.densify_case(8, 3000)
+    n = c["n"]
+    P, M, V = _dev(c["params"]), _dev(c["m"]), _dev(c["v"])
+    gs.gs_reset_opacity(P, M, V, n, 0.01)
+    torch.cuda.synchronize()
+    rp, rm, rv = od.reset_opacity(c["params"], c["m"], c["v"], n, 0.01)
+    assert np.array_equal(P.cpu().numpy(), rp.astype(np.float32))
+    assert np.array_equal(M.cpu().numpy(), rm.astype(np.float32))
+    assert np.array_equal(V.cpu().numpy(), rv.astype(np.float32))
+
+
+def test_densification_grows_the_map_and_lowers_the_loss():
+    """A coarse map of a finer scene: mapping with densification every 100
+    iterations ends with more primitives and a lower loss than without."""
+    from paper_2311_16728_amd.densify import Densifier
+    from paper_2311_16728_amd.mapper import Mapper, RenderPlan, mapping_lr_rows
+
+    rng = np.random.default_rng(21)
+    fine = scenes.draw_gaussians(rng, 40000, (-1, -1, 2), (1, 1, 4))
+    cams = [scenes.pinhole(256, 192, 220.0, R=np.eye(3), t=[0.3 * (i - 1.5), 0.1 * (i % 2), 0.0])
+            for i in range(4)]
+    specs = [(v, 0, (0, 0, 0), 1.0) for v in range(4)]
+    gt_plan = RenderPlan(cams, specs, fine.shape[1], 1 << 22)
+    gt_plan.render(_dev(fine), 40000)
+    gt = gt_plan.rgb.clone()
+    coarse = scenes.draw_gaussians(np.random.default_rng(22), 3000, (-1, -1, 2), (1, 1, 4), n_cap=131072)
+    coarse[10, :3000] = 0.0
+    results = {}
+    for densify in (False, True):
+        plan = RenderPlan(cams, specs, 131072, 1 << 22)
+        mp = Mapper(_dev(coarse), 3000, lr_rows=mapping_lr_rows(2.0))
+        d = Densifier(mp, extent=2.0) if densify else None
+        for it in range(1, 601):
+            mp.step(plan, gt)
+            if d is not None:
+                d.accumulate(plan)
+                if it % 100 == 0 and it <= 400:
+                    d.densify()
+        torch.cuda.synchronize()
+        assert not plan.overflowed()
+        results[densify] = (mp.n, float(plan.d_total[0]))
+    print("without / with densification (n, loss):", results)
+    assert results[True][0] > 1.5 * results[False][0]
+    assert results[True][1] < 0.9 * results[False][1]

@@ -91,6 +91,17 @@ def test_invalid_arguments_rejected():
     bad = gs.default_settings(batch=100)
     assert lib.gs_render_fwd(C.byref(bad), C.c_void_p(1), 256, 1, C.c_void_p(1), 1024, C.c_void_p(1),
                              1, 16, C.c_void_p(1), C.c_void_p(1), C.c_void_p(1), None, None) == 1
+    rule = gs.densify_rule(5.0)
+    one = C.c_void_p(16)
+    assert lib.gs_densify(C.byref(rule), None, one, one, one, one, 10, 256, one, one, one, 256, one, one,
+                          None) == 1
+    assert lib.gs_densify(C.byref(rule), one, one, one, one, one, 10, 100, one, one, one, 256, one, one,
+                          None) == 1                                # n_cap not a multiple of 64
+    assert lib.gs_densify(C.byref(rule), C.c_void_p(4), one, one, one, one, 10, 256, one, one, one, 256,
+                          one, one, None) == 1                      # rows need 16-byte alignment
+    assert lib.gs_densify_stats(None, 10, 256, one, 1, one, None) == 1
+    assert lib.gs_reset_opacity(one, None, None, 10, 256, 1.5, None) == 1
+    assert gs.gs_densify_workspace_bytes(1 << 20) >= 16 * (1 << 10)
 
 
 def test_binding_rejects_wrong_tensors():
