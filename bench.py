@@ -50,9 +50,10 @@ def parse():
                     help="after timing, copy a 256 MiB buffer once (HBM counter calibration)")
     ap.add_argument("--cpu-sample", type=float, default=1.0,
                     help="fraction of pixels the oracle baseline renders and differentiates")
-    ap.add_argument("--workload", choices=("single", "batched"), default="single",
+    ap.add_argument("--workload", choices=("single", "batched", "densify"), default="single",
                     help="single: one 1200x680 keyframe; batched: 32 mixed keyframes x 3 pyramid "
-                         "levels in one graph-captured iteration")
+                         "levels in one graph-captured iteration; densify: one split / clone / "
+                         "prune pass over a 1M-primitive map")
     ap.add_argument("--psnr-compare", type=int, default=0, metavar="ROUNDS",
                     help="batched workload: also compare with the per-frame mapper at equal final "
                          "PSNR after ROUNDS visits of every keyframe")
@@ -109,18 +110,19 @@ STAGES = ["bin_sort", "render_fwd", "loss", "raster_bwd", "project_bwd_adam"]
 
 
 KERNEL_SOURCES = {"project_bwd_adam": "paper_2311_16728_amd/csrc/gs_project.hip",
+                  "densify": "paper_2311_16728_amd/csrc/gs_densify.hip",
                   "raster_bwd": "paper_2311_16728_amd/csrc/gs_raster.hip",
                   "render_fwd": "paper_2311_16728_amd/csrc/gs_raster.hip"}
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, workload="1M_1200x680"):
     """HBM bytes per launch of `kernel` from the committed counter summary
-    (profiles/traffic_<kernel>_1M_1200x680.json: FETCH_SIZE and WRITE_SIZE per
+    (profiles/traffic_<kernel>_<workload>.json: FETCH_SIZE and WRITE_SIZE per
     dispatch, scaled by the same counters' reading of a plain copy of known
     size), or None when there is none or the kernel source has changed since."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_1M_1200x680.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     src = KERNEL_SOURCES.get(kernel)
     if not os.path.exists(path) or src is None:
         return None
@@ -378,6 +380,105 @@ def main_batched(args, torch):
     return 0
 
 
+def calibration_copy(torch):
+    """A plain device copy of known size (reads and writes 256 MiB), the
+    reference the HBM byte counters are scaled by."""
+    src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def densify_cpu_baseline(c, rule_kw, n_sample):
+    """The oracle's densification of the first n_sample primitives (decision,
+    layout and every output column), scaled to primitives per second."""
+    from oracle import densify as od
+
+    P, m, v = c["params"][:, :n_sample], c["m"][:, :n_sample], c["v"][:, :n_sample]
+    st, z = c["stats"][:, :n_sample], c["noise"][:, :n_sample]
+    t0 = time.perf_counter()
+    _, _, _, counts = od.densify(P, m, v, st, n_sample, z, od.densify_rule(c["extent"], **rule_kw))
+    t = time.perf_counter() - t0
+    return dict(value=round(n_sample / t, 1), unit="primitives/s", cores=1, kind="oracle",
+                sample=(f"FP64 oracle (numpy) densifying the first {n_sample} primitives of the same map"
+                        if n_sample < c["n"] else "FP64 oracle (numpy) densifying the whole map")
+                + f" ({counts['n_out']} outputs), {t:.1f} s of CPU work")
+
+
+def main_densify(args, torch):
+    """One densification pass (split / clone / prune with compaction into new
+    buffers) over a 1M-primitive map with a synthetic gradient statistic;
+    inputs resident in HBM, out-of-place so every pass sees the same input."""
+    import scenes
+    from paper_2311_16728_amd import gs
+
+    n = args.n
+    c = scenes.densify_case(args.seed, n, n_views=1, grad_median=8e-5)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()
+    P, M, V, S, Z = (dev(c[k]) for k in ("params", "m", "v", "stats", "noise"))
+    out_cap = c["n_cap"] + (c["n_cap"] // 4 + 63) // 64 * 64
+    outs = [torch.empty(59, out_cap, dtype=torch.float32, device="cuda") for _ in range(3)]
+    ws = torch.empty(gs.gs_densify_workspace_bytes(n), dtype=torch.uint8, device="cuda")
+    counts = torch.zeros(4, dtype=torch.int64, device="cuda")
+    rule = gs.densify_rule(c["extent"])
+    for _ in range(max(1, args.warmup)):
+        gs.gs_densify(rule, P, M, V, S, Z, n, *outs, ws, counts)
+    torch.cuda.synchronize()
+    n_out, cloned, split, pruned = (int(x) for x in counts.cpu())
+    if n_out > out_cap:
+        raise SystemExit("output capacity too small")
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    for a, b in evs:
+        a.record()
+        gs.gs_densify(rule, P, M, V, S, Z, n, *outs, ws, counts)
+        b.record()
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    print(f"# densify passes done: {args.steps}", file=sys.stderr, flush=True)
+    # the statistic's cost per mapping iteration: one 1200x680 view's accumulators
+    acc = dev(c["acc"].reshape(-1))
+    cam = scenes.pinhole(1200, 680, 600.0)
+    views = gs.to_device_struct_array((gs.gs_view * 1)(gs.make_view(cam)))
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s0.record()
+    for _ in range(args.steps):
+        gs.gs_densify_stats(acc, n, c["n_cap"], views, 1, S)
+    s1.record()
+    torch.cuda.synchronize()
+    stats_ms = s0.elapsed_time(s1) / args.steps
+    if args.calibrate:
+        calibration_copy(torch)
+    # algorithmic bytes: every input column once (59 rows of parameters, m and
+    # v, plus the 2 statistic rows: 716 B), the noise of each split (24 B) and
+    # every output column once (708 B)
+    algo = 716.0 * n + 24.0 * split + 708.0 * n_out
+    achieved = algo / (ms * 1e-3) / 1e9
+    out = {
+        "metric": "densification pass (split/clone/prune + compaction), 1M primitives",
+        "value": round(n / (ms * 1e-3), 1),
+        "unit": "primitives/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "1M primitives of the 10x4x10 m room map, log-scales N(ln 0.1, 1), "
+                               "opacity logits N(-1, 2.5), visits U{0..8}, mean NDC gradient "
+                               "log-normal (median 8e-5, sigma 0.7); rule: threshold 2e-4, "
+                               "percent_dense 0.01, min opacity 0.005, size 0.1 of extent 10",
+                   "primitives": n, "outputs": n_out, "cloned": cloned, "split": split, "pruned": pruned},
+        "roofline": {"kernel": "densify", "bound": "hbm", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic("densify", "1M")},
+        "stats_ms_per_view": round(stats_ms, 4),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = densify_cpu_baseline(c, {}, n)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -390,6 +491,8 @@ def main():
         raise SystemExit("bench.py needs a ROCm GPU")
     if args.workload == "batched":
         return main_batched(args, torch)
+    if args.workload == "densify":
+        return main_densify(args, torch)
     p, tp, cams, plan, mapper, target = build_workload(args, torch)
     torch.cuda.synchronize()
     print(f"# workload ready: pairs={plan.pair_count()}", file=sys.stderr, flush=True)
@@ -443,13 +546,7 @@ def main():
     render_ms = r0.elapsed_time(r1) / args.steps
 
     if args.calibrate:
-        # a plain device copy of known size: reads and writes 256 MiB
-        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        calibration_copy(torch)
 
     # algorithmic work of the heaviest kernels (see the design notes):
     # raster backward: 55 FP32 operations (FMA = 2) per composited (pixel,

@@ -3,14 +3,14 @@
 // gradient statistic, the split / clone / prune decision with compaction
 // into new buffers, and the opacity reset.
 //
-// gs_densify is three launches over blocks of 1024 primitives, four
-// consecutive ones per thread so that every row is read with one 16-byte
-// load per thread: count (decisions and per-block totals), a one-workgroup
-// scan of the block totals, and scatter (the decisions again, block-local
-// ranks, stores).  A decision reads 6 floats per primitive, so making it
-// twice costs less than storing it.  The whole pass moves about 1.4 KB per
-// primitive (59 rows of parameters and of both moments, read and written)
-// and is bound by HBM.
+// gs_densify is three launches over blocks of 256 primitives, one per
+// thread: count (decisions and per-block totals), a one-workgroup scan of
+// the block totals, and scatter (the decisions again, block-local ranks,
+// stores).  A decision reads 6 floats per primitive, so making it twice costs
+// less than storing it.  The whole pass moves about 1.4 KB per primitive (59
+// rows of parameters and of both moments, read and written) and is bound by
+// HBM: the copy loops keep several rows in flight per thread, and the stores
+// of a wave land on consecutive columns because the ranks are a scan.
 
 #include "gs_internal.hpp"
 
@@ -19,9 +19,9 @@
 namespace gs {
 namespace {
 
-constexpr int kDenThreads = 256;
-constexpr int kDenPer = 4;
-constexpr int kDenBlock = kDenThreads * kDenPer;
+constexpr int kDenThreads = 256;          // one primitive per thread
+constexpr int kDenBlock = kDenThreads;
+constexpr int kDenRows = 16;              // rows in flight per thread in the copy loops
 
 // Outcome for one original primitive.
 struct Fate {
@@ -50,46 +50,24 @@ __device__ __forceinline__ Fate decide(const gs_densify_rule &r, float s0, float
     return f;
 }
 
-__device__ __forceinline__ float4 row4(const float *__restrict__ a, int row, int64_t n_cap,
-                                       int64_t base) {
-    return *reinterpret_cast<const float4 *>(a + int64_t(row) * n_cap + base);
-}
-
-__device__ __forceinline__ float lane4(const float4 &v, int i) {
-    return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
-}
-
-// Fates of the (up to) four primitives base..base+3 below n.
-__device__ __forceinline__ void fates(const gs_densify_rule &r, const float *__restrict__ P,
-                                      const float *__restrict__ stats, int64_t n, int64_t n_cap,
-                                      int64_t base, Fate (&f)[kDenPer]) {
-#pragma unroll
-    for (int i = 0; i < kDenPer; ++i) f[i] = Fate{false, false, 0};
-    if (base >= n) return;
-    const float4 s0 = row4(stats, 0, n_cap, base), s1 = row4(stats, 1, n_cap, base);
-    const float4 l0 = row4(P, 3, n_cap, base), l1 = row4(P, 4, n_cap, base);
-    const float4 l2 = row4(P, 5, n_cap, base), op = row4(P, 10, n_cap, base);
-#pragma unroll
-    for (int i = 0; i < kDenPer; ++i)
-        if (base + i < n)
-            f[i] = decide(r, lane4(s0, i), lane4(s1, i), lane4(l0, i), lane4(l1, i), lane4(l2, i),
-                          lane4(op, i));
+// Fate of primitive g (nothing for g >= n).
+__device__ __forceinline__ Fate fate_of(const gs_densify_rule &r, const float *__restrict__ P,
+                                        const float *__restrict__ stats, int64_t n, int64_t n_cap,
+                                        int64_t g) {
+    if (g >= n) return Fate{false, false, 0};
+    return decide(r, stats[g], stats[n_cap + g], P[3 * n_cap + g], P[4 * n_cap + g],
+                  P[5 * n_cap + g], P[10 * n_cap + g]);
 }
 
 __global__ void __launch_bounds__(kDenThreads) densify_count_kernel(
     gs_densify_rule r, const float *__restrict__ P, const float *__restrict__ stats, int64_t n,
-    int64_t n_cap, int4 *__restrict__ blk) {
-    const int64_t base = int64_t(blockIdx.x) * kDenBlock + int64_t(threadIdx.x) * kDenPer;
-    Fate f[kDenPer];
-    fates(r, P, stats, n, n_cap, base, f);
-    int c[4] = {0, 0, 0, 0};   // kept originals, new primitives, copies made, splits
-#pragma unroll
-    for (int i = 0; i < kDenPer; ++i) {
-        c[0] += f[i].keep;
-        c[1] += f[i].nnew;
-        c[2] += (!f[i].split && f[i].nnew > 0);
-        c[3] += f[i].split;
-    }
+    int64_t n_cap, int64_t n_blocks, int4 *__restrict__ blk) {
+    const int64_t b = xcd_tile(blockIdx.x, n_blocks);
+    if (b >= n_blocks) return;
+    const int64_t g = b * kDenBlock + threadIdx.x;
+    const Fate f = fate_of(r, P, stats, n, n_cap, g);
+    // kept originals, new primitives, copies made, splits
+    int c[4] = {f.keep, f.nnew, !f.split && f.nnew > 0, f.split};
     __shared__ int part[kDenThreads / kWave][4];
     const int wave = threadIdx.x / kWave;
 #pragma unroll
@@ -102,29 +80,43 @@ __global__ void __launch_bounds__(kDenThreads) densify_count_kernel(
         int t[4] = {0, 0, 0, 0};
         for (int w = 0; w < kDenThreads / kWave; ++w)
             for (int k = 0; k < 4; ++k) t[k] += part[w][k];
-        blk[blockIdx.x] = make_int4(t[0], t[1], t[2], t[3]);
+        blk[b] = make_int4(t[0], t[1], t[2], t[3]);
     }
 }
 
 // One workgroup: exclusive offsets of the kept originals (x) and new
 // primitives (y) of every block, in place; totals to tot[0..1] and d_counts.
+// Each thread takes kScanItems consecutive blocks per round.
 __global__ void __launch_bounds__(kScanThreads) densify_scan_kernel(int4 *__restrict__ blk,
                                                                     int64_t n_blocks, int64_t n,
                                                                     int64_t *__restrict__ tot,
                                                                     int64_t *__restrict__ d_counts) {
     __shared__ uint32_t lds[8];
     int64_t carry_k = 0, carry_n = 0, copies = 0, splits = 0;
-    for (int64_t c0 = 0; c0 < n_blocks; c0 += kScanThreads) {
-        const int64_t b = c0 + threadIdx.x;
-        const int4 v = b < n_blocks ? blk[b] : make_int4(0, 0, 0, 0);
+    for (int64_t c0 = 0; c0 < n_blocks; c0 += kScanTile) {
+        const int64_t b0 = c0 + int64_t(threadIdx.x) * kScanItems;
+        int4 e[kScanItems];
+        uint32_t sk = 0, sn = 0;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            e[i] = b0 + i < n_blocks ? blk[b0 + i] : make_int4(0, 0, 0, 0);
+            sk += uint32_t(e[i].x);
+            sn += uint32_t(e[i].y);
+            copies += e[i].z;
+            splits += e[i].w;
+        }
         uint32_t tk, tn;
-        const uint32_t ek = block_exclusive_scan(uint32_t(v.x), lds, &tk);
-        const uint32_t en = block_exclusive_scan(uint32_t(v.y), lds, &tn);
-        if (b < n_blocks) blk[b] = make_int4(int(carry_k + ek), int(carry_n + en), v.z, v.w);
+        uint32_t ek = block_exclusive_scan(sk, lds, &tk);
+        uint32_t en = block_exclusive_scan(sn, lds, &tn);
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            if (b0 + i < n_blocks)
+                blk[b0 + i] = make_int4(int(carry_k + ek), int(carry_n + en), e[i].z, e[i].w);
+            ek += uint32_t(e[i].x);
+            en += uint32_t(e[i].y);
+        }
         carry_k += tk;
         carry_n += tn;
-        copies += v.z;
-        splits += v.w;
     }
     copies = wave_sum(copies);
     splits = wave_sum(splits);
@@ -144,107 +136,96 @@ __global__ void __launch_bounds__(kScanThreads) densify_scan_kernel(int4 *__rest
     }
 }
 
+// Stores of one output column's value for row `row`: the surviving original,
+// then its copy or its two children (child values given).
+__device__ __forceinline__ void put(float *__restrict__ o, const Fate &f, int64_t dk, int64_t dn,
+                                    float x, float c0, float c1) {
+    if (f.keep) o[dk] = x;
+    if (f.nnew == 1) o[dn] = x;
+    if (f.nnew == 2) { o[dn] = c0; o[dn + 1] = c1; }
+}
+
 __global__ void __launch_bounds__(kDenThreads) densify_scatter_kernel(
     gs_densify_rule r, const float *__restrict__ P, const float *__restrict__ m,
     const float *__restrict__ v, const float *__restrict__ stats, const float *__restrict__ noise,
     int64_t n, int64_t n_cap, float *__restrict__ oP, float *__restrict__ om, float *__restrict__ ov,
-    int64_t out_cap, const int4 *__restrict__ blk, const int64_t *__restrict__ tot) {
+    int64_t out_cap, int64_t n_blocks, const int4 *__restrict__ blk, const int64_t *__restrict__ tot) {
+    // neighbouring blocks write the two ends of the same cache lines: keep
+    // them on one XCD (one L2)
+    const int64_t b = xcd_tile(blockIdx.x, n_blocks);
     const int64_t K = tot[0];
-    if (K + tot[1] > out_cap) return;   // the same for every thread of the grid
-    const int64_t base = int64_t(blockIdx.x) * kDenBlock + int64_t(threadIdx.x) * kDenPer;
-    Fate f[kDenPer];
-    fates(r, P, stats, n, n_cap, base, f);
-    uint32_t kc = 0, nc = 0;
-#pragma unroll
-    for (int i = 0; i < kDenPer; ++i) { kc += f[i].keep; nc += f[i].nnew; }
+    if (b >= n_blocks || K + tot[1] > out_cap) return;   // uniform per block
+    const int64_t g = b * kDenBlock + threadIdx.x;
+    const Fate f = fate_of(r, P, stats, n, n_cap, g);
     __shared__ uint32_t lds[8];
     uint32_t tk, tn;
-    const uint32_t ek = block_exclusive_scan(kc, lds, &tk);
-    const uint32_t en = block_exclusive_scan(nc, lds, &tn);
-    if (base >= n) return;
-    const int4 off = blk[blockIdx.x];
-    int64_t dk[kDenPer], dn[kDenPer];
+    const uint32_t ek = block_exclusive_scan(uint32_t(f.keep), lds, &tk);
+    const uint32_t en = block_exclusive_scan(uint32_t(f.nnew), lds, &tn);
+    if (!f.keep && f.nnew == 0) return;   // also every g >= n
+    const int4 off = blk[b];
+    const int64_t dk = int64_t(off.x) + ek, dn = K + int64_t(off.y) + en;
+
+    // rows 0-5: children move their centre by Rq (s * z_c) and shrink
     {
-        int64_t k = int64_t(off.x) + ek, q = K + int64_t(off.y) + en;
+        float raw[10];
 #pragma unroll
-        for (int i = 0; i < kDenPer; ++i) {
-            dk[i] = k; k += f[i].keep;
-            dn[i] = q; q += f[i].nnew;
-        }
-    }
-    bool any_split = false;
+        for (int k = 0; k < 10; ++k) raw[k] = P[int64_t(k) * n_cap + g];
+        float d0[3] = {0.f, 0.f, 0.f}, d1[3] = {0.f, 0.f, 0.f};
+        if (f.nnew == 2) {
+            float z[6];
 #pragma unroll
-    for (int i = 0; i < kDenPer; ++i) any_split |= (f[i].split && f[i].nnew == 2);
-
-    // child offsets Rq (s * z_c), only where a split is written
-    float off3[kDenPer][2][3];
+            for (int k = 0; k < 6; ++k) z[k] = noise[int64_t(k) * n_cap + g];
+            float w = raw[6], x = raw[7], y = raw[8], zz = raw[9];
+            const float inv = 1.f / sqrtf(w * w + x * x + y * y + zz * zz);
+            w *= inv; x *= inv; y *= inv; zz *= inv;
+            const float R[9] = {1.f - 2.f * (y * y + zz * zz), 2.f * (x * y - w * zz), 2.f * (x * zz + w * y),
+                                2.f * (x * y + w * zz), 1.f - 2.f * (x * x + zz * zz), 2.f * (y * zz - w * x),
+                                2.f * (x * zz - w * y), 2.f * (y * zz + w * x), 1.f - 2.f * (x * x + y * y)};
+            const float s[3] = {expf(raw[3]), expf(raw[4]), expf(raw[5])};
+            const float u0[3] = {s[0] * z[0], s[1] * z[1], s[2] * z[2]};
+            const float u1[3] = {s[0] * z[3], s[1] * z[4], s[2] * z[5]};
 #pragma unroll
-    for (int i = 0; i < kDenPer; ++i)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) off3[i][c][0] = off3[i][c][1] = off3[i][c][2] = 0.f;
-    if (any_split) {
-        float4 q4[4], ls4[3], z4[6];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) q4[k] = row4(P, 6 + k, n_cap, base);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) ls4[k] = row4(P, 3 + k, n_cap, base);
-#pragma unroll
-        for (int k = 0; k < 6; ++k) z4[k] = row4(noise, k, n_cap, base);
-#pragma unroll
-        for (int i = 0; i < kDenPer; ++i) {
-            if (!(f[i].split && f[i].nnew == 2)) continue;
-            float w = lane4(q4[0], i), x = lane4(q4[1], i), y = lane4(q4[2], i), z = lane4(q4[3], i);
-            const float inv = 1.f / sqrtf(w * w + x * x + y * y + z * z);
-            w *= inv; x *= inv; y *= inv; z *= inv;
-            const float R[9] = {1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y),
-                                2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x),
-                                2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)};
-            const float s[3] = {expf(lane4(ls4[0], i)), expf(lane4(ls4[1], i)), expf(lane4(ls4[2], i))};
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const float u[3] = {s[0] * lane4(z4[3 * c], i), s[1] * lane4(z4[3 * c + 1], i),
-                                    s[2] * lane4(z4[3 * c + 2], i)};
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-                    off3[i][c][a] = R[3 * a] * u[0] + R[3 * a + 1] * u[1] + R[3 * a + 2] * u[2];
+            for (int a = 0; a < 3; ++a) {
+                d0[a] = R[3 * a] * u0[0] + R[3 * a + 1] * u0[1] + R[3 * a + 2] * u0[2];
+                d1[a] = R[3 * a] * u1[0] + R[3 * a + 1] * u1[1] + R[3 * a + 2] * u1[2];
             }
         }
-    }
-
-    // parameters: rows 0-2 and 3-5 differ for children, the rest are copies
-#pragma unroll 1
-    for (int row = 0; row < kRows; ++row) {
-        const float4 pv = row4(P, row, n_cap, base);
-        float *o = oP + int64_t(row) * out_cap;
 #pragma unroll
-        for (int i = 0; i < kDenPer; ++i) {
-            const float x = lane4(pv, i);
-            if (f[i].keep) o[dk[i]] = x;
-            if (f[i].nnew == 0) continue;
-            if (!f[i].split) {
-                o[dn[i]] = x;
-            } else if (row < 3) {
-                o[dn[i]] = x + off3[i][0][row];
-                o[dn[i] + 1] = x + off3[i][1][row];
-            } else if (row < 6) {
-                const float y = x - r.log_shrink;
-                o[dn[i]] = y;
-                o[dn[i] + 1] = y;
-            } else {
-                o[dn[i]] = x;
-                o[dn[i] + 1] = x;
-            }
+        for (int a = 0; a < 3; ++a)
+            put(oP + int64_t(a) * out_cap, f, dk, dn, raw[a], raw[a] + d0[a], raw[a] + d1[a]);
+#pragma unroll
+        for (int a = 3; a < 6; ++a) {
+            const float y = raw[a] - r.log_shrink;
+            put(oP + int64_t(a) * out_cap, f, dk, dn, raw[a], y, y);
         }
+#pragma unroll
+        for (int a = 6; a < 10; ++a) put(oP + int64_t(a) * out_cap, f, dk, dn, raw[a], raw[a], raw[a]);
+    }
+    // rows 10-58: copies, kDenRows loads in flight
+    for (int row = 10; row < kRows; row += kDenRows) {
+        float x[kDenRows];
+#pragma unroll
+        for (int k = 0; k < kDenRows; ++k)
+            if (row + k < kRows) x[k] = P[int64_t(row + k) * n_cap + g];
+#pragma unroll
+        for (int k = 0; k < kDenRows; ++k)
+            if (row + k < kRows) put(oP + int64_t(row + k) * out_cap, f, dk, dn, x[k], x[k], x[k]);
     }
     // moments: survivors keep theirs, new primitives start at zero
-#pragma unroll 1
-    for (int row = 0; row < kRows; ++row) {
-        const float4 mv = row4(m, row, n_cap, base), vv = row4(v, row, n_cap, base);
-        float *o1 = om + int64_t(row) * out_cap, *o2 = ov + int64_t(row) * out_cap;
+    for (int row = 0; row < kRows; row += kDenRows / 2) {
+        float a[kDenRows / 2], b[kDenRows / 2];
 #pragma unroll
-        for (int i = 0; i < kDenPer; ++i) {
-            if (f[i].keep) { o1[dk[i]] = lane4(mv, i); o2[dk[i]] = lane4(vv, i); }
-            for (int c = 0; c < f[i].nnew; ++c) { o1[dn[i] + c] = 0.f; o2[dn[i] + c] = 0.f; }
+        for (int k = 0; k < kDenRows / 2; ++k)
+            if (row + k < kRows && f.keep) {
+                a[k] = m[int64_t(row + k) * n_cap + g];
+                b[k] = v[int64_t(row + k) * n_cap + g];
+            }
+#pragma unroll
+        for (int k = 0; k < kDenRows / 2; ++k) {
+            if (row + k >= kRows) continue;
+            float *o1 = om + int64_t(row + k) * out_cap, *o2 = ov + int64_t(row + k) * out_cap;
+            if (f.keep) { o1[dk] = a[k]; o2[dk] = b[k]; }
+            for (int c = 0; c < f.nnew; ++c) { o1[dn + c] = 0.f; o2[dn + c] = 0.f; }
         }
     }
 }
@@ -337,11 +318,6 @@ extern "C" gs_status gs_densify(const gs_densify_rule *rule, const float *params
         !d_counts || n < 0 || n > n_cap || n_cap % 64 || out_cap < 0 || out_cap % 64 ||
         n_cap >= (int64_t(1) << 31) || out_cap >= (int64_t(1) << 31))
         return GS_ERR_INVALID_ARGUMENT;
-    // rows are read with 16-byte loads
-    for (const void *p : {static_cast<const void *>(params), static_cast<const void *>(m),
-                          static_cast<const void *>(v), static_cast<const void *>(stats),
-                          static_cast<const void *>(noise)})
-        if (reinterpret_cast<uintptr_t>(p) % 16) return GS_ERR_INVALID_ARGUMENT;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const DensifyWs L = DensifyWs::make(n);
     char *b = static_cast<char *>(ws);
@@ -349,13 +325,14 @@ extern "C" gs_status gs_densify(const gs_densify_rule *rule, const float *params
     int64_t *tot = reinterpret_cast<int64_t *>(b + L.tot);
     const int64_t nb = (n + kDenBlock - 1) / kDenBlock;
     if (nb > 0)
-        hipLaunchKernelGGL(densify_count_kernel, dim3(nb), dim3(kDenThreads), 0, st, *rule, params,
-                           stats, n, n_cap, blk);
+        hipLaunchKernelGGL(densify_count_kernel, dim3(xcd_grid(nb)), dim3(kDenThreads), 0, st, *rule,
+                           params, stats, n, n_cap, nb, blk);
     hipLaunchKernelGGL(densify_scan_kernel, dim3(1), dim3(kScanThreads), 0, st, blk, nb, n, tot,
                        d_counts);
     if (nb > 0)
-        hipLaunchKernelGGL(densify_scatter_kernel, dim3(nb), dim3(kDenThreads), 0, st, *rule, params,
-                           m, v, stats, noise, n, n_cap, out_params, out_m, out_v, out_cap, blk, tot);
+        hipLaunchKernelGGL(densify_scatter_kernel, dim3(xcd_grid(nb)), dim3(kDenThreads), 0, st, *rule,
+                           params, m, v, stats, noise, n, n_cap, out_params, out_m, out_v, out_cap, nb,
+                           blk, tot);
     GS_CHECK_LAUNCH();
     return GS_OK;
 }

@@ -97,8 +97,6 @@ def test_invalid_arguments_rejected():
                           None) == 1
     assert lib.gs_densify(C.byref(rule), one, one, one, one, one, 10, 100, one, one, one, 256, one, one,
                           None) == 1                                # n_cap not a multiple of 64
-    assert lib.gs_densify(C.byref(rule), C.c_void_p(4), one, one, one, one, 10, 256, one, one, one, 256,
-                          one, one, None) == 1                      # rows need 16-byte alignment
     assert lib.gs_densify_stats(None, 10, 256, one, 1, one, None) == 1
     assert lib.gs_reset_opacity(one, None, None, 10, 256, 1.5, None) == 1
     assert gs.gs_densify_workspace_bytes(1 << 20) >= 16 * (1 << 10)
