@@ -176,14 +176,15 @@ def smooth_image(rng: np.random.Generator, height: int, width: int, channels: in
     return img.astype(np.float32)
 
 
-def densify_case(seed: int, n: int, n_views: int = 2, extent: float = 10.0, n_cap: int | None = None):
+def densify_case(seed: int, n: int, n_views: int = 2, extent: float = 10.0, n_cap: int | None = None,
+                 grad_median: float = 2e-4):
     """Inputs of the densification rule for a map of ``n`` Gaussians.
 
     The laws straddle the rule's thresholds for a scene of the given extent:
     log-scales ~ N(ln(0.01 extent), 1) per axis (so both clones and splits
     occur, and a few primitives exceed 0.1 extent), opacity logits ~ N(-1, 2.5)
     (a few percent below logit(0.005)), visit counts uniform on 0..8 and mean
-    gradient norms log-normal around 2e-4.  Also per-view 2D-gradient
+    gradient norms log-normal around ``grad_median`` (sigma 0.7).  Also per-view 2D-gradient
     accumulators ``[n_views, n_cap, 9]`` with about a third of the records
     zero and a tenth carrying colour gradients only, the views' level-0 sizes,
     Adam moments and the split noise ``[6, n_cap]``.  Returns a dict.
@@ -199,7 +200,7 @@ def densify_case(seed: int, n: int, n_views: int = 2, extent: float = 10.0, n_ca
     v[:, :n] = rng.uniform(0.0, 1e-6, size=(NROWS, n))
     stats = np.zeros((2, n_cap), np.float32)
     visits = rng.integers(0, 9, size=n).astype(np.float32)
-    mean = np.exp(rng.normal(math.log(2e-4), 0.7, size=n))
+    mean = np.exp(rng.normal(math.log(grad_median), 0.7, size=n))
     stats[0, :n] = (visits * mean).astype(np.float32)
     stats[1, :n] = visits
     noise = np.zeros((6, n_cap), np.float32)
