@@ -402,6 +402,37 @@ gs_status gs_densify(const gs_densify_rule *rule, const float *params, const flo
 gs_status gs_reset_opacity(float *params, float *m, float *v, int64_t n, int64_t n_cap,
                            double max_opacity, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Loop-closure correction of the primitives (Section 3.5: keyframes and map
+ * points move by similarity corrections when a loop is closed; the hyper
+ * primitives follow).
+ * ------------------------------------------------------------------------- */
+
+/* The similarity x' = s R(q) x + t: q a quaternion (w, x, y, z; normalised by
+ * the library), s > 0. */
+typedef struct {
+    float q[4];
+    float t[3];
+    float s;
+} gs_sim3;
+
+/* Bytes of device workspace gs_sim3_apply needs for n_transforms transforms. */
+size_t gs_sim3_workspace_bytes(int32_t n_transforms);
+
+/* Moves primitives 0..n-1 of params (device [59][n_cap], in place) by
+ * transforms[assign[g]] (transforms: device gs_sim3[n_transforms]; assign:
+ * device int32 [n], or NULL for transform 0 everywhere): mean -> s R mean + t,
+ * log-scale -> log-scale + ln s, quaternion -> q_R * q (Hamilton product,
+ * q_R the normalised transform quaternion), opacity unchanged, and every
+ * colour channel's SH bands 1-3 rotated so that the colour seen along d
+ * equals the old colour seen along R^T d (band l: c -> D_l(R)^T c with
+ * Y_l(R^T d) = D_l(R) Y_l(d); band 0 unchanged).  Primitives whose index is
+ * outside [0, n_transforms), or whose transform has s <= 0 or a zero
+ * quaternion, are left unchanged.  Adam moments are not touched.
+ * ws: device, gs_sim3_workspace_bytes(n_transforms). */
+gs_status gs_sim3_apply(float *params, int64_t n, int64_t n_cap, const gs_sim3 *transforms,
+                        int32_t n_transforms, const int32_t *assign, void *ws, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

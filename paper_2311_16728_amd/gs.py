@@ -48,6 +48,10 @@ class gs_densify_rule(C.Structure):
                 ("logit_min", C.c_float), ("log_shrink", C.c_float)]
 
 
+class gs_sim3(C.Structure):
+    _fields_ = [("q", C.c_float * 4), ("t", C.c_float * 3), ("s", C.c_float)]
+
+
 class gs_sizes(C.Structure):
     _fields_ = [("proj_bytes", C.c_size_t), ("sort_bytes", C.c_size_t),
                 ("accum_bytes", C.c_size_t), ("loss_bytes", C.c_size_t)]
@@ -97,6 +101,8 @@ def _load():
         "gs_densify": ([C.POINTER(gs_densify_rule), vp, vp, vp, vp, vp, i64, i64, vp, vp, vp, i64, vp,
                         vp, vp], C.c_int),
         "gs_reset_opacity": ([vp, vp, vp, i64, i64, C.c_double, vp], C.c_int),
+        "gs_sim3_workspace_bytes": ([i32], C.c_size_t),
+        "gs_sim3_apply": ([vp, i64, i64, vp, i32, vp, vp, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -113,7 +119,8 @@ EXPORTED = ["gs_status_string", "gs_default_settings", "gs_targets_layout", "gs_
             "gs_pyramid_loss", "gs_adam_step", "gs_step_advance", "gs_fill", "gs_init_features",
             "gs_init_mlp_fwd", "gs_init_mlp_bwd", "gs_init_mlp_adam", "gs_to_bf16", "gs_init_heuristic",
             "gs_init_decode", "gs_append", "gs_densify_rule_make", "gs_densify_stats",
-            "gs_densify_workspace_bytes", "gs_densify", "gs_reset_opacity"]
+            "gs_densify_workspace_bytes", "gs_densify", "gs_reset_opacity", "gs_sim3_workspace_bytes",
+            "gs_sim3_apply"]
 
 
 def _check(status: int, what: str):
@@ -408,3 +415,28 @@ def gs_reset_opacity(params, m, v, n, max_opacity=0.01, stream=None):
     _check(_lib.gs_reset_opacity(_store(params, "params"), _store(m, "m", params), _store(v, "v", params),
                                  n, params.shape[1], float(max_opacity), _stream(stream)),
            "gs_reset_opacity")
+
+
+def sim3_table(sims, device="cuda") -> torch.Tensor:
+    """Device array of gs_sim3 from ((w, x, y, z), t, s) triples."""
+    arr = (gs_sim3 * len(sims))()
+    for i, (q, t, s) in enumerate(sims):
+        arr[i].q[:] = [float(x) for x in q]
+        arr[i].t[:] = [float(x) for x in t]
+        arr[i].s = float(s)
+    return to_device_struct_array(arr, device)
+
+
+def gs_sim3_workspace_bytes(n_transforms) -> int:
+    return int(_lib.gs_sim3_workspace_bytes(n_transforms))
+
+
+def gs_sim3_apply(params, n, transforms_dev, n_transforms, ws, assign=None, stream=None):
+    if assign is not None and assign.numel() < n:
+        raise GsError("assign needs one entry per primitive")
+    if transforms_dev.numel() * transforms_dev.element_size() < n_transforms * C.sizeof(gs_sim3):
+        raise GsError("transform array too small")
+    if ws.numel() * ws.element_size() < gs_sim3_workspace_bytes(n_transforms):
+        raise GsError("workspace too small")
+    _check(_lib.gs_sim3_apply(_store(params, "params"), n, params.shape[1], _p(transforms_dev), n_transforms,
+                              _i32(assign, "assign"), _p(ws), _stream(stream)), "gs_sim3_apply")
