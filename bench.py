@@ -50,14 +50,17 @@ def parse():
                     help="after timing, copy a 256 MiB buffer once (HBM counter calibration)")
     ap.add_argument("--cpu-sample", type=float, default=1.0,
                     help="fraction of pixels the oracle baseline renders and differentiates")
-    ap.add_argument("--workload", choices=("single", "batched", "densify", "loopfix"), default="single",
+    ap.add_argument("--workload", choices=("single", "batched", "densify", "loopfix", "gp-study"),
+                    default="single",
                     help="single: one 1200x680 keyframe; batched: 32 mixed keyframes x 3 pyramid "
                          "levels in one graph-captured iteration; densify: one split / clone / "
                          "prune pass over a 1M-primitive map; loopfix: loop-closure similarity "
-                         "correction of a 1M-primitive map by 128 keyframe transforms")
+                         "correction of a 1M-primitive map by 128 keyframe transforms; gp-study: online "
+                         "mapping with 1-4 pyramid levels, with and without keypoint densification")
     ap.add_argument("--psnr-compare", type=int, default=0, metavar="ROUNDS",
                     help="batched workload: also compare with the per-frame mapper at equal final "
                          "PSNR after ROUNDS visits of every keyframe")
+    ap.add_argument("--gp-seeds", type=int, default=3, help="gp-study: scenes per configuration")
     ap.add_argument("--batched-lr-scales", default="1,2,4,8",
                     help="learning-rate multipliers tried for the batched mapper in --psnr-compare")
     return ap.parse_args()
@@ -561,6 +564,55 @@ def main_loopfix(args, torch):
     return 0
 
 
+def main_gpstudy(args, torch):
+    """Synthetic analogue of the pyramid-level / geometric-densification
+    ablation: online mapping of a 300k-Gaussian room seen by 16 keyframes at
+    1200x680 that join every 100 iterations, 2,400 iterations in all; for an
+    RGB-D-like start (exact keypoint depths) and a monocular-like one (centres
+    jittered by 10 cm), with and without keypoint densification, at 1-4
+    pyramid levels, over --gp-seeds scenes (mean and standard deviation)."""
+    from paper_2311_16728_amd.online import online_scene, run_online
+
+    runs = {}
+    for seed in range(args.seed, args.seed + args.gp_seeds):
+        for sensor, noise in (("rgbd", 0.0), ("mono", 0.10)):
+            sc = online_scene(seed, pos_noise=noise)
+            print(f"# seed {seed} {sensor} scene ready: {sc['n']} initial primitives", file=sys.stderr, flush=True)
+            for geo in (True, False):
+                for levels in (1, 2, 3, 4):
+                    r = run_online(sc, levels=levels, geo=geo, seed=seed)
+                    r.pop("mapper")
+                    runs.setdefault((sensor, geo, levels), []).append(r)
+                    print(f"# seed {seed} {sensor} geo={geo} levels={levels}: psnr {r['psnr']} "
+                          f"fps {r['fps']} n {r['primitives']} {r['iters_per_s']} it/s",
+                          file=sys.stderr, flush=True)
+                    torch.cuda.empty_cache()
+            del sc
+    rows = []
+    for (sensor, geo, levels), rs in runs.items():
+        ps = np.array([r["psnr"] for r in rs])
+        rows.append({"sensor": sensor, "geo": geo, "levels": levels, "seeds": len(rs),
+                     "psnr_mean": round(float(ps.mean()), 3), "psnr_std": round(float(ps.std()), 3),
+                     "fps": round(float(np.mean([r["fps"] for r in rs])), 1),
+                     "mb": round(float(np.mean([r["mb"] for r in rs])), 3),
+                     "iters_per_s": round(float(np.mean([r["iters_per_s"] for r in rs])), 1)})
+    default_ips = [r for r in rows if r["sensor"] == "rgbd" and r["geo"] and r["levels"] == 3][0]["iters_per_s"]
+    out = {
+        "metric": "online mapping iters/s, 16 keyframes joining over time, 300k-Gaussian room at 1200x680",
+        "value": default_ips, "unit": "iters/s", "n_gpus": 1, "steps": 2400, "warmup": 0,
+        "ms_per_step": round(1000.0 / default_ips, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "online mapping (Eq. 5 per keyframe, tau 4, uniform keyframe choice, "
+                               "gradient densification every 100 iterations); value = default setting "
+                               "(RGB-D-like, keypoint densification, 3 levels); ablation rows give level-0 "
+                               "PSNR over all keyframes, render FPS and model size",
+                   "seeds": args.gp_seeds},
+        "ablation": rows,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -577,6 +629,8 @@ def main():
         return main_densify(args, torch)
     if args.workload == "loopfix":
         return main_loopfix(args, torch)
+    if args.workload == "gp-study":
+        return main_gpstudy(args, torch)
     p, tp, cams, plan, mapper, target = build_workload(args, torch)
     torch.cuda.synchronize()
     print(f"# workload ready: pairs={plan.pair_count()}", file=sys.stderr, flush=True)
