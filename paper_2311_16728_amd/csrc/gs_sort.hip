@@ -185,33 +185,47 @@ __global__ void __launch_bounds__(256) compact_reduce_kernel(const uint32_t *__r
     block_reduce_to(uint32_t(S), bsum, [&](int64_t e) { return counts[e] ? 1u : 0u; });
 }
 
-// Thread t of a block takes the kScanItems consecutive elements
-// [base + t * kScanItems, ...): one block scan of the per-thread totals places
-// them, in element order.
+// Scatter side of the two block scans below.  Element e = base + k * 256 +
+// t (k < kScanItems) is read by thread t in round k, so loads and stores are
+// coalesced; ranks inside a wave come from a wave scan (or a ballot), and the
+// (round, wave) totals, in element order, are scanned by one wave.
+__device__ __forceinline__ void round_wave_offsets(uint32_t (*wtot)[kScanThreads / kWave]) {
+    __syncthreads();
+    if (threadIdx.x < kWave) {
+        const int lane = threadIdx.x, k = lane / (kScanThreads / kWave), w = lane % (kScanThreads / kWave);
+        const uint32_t v = wtot[k][w];
+        wtot[k][w] = wave_inclusive_scan(v) - v;
+    }
+    __syncthreads();
+}
+static_assert(kScanItems * (kScanThreads / kWave) == kWave, "one wave scans the round totals");
+
 __global__ void __launch_bounds__(256) compact_scatter_kernel(const uint32_t *__restrict__ counts,
                                                               int64_t S, Proj proj,
                                                               const uint32_t *__restrict__ bsum,
                                                               uint32_t *__restrict__ vis_key,
                                                               uint32_t *__restrict__ vis_val) {
-    __shared__ uint32_t lds[8];
+    __shared__ uint32_t wtot[kScanItems][kScanThreads / kWave];
     const int64_t base = int64_t(blockIdx.x) * kScanTile;
     if (base >= S) return;
-    const int64_t e0 = base + int64_t(threadIdx.x) * kScanItems;
-    uint32_t flags = 0, mine = 0;
+    const int wave = threadIdx.x / kWave, lane = lane_id();
+    uint64_t masks[kScanItems];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        const int64_t e = e0 + k;
-        if (e < S && counts[e]) { flags |= 1u << k; ++mine; }
+        const int64_t e = base + k * kScanThreads + threadIdx.x;
+        const bool f = e < S && counts[e] != 0u;
+        masks[k] = __ballot(f);
+        if (lane == 0) wtot[k][wave] = uint32_t(__popcll(masks[k]));
     }
-    uint32_t total;
-    uint32_t at = bsum[blockIdx.x] + block_exclusive_scan(mine, lds, &total);
+    round_wave_offsets(wtot);
+    const uint32_t b0 = bsum[blockIdx.x];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        if (flags & (1u << k)) {
-            const int64_t e = e0 + k;
+        if ((masks[k] >> lane) & 1u) {
+            const int64_t e = base + k * kScanThreads + threadIdx.x;
+            const uint32_t at = b0 + wtot[k][wave] + uint32_t(mask_rank(masks[k]));
             vis_key[at] = __float_as_uint(proj.rgb_z[e].w);
             vis_val[at] = uint32_t(e);
-            ++at;
         }
     }
 }
@@ -231,30 +245,33 @@ __global__ void __launch_bounds__(256) offsets_scatter_kernel(const uint32_t *__
                                                               uint32_t *__restrict__ vis_off,
                                                               uint32_t *__restrict__ chunk_first,
                                                               int64_t n_chunks) {
-    __shared__ uint32_t lds[8];
+    __shared__ uint32_t wtot[kScanItems][kScanThreads / kWave];
     const uint32_t n = *n_ptr;
     const int64_t base = int64_t(blockIdx.x) * kScanTile;
     if (base >= n) return;
-    const int64_t e0 = base + int64_t(threadIdx.x) * kScanItems;   // consecutive elements per thread
-    uint32_t c[kScanItems], mine = 0;
+    const int wave = threadIdx.x / kWave, lane = lane_id();
+    uint32_t c[kScanItems], pre[kScanItems];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        c[k] = (e0 + k < int64_t(n)) ? counts[vis_val[e0 + k]] : 0u;
-        mine += c[k];
+        const int64_t e = base + k * kScanThreads + threadIdx.x;
+        c[k] = e < int64_t(n) ? counts[vis_val[e]] : 0u;
+        const uint32_t inc = wave_inclusive_scan(c[k]);
+        pre[k] = inc - c[k];
+        if (lane == kWave - 1) wtot[k][wave] = inc;
     }
-    uint32_t total;
-    uint32_t o = bsum[blockIdx.x] + block_exclusive_scan(mine, lds, &total);
+    round_wave_offsets(wtot);
+    const uint32_t b0 = bsum[blockIdx.x];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        const int64_t e = e0 + k;
+        const int64_t e = base + k * kScanThreads + threadIdx.x;
         if (e < int64_t(n)) {
+            const uint32_t o = b0 + wtot[k][wave] + pre[k];
             vis_off[e] = o;
             // this record holds the first slot of every chunk starting in [o, o + c)
             const uint64_t end = uint64_t(o) + c[k];
             for (uint64_t q = (uint64_t(o) + 255) / 256; q * 256 < end && int64_t(q) < n_chunks; ++q)
                 chunk_first[q] = uint32_t(e);
         }
-        o += c[k];
     }
 }
 
@@ -278,6 +295,7 @@ __device__ __forceinline__ void divmod_small(uint32_t k, uint32_t w, uint32_t &q
 // keys and values as one vector each.
 constexpr int kEmitPer = 4;
 constexpr int kEmitChunk = kScanThreads * kEmitPer;
+constexpr int kEmitCache = 4;   // targets per view held in registers (pyramid levels)
 
 __global__ void __launch_bounds__(256) emit_kernel(int64_t n_cap, const gs_target *__restrict__ targets,
                                                    uint32_t *__restrict__ counters,
@@ -305,13 +323,18 @@ __global__ void __launch_bounds__(256) emit_kernel(int64_t n_cap, const gs_targe
     for (int64_t chunk = blockIdx.x; chunk * kEmitChunk < Pc; chunk += gridDim.x) {
         const uint32_t o0 = uint32_t(chunk * kEmitChunk);
         const uint32_t j0 = chunk_first[chunk * (kEmitChunk / kScanThreads)];   // record holding slot o0
+        // the record holding the next chunk's first slot is the last one this
+        // chunk can touch: only the offsets up to it are loaded
+        const uint32_t j1 = (chunk + 1) * kEmitChunk < Pc
+                                ? chunk_first[(chunk + 1) * (kEmitChunk / kScanThreads)]
+                                : V - 1u;
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < kEmitPer; ++r) {
             const int i = tid + r * kScanThreads;
             mark[i] = 0u;
             const uint32_t j = j0 + uint32_t(i);
-            off[i] = j < V ? vis_off[j] : 0xffffffffu;
+            off[i] = (j <= j1 && j < V) ? vis_off[j] : 0xffffffffu;
         }
         __syncthreads();
         // records after the first start strictly after o0
@@ -330,6 +353,10 @@ __global__ void __launch_bounds__(256) emit_kernel(int64_t n_cap, const gs_targe
         uint32_t key[kEmitPer], val[kEmitPer];
         uint32_t cur = 0xffffffffu, src = 0, base = 0, v = 0, g = 0, q0 = 0, mv = 0;
         const uint2 *rc_v = rects;
+        // the record's first kEmitCache targets: rectangle, tile count, tile
+        // offset and row length, loaded once per record
+        uint2 rcc[kEmitCache];
+        uint32_t cnt[kEmitCache], toff[kEmitCache], tx[kEmitCache];
 #pragma unroll
         for (int i = 0; i < kEmitPer; ++i) {
             rec += mk[i];
@@ -346,10 +373,36 @@ __global__ void __launch_bounds__(256) emit_kernel(int64_t n_cap, const gs_targe
                 q0 = view_off[v];
                 mv = view_off[v + 1] - q0;
                 rc_v = rects + int64_t(q0) * n_cap + int64_t(g) * mv;
+#pragma unroll
+                for (int q = 0; q < kEmitCache; ++q) {
+                    rcc[q] = make_uint2(1u, 0u);
+                    cnt[q] = toff[q] = tx[q] = 0u;
+                    if (uint32_t(q) < mv) {
+                        rcc[q] = rc_v[q];
+                        cnt[q] = rect_count(rcc[q]);
+                        const gs_target &t = targets[view_list[q0 + q]];
+                        toff[q] = uint32_t(t.tile_offset);
+                        tx[q] = uint32_t(t.tiles_x);
+                    }
+                }
             }
             // the k-th pair of the record: targets of its view in order, tiles row-major
             uint32_t k = o - base;
-            for (uint32_t q = 0; q < mv; ++q) {
+            bool found = false;
+#pragma unroll
+            for (int q = 0; q < kEmitCache; ++q) {
+                if (found || uint32_t(q) >= mv) continue;
+                if (k < cnt[q]) {
+                    const uint32_t x0 = rcc[q].x & 0xffffu, x1 = rcc[q].x >> 16, y0 = rcc[q].y & 0xffffu;
+                    uint32_t dy, dx;
+                    divmod_small(k, x1 - x0 + 1, dy, dx);
+                    key[i] = toff[q] + (y0 + dy) * tx[q] + x0 + dx;
+                    found = true;
+                } else {
+                    k -= cnt[q];
+                }
+            }
+            for (uint32_t q = kEmitCache; !found && q < mv; ++q) {
                 const uint2 rc = rc_v[q];
                 const uint32_t c = rect_count(rc);
                 if (k < c) {
@@ -358,7 +411,7 @@ __global__ void __launch_bounds__(256) emit_kernel(int64_t n_cap, const gs_targe
                     divmod_small(k, x1 - x0 + 1, dy, dx);
                     const gs_target &t = targets[view_list[q0 + q]];
                     key[i] = uint32_t(t.tile_offset) + (y0 + dy) * uint32_t(t.tiles_x) + x0 + dx;
-                    break;
+                    found = true;
                 }
                 k -= c;
             }
