@@ -15,8 +15,7 @@ constexpr int kTilePix = kTile * kTile;          // 256 pixels, one thread each
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;   // 4096 elements per block
-constexpr int kRadixBits = 8;                 // digit width of the depth sort
-constexpr int kRadixBitsMax = 9;              // widest digit (tile sort)
+constexpr int kRadixBitsMax = 9;              // widest radix digit (depth sort, large tile sorts)
 constexpr int kRadixBinsMax = 1 << kRadixBitsMax;
 constexpr int kRadixPersist = 2048;           // workgroups of the grid-stride radix kernels
 

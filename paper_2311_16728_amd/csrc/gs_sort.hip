@@ -200,8 +200,20 @@ __device__ __forceinline__ void round_wave_offsets(uint32_t (*wtot)[kScanThreads
 }
 static_assert(kScanItems * (kScanThreads / kWave) == kWave, "one wave scans the round totals");
 
+// Depth sort key of a visible record: the bit pattern of its (positive,
+// float) depth minus that of the near plane, which orders depths exactly as
+// the floats do while they stay within 2^27 ulps of the near plane (below
+// znear * 2^16: 13 km at znear 0.2 m); deeper ones share the largest key and
+// keep record order.  27 bits: three 9-bit radix passes.
+constexpr int kDepthKeyBits = 27;
+__device__ __forceinline__ uint32_t depth_key(float z, float znear) {
+    const uint32_t a = __float_as_uint(z), b = __float_as_uint(znear);
+    const uint32_t d = a > b ? a - b : 0u;
+    return d < (1u << kDepthKeyBits) ? d : (1u << kDepthKeyBits) - 1u;
+}
+
 __global__ void __launch_bounds__(256) compact_scatter_kernel(const uint32_t *__restrict__ counts,
-                                                              int64_t S, Proj proj,
+                                                              int64_t S, Proj proj, float znear,
                                                               const uint32_t *__restrict__ bsum,
                                                               uint32_t *__restrict__ vis_key,
                                                               uint32_t *__restrict__ vis_val) {
@@ -224,7 +236,7 @@ __global__ void __launch_bounds__(256) compact_scatter_kernel(const uint32_t *__
         if ((masks[k] >> lane) & 1u) {
             const int64_t e = base + k * kScanThreads + threadIdx.x;
             const uint32_t at = b0 + wtot[k][wave] + uint32_t(mask_rank(masks[k]));
-            vis_key[at] = __float_as_uint(proj.rgb_z[e].w);
+            vis_key[at] = depth_key(proj.rgb_z[e].w, znear);
             vis_val[at] = uint32_t(e);
         }
     }
@@ -689,10 +701,11 @@ extern "C" gs_status gs_bin_sort(const gs_settings *s, const void *proj_ws, int6
     hipLaunchKernelGGL(compact_reduce_kernel, dim3(sblocks), dim3(256), 0, st, B.counts, S, B.bsum);
     hipLaunchKernelGGL(scan_bsums_kernel, dim3(1), dim3(1024), 0, st, nullptr, B.bsum,
                        B.counters + kVisible, S);
-    hipLaunchKernelGGL(compact_scatter_kernel, dim3(sblocks), dim3(256), 0, st, B.counts, S, proj, B.bsum,
-                       B.vk[0], B.vv[0]);
-    // depth order (4 passes: result back in buffer 0)
-    int cur = radix_sort<4, kRadixBits>(B.counters + kVisible, B.vk, B.vv, 0, 0, 32 / kRadixBits, S, B, st);
+    hipLaunchKernelGGL(compact_scatter_kernel, dim3(sblocks), dim3(256), 0, st, B.counts, S, proj, s->znear,
+                       B.bsum, B.vk[0], B.vv[0]);
+    // depth order (three 9-bit passes over the 27-bit keys)
+    static_assert(kDepthKeyBits == 3 * 9, "depth key width");
+    int cur = radix_sort<4, 9>(B.counters + kVisible, B.vk, B.vv, 0, 0, 3, S, B, st);
     // pair offsets in depth order
     hipLaunchKernelGGL(offsets_reduce_kernel, dim3(sblocks), dim3(256), 0, st, B.counters + kVisible,
                        B.counts, B.vv[cur], B.bsum);
