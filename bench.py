@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--batch", type=int, default=None, help="forward LDS batch (skips autotuning)")
     ap.add_argument("--bwd-waves", type=int, default=None, help="backward waves per tile (skips autotuning)")
+    ap.add_argument("--tile-w", type=int, default=None,
+                    help="tile width, tiles of tile_w x 256/tile_w pixels (skips autotuning)")
     ap.add_argument("--calibrate", action="store_true",
                     help="after timing, copy a 256 MiB buffer once (HBM counter calibration)")
     ap.add_argument("--cpu-sample", type=float, default=1.0,
@@ -311,17 +313,17 @@ def main_batched(args, torch):
     ref.render(torch.as_tensor(tp).cuda(), n)
     gt = [ref.image(ref.rgb, v).clone() for v in range(len(cams))]
     del ref
-    bm = BatchedMapper(torch.as_tensor(p).cuda(), n, cams, gt, 3)
-    plan = bm.plan
+    bm = BatchedMapper(torch.as_tensor(p).cuda(), n, cams, gt, 3, tile_w=args.tile_w or 16)
     torch.cuda.synchronize()
     tuned = None
-    if args.batch or args.bwd_waves:
-        plan.settings.batch = args.batch or plan.settings.batch
-        plan.settings.bwd_waves = args.bwd_waves or plan.settings.bwd_waves
+    if args.batch or args.bwd_waves or args.tile_w:
+        bm.plan.settings.batch = args.batch or bm.plan.settings.batch
+        bm.plan.settings.bwd_waves = args.bwd_waves or bm.plan.settings.bwd_waves
     elif not args.no_autotune:
-        tuned = autotune.tune(plan, bm.params, n, bm.target)
-        print(f"# autotuned: batch={tuned['batch']} bwd_waves={tuned['bwd_waves']} {tuned['ms']}",
-              file=sys.stderr, flush=True)
+        bm.plan, tuned = autotune.tune_tiles(bm.make_plan, bm.params, n, bm.target)
+        print(f"# autotuned: tile_w={tuned['tile_w']} batch={tuned['batch']} bwd_waves={tuned['bwd_waves']} "
+              f"{tuned['ms']}", file=sys.stderr, flush=True)
+    plan = bm.plan
     bm.invalidate()
     bm.capture(warmup=max(1, args.warmup))
     torch.cuda.synchronize()
@@ -373,7 +375,7 @@ def main_batched(args, torch):
         "targets_per_s": round(plan.n_targets * 1000.0 / ms_step, 1),
         "megapixels_per_s": round(plan.total_pixels * 1e-3 / ms_step, 1),
         "stage_ms_eager": stage_ms,
-        "launch": {"batch": plan.settings.batch, "bwd_waves": plan.settings.bwd_waves,
+        "launch": {"tile_w": plan.tile_w, "batch": plan.settings.batch, "bwd_waves": plan.settings.bwd_waves,
                    "autotune_ms": tuned["ms"] if tuned else None},
     }
     if args.psnr_compare:
@@ -632,18 +634,25 @@ def main():
     if args.workload == "gp-study":
         return main_gpstudy(args, torch)
     p, tp, cams, plan, mapper, target = build_workload(args, torch)
+    from paper_2311_16728_amd.mapper import RenderPlan
+
+    def make_plan(tw):
+        return RenderPlan(cams, [(0, 0, (0.0, 0.0, 0.0), 1.0)], p.shape[1], args.pair_cap, tile_w=tw)
     torch.cuda.synchronize()
     print(f"# workload ready: pairs={plan.pair_count()}", file=sys.stderr, flush=True)
     tuned = None
-    if args.batch or args.bwd_waves:
+    if args.batch or args.bwd_waves or args.tile_w:
+        if args.tile_w:
+            plan = make_plan(args.tile_w)
         plan.settings.batch = args.batch or plan.settings.batch
         plan.settings.bwd_waves = args.bwd_waves or plan.settings.bwd_waves
     elif not args.no_autotune:
         from paper_2311_16728_amd import autotune
 
-        tuned = autotune.tune(plan, mapper.params, mapper.n, target)
-        print(f"# autotuned: batch={tuned['batch']} bwd_waves={tuned['bwd_waves']} {tuned['ms']}",
-              file=sys.stderr, flush=True)
+        del plan
+        plan, tuned = autotune.tune_tiles(make_plan, mapper.params, mapper.n, target)
+        print(f"# autotuned: tile_w={tuned['tile_w']} batch={tuned['batch']} bwd_waves={tuned['bwd_waves']} "
+              f"{tuned['ms']}", file=sys.stderr, flush=True)
 
     for _ in range(max(1, args.warmup)):
         mapper.step(plan, target)   # leaves the records of the updated parameters in the plan
@@ -738,7 +747,7 @@ def main():
                     for k, v in kernels.items()},
         "composited_pairs": composited,
         "iteration_roofline": iteration_roofline(n, plan, composited, ms_step),
-        "launch": {"batch": plan.settings.batch, "bwd_waves": plan.settings.bwd_waves,
+        "launch": {"tile_w": plan.tile_w, "batch": plan.settings.batch, "bwd_waves": plan.settings.bwd_waves,
                    "autotune_ms": tuned["ms"] if tuned else None},
     }
     if not args.no_cpu_baseline:

@@ -56,7 +56,8 @@ typedef enum {
 #define GS_STATUS_PAIR_OVERFLOW 1u
 
 #define GS_NUM_ROWS 59
-#define GS_TILE 16            /* pixels per tile side */
+#define GS_TILE 16            /* default tile width (square 16 x 16 tiles) */
+#define GS_TILE_PIXELS 256    /* pixels per tile, whatever its shape */
 
 /* Rasteriser settings.  Defaults (gs_default_settings): alpha_min 1/255,
  * alpha_max 0.99, t_min 1e-4, znear 0.2, dilation 0.3 px^2, fov_clamp 1.3,
@@ -68,7 +69,7 @@ typedef struct {
     float alpha_min, alpha_max, t_min, znear, dilation, fov_clamp;
     int32_t sh_degree;   /* 0..3 */
     int32_t batch;       /* forward: Gaussians staged per LDS round: 64, 128 or 256 */
-    int32_t bwd_waves;   /* backward: waves per 16x16 tile, 1, 2 or 4 (4, 2 or 1 pixels per lane) */
+    int32_t bwd_waves;   /* backward: waves per tile, 1, 2 or 4 (4, 2 or 1 pixels per lane) */
 } gs_settings;
 
 /* A keyframe pose with its level-0 intrinsics and image size. */
@@ -80,15 +81,16 @@ typedef struct {
 } gs_view;
 
 /* A render target: one pyramid level of one view.  Level l renders at
- * ceil(size / 2^l) with intrinsics divided by 2^l (Eq. 5).  tile_offset and
- * pix_offset are filled by gs_targets_layout. */
+ * ceil(size / 2^l) with intrinsics divided by 2^l (Eq. 5).  Its image is cut
+ * into tiles of tile_w x (256 / tile_w) pixels (tile_w 8, 16 or 32; 0
+ * means 16).  tile_offset and pix_offset are filled by gs_targets_layout. */
 typedef struct {
     int32_t view;        /* index into the view array */
     int32_t level;       /* pyramid level, 0 = full resolution */
     int32_t width, height;
     int32_t tiles_x, tiles_y;
     int32_t tile_offset; /* first global tile index of this target */
-    int32_t pad0;
+    int32_t tile_w;      /* tile width in pixels (set by the caller; 0 -> 16) */
     int64_t pix_offset;  /* first pixel of this target in packed images */
     float bg[3];         /* background colour */
     float weight;        /* weight of this target's loss in the total */
@@ -109,8 +111,11 @@ const char *gs_status_string(gs_status s);
 void gs_default_settings(gs_settings *s);
 
 /* (host) Completes targets[0..n_targets): derives width/height from the
- * view's size and the level, the tile grid, tile_offset and pix_offset
- * (targets packed in order).  Writes the totals.  views is host memory. */
+ * view's size and the level, the tile grid for the target's tile_w (0 becomes
+ * 16; other values than 8, 16, 32 are rejected), tile_offset and
+ * pix_offset (targets packed in order).  Writes the totals.  views is host
+ * memory.  The tile shape changes no rendered value (a pixel composites the
+ * same Gaussians in the same order whatever tile holds it). */
 gs_status gs_targets_layout(const gs_view *views, int32_t n_views, gs_target *targets,
                             int32_t n_targets, int64_t *total_pixels, int32_t *total_tiles);
 
@@ -132,7 +137,7 @@ gs_status gs_preprocess(const gs_settings *s, const float *params, int64_t n, in
                         const gs_view *views, int32_t n_views, void *proj_ws, void *stream);
 
 /* Tile binning: for every target, each valid Gaussian whose cutoff ellipse
- * {alpha >= alpha_min} overlaps a 16x16 tile is paired with that tile; the
+ * {alpha >= alpha_min} overlaps a tile of the target is paired with that tile; the
  * pairs are sorted by (target tile, depth, Gaussian index) with a device
  * radix sort and each tile's range of pairs is recorded.  targets (device,
  * laid out), total_tiles from gs_targets_layout.  sort_ws (device)

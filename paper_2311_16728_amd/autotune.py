@@ -1,12 +1,14 @@
 """Autotuner for the rasteriser's launch shape.
 
-Candidates: forward LDS batch (64, 128, 256 Gaussians staged per round) x
-backward waves per 16x16 tile (1, 2, 4; i.e. 4, 2, 1 pixels per lane).  Each
-candidate runs whole mapping iterations on the caller's plan (preprocess, sort,
-forward, loss, backward, Adam on a scratch copy of the parameters), timed with
-HIP events on the launch stream; the fastest is kept.  The forward result does
-not depend on the choice (inclusion is per pixel and the list order is fixed),
-which `tune` checks bitwise.  Choices are cached per (device, shape class).
+Candidates: tile shape (tile_w x 256/tile_w pixels, tile_w 8, 16, 32; one
+render plan per shape, built by the caller's factory) x forward LDS batch
+(64, 128, 256 Gaussians staged per round) x backward waves per tile (1, 2, 4;
+i.e. 4, 2, 1 pixels per lane).  Each candidate runs whole mapping iterations
+(preprocess, sort, forward, loss, backward, Adam on a scratch copy of the
+parameters), timed with HIP events on the launch stream; the fastest is kept.
+The forward image does not depend on the choice (inclusion is per pixel and
+the list order is fixed), which the tuner checks bitwise across every
+candidate.  Choices are cached per (device, shape class).
 """
 
 from __future__ import annotations
@@ -21,6 +23,7 @@ from . import gs
 
 BATCHES = (64, 128, 256)
 BWD_WAVES = (1, 2, 4)
+TILE_WIDTHS = (8, 16, 32)
 _cache: dict = {}
 
 
@@ -33,7 +36,7 @@ def shape_class(plan, n: int) -> str:
 
 def _key(plan, n):
     dev = torch.cuda.get_device_name(plan.device)
-    return f"{dev}|{shape_class(plan, n)}"
+    return f"{dev}|{shape_class(plan, n)}|w{plan.tile_w}"
 
 
 def load(path: str):
@@ -49,9 +52,13 @@ def save(path: str):
 
 
 def tune(plan, params: torch.Tensor, n: int, target: torch.Tensor, iters: int = 5, warmup: int = 2,
-         path: str | None = None, force: bool = False):
-    """Pick (batch, bwd_waves) for `plan`; sets plan.settings and returns the choice
-    with the measured ms per iteration of every candidate."""
+         path: str | None = None, force: bool = False, ref_img: torch.Tensor | None = None):
+    """Pick (batch, bwd_waves) for `plan` (its tile shape fixed); sets
+    plan.settings and returns the choice with the measured ms per iteration
+    of every candidate.  Every candidate's forward image must equal the first
+    one bitwise; ref_img (from another tile shape) must be matched to within
+    1e-2 (the staged offsets' FP32 rounding depends on the tile origin, so a
+    near-cutoff decision can flip, moving a pixel by about alpha_min)."""
     load(path)
     key = _key(plan, n)
     if key in _cache and not force:
@@ -63,17 +70,20 @@ def tune(plan, params: torch.Tensor, n: int, target: torch.Tensor, iters: int = 
     m = torch.zeros_like(p)
     v = torch.zeros_like(p)
     lr = [1e-4] * gs.NUM_ROWS
-    ref_img = None
     timings = {}
+    other, ref_img = ref_img, None
     for batch, waves in itertools.product(BATCHES, BWD_WAVES):
         plan.settings.batch, plan.settings.bwd_waves = batch, waves
         plan.render(params, n)
         torch.cuda.synchronize()
         img = plan.rgb.clone()
+        if other is not None and float((img - other).abs().max()) > 1e-2:
+            raise RuntimeError(f"forward of tile_w={plan.tile_w} differs from another tile shape")
         if ref_img is None:
             ref_img = img
         elif not torch.equal(img, ref_img):
-            raise RuntimeError(f"forward differs for batch={batch}: results must not depend on it")
+            raise RuntimeError(f"forward differs for tile_w={plan.tile_w} batch={batch} bwd_waves={waves}: "
+                               "results must not depend on the launch shape")
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         step = 0
         for it in range(warmup + iters):
@@ -96,3 +106,32 @@ def tune(plan, params: torch.Tensor, n: int, target: torch.Tensor, iters: int = 
     save(path)
     del base
     return _cache[key]
+
+
+def tune_tiles(make_plan, params: torch.Tensor, n: int, target: torch.Tensor,
+               tile_ws=TILE_WIDTHS, iters: int = 5, warmup: int = 2, path: str | None = None):
+    """Tile shape as well: make_plan(tile_w) builds a render plan for each
+    candidate width; each is tuned with `tune`, the forward images of all
+    candidates must agree bitwise.  Returns (plan, choice) for the fastest;
+    the other plans are released."""
+    best_plan, best, per_shape, ref_img = None, None, {}, None
+    for tw in tile_ws:
+        plan = make_plan(tw)
+        c = tune(plan, params, n, target, iters, warmup, path, force=True, ref_img=ref_img)
+        if ref_img is None:
+            plan.render(params, n)
+            torch.cuda.synchronize()
+            ref_img = plan.rgb.clone()
+        ms = c["ms"][f"{c['batch']}x{c['bwd_waves']}"]
+        per_shape[tw] = c["ms"]
+        if best is None or ms < best["best_ms"]:
+            if best_plan is not None:
+                del best_plan
+                torch.cuda.empty_cache()
+            best_plan = plan
+            best = {"tile_w": tw, "batch": c["batch"], "bwd_waves": c["bwd_waves"], "best_ms": ms}
+        else:
+            del plan
+            torch.cuda.empty_cache()
+    best["ms"] = per_shape
+    return best_plan, best

@@ -23,7 +23,7 @@ from .mapper import LAMBDA, PYRAMID_LEVELS, RenderPlan
 class BatchedMapper:
     def __init__(self, params: torch.Tensor, n: int, cams, gt_images, levels: int = PYRAMID_LEVELS,
                  pair_cap: int = 1 << 28, settings=None, lr_rows=None, lam: float = LAMBDA,
-                 beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-15):
+                 beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-15, tile_w: int = gs.TILE):
         self.params = params
         self.n = n
         self.levels = levels
@@ -32,13 +32,21 @@ class BatchedMapper:
         self.lr_rows = np.full(59, 1e-3, np.float32) if lr_rows is None else np.asarray(lr_rows, np.float32)
         specs = [(v, l, tuple(np.asarray(c.get("bg", (0, 0, 0)), np.float64)), 1.0)
                  for v, c in enumerate(cams) for l in range(levels)]
-        self.plan = RenderPlan(cams, specs, params.shape[1], pair_cap, settings, params.device)
+        self._plan_args = (cams, specs, params.shape[1], pair_cap)
+        self.plan = self.make_plan(tile_w, settings)
         self.target = torch.empty(3 * self.plan.total_pixels, dtype=torch.float32, device=params.device)
         self._build_targets(gt_images)
         self.m = torch.zeros_like(params)
         self.v = torch.zeros_like(params)
         self.d_step = torch.zeros(1, dtype=torch.int32, device=params.device)
         self.graph = None
+
+    def make_plan(self, tile_w: int, settings=None) -> RenderPlan:
+        """A render plan over this mapper's targets with tiles tile_w wide (the
+        packed image layout, and so the ground truth, does not depend on it);
+        assign it to .plan to use it."""
+        cams, specs, n_cap, pair_cap = self._plan_args
+        return RenderPlan(cams, specs, n_cap, pair_cap, settings, self.params.device, tile_w)
 
     def _build_targets(self, gt_images):
         """Level l of every keyframe's Gaussian pyramid into its target slot."""

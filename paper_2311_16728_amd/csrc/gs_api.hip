@@ -42,12 +42,15 @@ extern "C" gs_status gs_targets_layout(const gs_view *views, int32_t n_views, gs
             w = (w + 1) / 2;
             h = (h + 1) / 2;
         }
+        if (t.tile_w == 0) t.tile_w = gs::kTile;
+        if (t.tile_w != 8 && t.tile_w != 16 && t.tile_w != 32)
+            return GS_ERR_INVALID_ARGUMENT;
+        const int tw = t.tile_w, th = gs::kTilePix / tw;
         t.width = w;
         t.height = h;
-        t.tiles_x = (w + gs::kTile - 1) / gs::kTile;
-        t.tiles_y = (h + gs::kTile - 1) / gs::kTile;
+        t.tiles_x = (w + tw - 1) / tw;
+        t.tiles_y = (h + th - 1) / th;
         t.tile_offset = int32_t(tiles);
-        t.pad0 = 0;
         t.pix_offset = pix;
         tiles += int64_t(t.tiles_x) * t.tiles_y;
         pix += int64_t(w) * h;

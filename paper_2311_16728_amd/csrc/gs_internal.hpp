@@ -10,8 +10,19 @@ namespace gs {
 
 constexpr int kWave = 64;
 constexpr int kRows = GS_NUM_ROWS;
-constexpr int kTile = GS_TILE;
-constexpr int kTilePix = kTile * kTile;          // 256 pixels, one thread each
+constexpr int kTile = GS_TILE;                   // default tile width
+constexpr int kTilePix = GS_TILE_PIXELS;         // 256 pixels per tile, one thread each
+static_assert(kTile * kTile == kTilePix, "the default tile is square");
+
+// A target's tile: tile_w x (256 / tile_w) pixels (set by gs_targets_layout).
+struct TileShape {
+    int w, h, wlog;   // width, height, log2(width)
+};
+__host__ __device__ __forceinline__ TileShape tile_shape(int tile_w) {
+    // widths other than 8, 16, 32 (rejected by gs_targets_layout) read as 16
+    const int wlog = tile_w == 8 ? 3 : tile_w == 32 ? 5 : 4;
+    return TileShape{1 << wlog, kTilePix >> wlog, wlog};
+}
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;   // 4096 elements per block

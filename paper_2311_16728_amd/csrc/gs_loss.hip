@@ -1,8 +1,9 @@
 // Gaussian pyramid (Section 3.4) and the photometric loss of Eq. 4 with its
 // gradient, over every render target at once.
 //
-// The loss uses the same 16x16 tiling as the rasteriser: one 256-thread
-// workgroup per tile stages the tile plus a 5-pixel halo of render and target
+// The loss uses the rasteriser's tiling (the target's tile shape, 256 pixels):
+// one 256-thread workgroup per tile stages the tile plus a 5-pixel halo of
+// render and target
 // in LDS, runs the separable 11-tap Gaussian window horizontally then
 // vertically for the five SSIM moments, and writes per-pixel partial
 // derivatives of the SSIM map (with respect to the window mean, the second
@@ -14,7 +15,6 @@
 namespace gs {
 
 constexpr int kR = 5;                       // SSIM window radius (11 taps)
-constexpr int kHalo = kTile + 2 * kR;       // 26
 
 struct Window {
     float w[2 * kR + 1];
@@ -41,33 +41,45 @@ __device__ __forceinline__ int find_target_loss(const gs_target *__restrict__ ta
     return lo;
 }
 
-// Loads a (16 + 2R)^2 window of one channel plane into LDS, zero outside.
+// Tile geometry of the loss kernels: the target's raster tile (TW x TH
+// pixels, TW * TH = 256) plus an R-pixel halo, HX x HY.  Each kernel
+// dispatches on the target's tile width to a body compiled for that shape;
+// LDS is sized for the largest (8 x 32 and 32 x 8: 756-float halo; 32 x 8:
+// 18 x 32 horizontal pass).
+constexpr int kHaloMax = (32 + 2 * kR) * (8 + 2 * kR);
+constexpr int kHPassMax = 32 * (8 + 2 * kR);
+
+// Loads the HX x HY window of one channel plane around the tile into LDS
+// (row stride HX), zero outside the image.
+template <int TW>
 __device__ __forceinline__ void load_halo(const float *__restrict__ plane, int W, int H, int x0,
-                                          int y0, float (*dst)[kHalo]) {
-    for (int i = threadIdx.x; i < kHalo * kHalo; i += blockDim.x) {
-        const int yy = i / kHalo, xx = i % kHalo;
+                                          int y0, float *dst) {
+    constexpr int TH = kTilePix / TW, HX = TW + 2 * kR, HY = TH + 2 * kR;
+    for (int i = threadIdx.x; i < HX * HY; i += blockDim.x) {
+        const int yy = i / HX, xx = i % HX;
         const int gx = x0 - kR + xx, gy = y0 - kR + yy;
-        dst[yy][xx] = (gx >= 0 && gx < W && gy >= 0 && gy < H) ? plane[int64_t(gy) * W + gx] : 0.f;
+        dst[i] = (gx >= 0 && gx < W && gy >= 0 && gy < H) ? plane[int64_t(gy) * W + gx] : 0.f;
     }
 }
 
-__global__ void __launch_bounds__(256) ssim_fwd_kernel(const float *__restrict__ render,
-                                                       const float *__restrict__ target,
-                                                       const gs_target *__restrict__ targets,
-                                                       int n_targets, int total_tiles, Window win,
-                                                       float *__restrict__ maps,
-                                                       float *__restrict__ partial) {
-    __shared__ float sx[kHalo][kHalo];
-    __shared__ float sy[kHalo][kHalo];
-    __shared__ float h[5][kHalo][kTile];
-    __shared__ float red[2][kTilePix / kWave];
+struct SsimLds {
+    float sx[kHaloMax];
+    float sy[kHaloMax];
+    float h[5][kHPassMax];
+    float red[2][kTilePix / kWave];
+};
+
+template <int TW>
+__device__ __forceinline__ void ssim_fwd_tile(const float *__restrict__ render,
+                                              const float *__restrict__ target, const gs_target &t,
+                                              int tile, const Window &win, float *__restrict__ maps,
+                                              float *__restrict__ partial, SsimLds &L) {
+    constexpr int TH = kTilePix / TW, HX = TW + 2 * kR, HY = TH + 2 * kR;
     const float C1 = 0.01f * 0.01f, C2 = 0.03f * 0.03f;
-    const int tile = int(xcd_tile(blockIdx.x, total_tiles)), tid = threadIdx.x;
-    if (tile >= total_tiles) return;
-    const gs_target t = targets[find_target_loss(targets, n_targets, tile)];
+    const int tid = threadIdx.x;
     const int local = tile - t.tile_offset;
-    const int x0 = (local % t.tiles_x) * kTile, y0 = (local / t.tiles_x) * kTile;
-    const int lx = tid % kTile, ly = tid / kTile;
+    const int x0 = (local % t.tiles_x) * TW, y0 = (local / t.tiles_x) * TH;
+    const int lx = tid % TW, ly = tid / TW;
     const int px = x0 + lx, py = y0 + ly;
     const bool inside = px < t.width && py < t.height;
     const int64_t HW = int64_t(t.width) * t.height;
@@ -77,33 +89,35 @@ __global__ void __launch_bounds__(256) ssim_fwd_kernel(const float *__restrict__
         const float *xp = render + 3 * t.pix_offset + c * HW;
         const float *yp = target + 3 * t.pix_offset + c * HW;
         __syncthreads();
-        load_halo(xp, t.width, t.height, x0, y0, sx);
-        load_halo(yp, t.width, t.height, x0, y0, sy);
+        load_halo<TW>(xp, t.width, t.height, x0, y0, L.sx);
+        load_halo<TW>(yp, t.width, t.height, x0, y0, L.sy);
         __syncthreads();
-        for (int i = tid; i < kHalo * kTile; i += blockDim.x) {
-            const int r = i / kTile, cc = i % kTile;
+        for (int i = tid; i < HY * TW; i += blockDim.x) {
+            const int r = i / TW, cc = i % TW;
+            const float *rx = L.sx + r * HX + cc, *ry = L.sy + r * HX + cc;
             float m1 = 0, m2 = 0, e11 = 0, e22 = 0, e12 = 0;
 #pragma unroll
             for (int k = 0; k < 2 * kR + 1; ++k) {
-                const float a = sx[r][cc + k], b = sy[r][cc + k], w = win.w[k];
+                const float a = rx[k], b = ry[k], w = win.w[k];
                 m1 = fmaf(w, a, m1);
                 m2 = fmaf(w, b, m2);
                 e11 = fmaf(w, a * a, e11);
                 e22 = fmaf(w, b * b, e22);
                 e12 = fmaf(w, a * b, e12);
             }
-            h[0][r][cc] = m1; h[1][r][cc] = m2; h[2][r][cc] = e11; h[3][r][cc] = e22; h[4][r][cc] = e12;
+            L.h[0][i] = m1; L.h[1][i] = m2; L.h[2][i] = e11; L.h[3][i] = e22; L.h[4][i] = e12;
         }
         __syncthreads();
         float mx = 0, my = 0, exx = 0, eyy = 0, exy = 0;
 #pragma unroll
         for (int k = 0; k < 2 * kR + 1; ++k) {
             const float w = win.w[k];
-            mx = fmaf(w, h[0][ly + k][lx], mx);
-            my = fmaf(w, h[1][ly + k][lx], my);
-            exx = fmaf(w, h[2][ly + k][lx], exx);
-            eyy = fmaf(w, h[3][ly + k][lx], eyy);
-            exy = fmaf(w, h[4][ly + k][lx], exy);
+            const int i = (ly + k) * TW + lx;
+            mx = fmaf(w, L.h[0][i], mx);
+            my = fmaf(w, L.h[1][i], my);
+            exx = fmaf(w, L.h[2][i], exx);
+            eyy = fmaf(w, L.h[3][i], eyy);
+            exy = fmaf(w, L.h[4][i], exy);
         }
         if (inside) {
             const float vx = exx - mx * mx, vy = eyy - my * my, cxy = exy - mx * my;
@@ -112,7 +126,8 @@ __global__ void __launch_bounds__(256) ssim_fwd_kernel(const float *__restrict__
             const float iB1B2 = 1.f / (B1 * B2);
             const float S = A1 * A2 * iB1B2;
             ss += S;
-            l1 += fabsf(sx[ly + kR][lx + kR] - sy[ly + kR][lx + kR]);
+            const int ci = (ly + kR) * HX + lx + kR;
+            l1 += fabsf(L.sx[ci] - L.sy[ci]);
             float *mp = maps + 9 * t.pix_offset + (3 * c) * HW;
             mp[pix] = 2.f * my * (A2 - A1) * iB1B2 - 2.f * mx * S * (1.f / B1 - 1.f / B2);
             mp[HW + pix] = -S / B2;
@@ -121,31 +136,49 @@ __global__ void __launch_bounds__(256) ssim_fwd_kernel(const float *__restrict__
     }
     l1 = wave_sum(l1);
     ss = wave_sum(ss);
-    if (lane_id() == 0) { red[0][tid / kWave] = l1; red[1][tid / kWave] = ss; }
+    if (lane_id() == 0) { L.red[0][tid / kWave] = l1; L.red[1][tid / kWave] = ss; }
     __syncthreads();
     if (tid == 0) {
         float a = 0, b = 0;
-        for (int w = 0; w < kTilePix / kWave; ++w) { a += red[0][w]; b += red[1][w]; }
+        for (int w = 0; w < kTilePix / kWave; ++w) { a += L.red[0][w]; b += L.red[1][w]; }
         partial[2 * int64_t(tile)] = a;
         partial[2 * int64_t(tile) + 1] = b;
     }
 }
 
-__global__ void __launch_bounds__(256) ssim_bwd_kernel(const float *__restrict__ render,
+__global__ void __launch_bounds__(256) ssim_fwd_kernel(const float *__restrict__ render,
                                                        const float *__restrict__ target,
                                                        const gs_target *__restrict__ targets,
                                                        int n_targets, int total_tiles, Window win,
-                                                       float lambda,
-                                                       const float *__restrict__ maps,
-                                                       float *__restrict__ dL) {
-    __shared__ float sm[3][kHalo][kHalo];
-    __shared__ float h[3][kHalo][kTile];
-    const int tile = int(xcd_tile(blockIdx.x, total_tiles)), tid = threadIdx.x;
+                                                       float *__restrict__ maps,
+                                                       float *__restrict__ partial) {
+    __shared__ SsimLds L;
+    const int tile = int(xcd_tile(blockIdx.x, total_tiles));
     if (tile >= total_tiles) return;
     const gs_target t = targets[find_target_loss(targets, n_targets, tile)];
+    switch (tile_shape(t.tile_w).w) {
+        case 8: ssim_fwd_tile<8>(render, target, t, tile, win, maps, partial, L); break;
+        case 32: ssim_fwd_tile<32>(render, target, t, tile, win, maps, partial, L); break;
+        default: ssim_fwd_tile<16>(render, target, t, tile, win, maps, partial, L); break;
+    }
+}
+
+struct SsimBwdLds {
+    float sm[3][kHaloMax];
+    float h[3][kHPassMax];
+};
+
+template <int TW>
+__device__ __forceinline__ void ssim_bwd_tile(const float *__restrict__ render,
+                                              const float *__restrict__ target, const gs_target &t,
+                                              int tile, const Window &win, float lambda,
+                                              const float *__restrict__ maps, float *__restrict__ dL,
+                                              SsimBwdLds &L) {
+    constexpr int TH = kTilePix / TW, HX = TW + 2 * kR, HY = TH + 2 * kR;
+    const int tid = threadIdx.x;
     const int local = tile - t.tile_offset;
-    const int x0 = (local % t.tiles_x) * kTile, y0 = (local / t.tiles_x) * kTile;
-    const int lx = tid % kTile, ly = tid / kTile;
+    const int x0 = (local % t.tiles_x) * TW, y0 = (local / t.tiles_x) * TH;
+    const int lx = tid % TW, ly = tid / TW;
     const int px = x0 + lx, py = y0 + ly;
     const bool inside = px < t.width && py < t.height;
     const int64_t HW = int64_t(t.width) * t.height;
@@ -154,28 +187,30 @@ __global__ void __launch_bounds__(256) ssim_bwd_kernel(const float *__restrict__
     for (int c = 0; c < 3; ++c) {
         const float *mp = maps + 9 * t.pix_offset + (3 * c) * HW;
         __syncthreads();
-        for (int k = 0; k < 3; ++k) load_halo(mp + k * HW, t.width, t.height, x0, y0, sm[k]);
+        for (int k = 0; k < 3; ++k) load_halo<TW>(mp + k * HW, t.width, t.height, x0, y0, L.sm[k]);
         __syncthreads();
-        for (int i = tid; i < kHalo * kTile; i += blockDim.x) {
-            const int r = i / kTile, cc = i % kTile;
+        for (int i = tid; i < HY * TW; i += blockDim.x) {
+            const int r = i / TW, cc = i % TW;
+            const int o = r * HX + cc;
             float a0 = 0, a1 = 0, a2 = 0;
 #pragma unroll
             for (int k = 0; k < 2 * kR + 1; ++k) {
                 const float w = win.w[k];
-                a0 = fmaf(w, sm[0][r][cc + k], a0);
-                a1 = fmaf(w, sm[1][r][cc + k], a1);
-                a2 = fmaf(w, sm[2][r][cc + k], a2);
+                a0 = fmaf(w, L.sm[0][o + k], a0);
+                a1 = fmaf(w, L.sm[1][o + k], a1);
+                a2 = fmaf(w, L.sm[2][o + k], a2);
             }
-            h[0][r][cc] = a0; h[1][r][cc] = a1; h[2][r][cc] = a2;
+            L.h[0][i] = a0; L.h[1][i] = a1; L.h[2][i] = a2;
         }
         __syncthreads();
         float f0 = 0, f1 = 0, f2 = 0;
 #pragma unroll
         for (int k = 0; k < 2 * kR + 1; ++k) {
             const float w = win.w[k];
-            f0 = fmaf(w, h[0][ly + k][lx], f0);
-            f1 = fmaf(w, h[1][ly + k][lx], f1);
-            f2 = fmaf(w, h[2][ly + k][lx], f2);
+            const int i = (ly + k) * TW + lx;
+            f0 = fmaf(w, L.h[0][i], f0);
+            f1 = fmaf(w, L.h[1][i], f1);
+            f2 = fmaf(w, L.h[2][i], f2);
         }
         if (inside) {
             const float x = render[3 * t.pix_offset + c * HW + pix];
@@ -186,6 +221,24 @@ __global__ void __launch_bounds__(256) ssim_bwd_kernel(const float *__restrict__
             dL[3 * t.pix_offset + c * HW + pix] =
                 t.weight * inv * ((1.f - lambda) * sgn - lambda * dssim);
         }
+    }
+}
+
+__global__ void __launch_bounds__(256) ssim_bwd_kernel(const float *__restrict__ render,
+                                                       const float *__restrict__ target,
+                                                       const gs_target *__restrict__ targets,
+                                                       int n_targets, int total_tiles, Window win,
+                                                       float lambda,
+                                                       const float *__restrict__ maps,
+                                                       float *__restrict__ dL) {
+    __shared__ SsimBwdLds L;
+    const int tile = int(xcd_tile(blockIdx.x, total_tiles));
+    if (tile >= total_tiles) return;
+    const gs_target t = targets[find_target_loss(targets, n_targets, tile)];
+    switch (tile_shape(t.tile_w).w) {
+        case 8: ssim_bwd_tile<8>(render, target, t, tile, win, lambda, maps, dL, L); break;
+        case 32: ssim_bwd_tile<32>(render, target, t, tile, win, lambda, maps, dL, L); break;
+        default: ssim_bwd_tile<16>(render, target, t, tile, win, lambda, maps, dL, L); break;
     }
 }
 

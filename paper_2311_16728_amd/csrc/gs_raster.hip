@@ -55,32 +55,34 @@ __device__ __forceinline__ void stage_record(const gs_settings &s, const Proj &p
 }
 
 // Minimum of the quadratic form q(d) = a dx^2 + 2 b dx dy + c dy^2, d = p - m,
-// over pixel centres p in [0, 15]^2 (tile-relative), relaxed to the square.
-__device__ __forceinline__ float qmin_tile(const float4 &A, const float4 &B) {
+// over pixel centres p in [0, hx] x [0, hy] (tile-relative), relaxed to the
+// rectangle.
+__device__ __forceinline__ float qmin_tile(const float4 &A, const float4 &B, float hx, float hy) {
     const float mx = A.x, my = A.y, a = A.z, b = A.w, c = B.x;
-    const float lo = 0.f, hi = float(kTile - 1);
-    if (mx >= lo && mx <= hi && my >= lo && my <= hi) return 0.f;
+    const float lo = 0.f;
+    if (mx >= lo && mx <= hx && my >= lo && my <= hy) return 0.f;
     float best = 3.4e38f;
     // edges x = const: minimise over dy
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-        const float dx = (e ? hi : lo) - mx;
-        const float dy = fminf(fmaxf(-b * dx / c, lo - my), hi - my);
+        const float dx = (e ? hx : lo) - mx;
+        const float dy = fminf(fmaxf(-b * dx / c, lo - my), hy - my);
         best = fminf(best, a * dx * dx + 2.f * b * dx * dy + c * dy * dy);
     }
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-        const float dy = (e ? hi : lo) - my;
-        const float dx = fminf(fmaxf(-b * dy / a, lo - mx), hi - mx);
+        const float dy = (e ? hy : lo) - my;
+        const float dx = fminf(fmaxf(-b * dy / a, lo - mx), hx - mx);
         best = fminf(best, a * dx * dx + 2.f * b * dx * dy + c * dy * dy);
     }
     return best;
 }
 
-// True when some pixel of the tile may reach the cutoff (conservative).
-__device__ __forceinline__ bool touches_tile(const float4 &A, const float4 &B, const float2 &C) {
+// True when some pixel of the tile (ts) may reach the cutoff (conservative).
+__device__ __forceinline__ bool touches_tile(const float4 &A, const float4 &B, const float2 &C,
+                                             const TileShape &ts) {
     const float tq = -2.f * C.y;   // q <= tq  <=>  exponent >= thr
-    return qmin_tile(A, B) <= tq * 1.0001f + 1e-3f;
+    return qmin_tile(A, B, float(ts.w - 1), float(ts.h - 1)) <= tq * 1.0001f + 1e-3f;
 }
 
 // Opacity of a staged Gaussian at offset (dx, dy) = mean - pixel.  The same
@@ -106,11 +108,13 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(
     const gs_target t = targets[find_target(targets, n_targets, tile)];
     const int local = tile - t.tile_offset;
     const int tx = local % t.tiles_x, ty = local / t.tiles_x;
-    const int px = tx * kTile + (tid % kTile), py = ty * kTile + tid / kTile;
+    const TileShape ts = tile_shape(t.tile_w);
+    const int lxp = tid & (ts.w - 1), lyp = tid >> ts.wlog;   // pixel inside the tile
+    const int px = tx * ts.w + lxp, py = ty * ts.h + lyp;
     const bool inside = px < t.width && py < t.height;
     const uint2 range = srt.ranges[tile];
-    const double ox = double(tx * kTile), oy = double(ty * kTile);
-    const float fpx = float(tid % kTile), fpy = float(tid / kTile);   // relative to the tile origin
+    const double ox = double(tx * ts.w), oy = double(ty * ts.h);
+    const float fpx = float(lxp), fpy = float(lyp);   // relative to the tile origin
 
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
     int32_t nc = 0, last = 0;
@@ -126,7 +130,7 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(
         bool keep = false;
         if (tid < batch && idx < range.y) {
             stage_record(s, proj, n_cap, t.view, t.level, ox, oy, srt.pair_val[idx], A, B, Cc, rec);
-            keep = touches_tile(A, B, Cc);
+            keep = touches_tile(A, B, Cc, ts);
         }
         uint32_t cnt;
         const uint32_t at_pos = block_exclusive_scan(keep ? 1u : 0u, scan_lds, &cnt);
@@ -242,8 +246,9 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
     const gs_target t = targets[find_target(targets, n_targets, tile)];
     const int local = tile - t.tile_offset;
     const int tx = local % t.tiles_x, ty = local / t.tiles_x;
+    const TileShape ts = tile_shape(t.tile_w);
     const uint2 range = srt.ranges[tile];
-    const double ox = double(tx * kTile), oy = double(ty * kTile);
+    const double ox = double(tx * ts.w), oy = double(ty * ts.h);
     const float sc = ldexpf(1.f, -t.level);
     const int64_t HW = int64_t(t.width) * t.height;
     const float *dLt = dL_drgb + 3 * t.pix_offset;
@@ -251,14 +256,15 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
 
     float T[kPix], g0[kPix], g1[kPix], g2[kPix], B0[kPix], B1[kPix], B2[kPix], fpy[kPix];
     int32_t last[kPix];
-    const float fpx = float(tid % kTile);
+    // the tile width divides 64, so a lane keeps its column in every row it owns
+    const float fpx = float(tid & (ts.w - 1));
     int my_max = 0;
 #pragma unroll
     for (int i = 0; i < kPix; ++i) {
         const int lp = tid + i * kThreads;   // tile-local pixel index
-        const int ly = lp / kTile;
+        const int ly = lp >> ts.wlog;
         fpy[i] = float(ly);
-        const int px = tx * kTile + (lp % kTile), py = ty * kTile + ly;
+        const int px = tx * ts.w + (lp & (ts.w - 1)), py = ty * ts.h + ly;
         T[i] = 0.f; g0[i] = g1[i] = g2[i] = 0.f; last[i] = 0;
         if (px < t.width && py < t.height) {
             const int64_t pix = int64_t(py) * t.width + px;
@@ -309,7 +315,7 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
         if (tid < end - start) {
             stage_record(s, proj, n_cap, t.view, t.level, ox, oy, srt.pair_val[range.x + start + tid],
                          A, Bv, Cc, rec);
-            keep = touches_tile(A, Bv, Cc);
+            keep = touches_tile(A, Bv, Cc, ts);
         }
         uint32_t cnt;
         const uint32_t at_pos = block_scan_n<kThreads>(keep ? 1u : 0u, scan_lds, &cnt);

@@ -43,8 +43,9 @@ __device__ __forceinline__ bool tile_rect(const gs_settings &s, double2 md, floa
         return false;
     const int px0 = max(0, int(fx0)), px1 = min(t.width - 1, int(fx1));
     const int py0 = max(0, int(fy0)), py1 = min(t.height - 1, int(fy1));
-    r.x0 = px0 / kTile; r.x1 = px1 / kTile;
-    r.y0 = py0 / kTile; r.y1 = py1 / kTile;
+    const TileShape ts = tile_shape(t.tile_w);
+    r.x0 = px0 >> ts.wlog; r.x1 = px1 >> ts.wlog;
+    r.y0 = py0 / ts.h; r.y1 = py1 / ts.h;
     return true;
 }
 

@@ -39,7 +39,7 @@ class gs_view(C.Structure):
 class gs_target(C.Structure):
     _fields_ = [("view", C.c_int32), ("level", C.c_int32), ("width", C.c_int32),
                 ("height", C.c_int32), ("tiles_x", C.c_int32), ("tiles_y", C.c_int32),
-                ("tile_offset", C.c_int32), ("pad0", C.c_int32), ("pix_offset", C.c_int64),
+                ("tile_offset", C.c_int32), ("tile_w", C.c_int32), ("pix_offset", C.c_int64),
                 ("bg", C.c_float * 3), ("weight", C.c_float)]
 
 
@@ -202,13 +202,15 @@ def _flat(a):
         return a
 
 
-def gs_targets_layout(views, specs):
-    """specs: list of (view, level, bg(3), weight).  Returns (targets array, total_pixels, total_tiles)."""
+def gs_targets_layout(views, specs, tile_w: int = TILE):
+    """specs: list of (view, level, bg(3), weight); tiles of tile_w x (256 / tile_w)
+    pixels.  Returns (targets array, total_pixels, total_tiles)."""
     nv = len(views)
     varr = (gs_view * nv)(*views)
     tarr = (gs_target * len(specs))()
     for i, (view, level, bg, weight) in enumerate(specs):
         tarr[i].view, tarr[i].level, tarr[i].weight = int(view), int(level), float(weight)
+        tarr[i].tile_w = int(tile_w)
         for c in range(3):
             tarr[i].bg[c] = float(bg[c])
     tp, tt = C.c_int64(), C.c_int32()

@@ -68,8 +68,10 @@ def _bytes(n: int, device) -> torch.Tensor:
 class RenderPlan:
     """Render targets = (view, pyramid level) pairs over a set of keyframe views."""
 
-    def __init__(self, cams, specs, n_cap: int, pair_cap: int, settings=None, device="cuda"):
+    def __init__(self, cams, specs, n_cap: int, pair_cap: int, settings=None, device="cuda",
+                 tile_w: int = gs.TILE):
         self.device = torch.device(device)
+        self.tile_w = int(tile_w)   # tiles of tile_w x (256 / tile_w) pixels
         self.settings = settings if settings is not None else gs.default_settings()
         self.n_cap = int(n_cap)
         self.pair_cap = int(pair_cap)
@@ -77,7 +79,8 @@ class RenderPlan:
         self.views = [gs.make_view(c) for c in self.cams]
         self.n_views = len(self.views)
         self.specs = [(int(v), int(l), tuple(bg), float(w)) for (v, l, bg, w) in specs]
-        self.targets, self.total_pixels, self.total_tiles = gs.gs_targets_layout(self.views, self.specs)
+        self.targets, self.total_pixels, self.total_tiles = gs.gs_targets_layout(self.views, self.specs,
+                                                                                 self.tile_w)
         self.n_targets = len(self.specs)
         varr = (gs.gs_view * self.n_views)(*self.views)
         self.views_dev = gs.to_device_struct_array(varr, self.device)

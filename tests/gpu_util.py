@@ -14,7 +14,8 @@ def require_gpu():
     from paper_2311_16728_amd import gs  # noqa: F401  (fails loudly without libgs.so)
 
 
-def plan_for(cams, levels=(0,), bgs=None, n_cap=256, pair_cap=1 << 20, settings=None, weights=None):
+def plan_for(cams, levels=(0,), bgs=None, n_cap=256, pair_cap=1 << 20, settings=None, weights=None,
+             tile_w=16):
     from paper_2311_16728_amd.mapper import RenderPlan
 
     specs = []
@@ -23,7 +24,7 @@ def plan_for(cams, levels=(0,), bgs=None, n_cap=256, pair_cap=1 << 20, settings=
             bg = tuple(np.asarray(cams[vi].get("bg", (0, 0, 0)), np.float64)) if bgs is None else bgs
             w = 1.0 if weights is None else weights[len(specs)]
             specs.append((vi, l, bg, w))
-    return RenderPlan(cams, specs, n_cap, pair_cap, settings)
+    return RenderPlan(cams, specs, n_cap, pair_cap, settings, tile_w=tile_w)
 
 
 def proj_records(plan, n):

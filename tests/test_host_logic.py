@@ -85,3 +85,18 @@ def test_pyramid_schedule_coarse_to_fine():
     assert [one.use(0) for _ in range(3)] == [0, 0, 0]
     with pytest.raises(ValueError):
         PyramidSchedule(levels=0)
+
+
+def test_tile_shapes_in_layout():
+    from paper_2311_16728_amd import gs
+
+    views = [gs.make_view(scenes.pinhole(150, 110, 100.0))]
+    for tw, tx, ty in [(8, 19, 4), (16, 10, 7), (32, 5, 14)]:
+        t, pix, tiles = gs.gs_targets_layout(views, [(0, 0, (0, 0, 0), 1.0)], tw)
+        assert (t[0].tile_w, t[0].tiles_x, t[0].tiles_y, tiles, pix) == (tw, tx, ty, tx * ty, 150 * 110)
+    t, _, _ = gs.gs_targets_layout(views, [(0, 0, (0, 0, 0), 1.0)], 0)
+    assert t[0].tile_w == 16
+    with pytest.raises(gs.GsError):
+        gs.gs_targets_layout(views, [(0, 0, (0, 0, 0), 1.0)], 12)
+    with pytest.raises(gs.GsError):
+        gs.gs_targets_layout(views, [(0, 0, (0, 0, 0), 1.0)], 64)
