@@ -246,13 +246,10 @@ __global__ void __launch_bounds__(256) ssim_bwd_kernel(const float *__restrict__
 // weighted total.
 // Eq. 4 per target (one workgroup each, tile partials summed in double in a
 // fixed order), then the weighted sum over targets in target order.
-__global__ void __launch_bounds__(256) loss_target_kernel(const gs_target *__restrict__ targets,
-                                                          float lambda,
-                                                          const float *__restrict__ partial,
-                                                          double *__restrict__ tloss,
-                                                          float *__restrict__ d_loss) {
+__device__ __forceinline__ void loss_of_target(const gs_target *__restrict__ targets, int ti,
+                                               float lambda, const float *__restrict__ partial,
+                                               double *__restrict__ tloss, float *__restrict__ d_loss) {
     __shared__ double red[2][kTilePix / kWave];
-    const int ti = blockIdx.x;
     const gs_target t = targets[ti];
     const int nt = t.tiles_x * t.tiles_y;
     double a = 0, b = 0;
@@ -271,6 +268,32 @@ __global__ void __launch_bounds__(256) loss_target_kernel(const gs_target *__res
         const double L = (1.0 - lambda) * sa / n + lambda * (1.0 - sb / n);
         tloss[ti] = double(t.weight) * L;
         if (d_loss) d_loss[ti] = float(L);
+    }
+    __syncthreads();   // red is reused by the next call
+}
+
+__global__ void __launch_bounds__(256) loss_target_kernel(const gs_target *__restrict__ targets,
+                                                          float lambda,
+                                                          const float *__restrict__ partial,
+                                                          double *__restrict__ tloss,
+                                                          float *__restrict__ d_loss) {
+    loss_of_target(targets, blockIdx.x, lambda, partial, tloss, d_loss);
+}
+
+// A few targets: one workgroup takes them in order and forms the total
+// (the same sums in the same order as the two kernels above and below).
+constexpr int kLossOneBlockTargets = 8;
+__global__ void __launch_bounds__(256) loss_few_kernel(const gs_target *__restrict__ targets,
+                                                       int n_targets, float lambda,
+                                                       const float *__restrict__ partial,
+                                                       double *__restrict__ tloss,
+                                                       float *__restrict__ d_loss,
+                                                       float *__restrict__ d_total) {
+    for (int ti = 0; ti < n_targets; ++ti) loss_of_target(targets, ti, lambda, partial, tloss, d_loss);
+    if (threadIdx.x == 0 && d_total) {
+        double total = 0.0;
+        for (int ti = 0; ti < n_targets; ++ti) total += tloss[ti];
+        *d_total = float(total);
     }
 }
 
@@ -368,9 +391,14 @@ extern "C" gs_status gs_pyramid_loss(const float *render, const float *target,
         hipLaunchKernelGGL(ssim_bwd_kernel, dim3(grid), dim3(kTilePix), 0, st, render, target, targets,
                            n_targets, total_tiles, win, lambda, maps, dL_drender);
     double *tloss = reinterpret_cast<double *>(b + L.tloss);
-    hipLaunchKernelGGL(loss_target_kernel, dim3(n_targets), dim3(256), 0, st, targets, lambda, partial, tloss,
-                       d_loss);
-    hipLaunchKernelGGL(loss_total_kernel, dim3(1), dim3(64), 0, st, n_targets, tloss, d_total);
+    if (n_targets <= kLossOneBlockTargets) {
+        hipLaunchKernelGGL(loss_few_kernel, dim3(1), dim3(256), 0, st, targets, n_targets, lambda, partial,
+                           tloss, d_loss, d_total);
+    } else {
+        hipLaunchKernelGGL(loss_target_kernel, dim3(n_targets), dim3(256), 0, st, targets, lambda, partial,
+                           tloss, d_loss);
+        hipLaunchKernelGGL(loss_total_kernel, dim3(1), dim3(64), 0, st, n_targets, tloss, d_total);
+    }
     GS_CHECK_LAUNCH();
     return GS_OK;
 }
