@@ -376,7 +376,7 @@ size_t gs_densify_workspace_bytes(int64_t n);
 /* Applies the rule to primitives 0..n-1 of params, m, v (device [59][n_cap])
  * with the statistic stats (device [2][n_cap]; mean = row 0 / row 1, 0 where
  * row 1 is 0) and writes the result to out_params, out_m, out_v (device
- * [59][out_cap], not overlapping the inputs):
+ * [59][out_cap], out_cap a multiple of 64, not overlapping the inputs):
  *   - densified (mean >= grad_threshold) and largest log-scale <= log_dense:
  *     cloned (the original and an identical copy);
  *   - densified and larger: split into two children with the parent's
