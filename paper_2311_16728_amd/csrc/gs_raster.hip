@@ -143,6 +143,7 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(
         __syncthreads();
         if (!done) {
             int lj = -1;   // staged index of this batch's last composited Gaussian
+#pragma unroll 4
             for (int j = 0; j < int(cnt); ++j) {
                 const float4 A = sA[j];
                 const float4 B = sB[j];
