@@ -55,10 +55,20 @@ template <int TW>
 __device__ __forceinline__ void load_halo(const float *__restrict__ plane, int W, int H, int x0,
                                           int y0, float *dst) {
     constexpr int TH = kTilePix / TW, HX = TW + 2 * kR, HY = TH + 2 * kR;
-    for (int i = threadIdx.x; i < HX * HY; i += blockDim.x) {
+    constexpr int kRounds = (HX * HY + kTilePix - 1) / kTilePix;
+    // all of a thread's loads are issued before its first LDS store
+    float v[kRounds];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const int i = threadIdx.x + r * kTilePix;
         const int yy = i / HX, xx = i % HX;
         const int gx = x0 - kR + xx, gy = y0 - kR + yy;
-        dst[i] = (gx >= 0 && gx < W && gy >= 0 && gy < H) ? plane[int64_t(gy) * W + gx] : 0.f;
+        v[r] = (i < HX * HY && gx >= 0 && gx < W && gy >= 0 && gy < H) ? plane[int64_t(gy) * W + gx] : 0.f;
+    }
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const int i = threadIdx.x + r * kTilePix;
+        if (i < HX * HY) dst[i] = v[r];
     }
 }
 
