@@ -463,10 +463,16 @@ __global__ void __launch_bounds__(256) radix_hist_kernel(const uint32_t *__restr
         for (int i = threadIdx.x; i < kBins; i += kScanThreads) h[i] = 0;
         __syncthreads();
         const int64_t base = b * kTileN;
+        uint32_t kk[kItems];   // every key load in flight before the first LDS atomic
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             const int64_t e = base + k * kScanThreads + threadIdx.x;
-            if (e < n) atomicAdd(&h[(keys[e] >> shift) & (kBins - 1)], 1u);
+            kk[k] = e < n ? keys[e] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const int64_t e = base + k * kScanThreads + threadIdx.x;
+            if (e < n) atomicAdd(&h[(kk[k] >> shift) & (kBins - 1)], 1u);
         }
         __syncthreads();
         for (int i = threadIdx.x; i < kBins; i += kScanThreads) hist[int64_t(i) * max_blocks + b] = h[i];
