@@ -3,14 +3,17 @@
 // gradient statistic, the split / clone / prune decision with compaction
 // into new buffers, and the opacity reset.
 //
-// gs_densify is three launches over blocks of 256 primitives, one per
-// thread: count (decisions and per-block totals), a one-workgroup scan of
-// the block totals, and scatter (the decisions again, block-local ranks,
-// stores).  A decision reads 6 floats per primitive, so making it twice costs
-// less than storing it.  The whole pass moves about 1.4 KB per primitive (59
-// rows of parameters and of both moments, read and written) and is bound by
-// HBM: the copy loops keep several rows in flight per thread, and the stores
-// of a wave land on consecutive columns because the ranks are a scan.
+// gs_densify is four launches.  Count, over blocks of 256 primitives, one
+// per thread: the decisions, kept as three 256-bit masks per block (survives;
+// the two bits of the number of new primitives) and per-block totals.  A
+// one-workgroup scan of the totals into output offsets.  Tables: per 256-wide
+// output tile, the source block holding its first column.  Gather, one output
+// column per thread: it finds its source primitive by a search over the block
+// offsets and a rank select in the block's mask, then copies.  The whole pass
+// moves about 1.4 KB per primitive (59 rows of parameters and of both moments,
+// read and written) and is bound by HBM; gathering makes every workgroup's
+// stores fill 256 consecutive columns of each row, so the writes (the larger
+// half of the traffic) are whole cache lines.
 
 #include "gs_internal.hpp"
 
@@ -59,9 +62,15 @@ __device__ __forceinline__ Fate fate_of(const gs_densify_rule &r, const float *_
                   P[5 * n_cap + g], P[10 * n_cap + g]);
 }
 
+// Per block of 256 primitives, bit i of word i / 64: the original survives
+// (keep), and the two bits of its number of new primitives (lo, hi).
+struct BlockMasks {
+    uint64_t keep[4], lo[4], hi[4];
+};
+
 __global__ void __launch_bounds__(kDenThreads) densify_count_kernel(
     gs_densify_rule r, const float *__restrict__ P, const float *__restrict__ stats, int64_t n,
-    int64_t n_cap, int64_t n_blocks, int4 *__restrict__ blk) {
+    int64_t n_cap, int64_t n_blocks, int4 *__restrict__ blk, BlockMasks *__restrict__ masks) {
     const int64_t b = xcd_tile(blockIdx.x, n_blocks);
     if (b >= n_blocks) return;
     const int64_t g = b * kDenBlock + threadIdx.x;
@@ -70,6 +79,14 @@ __global__ void __launch_bounds__(kDenThreads) densify_count_kernel(
     int c[4] = {f.keep, f.nnew, !f.split && f.nnew > 0, f.split};
     __shared__ int part[kDenThreads / kWave][4];
     const int wave = threadIdx.x / kWave;
+    {
+        const uint64_t km = __ballot(f.keep), lm = __ballot(f.nnew & 1), hm = __ballot(f.nnew >> 1);
+        if (lane_id() == 0) {
+            masks[b].keep[wave] = km;
+            masks[b].lo[wave] = lm;
+            masks[b].hi[wave] = hm;
+        }
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int s = wave_sum(c[k]);
@@ -136,70 +153,125 @@ __global__ void __launch_bounds__(kScanThreads) densify_scan_kernel(int4 *__rest
     }
 }
 
-// Stores of one output column's value for row `row`: the surviving original,
-// then its copy or its two children (child values given).
-__device__ __forceinline__ void put(float *__restrict__ o, const Fate &f, int64_t dk, int64_t dn,
-                                    float x, float c0, float c1) {
-    if (f.keep) o[dk] = x;
-    if (f.nnew == 1) o[dn] = x;
-    if (f.nnew == 2) { o[dn] = c0; o[dn + 1] = c1; }
+// First source block of every 256-column output tile, for the surviving
+// originals (first_keep) and the new primitives (first_new, tiles counted
+// from the first new column).  One thread per source block writes the tiles
+// whose first column it holds.
+__global__ void __launch_bounds__(kDenThreads) densify_tables_kernel(
+    const int4 *__restrict__ blk, int64_t n_blocks, const int64_t *__restrict__ tot,
+    int32_t *__restrict__ first_keep, int32_t *__restrict__ first_new) {
+    const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= n_blocks) return;
+    const int4 e = blk[b];
+    const int64_t k1 = b + 1 < n_blocks ? blk[b + 1].x : tot[0];
+    const int64_t n1 = b + 1 < n_blocks ? blk[b + 1].y : tot[1];
+    for (int64_t o = (int64_t(e.x) + kDenBlock - 1) / kDenBlock; o * kDenBlock < k1; ++o)
+        first_keep[o] = int32_t(b);
+    for (int64_t o = (int64_t(e.y) + kDenBlock - 1) / kDenBlock; o * kDenBlock < n1; ++o)
+        first_new[o] = int32_t(b);
 }
 
-__global__ void __launch_bounds__(kDenThreads) densify_scatter_kernel(
-    gs_densify_rule r, const float *__restrict__ P, const float *__restrict__ m,
-    const float *__restrict__ v, const float *__restrict__ stats, const float *__restrict__ noise,
-    int64_t n, int64_t n_cap, float *__restrict__ oP, float *__restrict__ om, float *__restrict__ ov,
-    int64_t out_cap, int64_t n_blocks, const int4 *__restrict__ blk, const int64_t *__restrict__ tot) {
-    // neighbouring blocks write the two ends of the same cache lines: keep
-    // them on one XCD (one L2)
-    const int64_t b = xcd_tile(blockIdx.x, n_blocks);
-    const int64_t K = tot[0];
-    if (b >= n_blocks || K + tot[1] > out_cap) return;   // uniform per block
-    const int64_t g = b * kDenBlock + threadIdx.x;
-    const Fate f = fate_of(r, P, stats, n, n_cap, g);
-    __shared__ uint32_t lds[8];
-    uint32_t tk, tn;
-    const uint32_t ek = block_exclusive_scan(uint32_t(f.keep), lds, &tk);
-    const uint32_t en = block_exclusive_scan(uint32_t(f.nnew), lds, &tn);
-    if (!f.keep && f.nnew == 0) return;   // also every g >= n
-    const int4 off = blk[b];
-    const int64_t dk = int64_t(off.x) + ek, dn = K + int64_t(off.y) + en;
+// Index of the r-th set bit (0-based) of the 256-bit mask m.
+__device__ __forceinline__ int select_bit(const uint64_t (&m)[4], uint32_t r) {
+    int w = 0;
+    while (w < 3 && r >= uint32_t(__popcll(m[w]))) { r -= uint32_t(__popcll(m[w])); ++w; }
+    uint64_t x = m[w];
+    int pos = 0;
+#pragma unroll
+    for (int sft = 32; sft >= 1; sft >>= 1) {
+        const uint32_t c = uint32_t(__popcll(x & ((uint64_t(1) << sft) - 1)));
+        if (r >= c) { r -= c; x >>= sft; pos += sft; }
+    }
+    return w * 64 + pos;
+}
 
-    // rows 0-5: children move their centre by Rq (s * z_c) and shrink
+// Item i and child c (r = new primitives before i + c) for per-item counts
+// lo_i + 2 hi_i over the 256 items.
+__device__ __forceinline__ int select_new(const uint64_t (&lo)[4], const uint64_t (&hi)[4], uint32_t r,
+                                          uint32_t &child) {
+    int w = 0;
+    while (w < 3) {
+        const uint32_t c = uint32_t(__popcll(lo[w]) + 2 * __popcll(hi[w]));
+        if (r < c) break;
+        r -= c;
+        ++w;
+    }
+    uint64_t xl = lo[w], xh = hi[w];
+    int pos = 0;
+#pragma unroll
+    for (int sft = 32; sft >= 1; sft >>= 1) {
+        const uint64_t msk = (uint64_t(1) << sft) - 1;
+        const uint32_t c = uint32_t(__popcll(xl & msk) + 2 * __popcll(xh & msk));
+        if (r >= c) { r -= c; xl >>= sft; xh >>= sft; pos += sft; }
+    }
+    child = r;
+    return w * 64 + pos;
+}
+
+// One output column per thread: the surviving original it copies, or the
+// original whose copy or child it is.  Stores of a workgroup fill 256
+// consecutive columns of every row (whole cache lines for the survivors).
+__global__ void __launch_bounds__(kDenThreads) densify_gather_kernel(
+    gs_densify_rule r, const float *__restrict__ P, const float *__restrict__ m,
+    const float *__restrict__ v, const float *__restrict__ noise, int64_t n_cap,
+    float *__restrict__ oP, float *__restrict__ om, float *__restrict__ ov, int64_t out_cap,
+    int64_t n_blocks, int64_t keep_tiles, const int4 *__restrict__ blk,
+    const BlockMasks *__restrict__ masks, const int32_t *__restrict__ first_keep,
+    const int32_t *__restrict__ first_new, const int64_t *__restrict__ tot) {
+    const int64_t K = tot[0], N = tot[1];
+    if (K + N > out_cap) return;   // the same for every thread of the grid
+    const bool kept = int64_t(blockIdx.x) < keep_tiles;
+    const int64_t tile = kept ? int64_t(blockIdx.x) : int64_t(blockIdx.x) - keep_tiles;
+    const int64_t j = tile * kDenBlock + threadIdx.x;   // column among survivors or new ones
+    if (j >= (kept ? K : N)) return;
+    // source block: the last one whose first column is at or before j, between
+    // the blocks holding this tile's first column and the next tile's
+    const int32_t *first = kept ? first_keep : first_new;
+    const int64_t n_out_tiles = ((kept ? K : N) + kDenBlock - 1) / kDenBlock;
+    int64_t b = first[tile];
+    int64_t hi = tile + 1 < n_out_tiles ? int64_t(first[tile + 1]) : n_blocks - 1;
+    while (b < hi) {
+        const int64_t mid = (b + hi + 1) >> 1;
+        const int4 e = blk[mid];
+        if (int64_t(kept ? e.x : e.y) <= j) b = mid; else hi = mid - 1;
+    }
+    const BlockMasks bm = masks[b];
+    uint32_t child = 0;
+    int nnew = 0;
+    int item;
+    if (kept) {
+        item = select_bit(bm.keep, uint32_t(j - blk[b].x));
+    } else {
+        item = select_new(bm.lo, bm.hi, uint32_t(j - blk[b].y), child);
+        nnew = int((bm.lo[item >> 6] >> (item & 63)) & 1) + 2 * int((bm.hi[item >> 6] >> (item & 63)) & 1);
+    }
+    const int64_t g = b * kDenBlock + item;
+    const int64_t col = kept ? j : K + j;
+
+    // rows 0-9: a child moves its centre by Rq (s * z_child) and shrinks
     {
         float raw[10];
 #pragma unroll
         for (int k = 0; k < 10; ++k) raw[k] = P[int64_t(k) * n_cap + g];
-        float d0[3] = {0.f, 0.f, 0.f}, d1[3] = {0.f, 0.f, 0.f};
-        if (f.nnew == 2) {
-            float z[6];
+        if (nnew == 2) {
+            float z[3];
 #pragma unroll
-            for (int k = 0; k < 6; ++k) z[k] = noise[int64_t(k) * n_cap + g];
+            for (int k = 0; k < 3; ++k) z[k] = noise[int64_t(3 * child + k) * n_cap + g];
             float w = raw[6], x = raw[7], y = raw[8], zz = raw[9];
             const float inv = 1.f / sqrtf(w * w + x * x + y * y + zz * zz);
             w *= inv; x *= inv; y *= inv; zz *= inv;
             const float R[9] = {1.f - 2.f * (y * y + zz * zz), 2.f * (x * y - w * zz), 2.f * (x * zz + w * y),
                                 2.f * (x * y + w * zz), 1.f - 2.f * (x * x + zz * zz), 2.f * (y * zz - w * x),
                                 2.f * (x * zz - w * y), 2.f * (y * zz + w * x), 1.f - 2.f * (x * x + y * y)};
-            const float s[3] = {expf(raw[3]), expf(raw[4]), expf(raw[5])};
-            const float u0[3] = {s[0] * z[0], s[1] * z[1], s[2] * z[2]};
-            const float u1[3] = {s[0] * z[3], s[1] * z[4], s[2] * z[5]};
+            const float u[3] = {expf(raw[3]) * z[0], expf(raw[4]) * z[1], expf(raw[5]) * z[2]};
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                d0[a] = R[3 * a] * u0[0] + R[3 * a + 1] * u0[1] + R[3 * a + 2] * u0[2];
-                d1[a] = R[3 * a] * u1[0] + R[3 * a + 1] * u1[1] + R[3 * a + 2] * u1[2];
-            }
+            for (int a = 0; a < 3; ++a)
+                raw[a] = raw[a] + (R[3 * a] * u[0] + R[3 * a + 1] * u[1] + R[3 * a + 2] * u[2]);
+#pragma unroll
+            for (int a = 3; a < 6; ++a) raw[a] = raw[a] - r.log_shrink;
         }
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-            put(oP + int64_t(a) * out_cap, f, dk, dn, raw[a], raw[a] + d0[a], raw[a] + d1[a]);
-#pragma unroll
-        for (int a = 3; a < 6; ++a) {
-            const float y = raw[a] - r.log_shrink;
-            put(oP + int64_t(a) * out_cap, f, dk, dn, raw[a], y, y);
-        }
-#pragma unroll
-        for (int a = 6; a < 10; ++a) put(oP + int64_t(a) * out_cap, f, dk, dn, raw[a], raw[a], raw[a]);
+        for (int k = 0; k < 10; ++k) oP[int64_t(k) * out_cap + col] = raw[k];
     }
     // rows 10-58: copies, kDenRows loads in flight
     for (int row = 10; row < kRows; row += kDenRows) {
@@ -209,23 +281,30 @@ __global__ void __launch_bounds__(kDenThreads) densify_scatter_kernel(
             if (row + k < kRows) x[k] = P[int64_t(row + k) * n_cap + g];
 #pragma unroll
         for (int k = 0; k < kDenRows; ++k)
-            if (row + k < kRows) put(oP + int64_t(row + k) * out_cap, f, dk, dn, x[k], x[k], x[k]);
+            if (row + k < kRows) oP[int64_t(row + k) * out_cap + col] = x[k];
     }
     // moments: survivors keep theirs, new primitives start at zero
-    for (int row = 0; row < kRows; row += kDenRows / 2) {
-        float a[kDenRows / 2], b[kDenRows / 2];
+    if (kept) {
+        for (int row = 0; row < kRows; row += kDenRows / 2) {
+            float a[kDenRows / 2], c[kDenRows / 2];
 #pragma unroll
-        for (int k = 0; k < kDenRows / 2; ++k)
-            if (row + k < kRows && f.keep) {
-                a[k] = m[int64_t(row + k) * n_cap + g];
-                b[k] = v[int64_t(row + k) * n_cap + g];
-            }
+            for (int k = 0; k < kDenRows / 2; ++k)
+                if (row + k < kRows) {
+                    a[k] = m[int64_t(row + k) * n_cap + g];
+                    c[k] = v[int64_t(row + k) * n_cap + g];
+                }
 #pragma unroll
-        for (int k = 0; k < kDenRows / 2; ++k) {
-            if (row + k >= kRows) continue;
-            float *o1 = om + int64_t(row + k) * out_cap, *o2 = ov + int64_t(row + k) * out_cap;
-            if (f.keep) { o1[dk] = a[k]; o2[dk] = b[k]; }
-            for (int c = 0; c < f.nnew; ++c) { o1[dn + c] = 0.f; o2[dn + c] = 0.f; }
+            for (int k = 0; k < kDenRows / 2; ++k)
+                if (row + k < kRows) {
+                    om[int64_t(row + k) * out_cap + col] = a[k];
+                    ov[int64_t(row + k) * out_cap + col] = c[k];
+                }
+        }
+    } else {
+#pragma unroll 4
+        for (int row = 0; row < kRows; ++row) {
+            om[int64_t(row) * out_cap + col] = 0.f;
+            ov[int64_t(row) * out_cap + col] = 0.f;
         }
     }
 }
@@ -262,14 +341,25 @@ __global__ void reset_opacity_kernel(float *__restrict__ P, float *__restrict__ 
     if (v) v[i] = 0.f;
 }
 
+// Workspace: per source block its totals / offsets and masks; the first
+// source block of every output tile (at most n survivors and 2n new
+// primitives); the totals.
 struct DensifyWs {
-    size_t blk, tot, bytes;
+    size_t blk, masks, first_keep, first_new, tot, bytes;
+    int64_t nb, keep_tiles, new_tiles;
     static DensifyWs make(int64_t n) {
         DensifyWs L;
-        const int64_t nb = (n + kDenBlock - 1) / kDenBlock;
-        L.blk = 0;
-        L.tot = align_up(sizeof(int4) * (nb > 0 ? nb : 1), 256);
-        L.bytes = L.tot + 256;
+        L.nb = (n + kDenBlock - 1) / kDenBlock;
+        L.keep_tiles = L.nb;
+        L.new_tiles = (2 * n + kDenBlock - 1) / kDenBlock;
+        const int64_t nb1 = L.nb > 0 ? L.nb : 1;
+        size_t o = 0;
+        L.blk = o;        o = align_up(o + sizeof(int4) * nb1, 256);
+        L.masks = o;      o = align_up(o + sizeof(BlockMasks) * nb1, 256);
+        L.first_keep = o; o = align_up(o + sizeof(int32_t) * (L.keep_tiles + 1), 256);
+        L.first_new = o;  o = align_up(o + sizeof(int32_t) * (L.new_tiles + 1), 256);
+        L.tot = o;        o = align_up(o + 2 * sizeof(int64_t), 256);
+        L.bytes = o;
         return L;
     }
 };
@@ -322,17 +412,23 @@ extern "C" gs_status gs_densify(const gs_densify_rule *rule, const float *params
     const DensifyWs L = DensifyWs::make(n);
     char *b = static_cast<char *>(ws);
     int4 *blk = reinterpret_cast<int4 *>(b + L.blk);
+    BlockMasks *masks = reinterpret_cast<BlockMasks *>(b + L.masks);
+    int32_t *first_keep = reinterpret_cast<int32_t *>(b + L.first_keep);
+    int32_t *first_new = reinterpret_cast<int32_t *>(b + L.first_new);
     int64_t *tot = reinterpret_cast<int64_t *>(b + L.tot);
-    const int64_t nb = (n + kDenBlock - 1) / kDenBlock;
+    const int64_t nb = L.nb;
     if (nb > 0)
         hipLaunchKernelGGL(densify_count_kernel, dim3(xcd_grid(nb)), dim3(kDenThreads), 0, st, *rule,
-                           params, stats, n, n_cap, nb, blk);
+                           params, stats, n, n_cap, nb, blk, masks);
     hipLaunchKernelGGL(densify_scan_kernel, dim3(1), dim3(kScanThreads), 0, st, blk, nb, n, tot,
                        d_counts);
-    if (nb > 0)
-        hipLaunchKernelGGL(densify_scatter_kernel, dim3(xcd_grid(nb)), dim3(kDenThreads), 0, st, *rule,
-                           params, m, v, stats, noise, n, n_cap, out_params, out_m, out_v, out_cap, nb,
-                           blk, tot);
+    if (nb > 0) {
+        hipLaunchKernelGGL(densify_tables_kernel, dim3((nb + kDenThreads - 1) / kDenThreads),
+                           dim3(kDenThreads), 0, st, blk, nb, tot, first_keep, first_new);
+        hipLaunchKernelGGL(densify_gather_kernel, dim3(L.keep_tiles + L.new_tiles), dim3(kDenThreads), 0,
+                           st, *rule, params, m, v, noise, n_cap, out_params, out_m, out_v, out_cap, nb,
+                           L.keep_tiles, blk, masks, first_keep, first_new, tot);
+    }
     GS_CHECK_LAUNCH();
     return GS_OK;
 }
