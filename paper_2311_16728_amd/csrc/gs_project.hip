@@ -608,8 +608,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
 #pragma unroll
         for (int i = 0; i < 4; ++i) gq[i] = (dq[i] - G.q[i] * dot) * G.qinv;
     }
+    // d o / d logit = o (1 - o); for o > 1/2, 1 - o = e^-logit o avoids the
+    // cancellation that leaves saturated opacities few significant bits
+    const float one_minus_o = G.o > 0.5f ? __expf(-raw[10]) * G.o : 1.f - G.o;
     float geo[11] = {gmu[0], gmu[1], gmu[2], gls[0], gls[1], gls[2],
-                     gq[0], gq[1], gq[2], gq[3], gop * G.o * (1.f - G.o)};
+                     gq[0], gq[1], gq[2], gq[3], gop * G.o * one_minus_o};
     sink.group(0, 1, g, n_cap, geo, raw, sc);
     sink.finish_updated(s, g, n_cap, views, n_views, geo, &keep2[0][threadIdx.x]);
 }
