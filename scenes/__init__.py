@@ -40,4 +40,6 @@ from .gen import (  # noqa: F401
     ROOM_LO,
     ROOM_HI,
     densify_case,
+    degenerate_scene,
+    DEGENERATE_KINDS,
 )

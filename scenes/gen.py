@@ -215,3 +215,79 @@ def densify_case(seed: int, n: int, n_views: int = 2, extent: float = 10.0, n_ca
     sizes = [((1200, 680), (640, 480), (752, 480))[i % 3] for i in range(n_views)]
     return dict(params=p, m=m, v=v, stats=stats, noise=noise, acc=acc, sizes=sizes, n=n, n_cap=n_cap,
                 extent=extent)
+
+
+DEGENERATE_KINDS = {"normal": 200, "behind": 60, "near": 40, "near_plane": 80, "offscreen": 60,
+                    "huge": 12, "needle": 100, "faint": 60, "opaque": 40, "dark": 80, "tie": 6}
+
+
+def degenerate_scene(seed: int = 0):
+    """Edge cases of projection and compositing on a ragged 97x61 camera (f=80).
+
+    ``DEGENERATE_KINDS`` gives the number of primitives of each kind, all in
+    front of the camera at depth 1.5-3 m unless stated: normal (as
+    ``draw_gaussians``); behind (depth -3 to -0.05: culled); near (depth
+    0.21-0.5, small: large footprints); near_plane (depth within 0.002-0.03 of
+    0.2 on either side: culled or kept); offscreen (image coordinates up to
+    three half-widths outside the view, 0.3-1 m wide: the field-of-view clamp
+    of the projection Jacobian); huge (1-3 m wide, opacity 0.03-0.08: every
+    tile); needle (one axis 1000x the other two); faint (opacity below 1/255:
+    never composited); opaque (opacity logit 10-14: the 0.99 clamp and early
+    stops); dark (negative colour before the clamp); tie (exact copies of
+    normal primitives: equal depths, ordered by index).
+
+    Returns (params, cam, kinds) with ``kinds`` the kind index per column.
+    """
+    rng = np.random.default_rng(seed)
+    W, H, f = 97, 61, 80.0
+    cam = pinhole(W, H, f, f, W / 2.0 + 0.3, H / 2.0 - 0.2)
+    names = list(DEGENERATE_KINDS)
+    counts = [DEGENERATE_KINDS[k] for k in names]
+    n = sum(counts)
+    p = np.zeros((NROWS, pad_cap(n)), np.float32)
+    kinds = np.repeat(np.arange(len(names)), counts)
+    starts = np.concatenate([[0], np.cumsum(counts)])
+
+    def in_view(m, z, margin=1.0):
+        u = rng.uniform(-margin, margin, m) * (W / 2.0) / f
+        v = rng.uniform(-margin, margin, m) * (H / 2.0) / f
+        return np.stack([u * z, v * z, z])
+
+    base = draw_gaussians(rng, n, (0, 0, 0), (1, 1, 1))[:, :n]
+    mu = np.zeros((3, n))
+    for i, name in enumerate(names):
+        k = counts[i]
+        cols = slice(starts[i], starts[i + 1])
+        z = rng.uniform(1.5, 3.0, k)
+        if name == "behind":
+            z = rng.uniform(-3.0, -0.05, k)
+        elif name == "near":
+            z = rng.uniform(0.21, 0.5, k)
+        elif name == "near_plane":
+            z = 0.2 + rng.choice([-1.0, 1.0], k) * rng.uniform(0.002, 0.03, k)
+        mu[:, cols] = in_view(k, z, 3.0 if name == "offscreen" else 1.0)
+        if name == "behind":
+            mu[:2, cols] = rng.uniform(-1, 1, (2, k))
+        if name == "near":
+            base[3:6, cols] = rng.normal(-5.0, 0.3, (3, k))
+        elif name == "offscreen":
+            base[3:6, cols] = np.log(rng.uniform(0.3, 1.0, (3, k)))
+        elif name == "huge":
+            base[3:6, cols] = np.log(rng.uniform(1.0, 3.0, (3, k)))
+            base[10, cols] = rng.uniform(-3.5, -2.5, k)
+        elif name == "needle":
+            base[3, cols] = rng.normal(-2.0, 0.2, k)
+            base[4:6, cols] = base[3, cols] - math.log(1000.0)
+        elif name == "faint":
+            base[10, cols] = rng.uniform(-9.0, -6.0, k)
+        elif name == "opaque":
+            base[10, cols] = rng.uniform(10.0, 14.0, k)
+            base[3:6, cols] = rng.normal(-4.0, 0.3, (3, k))
+        elif name == "dark":
+            base[11:14, cols] = rng.normal(-2.0, 0.3, (3, k))
+    p[:, :n] = base
+    p[0:3, :n] = mu
+    t = names.index("tie")
+    src = rng.choice(counts[0], counts[t], replace=False)   # copies of normal primitives
+    p[:, starts[t]:starts[t + 1]] = p[:, src]
+    return p, cam, kinds

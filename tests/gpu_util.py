@@ -72,10 +72,10 @@ def group_rel_err(g, ref, ids):
     return out
 
 
-def check_gradients(g, ref, candidates, label="", n_sample=64, tol=1e-3, seed=0):
+def check_gradients(g, ref, candidates, label="", n_sample=64, tol=1e-3, seed=0, p99=0.1):
     """The gradient metric: 64 Gaussians drawn with `seed` from `candidates`
     (Gaussians with a composited pixel) must have relative error <= tol in every
-    group; over all candidates the 99th percentile must stay <= 0.1 tol and the
+    group; over all candidates the 99th percentile must stay <= p99 * tol and the
     worst case <= 5 tol (scalar groups such as the opacity can cancel over
     random-sign pixel weights, which amplifies FP32 rounding of single terms)."""
     candidates = np.asarray(candidates)
@@ -88,5 +88,5 @@ def check_gradients(g, ref, candidates, label="", n_sample=64, tol=1e-3, seed=0)
               f"max {every[k].max():.2e}")
     for k in sampled:
         assert sampled[k].max() <= tol, (k, float(sampled[k].max()))
-        assert np.quantile(every[k], 0.99) <= 0.1 * tol, k
+        assert np.quantile(every[k], 0.99) <= p99 * tol, k
         assert every[k].max() <= 5 * tol, k

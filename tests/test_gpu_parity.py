@@ -36,9 +36,27 @@ def _cases():
     yield "tiny", p, 2000, cam
     p1, _, _ = scenes.tiny_scene(3, n=1500)
     yield "ragged", p1, 1500, RAGGED
+    p2, cam2, kinds = scenes.degenerate_scene(0)
+    yield "degenerate", p2, kinds.size, cam2
 
 
-@pytest.mark.parametrize("case", ["tiny", "ragged"])
+CASES = ["tiny", "ragged", "degenerate"]
+# Share of pixels the oracle may flag as FP32-ambiguous.  The degenerate scene
+# holds exact copies (depth ties: every pixel a copy reaches is flagged, although
+# both orders give the same image) and 3 cm primitives just past the near plane
+# (long cutoff edges), about 7.5 % together.
+AMB_SHARE = {"tiny": 0.01, "ragged": 0.01, "degenerate": 0.08}
+# Gaussians with a nonzero gradient the backward case must reach at least.
+MIN_COMPOSITED = {"tiny": 500, "ragged": 500, "degenerate": 300}
+# 99th percentile of the relative gradient error over all composited Gaussians,
+# in units of the 1e-3 tolerance.  In the degenerate scene a few needles (axis
+# ratio 1000, a 2D covariance near the dilation floor) have log-scale gradients
+# that the random-sign pixel weights cancel to ~1 % of their size under |W|, so
+# FP32 rounding of the single terms shows up ~100x larger relative to the sum.
+GRAD_P99 = {"tiny": 0.1, "ragged": 0.1, "degenerate": 0.3}
+
+
+@pytest.mark.parametrize("case", CASES)
 def test_preprocess_records(orc, case):
     name, p, n, cam = [c for c in _cases() if c[0] == case][0]
     plan = plan_for([cam], n_cap=p.shape[1])
@@ -58,7 +76,7 @@ def test_preprocess_records(orc, case):
     np.testing.assert_allclose(rgbz[:n][v, :3], rec[v][:, 8:11], rtol=0, atol=5e-6)
 
 
-@pytest.mark.parametrize("case", ["tiny", "ragged"])
+@pytest.mark.parametrize("case", CASES)
 def test_render_forward(orc, case):
     name, p, n, cam = [c for c in _cases() if c[0] == case][0]
     plan = plan_for([cam], n_cap=p.shape[1])
@@ -73,7 +91,7 @@ def test_render_forward(orc, case):
     m_img, m_T, n_amb, _, ok = compare_image(img, T, o)
     print(f"{case}: max|dI|={m_img:.2e} max|dT|={m_T:.2e} ambiguous={n_amb}/{ok.size}")
     assert m_img <= 1e-4 and m_T <= 1e-4
-    assert n_amb <= 0.01 * ok.size
+    assert n_amb <= AMB_SHARE[case] * ok.size
     strict = o["amb"] == 0
     assert np.array_equal(nc[strict], o["n_contrib"][strict])
     assert T.min() >= 1e-4 and T.max() <= 1.0
@@ -90,11 +108,17 @@ def test_render_background_and_empty(orc):
     assert np.all(plan.plane(plan.T, 0).cpu().numpy() == 1.0)
 
 
-def test_tile_lists_sorted_and_complete(orc):
+@pytest.mark.parametrize("case", ["tiny", "degenerate"])
+def test_tile_lists_sorted_and_complete(orc, case):
     """Every tile list is in (depth, index) order without repeats and holds every
-    Gaussian the oracle composites at any of the tile's pixels."""
-    p, _, cam = scenes.tiny_scene(1)
-    n = 2000
+    Gaussian the oracle composites at any of the tile's pixels (exact depth ties
+    of the degenerate scene in index order)."""
+    if case == "tiny":
+        p, _, cam = scenes.tiny_scene(1)
+        n = 2000
+    else:
+        p, cam, kinds = scenes.degenerate_scene(0)
+        n = kinds.size
     plan = plan_for([cam], n_cap=p.shape[1])
     plan.render(_dev(p), n)
     torch.cuda.synchronize()
@@ -121,21 +145,25 @@ def test_tile_lists_sorted_and_complete(orc):
     vals = ws[offs[key]:offs[key] + 4 * plan.pair_cap].view(torch.int32).numpy()
     ranges = ws[offs["ranges"]:offs["ranges"] + 8 * tt].view(torch.int32).numpy().reshape(tt, 2)
     assert ranges[:, 1].max() == npairs
-    W = cam["width"]
+    W, H = cam["width"], cam["height"]
     tx_n = (W + 15) // 16
     rng = np.random.default_rng(0)
-    for tile in rng.choice(tt, size=12, replace=False):
+    ties = 0
+    for tile in (rng.choice(tt, size=12, replace=False) if case == "tiny" else range(tt)):
         a, b = ranges[tile]
         ids = vals[a:b] % plan.n_cap
         assert len(set(ids.tolist())) == len(ids)
         z = rec[ids, 3]
         assert np.all((np.diff(z) > 0) | ((np.diff(z) == 0) & (np.diff(ids) > 0)))
+        ties += int(np.sum(np.diff(z) == 0))
         ty, tx = divmod(int(tile), tx_n)
         want = set()
-        for py in range(ty * 16, ty * 16 + 16, 5):
-            for px in range(tx * 16, tx * 16 + 16, 5):
+        for py in range(ty * 16, min(ty * 16 + 16, H), 5):
+            for px in range(tx * 16, min(tx * 16 + 16, W), 5):
                 want.update(orc.pixel_list(p, n, cam, px, py).tolist())
         assert want <= set(ids.tolist())
+    if case == "degenerate":
+        assert ties > 0
 
 
 @pytest.mark.parametrize("shape", [(64, 64), (53, 37), (680, 1200)])
@@ -204,7 +232,7 @@ def test_pyramid_build(orc, shape):
         assert np.abs(got - lv).max() <= 1e-6
 
 
-@pytest.mark.parametrize("case", ["tiny", "ragged"])
+@pytest.mark.parametrize("case", CASES)
 def test_backward_gradients(orc, case):
     """<W, I> with W ~ U(-1, 1), zero at every pixel where the oracle finds a
     compositing decision within FP32 reach (cutoff, stop or depth order).  Both
@@ -227,8 +255,8 @@ def test_backward_gradients(orc, case):
     ref = orc.render_backward(p, n, cam, Wt)
     norms = np.linalg.norm(ref[:, :n], axis=0)
     ids = np.nonzero(norms > 0)[0]
-    assert len(ids) > 500
-    check_gradients(g, ref, ids, case)
+    assert len(ids) > MIN_COMPOSITED[case]
+    check_gradients(g, ref, ids, case, p99=GRAD_P99[case])
     assert np.all(g[:, n:] == 0)
 
 

@@ -143,3 +143,41 @@ def test_quaternion_normalisation(orc):
     p2[6:10] *= 3.7
     np.testing.assert_allclose(orc.preprocess(p, 50, cam), orc.preprocess(p2, 50, cam), rtol=1e-12,
                                atol=1e-14)
+
+
+def test_degenerate_scene_rules(orc):
+    """Each kind of the degenerate scene meets the rule it was built to reach
+    (camera at the origin looking along +z, so a primitive's depth is its z):
+    culled exactly when z <= 0.2; faint primitives (opacity below 1/255) in no
+    pixel's list; field-of-view clamp for off-screen ones (|x/z| beyond 1.3
+    half-widths); colour clamped for dark ones; an exact copy right behind its
+    source in every pixel list that holds both."""
+    p, cam, kinds = scenes.degenerate_scene(0)
+    n = kinds.size
+    names = list(scenes.DEGENERATE_KINDS)
+    k = {nm: np.nonzero(kinds == i)[0] for i, nm in enumerate(names)}
+    rec = orc.preprocess(p, n, cam)
+    z = p[2, :n].astype(np.float64)
+    assert np.array_equal(rec[:, 0] > 0, z > 0.2)
+    assert np.any(z[k["near_plane"]] > 0.2) and np.any(z[k["near_plane"]] <= 0.2)
+    assert not np.any(rec[k["behind"], 0])
+    u = np.abs(p[0, :n] / p[2, :n]).astype(np.float64)
+    limx = 1.3 * 0.5 * cam["width"] / cam["fx"]
+    assert np.sum(u[k["offscreen"]] > limx) >= 10
+    assert np.all(rec[k["dark"]][:, 11:14].sum(axis=1) >= 1)   # some channel clamped
+    faint = set(k["faint"].tolist())
+    pairs_seen = 0
+    src_of = {}
+    t = k["tie"]
+    for c in t:
+        same = np.nonzero(np.all(p[:, :n] == p[:, [c]], axis=0))[0]
+        src_of[int(c)] = int(same[0])
+    for py in range(0, cam["height"], 4):
+        for px in range(0, cam["width"], 4):
+            ids = orc.pixel_list(p, n, cam, px, py).tolist()
+            assert not faint.intersection(ids)
+            for c, s in src_of.items():
+                if c in ids and s in ids:
+                    assert ids.index(c) == ids.index(s) + 1
+                    pairs_seen += 1
+    assert pairs_seen > 0
