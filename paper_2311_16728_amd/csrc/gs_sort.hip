@@ -51,6 +51,15 @@ __device__ __forceinline__ bool tile_rect(const gs_settings &s, double2 md, floa
 
 // Set-up of a binning call: counters to zero, tile ranges to empty, and
 // (block 0) the targets of each view as a CSR list in target order.
+// Clears the counters and the tile ranges, and lists the targets of every
+// view: view_off[v] = number of targets of views before v, view_list holds
+// the targets view by view in index order.  Workgroup 0 does the lists from
+// the targets' view indices staged in LDS, kSetupChunk at a time: the offset
+// of view v counts the targets of smaller views, a target's place adds the
+// earlier targets of its own view (targets of a view outside [0, n_views) are
+// left out).
+constexpr int kSetupChunk = 1024;
+
 __global__ void __launch_bounds__(256) sort_setup_kernel(const gs_target *__restrict__ targets,
                                                          int32_t n_targets, int32_t n_views,
                                                          uint32_t *__restrict__ counters,
@@ -59,21 +68,47 @@ __global__ void __launch_bounds__(256) sort_setup_kernel(const gs_target *__rest
                                                          uint2 *__restrict__ ranges, int64_t total_tiles) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < total_tiles) ranges[i] = make_uint2(0u, 0u);
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    for (int c = 0; c < kNumCounters; ++c) counters[c] = 0u;
-    for (int v = 0; v <= n_views; ++v) view_off[v] = 0u;
-    for (int t = 0; t < n_targets; ++t) {
-        const int v = targets[t].view;
-        if (v >= 0 && v < n_views) ++view_off[v + 1];
+    if (blockIdx.x != 0) return;
+    const int tid = threadIdx.x;
+    if (tid < kNumCounters) counters[tid] = 0u;
+    __shared__ int32_t tv[kSetupChunk];
+    auto stage = [&](int32_t c0) {
+        __syncthreads();
+        for (int k = tid; k < kSetupChunk; k += 256) {
+            const int32_t t = c0 + k;
+            const int32_t v = t < n_targets ? targets[t].view : -1;
+            tv[k] = (v >= 0 && v < n_views) ? v : -1;
+        }
+        __syncthreads();
+    };
+    for (int32_t v0 = 0; v0 <= n_views; v0 += 256) {
+        const int32_t v = v0 + tid;
+        uint32_t below = 0;
+        for (int32_t c0 = 0; c0 < n_targets; c0 += kSetupChunk) {
+            stage(c0);
+            const int m = n_targets - c0 < kSetupChunk ? n_targets - c0 : kSetupChunk;
+            for (int k = 0; k < m; ++k) below += uint32_t(tv[k] >= 0 && tv[k] < v);
+        }
+        if (v <= n_views) view_off[v] = below;
     }
-    for (int v = 0; v < n_views; ++v) view_off[v + 1] += view_off[v];
-    // place each target at its view's cursor (view_off[v] runs to view_off[v + 1])
-    for (int t = 0; t < n_targets; ++t) {
-        const int v = targets[t].view;
-        if (v >= 0 && v < n_views) view_list[view_off[v]++] = uint32_t(t);
+    for (int32_t t0 = 0; t0 < n_targets; t0 += 256) {
+        const int32_t t = t0 + tid;
+        int32_t mv = -1;
+        if (t < n_targets) {
+            const int32_t v = targets[t].view;
+            mv = (v >= 0 && v < n_views) ? v : -1;
+        }
+        uint32_t place = 0;
+        for (int32_t c0 = 0; c0 < n_targets; c0 += kSetupChunk) {
+            stage(c0);
+            const int m = n_targets - c0 < kSetupChunk ? n_targets - c0 : kSetupChunk;
+            for (int k = 0; k < m; ++k) {
+                const int32_t w = tv[k];
+                place += uint32_t(w >= 0 && (w < mv || (w == mv && c0 + k < t)));
+            }
+        }
+        if (mv >= 0) view_list[place] = uint32_t(t);
     }
-    for (int v = n_views; v > 0; --v) view_off[v] = view_off[v - 1];
-    view_off[0] = 0u;
 }
 
 // A tile rectangle that holds no tile (x0 = 1 > x1 = 0): count 0.
@@ -310,19 +345,17 @@ constexpr int kEmitPer = 4;
 constexpr int kEmitChunk = kScanThreads * kEmitPer;
 constexpr int kEmitCache = 4;   // targets per view held in registers (pyramid levels)
 
-__global__ void __launch_bounds__(256) emit_kernel(int64_t n_cap, const gs_target *__restrict__ targets,
-                                                   uint32_t *__restrict__ counters,
-                                                   const uint32_t *__restrict__ vis_val,
-                                                   const uint32_t *__restrict__ vis_off,
-                                                   const uint2 *__restrict__ rects,
-                                                   const uint32_t *__restrict__ view_off,
-                                                   const uint32_t *__restrict__ view_list,
-                                                   const uint32_t *__restrict__ chunk_first,
-                                                   int64_t pair_cap, uint32_t *__restrict__ pkey,
-                                                   uint32_t *__restrict__ pval,
-                                                   uint32_t *__restrict__ d_status) {
+// 64 VGPRs: eight waves per SIMD for this latency-bound kernel (66 otherwise)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
+emit_kernel(int64_t n_cap, const gs_target *__restrict__ targets, uint32_t *__restrict__ counters,
+            const uint32_t *__restrict__ vis_val, const uint32_t *__restrict__ vis_off,
+            const uint2 *__restrict__ rects, const uint32_t *__restrict__ view_off,
+            const uint32_t *__restrict__ view_list, const uint32_t *__restrict__ chunk_first,
+            int64_t pair_cap, uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval,
+            uint32_t *__restrict__ d_status) {
     __shared__ uint32_t off[kEmitChunk];
-    __shared__ uint32_t mark[kEmitChunk];
+    __shared__ uint32_t srcs[kEmitChunk];            // record ids, staged with the offsets
+    __shared__ uint32_t mark[kEmitChunk / 32];       // bit per slot: a record starts there
     __shared__ uint32_t lds[8];
     const uint32_t V = counters[kVisible];
     const uint32_t P = counters[kPairs];
@@ -342,12 +375,14 @@ __global__ void __launch_bounds__(256) emit_kernel(int64_t n_cap, const gs_targe
                                 ? chunk_first[(chunk + 1) * (kEmitChunk / kScanThreads)]
                                 : V - 1u;
         __syncthreads();
+        if (tid < kEmitChunk / 32) mark[tid] = 0u;
 #pragma unroll
         for (int r = 0; r < kEmitPer; ++r) {
             const int i = tid + r * kScanThreads;
-            mark[i] = 0u;
             const uint32_t j = j0 + uint32_t(i);
-            off[i] = (j <= j1 && j < V) ? vis_off[j] : 0xffffffffu;
+            const bool in = j <= j1 && j < V;
+            off[i] = in ? vis_off[j] : 0xffffffffu;
+            srcs[i] = in ? vis_val[j] : 0u;
         }
         __syncthreads();
         // records after the first start strictly after o0
@@ -355,12 +390,15 @@ __global__ void __launch_bounds__(256) emit_kernel(int64_t n_cap, const gs_targe
         for (int r = 0; r < kEmitPer; ++r) {
             const int i = tid + r * kScanThreads;
             const uint32_t rel = off[i] - o0;
-            if (i > 0 && j0 + uint32_t(i) < V && rel < uint32_t(kEmitChunk)) mark[rel] = 1u;
+            if (i > 0 && j0 + uint32_t(i) < V && rel < uint32_t(kEmitChunk))
+                atomicOr(&mark[rel >> 5], 1u << (rel & 31u));
         }
         __syncthreads();
+        static_assert(32 % kEmitPer == 0, "a thread's slots lie in one mark word");
+        const uint32_t mword = mark[(tid * kEmitPer) >> 5] >> ((tid * kEmitPer) & 31);
         uint32_t mk[kEmitPer], msum = 0;
 #pragma unroll
-        for (int i = 0; i < kEmitPer; ++i) { mk[i] = mark[tid * kEmitPer + i]; msum += mk[i]; }
+        for (int i = 0; i < kEmitPer; ++i) { mk[i] = (mword >> i) & 1u; msum += mk[i]; }
         uint32_t total;
         uint32_t rec = block_exclusive_scan(msum, lds, &total);   // records started before my slots
         uint32_t key[kEmitPer], val[kEmitPer];
@@ -379,7 +417,7 @@ __global__ void __launch_bounds__(256) emit_kernel(int64_t n_cap, const gs_targe
             if (o >= Pc) continue;
             if (rec != cur) {   // first slot of this thread in a record
                 cur = rec;
-                src = vis_val[j0 + rec];   // record v * n_cap + g
+                src = srcs[rec];   // record v * n_cap + g
                 base = off[rec];
                 v = src / uint32_t(n_cap);
                 g = src - v * uint32_t(n_cap);
@@ -674,12 +712,31 @@ static int radix_sort(const uint32_t *n_ptr, uint32_t *kbuf[2], uint32_t *vbuf[2
 __global__ void __launch_bounds__(256) ranges_kernel(const uint32_t *__restrict__ counters,
                                                      const uint32_t *__restrict__ keys,
                                                      uint2 *__restrict__ ranges) {
-    const uint32_t P = counters[kPairsClamped];
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < P;
-         i += int64_t(gridDim.x) * blockDim.x) {
-        const uint32_t k = keys[i];
-        if (i == 0 || keys[i - 1] != k) ranges[k].x = uint32_t(i);
-        if (i == P - 1 || keys[i + 1] != k) ranges[k].y = uint32_t(i + 1);
+    // four consecutive keys per thread (one 16-byte load) and the keys on
+    // either side; 0xffffffff (never a tile index) stands beyond both ends
+    constexpr uint32_t kNone = 0xffffffffu;
+    const int64_t P = counters[kPairsClamped];
+    const int64_t groups = (P + 3) / 4;
+    for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < groups;
+         q += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t e0 = 4 * q;
+        uint32_t k[6];
+        k[0] = e0 > 0 ? keys[e0 - 1] : kNone;
+        if (e0 + 4 <= P) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(keys + e0);
+            k[1] = v.x; k[2] = v.y; k[3] = v.z; k[4] = v.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) k[1 + j] = e0 + j < P ? keys[e0 + j] : kNone;
+        }
+        k[5] = e0 + 4 < P ? keys[e0 + 4] : kNone;
+#pragma unroll
+        for (int j = 1; j <= 4; ++j) {
+            const int64_t e = e0 + j - 1;
+            if (e >= P) break;
+            if (k[j - 1] != k[j]) ranges[k[j]].x = uint32_t(e);
+            if (k[j + 1] != k[j]) ranges[k[j]].y = uint32_t(e + 1);
+        }
     }
 }
 
