@@ -565,7 +565,16 @@ __global__ void __launch_bounds__(256) radix_scatter_kernel(
     __shared__ uint32_t lds[8];
     const uint32_t n = *n_ptr;
     const int64_t nb = (int64_t(n) + kTileN - 1) / kTileN;
-    if (int64_t(blockIdx.x) >= nb) return;   // uniform over the workgroup
+    // each XCD takes consecutive sort blocks, whose digit runs meet in the same
+    // cache lines, so the partial lines at run ends are completed in one L2.
+    // The first T workgroups share the blocks (T a multiple of the XCD count,
+    // as is the grid, and no larger than the blocks need, so that every XCD
+    // gets some when there are fewer blocks than workgroups).
+    const int64_t nb8 = (nb + kXcds - 1) / kXcds * kXcds;
+    const int64_t T = nb8 < int64_t(gridDim.x) ? nb8 : int64_t(gridDim.x);
+    if (int64_t(blockIdx.x) >= T) return;
+    const int64_t w0 = xcd_tile(blockIdx.x, T);
+    if (w0 >= nb) return;   // uniform over the workgroup
     const int tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
     {
         uint32_t v[kPer], sum = 0, total;
@@ -575,7 +584,7 @@ __global__ void __launch_bounds__(256) radix_scatter_kernel(
 #pragma unroll
         for (int j = 0; j < kPer; ++j) { dbase[tid * kPer + j] = pre; pre += v[j]; }
     }
-    for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    for (int64_t b = w0; b < nb; b += T) {
         const int64_t base = b * kTileN;
 #pragma unroll
         for (int j = 0; j < kPer; ++j)
@@ -701,7 +710,7 @@ static int radix_sort(const uint32_t *n_ptr, uint32_t *kbuf[2], uint32_t *vbuf[2
                            kbuf[cur], shift, B.hist, B.max_blocks);
         hipLaunchKernelGGL(radix_rowscan_kernel<kItems>, dim3(1 << kBits), dim3(256), 0, st, n_ptr, B.hist,
                            B.max_blocks, B.digit);
-        hipLaunchKernelGGL((radix_scatter_kernel<kItems, kBits>), dim3(grid), dim3(256), 0, st, n_ptr,
+        hipLaunchKernelGGL((radix_scatter_kernel<kItems, kBits>), dim3(xcd_grid(grid)), dim3(256), 0, st, n_ptr,
                            kbuf[cur], vbuf[cur], kbuf[cur ^ 1], vbuf[cur ^ 1], shift, B.hist, B.max_blocks,
                            B.digit);
         cur ^= 1;
