@@ -237,7 +237,7 @@ extern "C" size_t gs_sim3_workspace_bytes(int32_t n_transforms) {
 
 extern "C" gs_status gs_sim3_apply(float *params, int64_t n, int64_t n_cap, const gs_sim3 *transforms,
                                    int32_t n_transforms, const int32_t *assign, void *ws, void *stream) {
-    if (!params || !transforms || !ws || n < 0 || n > n_cap || n_transforms <= 0)
+    if (!params || !transforms || !ws || n < 0 || n > n_cap || n_cap % 64 || n_transforms <= 0)
         return GS_ERR_INVALID_ARGUMENT;
     if (n == 0) return GS_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);

@@ -121,3 +121,44 @@ def test_binding_rejects_wrong_tensors():
     on_host = torch.zeros(59, 64, dtype=torch.float32)
     with pytest.raises(gs.GsError, match="device"):
         gs.gs_preprocess(s, on_host, 1, None, 1, None)
+
+
+def test_size_limits_rejected_on_the_host():
+    """The size limits the header states are checked before anything is
+    enqueued: pair capacity below 2^31 and (view, Gaussian) records below 2^32
+    for binning, column capacities below 2^31 for densification, a tile grid
+    that fits int32, tile widths 8 / 16 / 32 only, and column capacities that
+    are multiples of 64 for the loop-closure correction."""
+    from paper_2311_16728_amd import gs
+    import scenes
+
+    lib = gs._lib
+    one = C.c_void_p(16)
+    s = gs.default_settings()
+    INVALID, CAPACITY = 1, 2
+    # binning: pair_cap = 2^31, then 65 views x 2^26 columns (> 2^32 records)
+    assert lib.gs_bin_sort(C.byref(s), one, 10, 256, 1, one, 1, 16, one, 1 << 31, one, None) == INVALID
+    assert lib.gs_bin_sort(C.byref(s), one, 10, 1 << 26, 65, one, 1, 16, one, 1 << 20, one, None) == INVALID
+    # densification: input or output capacity 2^31
+    rule = gs.densify_rule(5.0)
+    assert lib.gs_densify(C.byref(rule), one, one, one, one, one, 10, 1 << 31, one, one, one, 256, one, one,
+                          None) == INVALID
+    assert lib.gs_densify(C.byref(rule), one, one, one, one, one, 10, 256, one, one, one, 1 << 31, one, one,
+                          None) == INVALID
+    assert lib.gs_densify(C.byref(rule), one, one, one, one, one, 10, 256, one, one, one, 100, one, one,
+                          None) == INVALID                          # out_cap not a multiple of 64
+    # loop closure: n_cap not a multiple of 64, no transform
+    assert lib.gs_sim3_apply(one, 10, 100, one, 1, None, one, None) == INVALID
+    assert lib.gs_sim3_apply(one, 10, 256, one, 0, None, one, None) == INVALID
+    # tile grid: 2^30 x 2^30 pixels in 16 x 16 tiles overflow int32 tile indices
+    big = [gs.make_view(scenes.pinhole(1 << 30, 1 << 30, 1000.0))]
+    vbig = (gs.gs_view * 1)(*big)
+    tg = (gs.gs_target * 1)()
+    tg[0].view, tg[0].level, tg[0].tile_w = 0, 0, 16
+    tot_p, tot_t = C.c_int64(), C.c_int32()
+    assert lib.gs_targets_layout(vbig, 1, tg, 1, C.byref(tot_p), C.byref(tot_t)) == CAPACITY
+    # tile widths other than 8 / 16 / 32
+    small = (gs.gs_view * 1)(gs.make_view(scenes.pinhole(64, 64, 64.0)))
+    for w, want in ((12, INVALID), (64, INVALID), (8, 0), (32, 0)):
+        tg[0].tile_w = w
+        assert lib.gs_targets_layout(small, 1, tg, 1, C.byref(tot_p), C.byref(tot_t)) == want, w
