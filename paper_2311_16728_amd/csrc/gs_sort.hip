@@ -87,6 +87,7 @@ __global__ void __launch_bounds__(256) sort_setup_kernel(const gs_target *__rest
         for (int32_t c0 = 0; c0 < n_targets; c0 += kSetupChunk) {
             stage(c0);
             const int m = n_targets - c0 < kSetupChunk ? n_targets - c0 : kSetupChunk;
+#pragma unroll 8
             for (int k = 0; k < m; ++k) below += uint32_t(tv[k] >= 0 && tv[k] < v);
         }
         if (v <= n_views) view_off[v] = below;
@@ -102,6 +103,7 @@ __global__ void __launch_bounds__(256) sort_setup_kernel(const gs_target *__rest
         for (int32_t c0 = 0; c0 < n_targets; c0 += kSetupChunk) {
             stage(c0);
             const int m = n_targets - c0 < kSetupChunk ? n_targets - c0 : kSetupChunk;
+#pragma unroll 8
             for (int k = 0; k < m; ++k) {
                 const int32_t w = tv[k];
                 place += uint32_t(w >= 0 && (w < mv || (w == mv && c0 + k < t)));

@@ -418,3 +418,17 @@ def test_pair_overflow_is_reported():
     T = small.plane(small.T, 0)
     assert torch.isfinite(img).all()
     assert bool(((T >= 1e-4) & (T <= 1.0)).all())
+
+
+@pytest.mark.parametrize("offset,count", [(0, 4096), (0, 1027), (1, 1024), (3, 5), (0, 3), (2, 1)])
+def test_fill_aligned_unaligned_and_tail(offset, count):
+    """gs_fill writes exactly [offset, offset + count) of a buffer, whether the
+    start is 16-byte aligned (four floats per store) or not."""
+    from paper_2311_16728_amd import gs
+
+    buf = torch.full((count + 16,), -1.0, dtype=torch.float32, device="cuda")
+    gs.gs_fill(buf[offset:offset + count], 2.5)
+    torch.cuda.synchronize()
+    h = buf.cpu().numpy()
+    assert np.all(h[offset:offset + count] == 2.5)
+    assert np.all(h[:offset] == -1.0) and np.all(h[offset + count:] == -1.0)
