@@ -280,17 +280,23 @@ __global__ void __launch_bounds__(256) compact_scatter_kernel(const uint32_t *__
     }
 }
 
-// Exclusive scan of counts[vis_val[j]] over the sorted visible list.
+// Exclusive scan of counts[vis_val[j]] over the sorted visible list.  The
+// reduce gathers the counts once and also stores them in list order
+// (sorted_cnt), so the scatter reads them sequentially.
 __global__ void __launch_bounds__(256) offsets_reduce_kernel(const uint32_t *__restrict__ n_ptr,
                                                              const uint32_t *__restrict__ counts,
                                                              const uint32_t *__restrict__ vis_val,
+                                                             uint32_t *__restrict__ sorted_cnt,
                                                              uint32_t *bsum) {
-    block_reduce_to(*n_ptr, bsum, [&](int64_t e) { return counts[vis_val[e]]; });
+    block_reduce_to(*n_ptr, bsum, [&](int64_t e) {
+        const uint32_t c = counts[vis_val[e]];
+        sorted_cnt[e] = c;
+        return c;
+    });
 }
 
 __global__ void __launch_bounds__(256) offsets_scatter_kernel(const uint32_t *__restrict__ n_ptr,
-                                                              const uint32_t *__restrict__ counts,
-                                                              const uint32_t *__restrict__ vis_val,
+                                                              const uint32_t *__restrict__ sorted_cnt,
                                                               const uint32_t *__restrict__ bsum,
                                                               uint32_t *__restrict__ vis_off,
                                                               uint32_t *__restrict__ chunk_first,
@@ -304,7 +310,7 @@ __global__ void __launch_bounds__(256) offsets_scatter_kernel(const uint32_t *__
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         const int64_t e = base + k * kScanThreads + threadIdx.x;
-        c[k] = e < int64_t(n) ? counts[vis_val[e]] : 0u;
+        c[k] = e < int64_t(n) ? sorted_cnt[e] : 0u;
         const uint32_t inc = wave_inclusive_scan(c[k]);
         pre[k] = inc - c[k];
         if (lane == kWave - 1) wtot[k][wave] = inc;
@@ -781,14 +787,16 @@ extern "C" gs_status gs_bin_sort(const gs_settings *s, const void *proj_ws, int6
     // depth order (three 9-bit passes over the 27-bit keys)
     static_assert(kDepthKeyBits == 3 * 9, "depth key width");
     int cur = radix_sort<4, 9>(B.counters + kVisible, B.vk, B.vv, 0, 0, 3, S, B, st);
-    // pair offsets in depth order
+    // pair offsets in depth order; the depth keys are not needed any more, so
+    // their other buffer takes the counts in list order
+    uint32_t *sorted_cnt = B.vk[cur ^ 1];
     hipLaunchKernelGGL(offsets_reduce_kernel, dim3(sblocks), dim3(256), 0, st, B.counters + kVisible,
-                       B.counts, B.vv[cur], B.bsum);
+                       B.counts, B.vv[cur], sorted_cnt, B.bsum);
     hipLaunchKernelGGL(scan_bsums_kernel, dim3(1), dim3(1024), 0, st, B.counters + kVisible, B.bsum,
                        B.counters + kPairs, int64_t(0));
     const int64_t n_chunks = pair_chunks(pair_cap);
     hipLaunchKernelGGL(offsets_scatter_kernel, dim3(sblocks), dim3(256), 0, st, B.counters + kVisible,
-                       B.counts, B.vv[cur], B.bsum, B.voff, B.chunk_first, n_chunks);
+                       sorted_cnt, B.bsum, B.voff, B.chunk_first, n_chunks);
     const int64_t persistent = 256 * 16;   // 16 workgroups per CU, grid-stride beyond
     const int64_t emit_chunks = (pair_cap + kEmitChunk - 1) / kEmitChunk;
     hipLaunchKernelGGL(emit_kernel, dim3(emit_chunks < persistent ? emit_chunks : persistent), dim3(256), 0, st,
