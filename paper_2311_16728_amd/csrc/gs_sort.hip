@@ -254,17 +254,19 @@ __global__ void __launch_bounds__(256) compact_scatter_kernel(const uint32_t *__
                                                               int64_t S, Proj proj, float znear,
                                                               const uint32_t *__restrict__ bsum,
                                                               uint32_t *__restrict__ vis_key,
-                                                              uint32_t *__restrict__ vis_val) {
+                                                              uint32_t *__restrict__ vis_val,
+                                                              uint32_t *__restrict__ vis_cnt) {
     __shared__ uint32_t wtot[kScanItems][kScanThreads / kWave];
     const int64_t base = int64_t(blockIdx.x) * kScanTile;
     if (base >= S) return;
     const int wave = threadIdx.x / kWave, lane = lane_id();
     uint64_t masks[kScanItems];
+    uint32_t c[kScanItems];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         const int64_t e = base + k * kScanThreads + threadIdx.x;
-        const bool f = e < S && counts[e] != 0u;
-        masks[k] = __ballot(f);
+        c[k] = e < S ? counts[e] : 0u;
+        masks[k] = __ballot(c[k] != 0u);
         if (lane == 0) wtot[k][wave] = uint32_t(__popcll(masks[k]));
     }
     round_wave_offsets(wtot);
@@ -276,23 +278,17 @@ __global__ void __launch_bounds__(256) compact_scatter_kernel(const uint32_t *__
             const uint32_t at = b0 + wtot[k][wave] + uint32_t(mask_rank(masks[k]));
             vis_key[at] = depth_key(proj.rgb_z[e].w, znear);
             vis_val[at] = uint32_t(e);
+            vis_cnt[at] = c[k];
         }
     }
 }
 
-// Exclusive scan of counts[vis_val[j]] over the sorted visible list.  The
-// reduce gathers the counts once and also stores them in list order
-// (sorted_cnt), so the scatter reads them sequentially.
+// Exclusive scan of the pair counts over the depth-sorted visible list
+// (sorted_cnt: the counts carried through the depth sort, in list order).
 __global__ void __launch_bounds__(256) offsets_reduce_kernel(const uint32_t *__restrict__ n_ptr,
-                                                             const uint32_t *__restrict__ counts,
-                                                             const uint32_t *__restrict__ vis_val,
-                                                             uint32_t *__restrict__ sorted_cnt,
+                                                             const uint32_t *__restrict__ sorted_cnt,
                                                              uint32_t *bsum) {
-    block_reduce_to(*n_ptr, bsum, [&](int64_t e) {
-        const uint32_t c = counts[vis_val[e]];
-        sorted_cnt[e] = c;
-        return c;
-    });
+    block_reduce_to(*n_ptr, bsum, [&](int64_t e) { return sorted_cnt[e]; });
 }
 
 __global__ void __launch_bounds__(256) offsets_scatter_kernel(const uint32_t *__restrict__ n_ptr,
@@ -554,10 +550,12 @@ __global__ void __launch_bounds__(256) radix_rowscan_kernel(const uint32_t *__re
 // in digit order in LDS and written so that consecutive threads write
 // consecutive addresses of each digit's run.  Order inside a digit is the
 // input order (stable).
-template <int kItems, int kBits>
+// kCarry: a second value array (cin -> cout) moves with the keys.
+template <int kItems, int kBits, bool kCarry>
 __global__ void __launch_bounds__(256) radix_scatter_kernel(
     const uint32_t *__restrict__ n_ptr, const uint32_t *__restrict__ kin,
     const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+    const uint32_t *__restrict__ cin, uint32_t *__restrict__ cout,
     int shift, const uint32_t *__restrict__ hist, int64_t max_blocks,
     const uint32_t *__restrict__ digit) {
     constexpr int kBins = 1 << kBits, kPer = kBins / kScanThreads;
@@ -570,6 +568,7 @@ __global__ void __launch_bounds__(256) radix_scatter_kernel(
     __shared__ uint32_t wcnt[kWaves][kBins];  // per-wave digit counts, then per-wave offsets
     __shared__ uint32_t skey[kTileN];
     __shared__ uint32_t sval[kTileN];
+    __shared__ uint32_t scar[kCarry ? kTileN : 1];
     __shared__ uint32_t lds[8];
     const uint32_t n = *n_ptr;
     const int64_t nb = (int64_t(n) + kTileN - 1) / kTileN;
@@ -599,7 +598,7 @@ __global__ void __launch_bounds__(256) radix_scatter_kernel(
 #pragma unroll
             for (int w = 0; w < kWaves; ++w) wcnt[w][tid * kPer + j] = 0;
         __syncthreads();
-        uint32_t key[kItems], val[kItems], pos[kItems];
+        uint32_t key[kItems], val[kItems], car[kItems], pos[kItems];
         const int64_t wbase = base + int64_t(wave) * kWaveN;
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
@@ -607,6 +606,7 @@ __global__ void __launch_bounds__(256) radix_scatter_kernel(
             const bool valid = e < n;
             key[k] = valid ? kin[e] : 0u;
             val[k] = valid ? vin[e] : 0u;
+            car[k] = (kCarry && valid) ? cin[e] : 0u;
         }
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
@@ -657,6 +657,7 @@ __global__ void __launch_bounds__(256) radix_scatter_kernel(
                 const uint32_t p = lstart[d] + wcnt[wave][d] + pos[k];
                 skey[p] = key[k];
                 sval[p] = val[k];
+                if (kCarry) scar[p] = car[k];
             }
         }
         __syncthreads();
@@ -667,6 +668,7 @@ __global__ void __launch_bounds__(256) radix_scatter_kernel(
             const uint32_t p = gbase[d] + (uint32_t(i) - lstart[d]);
             kout[p] = k2;
             vout[p] = sval[i];
+            if (kCarry) cout[p] = scar[i];
         }
         __syncthreads();
     }
@@ -706,10 +708,11 @@ static SortBufs sort_bufs(void *ws, int32_t n_views, int32_t n_targets, int64_t 
 
 // Sorts (kbuf[cur], vbuf[cur]) through the two buffers over `passes` kBits
 // digits starting at bit first_bit; returns the buffer index holding the result.
-template <int kItems, int kBits>
+// With kCarry, cbuf[cur] moves along as a second value array.
+template <int kItems, int kBits, bool kCarry = false>
 static int radix_sort(const uint32_t *n_ptr, uint32_t *kbuf[2], uint32_t *vbuf[2], int cur,
                       int first_bit, int passes, int64_t capacity, const SortBufs &B,
-                      hipStream_t st) {
+                      hipStream_t st, uint32_t *const *cbuf = nullptr) {
     const int64_t blocks = (capacity + kItems * kScanThreads - 1) / (kItems * kScanThreads);
     const int64_t grid = blocks < kRadixPersist ? blocks : kRadixPersist;
     for (int p = 0; p < passes; ++p) {
@@ -718,9 +721,10 @@ static int radix_sort(const uint32_t *n_ptr, uint32_t *kbuf[2], uint32_t *vbuf[2
                            kbuf[cur], shift, B.hist, B.max_blocks);
         hipLaunchKernelGGL(radix_rowscan_kernel<kItems>, dim3(1 << kBits), dim3(256), 0, st, n_ptr, B.hist,
                            B.max_blocks, B.digit);
-        hipLaunchKernelGGL((radix_scatter_kernel<kItems, kBits>), dim3(xcd_grid(grid)), dim3(256), 0, st, n_ptr,
-                           kbuf[cur], vbuf[cur], kbuf[cur ^ 1], vbuf[cur ^ 1], shift, B.hist, B.max_blocks,
-                           B.digit);
+        hipLaunchKernelGGL((radix_scatter_kernel<kItems, kBits, kCarry>), dim3(xcd_grid(grid)), dim3(256), 0, st,
+                           n_ptr, kbuf[cur], vbuf[cur], kbuf[cur ^ 1], vbuf[cur ^ 1],
+                           kCarry ? cbuf[cur] : nullptr, kCarry ? cbuf[cur ^ 1] : nullptr, shift, B.hist,
+                           B.max_blocks, B.digit);
         cur ^= 1;
     }
     return cur;
@@ -782,16 +786,20 @@ extern "C" gs_status gs_bin_sort(const gs_settings *s, const void *proj_ws, int6
     hipLaunchKernelGGL(compact_reduce_kernel, dim3(sblocks), dim3(256), 0, st, B.counts, S, B.bsum);
     hipLaunchKernelGGL(scan_bsums_kernel, dim3(1), dim3(1024), 0, st, nullptr, B.bsum,
                        B.counters + kVisible, S);
+    // the visible records' pair counts move with them through compaction and
+    // the depth sort, in two S-sized buffers that are free meanwhile: vis_off
+    // (written only after the sort) and counts (read only by the compaction)
+    uint32_t *cnt_buf[2] = {B.voff, B.counts};
     hipLaunchKernelGGL(compact_scatter_kernel, dim3(sblocks), dim3(256), 0, st, B.counts, S, proj, s->znear,
-                       B.bsum, B.vk[0], B.vv[0]);
+                       B.bsum, B.vk[0], B.vv[0], cnt_buf[0]);
     // depth order (three 9-bit passes over the 27-bit keys)
     static_assert(kDepthKeyBits == 3 * 9, "depth key width");
-    int cur = radix_sort<4, 9>(B.counters + kVisible, B.vk, B.vv, 0, 0, 3, S, B, st);
-    // pair offsets in depth order; the depth keys are not needed any more, so
-    // their other buffer takes the counts in list order
-    uint32_t *sorted_cnt = B.vk[cur ^ 1];
+    int cur = radix_sort<4, 9, true>(B.counters + kVisible, B.vk, B.vv, 0, 0, 3, S, B, st, cnt_buf);
+    // an odd number of passes leaves the counts in `counts`, so the offsets
+    // scan reads them there while it writes vis_off
+    const uint32_t *sorted_cnt = cnt_buf[cur];
     hipLaunchKernelGGL(offsets_reduce_kernel, dim3(sblocks), dim3(256), 0, st, B.counters + kVisible,
-                       B.counts, B.vv[cur], sorted_cnt, B.bsum);
+                       sorted_cnt, B.bsum);
     hipLaunchKernelGGL(scan_bsums_kernel, dim3(1), dim3(1024), 0, st, B.counters + kVisible, B.bsum,
                        B.counters + kPairs, int64_t(0));
     const int64_t n_chunks = pair_chunks(pair_cap);
