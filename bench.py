@@ -618,7 +618,7 @@ def main_gpstudy(args, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "the benchmark runs on one GPU only; multi-GPU runs are not supported",
                           "n_gpus": args.gpus}))
         return 2
     import torch

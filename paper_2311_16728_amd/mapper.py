@@ -40,8 +40,8 @@ class PyramidSchedule:
     """Eq. 5 coarse-to-fine supervision per keyframe (Section 3.4): a keyframe
     is first supervised at the top level n of its Gaussian pyramid and moves
     one level finer every `tau` times it is used, down to level 0.  The paper
-    does not give the number of uses per level; tau = 4 is this build's
-    choice."""
+    does not give the number of uses per level; tau = 4 is the reading taken
+    here (a keyframe spends its first uses on the coarse levels)."""
 
     def __init__(self, levels: int = PYRAMID_LEVELS, tau: int = 4):
         if levels < 1 or tau < 1:
