@@ -98,6 +98,30 @@ def test_densify_rule_variants():
         _check_columns(c, outs, rule, action, keep, new)
 
 
+@pytest.mark.parametrize("case", ["all_split", "all_pruned", "all_cloned"])
+def test_densify_extremes(case):
+    """The output layouts at their limits, on a ragged n (4000 = 15 * 256 + 160):
+    every primitive split (no survivor, 2n new: the largest grid of new
+    tiles), every primitive pruned (empty output), every primitive cloned
+    (n survivors and n copies)."""
+    kw = {"all_split": dict(grad_threshold=0.0, percent_dense=1e-6, big_fraction=None, min_opacity=1e-6),
+          "all_pruned": dict(min_opacity=0.9999),
+          "all_cloned": dict(grad_threshold=0.0, percent_dense=1e3, big_fraction=None, min_opacity=1e-6)}[case]
+    c = scenes.densify_case(4, 4000)
+    n = c["n"]
+    outs, counts = _run(c, **kw)
+    rule, action, keep, new, expect = _expect_counts(c, n, **kw)
+    assert list(counts) == expect
+    n_out = {"all_split": 2 * n, "all_pruned": 0, "all_cloned": 2 * n}[case]
+    assert expect[0] == n_out
+    if case == "all_split":
+        assert expect[2] == n and not keep.any()
+    if case == "all_cloned":
+        assert expect[1] == n and keep.all()
+    _check_columns(c, outs, rule, action, keep, new)
+    assert all(np.all(o[:, n_out:] == SENTINEL) for o in outs)   # nothing beyond the output
+
+
 def test_densify_empty_and_capacity():
     c = scenes.densify_case(5, 3000)
     outs, counts = _run(c, n=0)
