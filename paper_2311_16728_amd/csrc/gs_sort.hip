@@ -348,10 +348,13 @@ __device__ __forceinline__ void divmod_small(uint32_t k, uint32_t w, uint32_t &q
 constexpr int kEmitPer = 4;
 constexpr int kEmitChunk = kScanThreads * kEmitPer;
 constexpr int kEmitCache = 4;   // targets per view held in registers (pyramid levels)
+constexpr int kEmitTab = 256;   // views and listed targets staged in LDS
 
-// 64 VGPRs: eight waves per SIMD for this latency-bound kernel (66 otherwise)
+// 64 VGPRs: eight waves per SIMD for this latency-bound kernel (66 and seven
+// waves otherwise, measured slower in spite of a small spill)
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
-emit_kernel(int64_t n_cap, const gs_target *__restrict__ targets, uint32_t *__restrict__ counters,
+emit_kernel(int64_t n_cap, int32_t n_views, const gs_target *__restrict__ targets,
+            uint32_t *__restrict__ counters,
             const uint32_t *__restrict__ vis_val, const uint32_t *__restrict__ vis_off,
             const uint2 *__restrict__ rects, const uint32_t *__restrict__ view_off,
             const uint32_t *__restrict__ view_list, const uint32_t *__restrict__ chunk_first,
@@ -361,6 +364,10 @@ emit_kernel(int64_t n_cap, const gs_target *__restrict__ targets, uint32_t *__re
     __shared__ uint32_t srcs[kEmitChunk];            // record ids, staged with the offsets
     __shared__ uint32_t mark[kEmitChunk / 32];       // bit per slot: a record starts there
     __shared__ uint32_t lds[8];
+    // the view offsets and, per listed target, its tile offset and row length,
+    // staged once (indices beyond the tables read global memory)
+    __shared__ uint32_t s_voff[kEmitTab + 1];
+    __shared__ uint2 s_tgt[kEmitTab];
     const uint32_t V = counters[kVisible];
     const uint32_t P = counters[kPairs];
     const uint32_t Pc = int64_t(P) > pair_cap ? uint32_t(pair_cap) : P;
@@ -370,6 +377,26 @@ emit_kernel(int64_t n_cap, const gs_target *__restrict__ targets, uint32_t *__re
     }
     if (V == 0) return;   // no visible record, no pair (Pc == 0)
     const int tid = threadIdx.x;
+    // lim_v / lim_t entries are in LDS, the rest in global memory
+    uint32_t lim_v = 0, lim_t = 0;
+    {
+        const int nv = n_views < kEmitTab ? n_views : kEmitTab;
+        for (int i = tid; i <= nv; i += kScanThreads) s_voff[i] = view_off[i];
+        const uint32_t listed = view_off[n_views];   // targets in the lists
+        lim_v = uint32_t(nv) + 1u;
+        lim_t = listed < uint32_t(kEmitTab) ? listed : uint32_t(kEmitTab);
+        for (uint32_t i = tid; i < lim_t; i += kScanThreads) {
+            const gs_target &t = targets[view_list[i]];
+            s_tgt[i] = make_uint2(uint32_t(t.tile_offset), uint32_t(t.tiles_x));
+        }
+        __syncthreads();
+    }
+    auto voff_of = [&](uint32_t v) { return v < lim_v ? s_voff[v] : view_off[v]; };
+    auto tgt_of = [&](uint32_t i) {
+        if (i < lim_t) return s_tgt[i];
+        const gs_target &t = targets[view_list[i]];
+        return make_uint2(uint32_t(t.tile_offset), uint32_t(t.tiles_x));
+    };
     for (int64_t chunk = blockIdx.x; chunk * kEmitChunk < Pc; chunk += gridDim.x) {
         const uint32_t o0 = uint32_t(chunk * kEmitChunk);
         const uint32_t j0 = chunk_first[chunk * (kEmitChunk / kScanThreads)];   // record holding slot o0
@@ -425,8 +452,8 @@ emit_kernel(int64_t n_cap, const gs_target *__restrict__ targets, uint32_t *__re
                 base = off[rec];
                 v = src / uint32_t(n_cap);
                 g = src - v * uint32_t(n_cap);
-                q0 = view_off[v];
-                mv = view_off[v + 1] - q0;
+                q0 = voff_of(v);
+                mv = voff_of(v + 1) - q0;
                 rc_v = rects + int64_t(q0) * n_cap + int64_t(g) * mv;
 #pragma unroll
                 for (int q = 0; q < kEmitCache; ++q) {
@@ -435,9 +462,9 @@ emit_kernel(int64_t n_cap, const gs_target *__restrict__ targets, uint32_t *__re
                     if (uint32_t(q) < mv) {
                         rcc[q] = rc_v[q];
                         cnt[q] = rect_count(rcc[q]);
-                        const gs_target &t = targets[view_list[q0 + q]];
-                        toff[q] = uint32_t(t.tile_offset);
-                        tx[q] = uint32_t(t.tiles_x);
+                        const uint2 tg = tgt_of(q0 + q);
+                        toff[q] = tg.x;
+                        tx[q] = tg.y;
                     }
                 }
             }
@@ -464,8 +491,8 @@ emit_kernel(int64_t n_cap, const gs_target *__restrict__ targets, uint32_t *__re
                     const uint32_t x0 = rc.x & 0xffffu, x1 = rc.x >> 16, y0 = rc.y & 0xffffu;
                     uint32_t dy, dx;
                     divmod_small(k, x1 - x0 + 1, dy, dx);
-                    const gs_target &t = targets[view_list[q0 + q]];
-                    key[i] = uint32_t(t.tile_offset) + (y0 + dy) * uint32_t(t.tiles_x) + x0 + dx;
+                    const uint2 tg = tgt_of(q0 + q);
+                    key[i] = tg.x + (y0 + dy) * tg.y + x0 + dx;
                     found = true;
                 }
                 k -= c;
@@ -808,7 +835,7 @@ extern "C" gs_status gs_bin_sort(const gs_settings *s, const void *proj_ws, int6
     const int64_t persistent = 256 * 16;   // 16 workgroups per CU, grid-stride beyond
     const int64_t emit_chunks = (pair_cap + kEmitChunk - 1) / kEmitChunk;
     hipLaunchKernelGGL(emit_kernel, dim3(emit_chunks < persistent ? emit_chunks : persistent), dim3(256), 0, st,
-                       n_cap, targets, B.counters, B.vv[cur], B.voff, B.rects, B.view_off, B.view_list,
+                       n_cap, n_views, targets, B.counters, B.vv[cur], B.voff, B.rects, B.view_off, B.view_list,
                        B.chunk_first, pair_cap, B.pk[0], B.pv[0], d_status);
     // tile order
     const TileSortPlan plan = tile_sort_plan(total_tiles);
