@@ -77,3 +77,38 @@ def test_gradients_match_oracle_for_tile_shape(orc, tw):
     ref = orc.render_backward(p, n, cam, Wt)
     ids = np.nonzero(np.linalg.norm(ref[:, :n], axis=0) > 0)[0]
     check_gradients(grad.cpu().numpy().astype(np.float64), ref, ids, f"tile_w {tw}")
+
+
+@pytest.mark.parametrize("tw", [8, 32])
+def test_degenerate_scene_for_tile_shape(orc, tw):
+    """The edge-case primitives (culled, near-plane, off-screen, huge, needle,
+    faint, opaque, dark, tied) on the ragged 97x61 view with 8x32 and 32x8
+    tiles: forward within the parity bar, gradients to the sampled bar."""
+    from tests.gpu_util import compare_image
+
+    p, cam, kinds = scenes.degenerate_scene(0)
+    n = kinds.size
+    plan = plan_for([cam], n_cap=p.shape[1], tile_w=tw)
+    P = _dev(p)
+    plan.render(P, n, with_ncontrib=True)
+    torch.cuda.synchronize()
+    assert not plan.overflowed()
+    o = orc.render(p, n, cam)
+    img = plan.image(plan.rgb, 0).cpu().numpy()
+    T = plan.plane(plan.T, 0).cpu().numpy()
+    m_img, m_T, n_amb, _, ok = compare_image(img, T, o)
+    print(f"degenerate, tile_w {tw}: max|dI|={m_img:.2e} ambiguous={n_amb}/{ok.size}")
+    assert m_img <= 1e-4 and m_T <= 1e-4
+    strict = o["amb"] == 0
+    nc = plan.plane(plan.ncontrib, 0).cpu().numpy()
+    assert np.array_equal(nc[strict], o["n_contrib"][strict])
+    rng = np.random.default_rng(tw)
+    Wt = rng.uniform(-1, 1, (3, cam["height"], cam["width"])).astype(np.float32)
+    Wt[:, o["amb"] != 0] = 0.0
+    grad = torch.zeros_like(P)
+    plan.backward(P, n, _dev(Wt).reshape(-1).contiguous(), grad)
+    torch.cuda.synchronize()
+    ref = orc.render_backward(p, n, cam, Wt)
+    ids = np.nonzero(np.linalg.norm(ref[:, :n], axis=0) > 0)[0]
+    # the degenerate scene's percentile bound (needle log-scales under random-sign weights)
+    check_gradients(grad.cpu().numpy().astype(np.float64), ref, ids, f"degenerate tile_w {tw}", p99=0.3)
