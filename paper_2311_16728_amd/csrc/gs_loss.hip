@@ -263,6 +263,9 @@ __device__ __forceinline__ void loss_of_target(const gs_target *__restrict__ tar
     const gs_target t = targets[ti];
     const int nt = t.tiles_x * t.tiles_y;
     double a = 0, b = 0;
+    // unrolled so that the loads of several tiles are in flight; the sums keep
+    // their order
+#pragma unroll 8
     for (int i = threadIdx.x; i < nt; i += blockDim.x) {
         a += partial[2 * int64_t(t.tile_offset + i)];
         b += partial[2 * int64_t(t.tile_offset + i) + 1];
