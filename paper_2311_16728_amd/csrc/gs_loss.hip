@@ -314,7 +314,8 @@ __global__ void __launch_bounds__(64) loss_total_kernel(int n_targets, const dou
                                                         float *__restrict__ d_total) {
     if (threadIdx.x != 0) return;
     double total = 0.0;
-    for (int ti = 0; ti < n_targets; ++ti) total += tloss[ti];
+#pragma unroll 8
+    for (int ti = 0; ti < n_targets; ++ti) total += tloss[ti];   // in target order
     if (d_total) *d_total = float(total);
 }
 
