@@ -143,3 +143,29 @@ def test_wide_tile_sort_equals_per_target():
         torch.cuda.synchronize()
         assert torch.equal(one.image(one.rgb, 0), big.image(big.rgb, v)), v
         assert torch.equal(one.plane(one.T, 0), big.plane(big.T, v)), v
+
+
+def test_many_targets_equal_per_target_bitwise():
+    """400 views x 3 levels = 1,200 targets: more views and listed targets than
+    the binning keeps in LDS (256) and more targets than one staging pass of
+    the per-view lists (1,024).  Sampled targets, among them ones beyond both
+    limits, render bitwise as they do alone."""
+    p, _, _ = scenes.tiny_scene(7, n=2000)
+    n = 2000
+    rng = np.random.default_rng(5)
+    cams = [scenes.pinhole(40, 24, 30.0, t=rng.uniform(-0.3, 0.3, 3)) for _ in range(400)]
+    P = _dev(p)
+    big = plan_for(cams, levels=(0, 1, 2), n_cap=p.shape[1], pair_cap=1 << 23)
+    assert big.n_targets == 1200
+    big.render(P, n)
+    torch.cuda.synchronize()
+    assert not big.overflowed()
+    for k in (0, 1, 255, 256, 257, 767, 1023, 1024, 1025, 1100, 1198, 1199):
+        v, l = divmod(k, 3)
+        one = plan_for([cams[v]], levels=(l,), n_cap=p.shape[1])
+        one.render(P, n)
+        torch.cuda.synchronize()
+        assert torch.equal(one.image(one.rgb, 0), big.image(big.rgb, k)), k
+        assert torch.equal(one.plane(one.T, 0), big.plane(big.T, k)), k
+    # the renders are not all background
+    assert float(big.rgb.abs().sum()) > 0
