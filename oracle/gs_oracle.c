@@ -406,7 +406,7 @@ typedef struct {
     int64_t extra;
 } scene_t;
 
-#define AMB_IMAGE 1   /* a flip FP32 may take changes the pixel by > AMB_EFFECT */
+#define AMB_IMAGE 1   /* the flips FP32 may take change the pixel by > AMB_EFFECT */
 #define AMB_COUNT 2   /* a flip FP32 may take changes n_contrib / T_final */
 #define AMB_EFFECT 2e-5
 
@@ -457,6 +457,16 @@ static void gather(const scene_t *S, int px, int py, scratch_t *s, int64_t *eval
     qsort(s->c, s->n, sizeof(cand_t), cmp_cand);
 }
 
+/* Two candidates whose FP32 depths may order them differently from FP64: the
+ * depths within 4 float32 ulp, unless the two means are bitwise equal (then
+ * every precision computes the same depth and both keep index order). */
+static int depth_near_tie(const scene_t *S, const cand_t *a, const cand_t *b) {
+    if (!(fabs(b->z - a->z) <= 4.8e-7 * (fabs(b->z) + 1.0))) return 0;
+    const gauss_t *Ga = &S->gs[a->g], *Gb = &S->gs[b->g];
+    if (Ga->mu[0] == Gb->mu[0] && Ga->mu[1] == Gb->mu[1] && Ga->mu[2] == Gb->mu[2]) return 0;
+    return 1;
+}
+
 typedef struct {
     double C[3], Tfin;
     int ncontrib;
@@ -483,66 +493,112 @@ static void composite(const scene_t *S, scratch_t *s, pix_out_t *o) {
      * out are recorded with the transmittance at which they would enter. */
     size_t nrej = 0;
     int stopped = 0;
+    size_t stop_i = 0;
     double stop_T = 0, stop_alpha = 0, stop_rmax = 0;
+    /* relative change of the transmittance that near-cutoff flips ahead of the
+     * stop could cause (each flip scales T by 1 - alpha_min or its inverse) */
+    double cut_rel = 0;
+    /* sum over every decision FP32 may take the other way of its effect on the
+     * pixel's colour or final transmittance: they may all flip together */
+    double eff = 0;
+    const double flip_rel = 1.01 * st->alpha_min / (1.0 - st->alpha_min);
     for (size_t i = 0; i < s->n; ++i) {
         const cand_t c = s->c[i];
         const gauss_t *G = &S->gs[c.g];
         const double rmax = fmax(fmax(G->rgb[0], G->rgb[1]), G->rgb[2]);
         if (!c.contributes) {
-            /* effect on the pixel had it been included: ~alpha_min * T * |rgb - behind| */
+            /* effect on the pixel had it been included: ~alpha_min * T * |rgb - behind|,
+             * and alpha_min * T_final on the final transmittance (T_final <= T) */
             amb |= AMB_COUNT;
-            if (st->alpha_min * T * (rmax + 1.0) > AMB_EFFECT) amb |= AMB_IMAGE;
+            eff += st->alpha_min * T * (rmax + 1.0);
             s->rejT[nrej++] = T;
+            cut_rel += flip_rel;
             continue;
         }
         const double alpha = fmin(st->alpha_max, c.atil);
         const double Tn = T * (1.0 - alpha);
         if (Tn < st->t_min) {   /* early stop: this entry is not added */
             stopped = 1;
+            stop_i = i;
             stop_T = T; stop_alpha = alpha; stop_rmax = rmax;
             break;
         }
+        if (c.near_cut) cut_rel += flip_rel;
         for (int ch = 0; ch < 3; ++ch) C[ch] += alpha * T * G->rgb[ch];
         s->T[K] = T;
         s->c[K] = c;
         ++K;
         T = Tn;
     }
-    /* depth near-ties among the composited entries (FP32 depth may swap them) */
-    for (int k = 1; k < K; ++k) {
-        const double z0 = s->c[k - 1].z, z1 = s->c[k].z;
-        if (fabs(z1 - z0) <= 4.8e-7 * (fabs(z1) + 1.0)) amb |= AMB_COUNT | AMB_IMAGE;
+    /* Depth near-ties: FP32 depths of two primitives within a few ulp may
+     * order them the other way.  Primitives with bitwise-equal means have the
+     * same depth in any precision and keep index order in both, so they are
+     * not a flip.  Swapping neighbours k-1, k changes the pixel by
+     * T a_{k-1} a_k |rgb_{k-1} - rgb_k| and leaves the final transmittance
+     * alone; a run of near-tied entries is bounded by the sum over its pairs. */
+    {
+        int k = 1;
+        while (k < K) {
+            if (!depth_near_tie(S, &s->c[k - 1], &s->c[k])) { ++k; continue; }
+            int k1 = k;
+            while (k1 + 1 < K && depth_near_tie(S, &s->c[k1], &s->c[k1 + 1])) ++k1;
+            /* entries k-1 .. k1 form a run */
+            amb |= AMB_COUNT;
+            double run = 0;
+            for (int i = k - 1; i <= k1; ++i)
+                for (int j = i + 1; j <= k1; ++j) {
+                    const gauss_t *Gi = &S->gs[s->c[i].g], *Gj = &S->gs[s->c[j].g];
+                    double d = 0;
+                    for (int ch = 0; ch < 3; ++ch) d = fmax(d, fabs(Gi->rgb[ch] - Gj->rgb[ch]));
+                    run += fmin(st->alpha_max, s->c[i].atil) * fmin(st->alpha_max, s->c[j].atil) * d;
+                }
+            eff += s->T[k - 1] * run;
+            k = k1 + 1;
+        }
+    }
+    /* the entry that stopped compositing, near-tied with the last composited
+     * one: swapped, it may be composited in its place */
+    if (stopped && K > 0 && depth_near_tie(S, &s->c[K - 1], &s->c[stop_i])) {
+        const gauss_t *G = &S->gs[s->c[K - 1].g];
+        const double rmax = fmax(fmax(G->rgb[0], G->rgb[1]), G->rgb[2]);
+        const double aK = fmin(st->alpha_max, s->c[K - 1].atil);
+        amb |= AMB_COUNT;
+        eff += s->T[K - 1] * (aK * (rmax + 1.0) + stop_alpha * (stop_rmax + 1.0));
     }
     /* composited near-cutoff entries: removing entry k changes the pixel by
-     * alpha_k T_k (rgb_k - colour behind k) */
+     * alpha_k T_k (rgb_k - colour behind k) and the final transmittance by at
+     * most alpha_k T_k */
     {
         double B[3] = {S->cam->bg[0], S->cam->bg[1], S->cam->bg[2]};
         for (int k = K - 1; k >= 0; --k) {
             const gauss_t *G = &S->gs[s->c[k].g];
             const double alpha = fmin(st->alpha_max, s->c[k].atil);
             if (s->c[k].near_cut) {
-                double diff = 0;
+                double diff = 1.0;
                 for (int ch = 0; ch < 3; ++ch) diff = fmax(diff, fabs(G->rgb[ch] - B[ch]));
                 amb |= AMB_COUNT;
-                if (alpha * s->T[k] * diff > AMB_EFFECT) amb |= AMB_IMAGE;
+                eff += alpha * s->T[k] * diff;
             }
             for (int ch = 0; ch < 3; ++ch) B[ch] = alpha * G->rgb[ch] + (1 - alpha) * B[ch];
         }
     }
-    /* early stop within FP32 reach of t_min, either way */
-    if (stopped && fabs(stop_T * (1.0 - stop_alpha) / st->t_min - 1.0) < 2e-3) {
+    /* early stop within FP32 reach of t_min, either way; near-cutoff flips
+     * ahead of it move the transmittance by cut_rel more */
+    const double stop_tol = 2e-3 + cut_rel;
+    if (stopped && fabs(stop_T * (1.0 - stop_alpha) / st->t_min - 1.0) < stop_tol) {
         amb |= AMB_COUNT;
-        if (stop_alpha * stop_T * (stop_rmax + 1.0) > AMB_EFFECT) amb |= AMB_IMAGE;
+        eff += stop_alpha * stop_T * (stop_rmax + 1.0);
     }
     if (K > 0) {
         const double aK = fmin(st->alpha_max, s->c[K - 1].atil);
-        if (fabs(s->T[K - 1] * (1.0 - aK) / st->t_min - 1.0) < 2e-3) {
+        if (fabs(s->T[K - 1] * (1.0 - aK) / st->t_min - 1.0) < stop_tol) {
             const gauss_t *G = &S->gs[s->c[K - 1].g];
             const double rmax = fmax(fmax(G->rgb[0], G->rgb[1]), G->rgb[2]);
             amb |= AMB_COUNT;
-            if (aK * s->T[K - 1] * (rmax + 1.0) > AMB_EFFECT) amb |= AMB_IMAGE;
+            eff += aK * s->T[K - 1] * (rmax + 1.0);
         }
     }
+    if (eff > AMB_EFFECT) amb |= AMB_IMAGE;
     s->n = (size_t)K;
     s->T[K] = T;
     for (int ch = 0; ch < 3; ++ch) o->C[ch] = C[ch] + T * S->cam->bg[ch];
@@ -961,12 +1017,14 @@ void orc_fd_gauss(const double *P, int64_t n, int64_t ncap, const double *camv,
         }
         int *ncs = (int *)malloc(sizeof(int) * 2 * npx);
         int64_t *ccs = (int64_t *)malloc(sizeof(int64_t) * 2 * npx);
+        /* per-pixel values of <W, C> at +h and -h; the difference is taken per
+         * pixel and summed in pixel order, so the result does not depend on
+         * the thread count and no two image-wide sums cancel */
+        double *Lpix = (double *)malloc(sizeof(double) * 2 * npx);
         for (int k = 0; k < nrows; ++k) {
-            double L[2] = {0, 0};
             for (int sgn = 0; sgn < 2; ++sgn) {
                 gs[gid] = Gp[2 * k + sgn];
-                double acc = 0;
-#pragma omp parallel reduction(+ : acc)
+#pragma omp parallel
                 {
                     scratch_t sc;
                     memset(&sc, 0, sizeof sc);
@@ -995,20 +1053,25 @@ void orc_fd_gauss(const double *P, int64_t n, int64_t ncap, const double *camv,
                             pix_out_t o;
                             composite(&S, &sc, &o);
                             const int64_t pix = (int64_t)py * cam.W + px;
+                            double acc = 0;
                             for (int ch = 0; ch < 3; ++ch) acc += W[ch * HW + pix] * o.C[ch];
+                            Lpix[sgn * npx + q] = acc;
                             ncs[sgn * npx + q] = o.ncontrib;
                             ccs[sgn * npx + q] = o.contrib_pairs;
                         }
                     free(sc.c); free(sc.T); free(sc.rejT);
                 }
-                L[sgn] = acc;
             }
             int chg = 0;
-            for (size_t q = 0; q < npx; ++q)
+            double dsum = 0;
+            for (size_t q = 0; q < npx; ++q) {
                 if (ncs[q] != ncs[q + npx] || ccs[q] != ccs[q + npx]) chg = 1;
-            fd[k] = (L[0] - L[1]) / (2 * h);
+                dsum += Lpix[q] - Lpix[q + npx];
+            }
+            fd[k] = dsum / (2 * h);
             changed[k] = chg;
         }
+        free(Lpix);
         gs[gid] = G0;
         S.extra = -1;
         for (size_t q = 0; q < npx; ++q) free(lists[q]);
@@ -1171,6 +1234,14 @@ void orc_adam(double *p, const double *g, double *m, double *v, int64_t n, int64
 }
 
 int orc_record_width(void) { return REC; }
+
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
 
 int orc_num_threads(void) {
 #ifdef _OPENMP

@@ -40,25 +40,39 @@ def _cases():
     yield "degenerate", p2, kinds.size, cam2
 
 
-CASES = ["tiny", "ragged", "degenerate"]
-# Share of pixels the oracle may flag as FP32-ambiguous.  The degenerate scene
-# holds exact copies (depth ties: every pixel a copy reaches is flagged, although
-# both orders give the same image) and 3 cm primitives just past the near plane
-# (long cutoff edges), about 7.5 % together.
-AMB_SHARE = {"tiny": 0.01, "ragged": 0.01, "degenerate": 0.08}
+def _knife_case(orc):
+    from tests.knife_edge import knife_edge_scene
+
+    p, n, cam, _ = knife_edge_scene(orc)
+    return "knife", p, n, cam
+
+
+def _case(orc, case):
+    if case == "knife":
+        return _knife_case(orc)
+    return [c for c in _cases() if c[0] == case][0]
+
+
+CASES = ["tiny", "ragged", "degenerate", "knife"]
+# Share of pixels the oracle may flag as FP32-ambiguous (image flag).  The
+# knife-edge scene is built to put decisions within float32 reach of the
+# cutoff, the stop and the depth order (its depth pins alone cover ~40 % of
+# the view); exact copies of the degenerate scene keep index order in every
+# precision and are compared.
+AMB_SHARE = {"tiny": 0.01, "ragged": 0.01, "degenerate": 0.01, "knife": 0.6}
 # Gaussians with a nonzero gradient the backward case must reach at least.
-MIN_COMPOSITED = {"tiny": 500, "ragged": 500, "degenerate": 300}
+MIN_COMPOSITED = {"tiny": 500, "ragged": 500, "degenerate": 300, "knife": 300}
 # 99th percentile of the relative gradient error over all composited Gaussians,
 # in units of the 1e-3 tolerance.  In the degenerate scene a few needles (axis
 # ratio 1000, a 2D covariance near the dilation floor) have log-scale gradients
 # that the random-sign pixel weights cancel to ~1 % of their size under |W|, so
 # FP32 rounding of the single terms shows up ~100x larger relative to the sum.
-GRAD_P99 = {"tiny": 0.1, "ragged": 0.1, "degenerate": 0.3}
+GRAD_P99 = {"tiny": 0.1, "ragged": 0.1, "degenerate": 0.3, "knife": 0.1}
 
 
 @pytest.mark.parametrize("case", CASES)
 def test_preprocess_records(orc, case):
-    name, p, n, cam = [c for c in _cases() if c[0] == case][0]
+    name, p, n, cam = _case(orc, case)
     plan = plan_for([cam], n_cap=p.shape[1])
     P = _dev(p)
     plan.preprocess(P, n)
@@ -78,7 +92,7 @@ def test_preprocess_records(orc, case):
 
 @pytest.mark.parametrize("case", CASES)
 def test_render_forward(orc, case):
-    name, p, n, cam = [c for c in _cases() if c[0] == case][0]
+    name, p, n, cam = _case(orc, case)
     plan = plan_for([cam], n_cap=p.shape[1])
     P = _dev(p)
     plan.render(P, n, with_ncontrib=True)
@@ -240,7 +254,7 @@ def test_backward_gradients(orc, case):
     opacity gradient by ~T/(255 o) even when the pixel barely moves, so those
     pixels are left out on both sides."""
 
-    name, p, n, cam = [c for c in _cases() if c[0] == case][0]
+    name, p, n, cam = _case(orc, case)
     plan = plan_for([cam], n_cap=p.shape[1])
     P = _dev(p)
     plan.render(P, n, with_ncontrib=True)

@@ -1,0 +1,358 @@
+"""Pin of the oracle's FP32-ambiguity classifier (Section 3.3, Eq. 3).
+
+Image and gradient parity skip the pixels the oracle flags as FP32-ambiguous:
+pixels where a float32 evaluation of Eq. 3 may legitimately take another
+discrete decision than FP64 (a pair within float32 reach of the 1/255 cutoff,
+a transmittance within reach of the 1e-4 stop, two depths that float32 may
+swap).  The classifier must flag every such pixel, and it must not flag
+decisions that cannot flip (exact copies of a primitive have the same depth in
+any precision and keep index order).
+
+This file evaluates the compositing decisions of every (pixel, primitive) pair
+in float32 with several independent realisations, vectorised in numpy:
+
+* ``gpu``: records rounded to float32 from the FP64 ones, the 2D mean kept in
+  FP64 and reduced to a float32 offset from the pixel's tile origin, conic
+  inverted in float32, the exponent with fused multiply-adds, the cutoff taken
+  in the log domain;
+* ``plain``: the whole projection in float32 from the float32 parameters,
+  absolute float32 pixel offsets, the cutoff taken on o * exp(power);
+* ``ulp<k>``: the ``gpu`` records moved by a random +-1 ulp per field.
+
+Every pixel whose float32 outcome (the ordered list of composited primitives)
+differs from FP64 must carry a flag; where the float32 image or final
+transmittance moves by more than the image bar used here (5e-5, half the
+parity tolerance), the flag must be AMB_IMAGE.  The share of flagged pixels
+where no realisation differs is reported (a conservative classifier
+over-flags; the parity tests cap the flagged share).  A numpy FP64 evaluation
+of the same decisions must reproduce the oracle's counts, transmittance and
+image, which also pins the compositing rules themselves.
+"""
+
+import numpy as np
+import pytest
+
+import scenes
+
+F32 = np.float32
+IMG_BAR = 2.5e-5   # the classifier's effect threshold 2e-5 plus float32 rounding of the sums
+RAGGED = scenes.pinhole(150, 110, 130.0, 125.0, 71.3, 52.6, R=np.eye(3), t=[0.05, -0.03, 0.1],
+                        bg=(0.2, 0.4, 0.1))
+
+
+def _room_view():
+    p, _, cams = scenes.room_scene(4, 60000, 1, width=160, height=96, f=80.0)
+    return p, 60000, cams[0]
+
+
+def _knife(orc, only):
+    """The knife-edge scene with one group of pins (the others made invisible)."""
+    from tests.knife_edge import knife_edge_scene
+
+    p, n, cam, groups = knife_edge_scene(orc)
+    p = p.copy()
+    for k, cols in groups.items():
+        if k not in ("clutter", only):
+            p[10, cols] = -30.0
+    return p, n, cam
+
+
+KNIFE = ["knife-cutoff", "knife-stop", "knife-depth"]
+
+
+def _cases(orc):
+    for name in KNIFE:
+        yield (name,) + _knife(orc, name.split("-")[1])
+    p, _, cam = scenes.tiny_scene(0)
+    yield "tiny", p, 2000, cam
+    p1, _, _ = scenes.tiny_scene(3, n=1500)
+    yield "ragged", p1, 1500, RAGGED
+    p2, cam2, kinds = scenes.degenerate_scene(0)
+    yield "degenerate", p2, kinds.size, cam2
+    yield ("saturated",) + _room_view()
+
+
+def _fma32(a, b, c):
+    """float32 fused multiply-add: the float32 product is exact in float64."""
+    return (a.astype(np.float64) * b.astype(np.float64) + c.astype(np.float64)).astype(F32)
+
+
+def _nudge(x, rng):
+    """x moved by -1, 0 or +1 ulp (float32), the step a function of x's bits and
+    a seeded salt: a deterministic arithmetic gives equal inputs equal results,
+    so bitwise-equal values (copies of a primitive) move alike."""
+    salt = np.uint64(rng.integers(1, 2**62))
+    h = (x.astype(F32).view(np.uint32).astype(np.uint64) + salt) * np.uint64(0x9E3779B97F4A7C15)
+    k = ((h >> np.uint64(33)) % np.uint64(3)).astype(np.int64) - 1
+    up = np.nextafter(x, F32(np.inf))
+    dn = np.nextafter(x, F32(-np.inf))
+    return np.where(k > 0, up, np.where(k < 0, dn, x)).astype(F32)
+
+
+def _project_plain32(p, n, cam, settings):
+    """Float32 projection of the raw parameters (a second, plainer realisation)."""
+    P = p[:, :n].astype(F32)
+    R = np.asarray(cam["R"], F32).reshape(3, 3)
+    t = np.asarray(cam["t"], F32)
+    mu = P[0:3]
+    xc = (R @ mu).astype(F32) + t[:, None]
+    z = xc[2]
+    s = np.exp(P[3:6]).astype(F32)
+    q = P[6:10] / np.sqrt((P[6:10] ** 2).sum(0)).astype(F32)
+    w, x, y, zq = q
+    Rq = np.stack([1 - 2 * (y * y + zq * zq), 2 * (x * y - w * zq), 2 * (x * zq + w * y),
+                   2 * (x * y + w * zq), 1 - 2 * (x * x + zq * zq), 2 * (y * zq - w * x),
+                   2 * (x * zq - w * y), 2 * (y * zq + w * x), 1 - 2 * (x * x + y * y)]).astype(F32)
+    Rq = Rq.T.reshape(-1, 3, 3)
+    M = Rq * s.T[:, None, :]
+    Sig = M @ np.transpose(M, (0, 2, 1))
+    fx, fy, cx, cy = (F32(cam[k]) for k in ("fx", "fy", "cx", "cy"))
+    zs = np.where(z > 0, z, F32(1))
+    u, v = xc[0] / zs, xc[1] / zs
+    limx = F32(settings["fov_clamp"] * 0.5 * cam["width"] / cam["fx"])
+    limy = F32(settings["fov_clamp"] * 0.5 * cam["height"] / cam["fy"])
+    ub, vb = np.clip(u, -limx, limx), np.clip(v, -limy, limy)
+    J = np.zeros((n, 2, 3), F32)
+    J[:, 0, 0] = fx / zs
+    J[:, 0, 2] = -fx * ub / zs
+    J[:, 1, 1] = fy / zs
+    J[:, 1, 2] = -fy * vb / zs
+    T = J @ R[None]
+    cov = T @ Sig @ np.transpose(T, (0, 2, 1))
+    d = F32(settings["dilation"])
+    c00, c01, c11 = cov[:, 0, 0] + d, cov[:, 0, 1], cov[:, 1, 1] + d
+    det = c00 * c11 - c01 * c01
+    conic = np.stack([c11 / det, -c01 / det, c00 / det])
+    m = np.stack([fx * u + cx, fy * v + cy])
+    o = (1 / (1 + np.exp(-P[10]))).astype(F32)
+    valid = (z > F32(settings["znear"])) & (det > 0)
+    return dict(m=m.astype(F32), conic=conic.astype(F32), o=o, z=z.astype(F32), valid=valid)
+
+
+def _records(orc, p, n, cam):
+    rec = orc.preprocess(p, n, cam)
+    f = {k: i for i, k in enumerate(orc.REC_FIELDS)}
+    valid = rec[:, f["valid"]] > 0
+    return dict(valid=valid, m=rec[:, [f["mx"], f["my"]]].T, z=rec[:, f["z"]],
+                conic=rec[:, [f["ca"], f["cb"], f["cc"]]].T, o=rec[:, f["opacity"]],
+                rgb=rec[:, [f["r"], f["g"], f["b"]]].T,
+                s2=rec[:, [f["s00"], f["s01"], f["s11"]]].T,
+                ext=rec[:, [f["extx"], f["exty"]]].T)
+
+
+def _evaluate(rec, cam, settings, mode, rng=None, plain=None):
+    """Per-pixel outcome of Eq. 3 in one precision/realisation.
+
+    Returns (ids, nc, T, img): ids is a list per pixel row-major of the
+    composited primitive ids in order, flattened with nc giving the counts."""
+    H, W = cam["height"], cam["width"]
+    n = rec["z"].size
+    a_min, a_max, t_min = settings["alpha_min"], settings["alpha_max"], settings["t_min"]
+    bg = np.asarray(cam["bg"], np.float64)
+    valid = rec["valid"].copy()
+    rgb = rec["rgb"]
+    if mode == "fp64":
+        dt = np.float64
+        z = rec["z"]
+    else:
+        dt = F32
+        if mode == "plain":
+            valid &= plain["valid"]
+            z = plain["z"]
+        else:
+            z = rec["z"].astype(F32)
+            if mode.startswith("ulp"):
+                z = _nudge(z, rng)
+        rgb = rgb.astype(F32)
+    order = np.lexsort((np.arange(n), z))
+    order = order[valid[order]]
+    # per-realisation quantities in sort order
+    if mode == "fp64":
+        m = rec["m"][:, order]
+        a, b, c = rec["conic"][:, order]
+        o = rec["o"][order]
+    elif mode == "plain":
+        m = plain["m"][:, order]
+        a, b, c = plain["conic"][:, order]
+        o = plain["o"][order]
+    else:
+        s2 = rec["s2"][:, order]
+        cov = (s2 - np.array([[settings["dilation"]], [0.0], [settings["dilation"]]])).astype(F32)
+        o = rec["o"][order].astype(F32)
+        if mode.startswith("ulp"):
+            cov = _nudge(cov, rng)
+            o = _nudge(o, rng)
+        d = F32(settings["dilation"])
+        c00, c01, c11 = cov[0] + d, cov[1], cov[2] + d
+        det = c00 * c11 - c01 * c01
+        idet = F32(1) / det
+        a, b, c = c11 * idet, -c01 * idet, c00 * idet
+        m = rec["m"][:, order]
+        thr = np.log(F32(a_min) / o).astype(F32)
+    ext = rec["ext"][:, order]
+    rgb_o = rgb[:, order]
+    N = order.size
+    ids_all, nc_all = [], np.zeros((H, W), np.int64)
+    T_all = np.ones((H, W), np.float64)
+    img = np.zeros((3, H, W), np.float64)
+    rows = 4
+    for y0 in range(0, H, rows):
+        y1 = min(H, y0 + rows)
+        # primitives whose cutoff box (plus a margin) meets this band of rows
+        sel = np.nonzero((ext[0] >= 0) & (m[1] + ext[1] + 3 >= y0) & (m[1] - ext[1] - 3 <= y1 - 1) &
+                         (m[0] + ext[0] + 3 >= 0) & (m[0] - ext[0] - 3 <= W - 1))[0]
+        py, px = np.mgrid[y0:y1, 0:W]
+        py, px = py.reshape(-1), px.reshape(-1)
+        P = py.size
+        if sel.size == 0:
+            img[:, y0:y1, :] = bg[:, None, None]
+            continue
+        if mode == "fp64":
+            dx = m[0, sel][None, :] - px[:, None]
+            dy = m[1, sel][None, :] - py[:, None]
+            pw = -0.5 * (a[sel] * dx * dx + c[sel] * dy * dy) - b[sel] * dx * dy
+            at = o[sel] * np.exp(pw)
+            contrib = at >= a_min
+            alpha = np.where(contrib, np.minimum(a_max, at), 0.0)
+        elif mode == "plain":
+            dx = (m[0, sel][None, :] - px[:, None].astype(F32)).astype(F32)
+            dy = (m[1, sel][None, :] - py[:, None].astype(F32)).astype(F32)
+            pw = (F32(-0.5) * (a[sel] * dx * dx + c[sel] * dy * dy) - b[sel] * dx * dy).astype(F32)
+            at = (o[sel] * np.exp(pw)).astype(F32)
+            contrib = at >= F32(a_min)
+            alpha = np.where(contrib, np.minimum(F32(a_max), at), F32(0)).astype(F32)
+        else:
+            # offsets from the 16x16 tile origin, reduced in FP64 and rounded once
+            ox = (px // 16 * 16).astype(np.float64)
+            oy = (py // 16 * 16).astype(np.float64)
+            mx = (m[0, sel][None, :] - ox[:, None]).astype(F32)
+            my = (m[1, sel][None, :] - oy[:, None]).astype(F32)
+            if mode.startswith("ulp"):
+                mx, my = _nudge(mx, rng), _nudge(my, rng)
+            dx = (mx - (px % 16).astype(F32)[:, None]).astype(F32)
+            dy = (my - (py % 16).astype(F32)[:, None]).astype(F32)
+            A, B, Cc = a[sel][None, :], b[sel][None, :], c[sel][None, :]
+            q = _fma32((A * dx).astype(F32), dx, (Cc * dy * dy).astype(F32))
+            pw = _fma32(np.full_like(q, F32(-0.5)), q, -(B * dx * dy).astype(F32))
+            contrib = pw >= thr[sel][None, :]
+            at = (o[sel][None, :] * np.exp(pw).astype(F32)).astype(F32)
+            alpha = np.where(contrib, np.minimum(F32(a_max), at), F32(0)).astype(F32)
+        dtp = np.float64 if mode == "fp64" else F32
+        fac = (dtp(1) - alpha).astype(dtp)
+        Tc = np.multiply.accumulate(fac, axis=1, dtype=dtp)
+        stop = contrib & (Tc < dtp(t_min))
+        ks = np.where(stop.any(1), stop.argmax(1), sel.size)
+        comp = contrib & (np.arange(sel.size)[None, :] < ks[:, None])
+        Tprev = np.concatenate([np.ones((P, 1), dtp), Tc[:, :-1]], axis=1)
+        Tfin = np.where(ks > 0, Tc[np.arange(P), np.maximum(ks - 1, 0)], dtp(1)).astype(np.float64)
+        w = np.where(comp, alpha.astype(np.float64) * Tprev.astype(np.float64), 0.0)
+        col = w @ rgb_o[:, sel].astype(np.float64).T + Tfin[:, None] * bg[None, :]
+        img[:, y0:y1, :] = col.T.reshape(3, y1 - y0, W)
+        T_all[y0:y1, :] = Tfin.reshape(y1 - y0, W)
+        nc_all[y0:y1, :] = comp.sum(1).reshape(y1 - y0, W)
+        r, k = np.nonzero(comp)
+        ids_all.append(order[sel[k]] + 0 * r)
+    ids = np.concatenate(ids_all) if ids_all else np.zeros(0, np.int64)
+    return ids, nc_all, T_all, img
+
+
+def _outcome_differs(ref, got):
+    """Pixels whose ordered composited list differs."""
+    ids0, nc0 = ref[0], ref[1].reshape(-1)
+    ids1, nc1 = got[0], got[1].reshape(-1)
+    diff = nc0 != nc1
+    same = ~diff
+    # compare the id sequences of the pixels with equal counts
+    r0 = np.repeat(np.arange(nc0.size), nc0)
+    r1 = np.repeat(np.arange(nc1.size), nc1)
+    keep0 = same[r0]
+    keep1 = same[r1]
+    bad = ids0[keep0] != ids1[keep1]
+    diff[np.unique(r0[keep0][bad])] = True
+    return diff.reshape(ref[1].shape)
+
+
+@pytest.fixture(scope="module")
+def results(orc):
+    out = {}
+    settings = dict(orc.DEFAULT_SETTINGS)
+    for name, p, n, cam in _cases(orc):
+        rec = _records(orc, p, n, cam)
+        o = orc.render(p, n, cam)
+        ref = _evaluate(rec, cam, settings, "fp64")
+        plain = _project_plain32(p, n, cam, settings)
+        reals = {"gpu": _evaluate(rec, cam, settings, "gpu"),
+                 "plain": _evaluate(rec, cam, settings, "plain", plain=plain)}
+        for s in range(3):
+            reals[f"ulp{s}"] = _evaluate(rec, cam, settings, f"ulp{s}", rng=np.random.default_rng(s))
+        out[name] = (o, ref, reals, p, n, cam)
+    return out
+
+
+ALL = KNIFE + ["tiny", "ragged", "degenerate", "saturated"]
+
+
+@pytest.mark.parametrize("case", ALL)
+def test_fp64_numpy_matches_oracle(results, case):
+    """An independent numpy FP64 evaluation of the cutoff, clamp, stop and order
+    rules gives the oracle's counts, transmittance and image."""
+    o, ref, _, _, _, _ = results[case]
+    assert np.array_equal(ref[1], o["n_contrib"])
+    np.testing.assert_allclose(ref[2], o["T"], rtol=1e-10, atol=1e-14)
+    np.testing.assert_allclose(ref[3], o["img"], rtol=0, atol=1e-10)
+
+
+@pytest.mark.parametrize("case", ALL)
+def test_classifier_flags_every_fp32_flip(results, case):
+    o, ref, reals, _, _, _ = results[case]
+    amb = o["amb"]
+    flagged = amb != 0
+    img_flag = (amb & 1) != 0
+    any_diff = np.zeros_like(flagged)
+    for name, got in reals.items():
+        diff = _outcome_differs(ref, got)
+        any_diff |= diff
+        moved = np.maximum(np.abs(got[3] - ref[3]).max(axis=0), np.abs(got[2] - ref[2]))
+        missed = diff & ~flagged
+        print(f"{case}/{name}: {int(diff.sum())} pixels decide differently, "
+              f"{int(missed.sum())} of them unflagged; max move on unflagged-image pixels "
+              f"{moved[~img_flag].max():.2e}")
+        assert not missed.any(), (name, np.argwhere(missed)[:5])
+        assert moved[~img_flag].max() <= IMG_BAR, name
+    if case in KNIFE:
+        # the planted decisions do flip: the check above is not vacuous
+        assert _outcome_differs(ref, reals["gpu"]).sum() >= 5, case
+    false_share = (flagged & ~any_diff).sum() / max(1, flagged.sum())
+    print(f"{case}: flagged {flagged.mean():.4%} of pixels (image {img_flag.mean():.4%}); "
+          f"{false_share:.1%} of the flagged pixels took the FP64 outcome in every realisation")
+
+
+def _pair_scene(shift):
+    """Two primitives on the optical axis, the second a copy of the first with its
+    mean moved by `shift` (metres, along x): opacity 0.5 each, so the centre
+    pixel is far from the cutoff and from the stop."""
+    cam = scenes.pinhole(33, 33, 33.0, 33.0, 16.0, 16.0)
+    p = np.zeros((59, 256), np.float32)
+    p[0:3, 0] = [0.0, 0.0, 2.5]
+    p[3:6, 0] = np.log(0.1)
+    p[6, 0] = 1.0
+    p[11:14, 0] = [1.0, -0.5, 0.3]
+    p[:, 1] = p[:, 0]
+    p[0, 1] += np.float32(shift)
+    p[11:14, 1] = [-0.8, 0.9, 0.1]   # another colour: a swap would change the pixel
+    return p, cam
+
+
+def test_exact_copies_are_not_flagged(orc):
+    """Bitwise-equal means give the same depth in any precision and the pair keeps
+    index order: the tie is not flagged.  A near-tie of different means is."""
+    p, cam = _pair_scene(0.0)
+    o = orc.render(p, 2, cam)
+    assert o["n_contrib"][16, 16] == 2
+    assert o["amb"][16, 16] == 0
+    # different means at (nearly) the same depth: float32 may order them either way
+    p, cam = _pair_scene(1e-3)
+    p[2, 1] = np.nextafter(p[2, 0], np.float32(np.inf))
+    o = orc.render(p, 2, cam)
+    assert o["n_contrib"][16, 16] == 2
+    assert o["amb"][16, 16] & 1
