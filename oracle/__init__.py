@@ -68,6 +68,7 @@ def _load():
         lib.orc_fd_gauss.argtypes = [dp, C.c_int64, C.c_int64, dp, dp, dp, i64p, C.c_int, i32p,
                                      C.c_int, C.c_double, dp, i32p]
         lib.orc_num_threads.restype = C.c_int
+        lib.orc_set_threads.argtypes = [C.c_int]
         _lib = lib
     return _lib
 
@@ -105,6 +106,11 @@ def set_vec(settings: dict | None = None) -> np.ndarray:
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Sets the number of OpenMP threads of later calls."""
+    _load().orc_set_threads(int(n))
 
 
 def preprocess(params, n: int, cam: dict, settings=None) -> np.ndarray:

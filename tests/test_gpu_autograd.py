@@ -119,26 +119,22 @@ def test_differentiation_stress_2M(orc):
 
     rec = orc.preprocess(p, n, cam)
     small = ids[np.argsort(rec[ids, 17] * rec[ids, 18])[:16]]
-    # Central differences carry their own error: truncation, and FP64 rounding
-    # of two image-wide sums divided by 2h, which for a gradient of ~1e-7
-    # reaches the percent level and moves with the order of the oracle's
-    # threaded sums.  The spread between steps h and h/2 estimates it and is
-    # added to the 1e-2 bound.
+    # Central differences of <W, I> in FP64, each pixel's change taken before
+    # the footprint sum (independent of the oracle's thread count); parameters
+    # whose +-h changes the composited set are skipped.
     fd, changed = orc.fd_gauss(p, n, cam, Wt, small, FD_ROWS, h=1e-4)
-    fd2, changed2 = orc.fd_gauss(p, n, cam, Wt, small, FD_ROWS, h=5e-5)
     checked, worst_fd = 0, 0.0
     for a, gid in enumerate(small):
         for name, rows in GROUPS.items():
-            sel = [i for i, r in enumerate(FD_ROWS) if r in rows and not changed[a, i] and not changed2[a, i]]
+            sel = [i for i, r in enumerate(FD_ROWS) if r in rows and not changed[a, i]]
             if not sel:
                 continue
             f = fd[a, sel]
             if np.linalg.norm(f) < 1e-8:
                 continue
             e = np.linalg.norm(g[FD_ROWS[sel], gid] - f) / np.linalg.norm(f)
-            spread = np.linalg.norm(f - fd2[a, sel]) / np.linalg.norm(f)
             worst_fd = max(worst_fd, e)
-            assert e <= 1e-2 + 2.0 * spread, (gid, name, e, spread)
+            assert e <= 1e-2, (gid, name, e)
             checked += 1
     print(f"GPU vs FP64 central differences: {checked} groups, max rel {worst_fd:.2e}", flush=True)
     assert checked >= 20
