@@ -31,8 +31,12 @@
  * - Errors: every call validates its arguments on the host and returns a
  *   non-zero gs_status without enqueuing anything when they are invalid.
  *   Launch failures return GS_ERR_HIP.  Conditions only the device can see
- *   (tile-pair buffer overflow) are reported through the device status word
- *   named in the call.  No C++ exception crosses this interface.
+ *   (tile-pair buffer overflow; non-finite values in checked mode) are OR-ed
+ *   into a device status word (uint32) that the caller reads after the stream
+ *   has synchronised and maps to a status with gs_status_word.  No C++
+ *   exception crosses this interface.
+ * - Sizes: n_views * n_cap (projection records) is at most 2^32 - 1 and
+ *   pair_cap at most 2^31 - 1.
  */
 #ifndef GS_H
 #define GS_H
@@ -49,11 +53,15 @@ typedef enum {
     GS_ERR_INVALID_ARGUMENT = 1,
     GS_ERR_CAPACITY = 2,      /* a buffer is too small for the request */
     GS_ERR_NOT_SUPPORTED = 3,
-    GS_ERR_HIP = 4
+    GS_ERR_HIP = 4,
+    GS_ERR_NUMERIC = 5        /* a non-finite value was met (checked mode) */
 } gs_status;
 
-/* Bits of the device status word written by gs_bin_sort. */
+/* Bits of a device status word.  GS_STATUS_PAIR_OVERFLOW: gs_bin_sort found
+ * more tile pairs than pair_cap.  GS_STATUS_NUMERIC: a checked-mode call
+ * (settings.checked = 1) met a NaN or infinity. */
 #define GS_STATUS_PAIR_OVERFLOW 1u
+#define GS_STATUS_NUMERIC 2u
 
 #define GS_NUM_ROWS 59
 #define GS_TILE 16            /* default tile width (square 16 x 16 tiles) */
@@ -61,15 +69,27 @@ typedef enum {
 
 /* Rasteriser settings.  Defaults (gs_default_settings): alpha_min 1/255,
  * alpha_max 0.99, t_min 1e-4, znear 0.2, dilation 0.3 px^2, fov_clamp 1.3,
- * sh_degree 3, batch 256, bwd_waves 2.  A pixel composites a Gaussian iff its opacity
+ * sh_degree 3, batch 256, bwd_waves 2, checked 0.  A pixel composites a Gaussian iff its opacity
  * there, o * exp(power), reaches alpha_min; the contribution uses
  * min(alpha_max, .); compositing stops before the Gaussian that would take
- * the transmittance below t_min (Eq. 3). */
+ * the transmittance below t_min (Eq. 3).
+ *
+ * Checked mode (checked = 1, status a device uint32 word, required): the
+ * guards below OR GS_STATUS_NUMERIC into *status; every kernel still runs to
+ * its end.  gs_preprocess checks the 59 parameters of every column < n and
+ * the record it computes; a column with a non-finite value gets the record
+ * of a culled Gaussian (opacity 0), so nothing downstream composites it.
+ * gs_project_bwd checks every gradient it adds; gs_project_bwd_adam checks
+ * every gradient and updated parameter, and writes the next records (when
+ * asked) through the guarded projection.  With checked = 0 no guard runs and
+ * status is ignored. */
 typedef struct {
     float alpha_min, alpha_max, t_min, znear, dilation, fov_clamp;
     int32_t sh_degree;   /* 0..3 */
     int32_t batch;       /* forward: Gaussians staged per LDS round: 64, 128 or 256 */
     int32_t bwd_waves;   /* backward: waves per tile, 1, 2 or 4 (4, 2 or 1 pixels per lane) */
+    int32_t checked;     /* 0 or 1: NaN / infinity guards */
+    uint32_t *status;    /* (device) status word of the guards; NULL when checked = 0 */
 } gs_settings;
 
 /* A keyframe pose with its level-0 intrinsics and image size. */
@@ -107,6 +127,12 @@ typedef struct {
 /* Human-readable name of a status code (static string). */
 const char *gs_status_string(gs_status s);
 
+/* (host) The status a device status word stands for, once the caller has read
+ * it back: GS_ERR_NUMERIC when GS_STATUS_NUMERIC is set, else
+ * GS_ERR_CAPACITY when GS_STATUS_PAIR_OVERFLOW is set, else GS_OK (unknown
+ * bits: GS_ERR_INVALID_ARGUMENT). */
+gs_status gs_status_word(uint32_t word);
+
 /* Fills *s with the defaults listed above. */
 void gs_default_settings(gs_settings *s);
 
@@ -136,7 +162,9 @@ gs_status gs_workspace_query(const gs_settings *s, int64_t n_cap, int32_t n_view
 gs_status gs_preprocess(const gs_settings *s, const float *params, int64_t n, int64_t n_cap,
                         const gs_view *views, int32_t n_views, void *proj_ws, void *stream);
 
-/* Tile binning: for every target, each valid Gaussian whose cutoff ellipse
+/* Tile binning of the tile-based renderer (Section 3.3: the keyframe is
+ * rendered tile by tile; Eq. 3's sum runs front to back over depth): for
+ * every target, each valid Gaussian whose cutoff ellipse
  * {alpha >= alpha_min} overlaps a tile of the target is paired with that tile; the
  * pairs are sorted by (target tile, depth, Gaussian index) with a device
  * radix sort and each tile's range of pairs is recorded.  targets (device,

@@ -9,6 +9,7 @@ extern "C" const char *gs_status_string(gs_status s) {
         case GS_ERR_CAPACITY: return "capacity exceeded";
         case GS_ERR_NOT_SUPPORTED: return "not supported";
         case GS_ERR_HIP: return "HIP launch error";
+        case GS_ERR_NUMERIC: return "non-finite value";
     }
     return "unknown status";
 }
@@ -24,6 +25,15 @@ extern "C" void gs_default_settings(gs_settings *s) {
     s->sh_degree = 3;
     s->batch = 256;
     s->bwd_waves = 2;
+    s->checked = 0;
+    s->status = nullptr;
+}
+
+extern "C" gs_status gs_status_word(uint32_t word) {
+    if (word & ~(GS_STATUS_PAIR_OVERFLOW | GS_STATUS_NUMERIC)) return GS_ERR_INVALID_ARGUMENT;
+    if (word & GS_STATUS_NUMERIC) return GS_ERR_NUMERIC;
+    if (word & GS_STATUS_PAIR_OVERFLOW) return GS_ERR_CAPACITY;
+    return GS_OK;
 }
 
 extern "C" gs_status gs_targets_layout(const gs_view *views, int32_t n_views, gs_target *targets,
@@ -64,8 +74,9 @@ extern "C" gs_status gs_targets_layout(const gs_view *views, int32_t n_views, gs
 extern "C" gs_status gs_workspace_query(const gs_settings *s, int64_t n_cap, int32_t n_views,
                                         const gs_target *targets, int32_t n_targets,
                                         int64_t pair_cap, gs_sizes *out) {
-    if (!s || !targets || !out || n_cap <= 0 || n_cap % 64 || n_views <= 0 || n_targets <= 0 ||
-        pair_cap <= 0)
+    if (!gs::valid_settings(s) || !targets || !out || n_cap <= 0 || n_cap % 64 || n_views <= 0 ||
+        n_targets <= 0 || pair_cap <= 0 || pair_cap > gs::kMaxPairs ||
+        int64_t(n_views) * n_cap > gs::kMaxRecords)
         return GS_ERR_INVALID_ARGUMENT;
     int64_t pix = 0, tiles = 0;
     for (int i = 0; i < n_targets; ++i) {

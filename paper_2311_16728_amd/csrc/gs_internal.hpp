@@ -32,6 +32,21 @@ constexpr int kRadixPersist = 2048;           // workgroups of the grid-stride r
 
 static inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Size limits of the interface: records are indexed by uint32, pair slots by
+// uint32 with the total kept below 2^31 (so a count past it is seen, not wrapped).
+constexpr int64_t kMaxRecords = 0xffffffffLL;
+constexpr int64_t kMaxPairs = 0x7fffffffLL;
+
+// Host-side validation of the rasteriser settings shared by every entry point.
+static inline bool valid_settings(const gs_settings *s) {
+    return s && s->sh_degree >= 0 && s->sh_degree <= 3 &&
+           (s->batch == 64 || s->batch == 128 || s->batch == 256) &&
+           (s->bwd_waves == 1 || s->bwd_waves == 2 || s->bwd_waves == 4) && s->alpha_min > 0.f &&
+           s->alpha_max <= 1.f && s->alpha_max >= s->alpha_min && s->t_min > 0.f &&
+           s->dilation >= 0.f && s->fov_clamp > 0.f && s->znear > 0.f &&
+           (s->checked == 0 || (s->checked == 1 && s->status != nullptr));
+}
+
 // ---------------------------------------------------------------------------
 // Workspace layouts.  All sub-buffers are 256-byte aligned.
 // ---------------------------------------------------------------------------
@@ -183,6 +198,13 @@ __device__ __forceinline__ int lane_id() {
 __device__ __forceinline__ int mask_rank(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
                                      __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0));
+}
+
+// Checked mode: the lowest lane of the wave on which `bad` holds ORs
+// GS_STATUS_NUMERIC into the status word (the guards' only device write).
+__device__ __forceinline__ void report_numeric(uint32_t *status, bool bad) {
+    const uint64_t b = __ballot(bad);
+    if (b != 0 && lane_id() == __builtin_ctzll(b)) atomicOr(status, GS_STATUS_NUMERIC);
 }
 
 __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {

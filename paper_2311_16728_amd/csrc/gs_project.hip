@@ -302,6 +302,31 @@ __device__ __forceinline__ void preprocess_one_lean(const gs_settings &s, const 
     project_records(s, P, n_cap, g, G, nullptr, views, n_views, out);
 }
 
+// Checked mode: a column with a non-finite parameter, or whose record holds a
+// non-finite value, gets culled records (the record of a Gaussian behind the
+// near plane) for every view, and the status word learns of it.
+__device__ __forceinline__ void guard_records(const gs_settings &s, const float *P, int64_t n_cap,
+                                              int64_t g, int32_t n_views, const Proj &out) {
+    bool bad = false;
+    for (int r = 0; r < kRows; ++r) bad |= !isfinite(P[int64_t(r) * n_cap + g]);
+    for (int v = 0; v < n_views && !bad; ++v) {
+        const int64_t r = int64_t(v) * n_cap + g;
+        const double2 m = out.mean[r];
+        const float4 a = out.cov_o[r], b = out.rgb_z[r];
+        bad |= !(isfinite(m.x) && isfinite(m.y) && isfinite(a.x) && isfinite(a.y) && isfinite(a.z) &&
+                 isfinite(a.w) && isfinite(b.x) && isfinite(b.y) && isfinite(b.z) && isfinite(b.w));
+    }
+    if (bad) {
+        for (int v = 0; v < n_views; ++v) {
+            const int64_t r = int64_t(v) * n_cap + g;
+            out.mean[r] = make_double2(0.0, 0.0);
+            out.cov_o[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+            out.rgb_z[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
+    report_numeric(s.status, bad);
+}
+
 __global__ void __launch_bounds__(256) preprocess_kernel(gs_settings s, const float *__restrict__ P,
                                                          int64_t n, int64_t n_cap,
                                                          const gs_view *__restrict__ views,
@@ -309,6 +334,7 @@ __global__ void __launch_bounds__(256) preprocess_kernel(gs_settings s, const fl
     const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (g >= n) return;
     preprocess_one(s, P, n_cap, g, views, n_views, out);
+    if (s.checked) guard_records(s, P, n_cap, g, n_views, out);
 }
 
 // Gradient sinks of the projection backward: accumulate into a gradient
@@ -317,6 +343,7 @@ __global__ void __launch_bounds__(256) preprocess_kernel(gs_settings s, const fl
 // count) so every load of the group is issued before the first store.
 struct GradSink {
     float *__restrict__ grad;
+    uint32_t *status;   // checked mode: non-finite gradients are reported here (else NULL)
     struct Scale {};
     __device__ __forceinline__ Scale prepare() const { return {}; }
     static constexpr int kKeepRows = 1;   // no colour rows kept (see AdamSink)
@@ -328,6 +355,12 @@ struct GradSink {
         for (int j = 0; j < N; ++j) cur[j] = grad[int64_t(first + j * stride) * n_cap + g];
 #pragma unroll
         for (int j = 0; j < N; ++j) grad[int64_t(first + j * stride) * n_cap + g] = cur[j] + val[j];
+        if (status) {
+            bool bad = false;
+#pragma unroll
+            for (int j = 0; j < N; ++j) bad |= !isfinite(val[j]);
+            if (bad) atomicOr(status, GS_STATUS_NUMERIC);
+        }
     }
     __device__ __forceinline__ void untouched(int64_t, int64_t, Scale) const {}
     __device__ __forceinline__ void finish(const gs_settings &, int64_t, int64_t, const gs_view *,
@@ -338,9 +371,10 @@ struct GradSink {
 };
 
 struct AdamSink {
-    float *__restrict__ p;
+    float *p;   // the parameter store, also read by the kernel through its P argument
     float *__restrict__ m;
     float *__restrict__ v;
+    uint32_t *status;   // checked mode: non-finite gradients or updates are reported here (else NULL)
     LrRows lr;
     float b1, omb1, b2, omb2, eps, ibc1, isqbc2;
     // Device step counter (graph replay): when set, the bias corrections come
@@ -367,12 +401,14 @@ struct AdamSink {
     __device__ __forceinline__ void group(int first, int stride, int64_t g, int64_t n_cap,
                                           float (&gv)[N], const float (&pcur)[N], Scale sc) const {
         float pp[N], mm[N], vv[N];
+        bool bad = false;
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             const int64_t i = int64_t(first + j * stride) * n_cap + g;
             pp[j] = pcur[j];
             mm[j] = m[i];
             vv[j] = v[i];
+            if (status) bad |= !isfinite(gv[j]);
         }
 #pragma unroll
         for (int j = 0; j < N; ++j) {
@@ -386,7 +422,9 @@ struct AdamSink {
             const float np = pp[j] - lr.lr[first + j * stride] * sc.ibc1 * mv * __builtin_amdgcn_rcpf(den);
             p[i] = np;
             gv[j] = np;
+            if (status) bad |= !isfinite(np);
         }
+        if (bad) atomicOr(status, GS_STATUS_NUMERIC);
     }
     __device__ __forceinline__ void untouched(int64_t g, int64_t n_cap, Scale sc) const {
 #pragma unroll 1
@@ -423,7 +461,7 @@ struct AdamSink {
 // channel's 16 SH coefficients and their gradients are live.
 template <class Sink>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) project_backward_kernel(
-    gs_settings s, const float *__restrict__ P, int64_t n, int64_t n_cap,
+    gs_settings s, const float *P, int64_t n, int64_t n_cap,
     const gs_view *__restrict__ views, int32_t n_views, const float *__restrict__ acc,
     int64_t records, Sink sink) {
     __shared__ float keep2[Sink::kKeepRows][256];   // updated coefficients of colour channel 2
@@ -623,7 +661,8 @@ gs_status launch_project_backward(const gs_settings &s, const float *params, int
     if (n == 0) return GS_OK;
     const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(project_backward_kernel<GradSink>, dim3(blocks), dim3(256), 0, st, s, params, n,
-                       n_cap, views, n_views, acc, int64_t(n_views) * n_cap, GradSink{grad});
+                       n_cap, views, n_views, acc, int64_t(n_views) * n_cap,
+                       GradSink{grad, s.checked ? s.status : nullptr});
     GS_CHECK_LAUNCH();
     return GS_OK;
 }
@@ -638,12 +677,14 @@ gs_status launch_project_backward_adam(const gs_settings &s, float *params, int6
     // with many views the separate projection kernel (parameters read once,
     // colour coefficients kept in registers across views) is faster.
     const Proj next = proj_out ? proj_at(proj_out, int64_t(n_views) * n_cap) : Proj{nullptr, nullptr, nullptr};
-    const bool fuse_next = proj_out && n_views <= kFuseProjectionViews;
+    // (in checked mode the next records come from the guarded projection kernel)
+    const bool fuse_next = proj_out && n_views <= kFuseProjectionViews && !s.checked;
     AdamSink a;
     a.next = fuse_next ? next : Proj{nullptr, nullptr, nullptr};
     a.p = params;
     a.m = m;
     a.v = v;
+    a.status = s.checked ? s.status : nullptr;
     for (int r = 0; r < kRows; ++r) a.lr.lr[r] = lr_rows[r];
     a.b1 = float(beta1);
     a.omb1 = float(1.0 - beta1);
@@ -671,8 +712,8 @@ gs_status launch_project_backward_adam(const gs_settings &s, float *params, int6
 extern "C" gs_status gs_preprocess(const gs_settings *s, const float *params, int64_t n,
                                    int64_t n_cap, const gs_view *views, int32_t n_views,
                                    void *proj_ws, void *stream) {
-    if (!s || !params || !views || !proj_ws || n < 0 || n_cap <= 0 || n > n_cap || n_cap % 64 ||
-        n_views <= 0 || s->sh_degree < 0 || s->sh_degree > 3)
+    if (!gs::valid_settings(s) || !params || !views || !proj_ws || n < 0 || n_cap <= 0 || n > n_cap ||
+        n_cap % 64 || n_views <= 0 || int64_t(n_views) * n_cap > gs::kMaxRecords)
         return GS_ERR_INVALID_ARGUMENT;
     if (n == 0) return GS_OK;
     gs::Proj out = gs::proj_at(proj_ws, int64_t(n_views) * n_cap);

@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
     __shared__ float4 sA[kThreads];
     __shared__ float4 sB[kThreads];
     __shared__ float2 sC[kThreads];
-    __shared__ int32_t sR[kThreads];
+    __shared__ uint32_t sR[kThreads];   // record view * n_cap + g (< 2^32)
     __shared__ int32_t sPos[kThreads];
     __shared__ uint32_t scan_lds[8];
     __shared__ float red[kWaves][kThreads][kAccRows];
@@ -324,7 +324,7 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
             sA[at_pos] = A;
             sB[at_pos] = Bv;
             sC[at_pos] = Cc;
-            sR[at_pos] = int32_t(rec);
+            sR[at_pos] = uint32_t(rec);
             sPos[at_pos] = start + tid;
         }
         __syncthreads();
@@ -436,7 +436,7 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
         for (int idx = tid; idx < int(cnt) * kAccRows; idx += kThreads) {
             const int k = idx / kAccRows, i = idx - k * kAccRows;
             const float v = red[0][k][i];
-            if (v != 0.f) atomicAdd(&acc[int64_t(sR[k]) * kAccRows + i], v);
+            if (v != 0.f) atomicAdd(&acc[int64_t(sR[k]) * kAccRows + i], v);   // sR unsigned
         }
     }
 }
@@ -473,14 +473,6 @@ gs_status launch_project_backward_adam(const gs_settings &s, float *params, int6
                                        double beta2, double eps, int32_t step, const int32_t *d_step,
                                        void *proj_out, hipStream_t st);
 
-static bool valid_settings(const gs_settings *s) {
-    return s && s->sh_degree >= 0 && s->sh_degree <= 3 &&
-           (s->batch == 64 || s->batch == 128 || s->batch == 256) &&
-           (s->bwd_waves == 1 || s->bwd_waves == 2 || s->bwd_waves == 4) && s->alpha_min > 0.f &&
-           s->alpha_max <= 1.f && s->alpha_max >= s->alpha_min && s->t_min > 0.f &&
-           s->dilation >= 0.f && s->fov_clamp > 0.f;
-}
-
 }  // namespace gs
 
 extern "C" gs_status gs_render_fwd(const gs_settings *s, const void *proj_ws, int64_t n_cap,
@@ -491,7 +483,7 @@ extern "C" gs_status gs_render_fwd(const gs_settings *s, const void *proj_ws, in
     using namespace gs;
     if (!valid_settings(s) || !proj_ws || !sort_ws || !targets || n_cap <= 0 || n_cap % 64 ||
         n_views <= 0 || n_targets <= 0 || total_tiles <= 0 || pair_cap <= 0 || !out_rgb ||
-        !out_T || !out_last)
+        !out_T || !out_last || pair_cap > kMaxPairs || int64_t(n_views) * n_cap > kMaxRecords)
         return GS_ERR_INVALID_ARGUMENT;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Sorted srt = sorted_at(sort_ws, n_views, n_targets, n_cap, pair_cap, total_tiles);
@@ -514,7 +506,8 @@ extern "C" gs_status gs_raster_bwd(const gs_settings *s, const void *proj_ws, in
     using namespace gs;
     if (!valid_settings(s) || !proj_ws || !sort_ws || !targets || !out_T || !out_last || !dL_drgb ||
         !accum_ws || n_cap <= 0 || n_cap % 64 || n_views <= 0 || n_targets <= 0 ||
-        total_tiles <= 0 || pair_cap <= 0)
+        total_tiles <= 0 || pair_cap <= 0 || pair_cap > kMaxPairs ||
+        int64_t(n_views) * n_cap > kMaxRecords)
         return GS_ERR_INVALID_ARGUMENT;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t records = int64_t(n_views) * n_cap;

@@ -184,36 +184,54 @@ __device__ __forceinline__ void block_reduce_to(uint32_t n, uint32_t *bsum, F f)
     if (threadIdx.x == 0) bsum[blockIdx.x] = total;
 }
 
+// 64-bit wave scans for the pair offsets: a sum of per-record pair counts may
+// pass 2^32, and is then saturated (a total past pair_cap <= 2^31 - 1 is an
+// overflow, reported as such) instead of wrapping.
+__device__ __forceinline__ uint64_t wave_inclusive_scan64(uint64_t v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t lo = __shfl_up(uint32_t(v), d, kWave);
+        const uint32_t hi = __shfl_up(uint32_t(v >> 32), d, kWave);
+        if (lane >= d) v += (uint64_t(hi) << 32) | lo;
+    }
+    return v;
+}
+__device__ __forceinline__ uint32_t sat32(uint64_t v) {
+    return v > 0xffffffffull ? 0xffffffffu : uint32_t(v);
+}
+
 // Exclusive scan of bsum[0..nb) in place (one block of 1024 threads); the
-// total goes to *total_out.
+// total goes to *total_out.  Sums are formed in 64 bits and stored saturated
+// at 2^32 - 1.
 __global__ void __launch_bounds__(1024) scan_bsums_kernel(const uint32_t *__restrict__ n_ptr,
                                                           uint32_t *bsum, uint32_t *total_out,
                                                           int64_t n_fixed) {
-    __shared__ uint32_t lds[16];
+    __shared__ uint64_t lds[16];
     const uint32_t n = n_ptr ? *n_ptr : uint32_t(n_fixed);
     const int64_t nb = active_blocks(n);
     const int64_t per = (nb + 1023) / 1024;
     const int64_t lo = int64_t(threadIdx.x) * per;
-    uint32_t local = 0;
+    uint64_t local = 0;
     for (int64_t i = lo; i < lo + per && i < nb; ++i) local += bsum[i];
     // block scan over 1024 threads (16 waves)
     const int lane = lane_id(), wave = threadIdx.x / kWave;
-    uint32_t inc = wave_inclusive_scan(local);
+    const uint64_t inc = wave_inclusive_scan64(local);
     if (lane == kWave - 1) lds[wave] = inc;
     __syncthreads();
-    uint32_t wbase = 0, all = 0;
+    uint64_t wbase = 0, all = 0;
     for (int w = 0; w < 16; ++w) {
-        const uint32_t v = lds[w];
+        const uint64_t v = lds[w];
         wbase += (w < wave) ? v : 0u;
         all += v;
     }
-    uint32_t run = wbase + inc - local;
+    uint64_t run = wbase + inc - local;
     for (int64_t i = lo; i < lo + per && i < nb; ++i) {
         const uint32_t v = bsum[i];
-        bsum[i] = run;
+        bsum[i] = sat32(run);
         run += v;
     }
-    if (threadIdx.x == 0) *total_out = all;
+    if (threadIdx.x == 0) *total_out = sat32(all);
 }
 
 // Compaction of visible sources: flags from counts, values = source index,
@@ -285,10 +303,28 @@ __global__ void __launch_bounds__(256) compact_scatter_kernel(const uint32_t *__
 
 // Exclusive scan of the pair counts over the depth-sorted visible list
 // (sorted_cnt: the counts carried through the depth sort, in list order).
+// Block sums in 64 bits, stored saturated.
 __global__ void __launch_bounds__(256) offsets_reduce_kernel(const uint32_t *__restrict__ n_ptr,
                                                              const uint32_t *__restrict__ sorted_cnt,
                                                              uint32_t *bsum) {
-    block_reduce_to(*n_ptr, bsum, [&](int64_t e) { return sorted_cnt[e]; });
+    __shared__ uint64_t lds[kScanThreads / kWave];
+    const uint32_t n = *n_ptr;
+    const int64_t base = int64_t(blockIdx.x) * kScanTile;
+    if (base >= n) return;
+    uint64_t acc = 0;
+#pragma unroll 4
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t e = base + k * kScanThreads + threadIdx.x;
+        if (e < n) acc += sorted_cnt[e];
+    }
+    acc = wave_inclusive_scan64(acc);
+    if (lane_id() == kWave - 1) lds[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (int w = 0; w < kScanThreads / kWave; ++w) t += lds[w];
+        bsum[blockIdx.x] = sat32(t);
+    }
 }
 
 __global__ void __launch_bounds__(256) offsets_scatter_kernel(const uint32_t *__restrict__ n_ptr,
@@ -297,31 +333,38 @@ __global__ void __launch_bounds__(256) offsets_scatter_kernel(const uint32_t *__
                                                               uint32_t *__restrict__ vis_off,
                                                               uint32_t *__restrict__ chunk_first,
                                                               int64_t n_chunks) {
-    __shared__ uint32_t wtot[kScanItems][kScanThreads / kWave];
+    __shared__ uint64_t wtot[kScanItems][kScanThreads / kWave];
     const uint32_t n = *n_ptr;
     const int64_t base = int64_t(blockIdx.x) * kScanTile;
     if (base >= n) return;
     const int wave = threadIdx.x / kWave, lane = lane_id();
-    uint32_t c[kScanItems], pre[kScanItems];
+    uint32_t c[kScanItems];
+    uint64_t pre[kScanItems];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         const int64_t e = base + k * kScanThreads + threadIdx.x;
         c[k] = e < int64_t(n) ? sorted_cnt[e] : 0u;
-        const uint32_t inc = wave_inclusive_scan(c[k]);
+        const uint64_t inc = wave_inclusive_scan64(c[k]);
         pre[k] = inc - c[k];
         if (lane == kWave - 1) wtot[k][wave] = inc;
     }
-    round_wave_offsets(wtot);
-    const uint32_t b0 = bsum[blockIdx.x];
+    __syncthreads();
+    if (threadIdx.x < kWave) {   // the (round, wave) totals in element order
+        const int k = threadIdx.x / (kScanThreads / kWave), w = threadIdx.x % (kScanThreads / kWave);
+        const uint64_t v = wtot[k][w];
+        wtot[k][w] = wave_inclusive_scan64(v) - v;
+    }
+    __syncthreads();
+    const uint64_t b0 = bsum[blockIdx.x];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         const int64_t e = base + k * kScanThreads + threadIdx.x;
         if (e < int64_t(n)) {
-            const uint32_t o = b0 + wtot[k][wave] + pre[k];
-            vis_off[e] = o;
+            const uint64_t o = b0 + wtot[k][wave] + pre[k];
+            vis_off[e] = sat32(o);
             // this record holds the first slot of every chunk starting in [o, o + c)
-            const uint64_t end = uint64_t(o) + c[k];
-            for (uint64_t q = (uint64_t(o) + 255) / 256; q * 256 < end && int64_t(q) < n_chunks; ++q)
+            const uint64_t end = o + c[k];
+            for (uint64_t q = (o + 255) / 256; q * 256 < end && int64_t(q) < n_chunks; ++q)
                 chunk_first[q] = uint32_t(e);
         }
     }
@@ -795,9 +838,9 @@ extern "C" gs_status gs_bin_sort(const gs_settings *s, const void *proj_ws, int6
                                  int32_t n_targets, int32_t total_tiles, void *sort_ws,
                                  int64_t pair_cap, uint32_t *d_status, void *stream) {
     using namespace gs;
-    if (!s || !proj_ws || !targets || !sort_ws || n < 0 || n_cap <= 0 || n > n_cap || n_cap % 64 ||
-        n_views <= 0 || n_targets <= 0 || total_tiles <= 0 || pair_cap <= 0 ||
-        pair_cap > 0x7fffffffLL || int64_t(n_views) * n_cap > 0xffffffffLL)
+    if (!valid_settings(s) || !proj_ws || !targets || !sort_ws || n < 0 || n_cap <= 0 || n > n_cap ||
+        n_cap % 64 || n_views <= 0 || n_targets <= 0 || total_tiles <= 0 || pair_cap <= 0 ||
+        pair_cap > kMaxPairs || int64_t(n_views) * n_cap > kMaxRecords)
         return GS_ERR_INVALID_ARGUMENT;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t S = int64_t(n_views) * n_cap;   // (view, Gaussian) records

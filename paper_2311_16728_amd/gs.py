@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libgs.so")
 NUM_ROWS = 59
 TILE = 16
 STATUS_PAIR_OVERFLOW = 1
+STATUS_NUMERIC = 2
 
 
 class GsError(RuntimeError):
@@ -28,7 +29,8 @@ class GsError(RuntimeError):
 class gs_settings(C.Structure):
     _fields_ = [("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float),
                 ("znear", C.c_float), ("dilation", C.c_float), ("fov_clamp", C.c_float),
-                ("sh_degree", C.c_int32), ("batch", C.c_int32), ("bwd_waves", C.c_int32)]
+                ("sh_degree", C.c_int32), ("batch", C.c_int32), ("bwd_waves", C.c_int32),
+                ("checked", C.c_int32), ("status", C.c_void_p)]
 
 
 class gs_view(C.Structure):
@@ -65,6 +67,7 @@ def _load():
     S, V, T = C.POINTER(gs_settings), C.POINTER(gs_view), C.POINTER(gs_target)
     sig = {
         "gs_status_string": ([C.c_int], C.c_char_p),
+        "gs_status_word": ([C.c_uint32], C.c_int),
         "gs_default_settings": ([S], None),
         "gs_targets_layout": ([V, i32, T, i32, C.POINTER(C.c_int64), C.POINTER(C.c_int32)], C.c_int),
         "gs_workspace_query": ([S, i64, i32, T, i32, i64, C.POINTER(gs_sizes)], C.c_int),
@@ -112,7 +115,7 @@ def _load():
 
 
 _lib = _load()
-EXPORTED = ["gs_status_string", "gs_default_settings", "gs_targets_layout", "gs_workspace_query",
+EXPORTED = ["gs_status_string", "gs_status_word", "gs_default_settings", "gs_targets_layout", "gs_workspace_query",
             "gs_preprocess", "gs_bin_sort", "gs_render_fwd", "gs_raster_bwd", "gs_project_bwd",
             "gs_project_bwd_adam", "gs_render_bwd", "gs_render_bwd_adam",
             "gs_pyramid_build",
@@ -173,11 +176,25 @@ def _stream(stream=None):
 
 
 def default_settings(**overrides) -> gs_settings:
+    """Library defaults with overrides; ``status`` may be a device int32/uint32
+    tensor of one element (checked mode's status word)."""
     s = gs_settings()
     _lib.gs_default_settings(C.byref(s))
     for k, v in overrides.items():
+        if k == "status" and isinstance(v, torch.Tensor):
+            v = _p(v).value
         setattr(s, k, v)
     return s
+
+
+def gs_status_word(word: int) -> int:
+    """Status code a device status word read back by the caller stands for."""
+    return int(_lib.gs_status_word(C.c_uint32(int(word) & 0xffffffff)))
+
+
+def check_status_word(word: int, what: str = "device status"):
+    """Raises GsError when the status word reports an overflow or a non-finite value."""
+    _check(gs_status_word(word), what)
 
 
 def make_view(cam: dict) -> gs_view:

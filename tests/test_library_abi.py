@@ -162,3 +162,46 @@ def test_size_limits_rejected_on_the_host():
     for w, want in ((12, INVALID), (64, INVALID), (8, 0), (32, 0)):
         tg[0].tile_w = w
         assert lib.gs_targets_layout(small, 1, tg, 1, C.byref(tot_p), C.byref(tot_t)) == want, w
+
+
+def test_checked_mode_and_status_word():
+    """Checked mode needs a status word; the status word maps to the status codes
+    the header states; record counts past 2^32 - 1 are refused by every call that
+    indexes projection records."""
+    from paper_2311_16728_amd import gs
+
+    lib = gs._lib
+    one = C.c_void_p(16)
+    INVALID = 1
+    s = gs.default_settings()
+    assert s.checked == 0 and not s.status
+    no_word = gs.default_settings(checked=1)
+    assert lib.gs_preprocess(C.byref(no_word), one, 10, 256, one, 1, one, None) == INVALID
+    with_word = gs.default_settings(checked=1, status=16)
+    views = [gs.make_view(__import__("scenes").pinhole(64, 64, 64.0))]
+    t, _, _ = gs.gs_targets_layout(views, [(0, 0, (0, 0, 0), 1.0)])
+    gs.gs_workspace_query(with_word, 256, 1, t, 1 << 10)
+    with pytest.raises(gs.GsError):
+        gs.gs_workspace_query(no_word, 256, 1, t, 1 << 10)
+    assert gs.gs_status_word(0) == 0
+    assert gs.gs_status_word(gs.STATUS_PAIR_OVERFLOW) == 2          # capacity
+    assert gs.gs_status_word(gs.STATUS_NUMERIC) == 5                # numeric
+    assert gs.gs_status_word(gs.STATUS_NUMERIC | gs.STATUS_PAIR_OVERFLOW) == 5
+    assert gs.gs_status_word(8) == INVALID
+    lib.gs_status_string.restype = C.c_char_p
+    assert lib.gs_status_string(5) == b"non-finite value"
+    with pytest.raises(gs.GsError, match="capacity"):
+        gs.check_status_word(gs.STATUS_PAIR_OVERFLOW)
+    # 65 views x 2^26 columns: more than 2^32 - 1 records
+    nv, ncap = 65, 1 << 26
+    assert lib.gs_preprocess(C.byref(s), one, 10, ncap, one, nv, one, None) == INVALID
+    assert lib.gs_render_fwd(C.byref(s), one, ncap, nv, one, 1024, one, 1, 16, one, one, one,
+                             None, None) == INVALID
+    assert lib.gs_raster_bwd(C.byref(s), one, ncap, nv, one, 1024, one, 1, 16, one, one, one, one,
+                             None) == INVALID
+    assert lib.gs_render_fwd(C.byref(s), one, 256, 1, one, 1 << 31, one, 1, 16, one, one, one,
+                             None, None) == INVALID
+    with pytest.raises(gs.GsError):
+        gs.gs_workspace_query(s, ncap, nv, t, 1 << 10)
+    with pytest.raises(gs.GsError):
+        gs.gs_workspace_query(s, 256, 1, t, 1 << 31)
