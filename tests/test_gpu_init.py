@@ -74,14 +74,48 @@ def test_mlp_forward(B):
     assert (g1 == h1).double().mean().item() >= 0.999
 
 
+def _fp32_bound(absum, k):
+    """Rigorous bound on the FP32 accumulation error of a length-k dot product
+    of exact BF16 products plus a bias, in any summation order, doubled."""
+    return 2.0 * (k + 1) * 2.0 ** -24 * absum
+
+
+def _unambiguous_batch(wb, b, B, rng):
+    """Inputs x (BF16) and upstream gradients dy whose hidden ReLU masks FP32
+    decides as float64 does: rows with a pre-activation whose sign FP32 could
+    decide differently are redrawn.  For the second layer that includes the
+    effect of first-layer BF16 roundings FP32 could take the other way (each
+    such hidden value may move by its rounding step).  A flipped mask moves a
+    whole hidden gradient, about 5e-3 of the weight gradient's norm per flip;
+    a BF16 rounding flip of one hidden value moves one product by one BF16 ulp
+    and is left in."""
+    W1, W2, W3 = unpack(wb)
+    bb = torch.as_tensor(b, dtype=torch.float64)
+    x = bf(rng.normal(size=(B, 160)))
+    dy = torch.as_tensor(rng.normal(size=(B, 16)), dtype=torch.float64)
+    for _ in range(100):
+        p1 = x @ W1.T + bb[:128]
+        d1 = _fp32_bound(x.abs() @ W1.abs().T + bb[:128].abs(), 160)
+        ok = (p1.abs() > d1).all(1)
+        h1 = bf(torch.relu(p1))
+        step = (bf(torch.relu(p1 + d1)) - bf(torch.relu(p1 - d1))).abs()
+        p2 = h1 @ W2.T + bb[128:256]
+        d2 = _fp32_bound(h1.abs() @ W2.abs().T + bb[128:256].abs(), 128) + step @ W2.abs().T
+        ok &= (p2.abs() > d2).all(1)
+        bad = (~ok).nonzero().flatten()
+        if bad.numel() == 0:
+            return x, dy
+        x[bad] = bf(rng.normal(size=(bad.numel(), 160)))
+    raise AssertionError("could not draw an unambiguous batch")
+
+
 def test_mlp_backward():
     from paper_2311_16728_amd import gs
 
     B = 2048
     w, b, wb = _model(7)
     rng = np.random.default_rng(2)
-    x = bf(rng.normal(size=(B, 160)))
-    dy = torch.as_tensor(rng.normal(size=(B, 16)), dtype=torch.float64)
+    x, dy = _unambiguous_batch(wb, b, B, rng)
     Wd = wb.to(torch.float32).to(torch.bfloat16).view(torch.int16).cuda()
     Xd = x.to(torch.float32).to(torch.bfloat16).view(torch.int16).cuda().contiguous()
     y = torch.zeros(B, 16, dtype=torch.float32, device="cuda")
@@ -93,7 +127,9 @@ def test_mlp_backward():
     gs.gs_init_mlp_bwd(Wd, Xd, act, dy.to(torch.float32).cuda(), dw, db)
     torch.cuda.synchronize()
     # reference with the same BF16 roundings, hidden activations recomputed in
-    # float64 from the inputs (nothing read back from the kernel's workspace)
+    # float64 from the inputs (nothing read back from the kernel's workspace);
+    # the inputs were drawn so that FP32 takes every ReLU mask decision the
+    # same way
     W1, W2, W3 = unpack(wb)
     _, h1, h2 = ref_forward(wb, b, x)
     dyb = bf(dy)
