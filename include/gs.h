@@ -14,7 +14,8 @@
  * --------------------------------
  * - Device pointers are marked (device); host pointers (host).  Every device
  *   buffer is owned by the caller; the library never allocates or frees
- *   device memory and keeps no state between calls.
+ *   device memory and keeps no state between calls (one exception:
+ *   gs_densify_noalloc keeps its workspace in a fixed device array).
  * - `stream` is a hipStream_t passed as void*.  Calls only enqueue work on it
  *   (stream-ordered, asynchronous) and never synchronise, so a sequence of
  *   calls can be captured into a HIP graph.  NULL means the default stream.
@@ -427,6 +428,25 @@ gs_status gs_densify(const gs_densify_rule *rule, const float *params, const flo
                      const float *v, const float *stats, const float *noise, int64_t n,
                      int64_t n_cap, float *out_params, float *out_m, float *out_v,
                      int64_t out_cap, void *ws, int64_t *d_counts, void *stream);
+
+/* Largest n that gs_densify_noalloc accepts. */
+#define GS_DENSIFY_NOALLOC_MAX_N 16777216
+
+/* gs_densify without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same kernels, arguments (less ws) and results as
+ * gs_densify.  Its workspace is a fixed device array inside the library,
+ * 8,127,232 bytes (the workspace of n = GS_DENSIFY_NOALLOC_MAX_N), which each
+ * device holds from the first call on it until the process ends; nothing in it
+ * needs to start cleared, and the call allocates nothing.  n above
+ * GS_DENSIFY_NOALLOC_MAX_N returns GS_ERR_CAPACITY and enqueues nothing.  All
+ * calls on one device share that device's array: calls that may overlap on the
+ * same device (other streams, other host threads) race on it and must be
+ * ordered by the caller. */
+gs_status gs_densify_noalloc(const gs_densify_rule *rule, const float *params, const float *m,
+                             const float *v, const float *stats, const float *noise, int64_t n,
+                             int64_t n_cap, float *out_params, float *out_m, float *out_v,
+                             int64_t out_cap, int64_t *d_counts, void *stream);
 
 /* Opacity reset of the same rule: the opacity logit of every primitive < n is
  * lowered to ln(max_opacity / (1 - max_opacity)) (computed in double, rounded

@@ -18,6 +18,7 @@
 #include "gs_internal.hpp"
 
 #include <cmath>
+#include <mutex>
 
 namespace gs {
 namespace {
@@ -347,8 +348,8 @@ __global__ void reset_opacity_kernel(float *__restrict__ P, float *__restrict__ 
 struct DensifyWs {
     size_t blk, masks, first_keep, first_new, tot, bytes;
     int64_t nb, keep_tiles, new_tiles;
-    static DensifyWs make(int64_t n) {
-        DensifyWs L;
+    static constexpr DensifyWs make(int64_t n) {
+        DensifyWs L{};
         L.nb = (n + kDenBlock - 1) / kDenBlock;
         L.keep_tiles = L.nb;
         L.new_tiles = (2 * n + kDenBlock - 1) / kDenBlock;
@@ -400,17 +401,16 @@ extern "C" size_t gs_densify_workspace_bytes(int64_t n) {
     return DensifyWs::make(n < 0 ? 0 : n).bytes;
 }
 
-extern "C" gs_status gs_densify(const gs_densify_rule *rule, const float *params, const float *m,
-                                const float *v, const float *stats, const float *noise, int64_t n,
-                                int64_t n_cap, float *out_params, float *out_m, float *out_v,
-                                int64_t out_cap, void *ws, int64_t *d_counts, void *stream) {
-    if (!rule || !params || !m || !v || !stats || !noise || !out_params || !out_m || !out_v || !ws ||
-        !d_counts || n < 0 || n > n_cap || n_cap % 64 || out_cap < 0 || out_cap % 64 ||
-        n_cap >= (int64_t(1) << 31) || out_cap >= (int64_t(1) << 31))
-        return GS_ERR_INVALID_ARGUMENT;
-    hipStream_t st = static_cast<hipStream_t>(stream);
+namespace gs {
+namespace {
+
+// One densification pass (count, scan, tables, gather) with its workspace at b
+// (DensifyWs::make(n) bytes).  Arguments already validated.
+void densify_launch(const gs_densify_rule &rule, const float *params, const float *m, const float *v,
+                    const float *stats, const float *noise, int64_t n, int64_t n_cap, float *out_params,
+                    float *out_m, float *out_v, int64_t out_cap, char *b, int64_t *d_counts,
+                    hipStream_t st) {
     const DensifyWs L = DensifyWs::make(n);
-    char *b = static_cast<char *>(ws);
     int4 *blk = reinterpret_cast<int4 *>(b + L.blk);
     BlockMasks *masks = reinterpret_cast<BlockMasks *>(b + L.masks);
     int32_t *first_keep = reinterpret_cast<int32_t *>(b + L.first_keep);
@@ -418,7 +418,7 @@ extern "C" gs_status gs_densify(const gs_densify_rule *rule, const float *params
     int64_t *tot = reinterpret_cast<int64_t *>(b + L.tot);
     const int64_t nb = L.nb;
     if (nb > 0)
-        hipLaunchKernelGGL(densify_count_kernel, dim3(xcd_grid(nb)), dim3(kDenThreads), 0, st, *rule,
+        hipLaunchKernelGGL(densify_count_kernel, dim3(xcd_grid(nb)), dim3(kDenThreads), 0, st, rule,
                            params, stats, n, n_cap, nb, blk, masks);
     hipLaunchKernelGGL(densify_scan_kernel, dim3(1), dim3(kScanThreads), 0, st, blk, nb, n, tot,
                        d_counts);
@@ -426,9 +426,79 @@ extern "C" gs_status gs_densify(const gs_densify_rule *rule, const float *params
         hipLaunchKernelGGL(densify_tables_kernel, dim3((nb + kDenThreads - 1) / kDenThreads),
                            dim3(kDenThreads), 0, st, blk, nb, tot, first_keep, first_new);
         hipLaunchKernelGGL(densify_gather_kernel, dim3(L.keep_tiles + L.new_tiles), dim3(kDenThreads), 0,
-                           st, *rule, params, m, v, noise, n_cap, out_params, out_m, out_v, out_cap, nb,
+                           st, rule, params, m, v, noise, n_cap, out_params, out_m, out_v, out_cap, nb,
                            L.keep_tiles, blk, masks, first_keep, first_new, tot);
     }
+}
+
+bool densify_args_ok(const gs_densify_rule *rule, const float *params, const float *m, const float *v,
+                     const float *stats, const float *noise, int64_t n, int64_t n_cap,
+                     const float *out_params, const float *out_m, const float *out_v, int64_t out_cap,
+                     const int64_t *d_counts) {
+    return rule && params && m && v && stats && noise && out_params && out_m && out_v && d_counts &&
+           n >= 0 && n <= n_cap && n_cap % 64 == 0 && out_cap >= 0 && out_cap % 64 == 0 &&
+           n_cap < (int64_t(1) << 31) && out_cap < (int64_t(1) << 31);
+}
+
+// Workspace of gs_densify_noalloc: a pass over up to GS_DENSIFY_NOALLOC_MAX_N
+// primitives.  Nothing in it has to start cleared (every word a pass reads is
+// written earlier in the same pass).  In host code `scratch` names a host-side
+// stand-in; kernels get the device address that hipGetSymbolAddress returns
+// for the current device.
+constexpr size_t kNoAllocScratchBytes = DensifyWs::make(GS_DENSIFY_NOALLOC_MAX_N).bytes;
+static_assert(kNoAllocScratchBytes == 8127232, "the header states the scratch size");
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::once_flag scratch_once[kMaxDevices];
+void *scratch_ptr[kMaxDevices];
+hipError_t scratch_err[kMaxDevices];
+
+// Device address of this device's scratch array, looked up once per device
+// (with that device current).
+gs_status scratch_address(void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return GS_ERR_HIP;
+    std::call_once(scratch_once[dev], [dev] {
+        void *ptr = nullptr;
+        scratch_err[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        scratch_ptr[dev] = ptr;
+    });
+    if (scratch_err[dev] != hipSuccess || !scratch_ptr[dev]) return GS_ERR_HIP;
+    *out = scratch_ptr[dev];
+    return GS_OK;
+}
+
+}  // namespace
+}  // namespace gs
+
+extern "C" gs_status gs_densify(const gs_densify_rule *rule, const float *params, const float *m,
+                                const float *v, const float *stats, const float *noise, int64_t n,
+                                int64_t n_cap, float *out_params, float *out_m, float *out_v,
+                                int64_t out_cap, void *ws, int64_t *d_counts, void *stream) {
+    if (!ws || !densify_args_ok(rule, params, m, v, stats, noise, n, n_cap, out_params, out_m, out_v,
+                                out_cap, d_counts))
+        return GS_ERR_INVALID_ARGUMENT;
+    densify_launch(*rule, params, m, v, stats, noise, n, n_cap, out_params, out_m, out_v, out_cap,
+                   static_cast<char *>(ws), d_counts, static_cast<hipStream_t>(stream));
+    GS_CHECK_LAUNCH();
+    return GS_OK;
+}
+
+extern "C" gs_status gs_densify_noalloc(const gs_densify_rule *rule, const float *params,
+                                        const float *m, const float *v, const float *stats,
+                                        const float *noise, int64_t n, int64_t n_cap,
+                                        float *out_params, float *out_m, float *out_v,
+                                        int64_t out_cap, int64_t *d_counts, void *stream) {
+    if (!densify_args_ok(rule, params, m, v, stats, noise, n, n_cap, out_params, out_m, out_v, out_cap,
+                         d_counts))
+        return GS_ERR_INVALID_ARGUMENT;
+    if (n > GS_DENSIFY_NOALLOC_MAX_N) return GS_ERR_CAPACITY;
+    void *ws = nullptr;
+    const gs_status st = scratch_address(&ws);
+    if (st != GS_OK) return st;
+    densify_launch(*rule, params, m, v, stats, noise, n, n_cap, out_params, out_m, out_v, out_cap,
+                   static_cast<char *>(ws), d_counts, static_cast<hipStream_t>(stream));
     GS_CHECK_LAUNCH();
     return GS_OK;
 }

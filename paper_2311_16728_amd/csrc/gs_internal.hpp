@@ -30,7 +30,7 @@ constexpr int kRadixBitsMax = 9;              // widest radix digit (depth sort,
 constexpr int kRadixBinsMax = 1 << kRadixBitsMax;
 constexpr int kRadixPersist = 2048;           // workgroups of the grid-stride radix kernels
 
-static inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+static constexpr size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Size limits of the interface: records are indexed by uint32, pair slots by
 // uint32 with the total kept below 2^31 (so a count past it is seen, not wrapped).

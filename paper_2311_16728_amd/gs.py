@@ -103,6 +103,8 @@ def _load():
         "gs_densify_workspace_bytes": ([i64], C.c_size_t),
         "gs_densify": ([C.POINTER(gs_densify_rule), vp, vp, vp, vp, vp, i64, i64, vp, vp, vp, i64, vp,
                         vp, vp], C.c_int),
+        "gs_densify_noalloc": ([C.POINTER(gs_densify_rule), vp, vp, vp, vp, vp, i64, i64, vp, vp, vp, i64,
+                                vp, vp], C.c_int),
         "gs_reset_opacity": ([vp, vp, vp, i64, i64, C.c_double, vp], C.c_int),
         "gs_sim3_workspace_bytes": ([i32], C.c_size_t),
         "gs_sim3_apply": ([vp, i64, i64, vp, i32, vp, vp, vp], C.c_int),
@@ -122,7 +124,7 @@ EXPORTED = ["gs_status_string", "gs_status_word", "gs_default_settings", "gs_tar
             "gs_pyramid_loss", "gs_adam_step", "gs_step_advance", "gs_fill", "gs_init_features",
             "gs_init_mlp_fwd", "gs_init_mlp_bwd", "gs_init_mlp_adam", "gs_to_bf16", "gs_init_heuristic",
             "gs_init_decode", "gs_append", "gs_densify_rule_make", "gs_densify_stats",
-            "gs_densify_workspace_bytes", "gs_densify", "gs_reset_opacity", "gs_sim3_workspace_bytes",
+            "gs_densify_workspace_bytes", "gs_densify", "gs_densify_noalloc", "gs_reset_opacity", "gs_sim3_workspace_bytes",
             "gs_sim3_apply"]
 
 
@@ -428,6 +430,21 @@ def gs_densify(rule, params, m, v, stats, noise, n, out_params, out_m, out_v, ws
                            _store(out_params, "out_params"), _store(out_m, "out_m", out_params),
                            _store(out_v, "out_v", out_params), out_params.shape[1], _p(ws),
                            _typed(d_counts, torch.int64, "d_counts"), _stream(stream)), "gs_densify")
+
+
+DENSIFY_NOALLOC_MAX_N = 16777216
+
+
+def gs_densify_noalloc(rule, params, m, v, stats, noise, n, out_params, out_m, out_v, d_counts, stream=None):
+    if stats.shape[1] != params.shape[1] or noise.shape[1] != params.shape[1]:
+        raise GsError("stats and noise need the parameters' column capacity")
+    _check(_lib.gs_densify_noalloc(C.byref(rule), _store(params, "params"), _store(m, "m", params),
+                                   _store(v, "v", params), _typed(stats, torch.float32, "stats", 2, 2),
+                                   _typed(noise, torch.float32, "noise", 2, 6), n, params.shape[1],
+                                   _store(out_params, "out_params"), _store(out_m, "out_m", out_params),
+                                   _store(out_v, "out_v", out_params), out_params.shape[1],
+                                   _typed(d_counts, torch.int64, "d_counts"), _stream(stream)),
+           "gs_densify_noalloc")
 
 
 def gs_reset_opacity(params, m, v, n, max_opacity=0.01, stream=None):

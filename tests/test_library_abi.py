@@ -147,6 +147,15 @@ def test_size_limits_rejected_on_the_host():
                           None) == INVALID
     assert lib.gs_densify(C.byref(rule), one, one, one, one, one, 10, 256, one, one, one, 100, one, one,
                           None) == INVALID                          # out_cap not a multiple of 64
+    # densification without a workspace: above its fixed scratch (n > 2^24) it
+    # reports the capacity; invalid arguments as gs_densify
+    big_n = gs.DENSIFY_NOALLOC_MAX_N + 1
+    assert lib.gs_densify_noalloc(C.byref(rule), one, one, one, one, one, big_n, big_n + 63, one, one, one,
+                                  256, one, None) == CAPACITY
+    assert lib.gs_densify_noalloc(C.byref(rule), one, one, one, one, one, 10, 256, one, one, one, 100, one,
+                                  None) == INVALID
+    assert lib.gs_densify_noalloc(C.byref(rule), one, one, one, one, one, 10, 256, one, one, one, 256, None,
+                                  None) == INVALID
     # loop closure: n_cap not a multiple of 64, no transform
     assert lib.gs_sim3_apply(one, 10, 100, one, 1, None, one, None) == INVALID
     assert lib.gs_sim3_apply(one, 10, 256, one, 0, None, one, None) == INVALID
