@@ -186,12 +186,15 @@ gs_status gs_bin_sort(const gs_settings *s, const void *proj_ws, int64_t n, int6
  * total_pixels, final transmittance), out_last (device, total_pixels, one
  * past the tile-list position of the last composited Gaussian; the backward
  * restarts from it) and, when not NULL, out_ncontrib (device, total_pixels,
- * number of composited Gaussians). */
+ * number of composited Gaussians) and out_nevals (device, total_pixels,
+ * number of (pixel, Gaussian) pairs the pixel evaluated: Gaussians of its
+ * tile's list that reach the tile, up to its early stop). */
 gs_status gs_render_fwd(const gs_settings *s, const void *proj_ws, int64_t n_cap,
                         int32_t n_views, const void *sort_ws, int64_t pair_cap,
                         const gs_target *targets,
                         int32_t n_targets, int32_t total_tiles, float *out_rgb, float *out_T,
-                        int32_t *out_last, int32_t *out_ncontrib, void *stream);
+                        int32_t *out_last, int32_t *out_ncontrib, int32_t *out_nevals,
+                        void *stream);
 
 /* Backward of the rasteriser (reverse mode of Eq. 3 per pixel): recomputes
  * compositing back to front from out_T and out_last (no per-pixel lists are

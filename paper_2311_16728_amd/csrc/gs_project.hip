@@ -655,6 +655,254 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
     sink.finish_updated(s, g, n_cap, views, n_views, geo, &keep2[0][threadIdx.x]);
 }
 
+// Element at byte offset `off` of row `row` of a [rows][n_cap] array: the row
+// base is uniform and the offset a 32-bit lane value, so a load or store takes
+// one offset register instead of a 64-bit address per row.
+template <class T>
+__device__ __forceinline__ T &at_row(T *base, int64_t row, int64_t n_cap, uint32_t off) {
+    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return *reinterpret_cast<T *>(reinterpret_cast<B *>(base + row * n_cap) + off);
+}
+
+// AdamSink::group with 32-bit offsets (same arithmetic).
+template <int N>
+__device__ __forceinline__ void adam_rows(const AdamSink &a, int first, int stride, int64_t n_cap,
+                                          uint32_t off, float (&gv)[N], const float (&pcur)[N],
+                                          AdamSink::Scale sc) {
+    float mm[N], vv[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        mm[j] = at_row(a.m, first + j * stride, n_cap, off);
+        vv[j] = at_row(a.v, first + j * stride, n_cap, off);
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const int row = first + j * stride;
+        const float mv = a.b1 * mm[j] + a.omb1 * gv[j];
+        const float vq = a.b2 * vv[j] + a.omb2 * gv[j] * gv[j];
+        at_row(a.m, row, n_cap, off) = mv;
+        at_row(a.v, row, n_cap, off) = vq;
+        const float den = __builtin_amdgcn_sqrtf(vq) * sc.isqbc2 + a.eps;
+        const float np = pcur[j] - a.lr.lr[row] * sc.ibc1 * mv * __builtin_amdgcn_rcpf(den);
+        at_row(a.p, row, n_cap, off) = np;
+        gv[j] = np;
+    }
+}
+
+// The same chain rule fused with Adam and the next records for one view, with
+// every parameter loaded once: the 48 colour coefficients stay in registers
+// from their load (the view-direction gradient needs them all) through their
+// update to the colour of the next record, and the 11 geometric rows
+// likewise.  Same arithmetic as project_backward_kernel<AdamSink> with one
+// view followed by preprocess_one, so updates and records equal theirs.
+// Compiled for SH degree 3 (kDeg), the degree of the mapping workloads.
+template <int kDeg>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) project_adam_one_view_kernel(
+    gs_settings s, int64_t n, int64_t n_cap, const gs_view *__restrict__ views,
+    const float *__restrict__ acc, AdamSink sink) {
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    // byte offsets of column g (the launch keeps n_cap below 2^26)
+    const uint32_t off = uint32_t(g) * 4u;
+    const float *P = sink.p;
+    const typename AdamSink::Scale sc = sink.prepare();
+    constexpr int nk = (kDeg + 1) * (kDeg + 1);
+    const Cam c = load_cam(views[0], s.fov_clamp);
+    float raw[11];
+#pragma unroll
+    for (int i = 0; i < 11; ++i) raw[i] = at_row(P, i, n_cap, off);
+    float a[kAccRows];
+#pragma unroll
+    for (int i = 0; i < kAccRows; ++i) a[i] = at_row(acc, 0, 0, uint32_t(g) * uint32_t(4 * kAccRows) + 4u * i);
+    float gmu[3] = {0, 0, 0}, gop = 0.f;
+    float dSig[6] = {0, 0, 0, 0, 0, 0};
+
+    // 1. geometry: 2D mean and covariance back to mean and Sigma
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) any |= (a[i] != 0.f);
+    if (any) {
+        Gauss G;
+        gauss_from_raw(raw, G);
+        Proj2 p;
+        if (project(G, c, s.znear, p)) {
+            const float z = p.xc[2], iz = 1.f / z, iz2 = iz * iz;
+            const float G00 = a[2], G01 = a[3], G11 = a[4];
+            {
+                float GT[6];
+#pragma unroll
+                for (int jj = 0; jj < 3; ++jj) {
+                    GT[jj] = G00 * p.T[jj] + G01 * p.T[3 + jj];
+                    GT[3 + jj] = G01 * p.T[jj] + G11 * p.T[3 + jj];
+                }
+                auto e = [&](int ii, int jj) { return p.T[ii] * GT[jj] + p.T[3 + ii] * GT[3 + jj]; };
+                dSig[0] += e(0, 0); dSig[1] += e(0, 1); dSig[2] += e(0, 2);
+                dSig[3] += e(1, 1); dSig[4] += e(1, 2); dSig[5] += e(2, 2);
+            }
+            float TS[6];
+            {
+                const float *S = G.Sig;
+#pragma unroll
+                for (int r2 = 0; r2 < 2; ++r2) {
+                    const float a0 = p.T[3 * r2], b0 = p.T[3 * r2 + 1], d0 = p.T[3 * r2 + 2];
+                    TS[3 * r2 + 0] = a0 * S[0] + b0 * S[1] + d0 * S[2];
+                    TS[3 * r2 + 1] = a0 * S[1] + b0 * S[3] + d0 * S[4];
+                    TS[3 * r2 + 2] = a0 * S[2] + b0 * S[4] + d0 * S[5];
+                }
+            }
+            float dT[6];
+#pragma unroll
+            for (int jj = 0; jj < 3; ++jj) {
+                dT[jj] = 2.f * (G00 * TS[jj] + G01 * TS[3 + jj]);
+                dT[3 + jj] = 2.f * (G01 * TS[jj] + G11 * TS[3 + jj]);
+            }
+            const float dJ00 = dT[0] * c.R[0] + dT[1] * c.R[1] + dT[2] * c.R[2];
+            const float dJ02 = dT[0] * c.R[6] + dT[1] * c.R[7] + dT[2] * c.R[8];
+            const float dJ11 = dT[3] * c.R[3] + dT[4] * c.R[4] + dT[5] * c.R[5];
+            const float dJ12 = dT[3] * c.R[6] + dT[4] * c.R[7] + dT[5] * c.R[8];
+            float gx[3] = {0.f, 0.f, 0.f};
+            gx[2] += -(dJ00 * c.fx + dJ11 * c.fy) * iz2 + (dJ02 * c.fx * p.ub + dJ12 * c.fy * p.vb) * iz2;
+            if (!p.clampx) {
+                gx[0] += -dJ02 * c.fx * iz2;
+                gx[2] += dJ02 * c.fx * p.xc[0] * iz2 * iz;
+            }
+            if (!p.clampy) {
+                gx[1] += -dJ12 * c.fy * iz2;
+                gx[2] += dJ12 * c.fy * p.xc[1] * iz2 * iz;
+            }
+            gx[0] += a[0] * c.fx * iz;
+            gx[1] += a[1] * c.fy * iz;
+            gx[2] += -(a[0] * c.fx * p.xc[0] + a[1] * c.fy * p.xc[1]) * iz2;
+#pragma unroll
+            for (int ii = 0; ii < 3; ++ii)
+                gmu[ii] += c.R[ii] * gx[0] + c.R[3 + ii] * gx[1] + c.R[6 + ii] * gx[2];
+            gop += a[5];
+        }
+    }
+
+    // 2. colour: rgb = max(0, raw), raw = 0.5 + sum_k Y_k(d) sh_k, per channel;
+    // a channel's coefficients are updated in place once its gradient is formed
+    float shv[48];   // coefficient k of channel ch at 3k + ch
+#pragma unroll
+    for (int i = 0; i < 48; ++i) shv[i] = at_row(P, 11 + i, n_cap, off);
+    {
+        float d[3] = {raw[0] - c.C[0], raw[1] - c.C[1], raw[2] - c.C[2]};
+        const float dinv = rsqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        const float dx = d[0] * dinv, dy = d[1] * dinv, dz = d[2] * dinv;
+        float Y[16];
+        sh_eval(kDeg, dx, dy, dz, Y);
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float drgb = a[6 + ch];
+            if (drgb != 0.f) {
+                float rawc = 0.5f;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) rawc += Y[k] * ((k < nk) ? shv[3 * k + ch] : 0.f);
+                if (rawc < 0.f) {
+                    drgb = 0.f;   // clamped colour passes no gradient
+                } else {
+                    float wk[16];
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) wk[k] = drgb * ((k < nk) ? shv[3 * k + ch] : 0.f);
+                    float gd[3];
+                    sh_grad(kDeg, dx, dy, dz, wk, gd);
+                    const float dot = gd[0] * dx + gd[1] * dy + gd[2] * dz;
+                    gmu[0] += (gd[0] - dx * dot) * dinv;
+                    gmu[1] += (gd[1] - dy * dot) * dinv;
+                    gmu[2] += (gd[2] - dz * dot) * dinv;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                float part[4], cur[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    part[j] = drgb != 0.f ? 0.f + Y[4 * q + j] * drgb : 0.f;
+                    cur[j] = shv[3 * (4 * q + j) + ch];
+                }
+                adam_rows(sink, 11 + ch + 12 * q, 3, n_cap, off, part, cur, sc);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) shv[3 * (4 * q + j) + ch] = part[j];
+            }
+        }
+    }
+
+    // 3. Sigma = M M^T, M = Rq diag(s)
+    float geo[11];
+    {
+        Gauss G;
+        gauss_from_raw(raw, G);
+        const float D[9] = {dSig[0], dSig[1], dSig[2], dSig[1], dSig[3], dSig[4], dSig[2], dSig[4], dSig[5]};
+        float dM[9];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int jj = 0; jj < 3; ++jj)
+                dM[3 * i + jj] =
+                    2.f * (D[3 * i] * G.M[jj] + D[3 * i + 1] * G.M[3 + jj] + D[3 * i + 2] * G.M[6 + jj]);
+        float dR[9], gls[3];
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) {
+            float acc_s = 0.f;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                acc_s += dM[3 * i + jj] * G.Rq[3 * i + jj];
+                dR[3 * i + jj] = dM[3 * i + jj] * G.s[jj];
+            }
+            gls[jj] = acc_s * G.s[jj];
+        }
+        float gq[4];
+        {
+            const float w = G.q[0], x = G.q[1], y = G.q[2], z = G.q[3];
+            float dq[4];
+            dq[0] = 2.f * (z * (dR[3] - dR[1]) + y * (dR[2] - dR[6]) + x * (dR[7] - dR[5]));
+            dq[1] = 2.f * (y * (dR[1] + dR[3]) + z * (dR[2] + dR[6]) + w * (dR[7] - dR[5]) -
+                           2.f * x * (dR[4] + dR[8]));
+            dq[2] = 2.f * (x * (dR[1] + dR[3]) + w * (dR[2] - dR[6]) + z * (dR[5] + dR[7]) -
+                           2.f * y * (dR[0] + dR[8]));
+            dq[3] = 2.f * (w * (dR[3] - dR[1]) + x * (dR[2] + dR[6]) + y * (dR[5] + dR[7]) -
+                           2.f * z * (dR[0] + dR[4]));
+            const float dot = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) gq[i] = (dq[i] - G.q[i] * dot) * G.qinv;
+        }
+        const float one_minus_o = G.o > 0.5f ? __expf(-raw[10]) * G.o : 1.f - G.o;
+        const float gv[11] = {gmu[0], gmu[1], gmu[2], gls[0], gls[1], gls[2],
+                              gq[0], gq[1], gq[2], gq[3], gop * G.o * one_minus_o};
+#pragma unroll
+        for (int i = 0; i < 11; ++i) geo[i] = gv[i];
+    }
+    adam_rows(sink, 0, 1, n_cap, off, geo, raw, sc);
+
+    // 4. the next record (as preprocess_one) from the updated registers
+    if (!sink.next.mean) return;
+    Gauss G;
+    gauss_from_raw(geo, G);
+    Proj2 p;
+    const uint32_t off16 = uint32_t(g) * 16u;
+    if (!project(G, c, s.znear, p)) {
+        at_row(sink.next.mean, 0, 0, off16) = make_double2(0.0, 0.0);
+        at_row(sink.next.cov_o, 0, 0, off16) = make_float4(0.f, 0.f, 0.f, 0.f);
+        at_row(sink.next.rgb_z, 0, 0, off16) = make_float4(0.f, 0.f, 0.f, 0.f);
+        return;
+    }
+    float d[3] = {G.mu[0] - c.C[0], G.mu[1] - c.C[1], G.mu[2] - c.C[2]};
+    const float dinv = rsqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    float Y[16];
+    sh_eval(kDeg, d[0] * dinv, d[1] * dinv, d[2] * dinv, Y);
+    float rgb[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        float acc_c = 0.5f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc_c += Y[k] * ((k < nk) ? shv[3 * k + ch] : 0.f);
+        rgb[ch] = fmaxf(acc_c, 0.f);
+    }
+    at_row(sink.next.mean, 0, 0, off16) = make_double2(p.md[0], p.md[1]);
+    at_row(sink.next.cov_o, 0, 0, off16) = make_float4(p.cov[0], p.cov[1], p.cov[2], G.o);
+    at_row(sink.next.rgb_z, 0, 0, off16) = make_float4(rgb[0], rgb[1], rgb[2], p.xc[2]);
+}
+
 gs_status launch_project_backward(const gs_settings &s, const float *params, int64_t n,
                                   int64_t n_cap, const gs_view *views, int32_t n_views,
                                   const float *acc, float *grad, hipStream_t st) {
@@ -698,8 +946,12 @@ gs_status launch_project_backward_adam(const gs_settings &s, float *params, int6
     a.ibc1 = float(1.0 / (1.0 - std::pow(beta1, t)));
     a.isqbc2 = float(1.0 / std::sqrt(1.0 - std::pow(beta2, t)));
     const int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL(project_backward_kernel<AdamSink>, dim3(blocks), dim3(256), 0, st, s, params, n,
-                       n_cap, views, n_views, acc, int64_t(n_views) * n_cap, a);
+    if (n_views == 1 && !s.checked && s.sh_degree == 3 && n_cap <= (int64_t(1) << 26))
+        hipLaunchKernelGGL(project_adam_one_view_kernel<3>, dim3(blocks), dim3(256), 0, st, s, n, n_cap, views,
+                           acc, a);
+    else
+        hipLaunchKernelGGL(project_backward_kernel<AdamSink>, dim3(blocks), dim3(256), 0, st, s, params, n,
+                           n_cap, views, n_views, acc, int64_t(n_views) * n_cap, a);
     if (proj_out && !fuse_next)
         hipLaunchKernelGGL(preprocess_kernel, dim3(blocks), dim3(256), 0, st, s, params, n, n_cap, views,
                            n_views, next);

@@ -97,7 +97,7 @@ template <bool kCount>
 __global__ void __launch_bounds__(256) render_fwd_kernel(
     gs_settings s, Proj proj, int64_t n_cap, Sorted srt, const gs_target *__restrict__ targets,
     int n_targets, float *__restrict__ out_rgb, float *__restrict__ out_T,
-    int32_t *__restrict__ out_last, int32_t *__restrict__ out_nc) {
+    int32_t *__restrict__ out_last, int32_t *__restrict__ out_nc, int32_t *__restrict__ out_ne) {
     __shared__ float4 sA[kTilePix];
     __shared__ float4 sB[kTilePix];
     __shared__ float2 sC[kTilePix];
@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(
     const float fpx = float(lxp), fpy = float(lyp);   // relative to the tile origin
 
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-    int32_t nc = 0, last = 0;
+    int32_t nc = 0, ne = 0, last = 0;
     bool done = !inside;
     const int batch = s.batch;
     for (uint32_t b0 = range.x; b0 < range.y; b0 += batch) {
@@ -150,6 +150,7 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(
                 const float2 Cj = sC[j];
                 const float dx = A.x - fpx, dy = A.y - fpy;
                 const float pw = eval_power(A, B, dx, dy);
+                if (kCount) ++ne;
                 if (pw < Cj.y) continue;
                 const float alpha = fminf(s.alpha_max, B.y * __expf(pw));
                 const float Tn = T * (1.f - alpha);
@@ -175,7 +176,8 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(
         rgb[2 * HW + pix] = fmaf(T, t.bg[2], C2);
         out_T[t.pix_offset + pix] = T;
         out_last[t.pix_offset + pix] = last;
-        if (kCount) out_nc[t.pix_offset + pix] = nc;
+        if (kCount && out_nc) out_nc[t.pix_offset + pix] = nc;
+        if (kCount && out_ne) out_ne[t.pix_offset + pix] = ne;
     }
 }
 
@@ -479,7 +481,7 @@ extern "C" gs_status gs_render_fwd(const gs_settings *s, const void *proj_ws, in
                                    int32_t n_views, const void *sort_ws, int64_t pair_cap,
                                    const gs_target *targets, int32_t n_targets, int32_t total_tiles,
                                    float *out_rgb, float *out_T, int32_t *out_last,
-                                   int32_t *out_ncontrib, void *stream) {
+                                   int32_t *out_ncontrib, int32_t *out_nevals, void *stream) {
     using namespace gs;
     if (!valid_settings(s) || !proj_ws || !sort_ws || !targets || n_cap <= 0 || n_cap % 64 ||
         n_views <= 0 || n_targets <= 0 || total_tiles <= 0 || pair_cap <= 0 || !out_rgb ||
@@ -488,12 +490,12 @@ extern "C" gs_status gs_render_fwd(const gs_settings *s, const void *proj_ws, in
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Sorted srt = sorted_at(sort_ws, n_views, n_targets, n_cap, pair_cap, total_tiles);
     const Proj proj = proj_at(const_cast<void *>(proj_ws), int64_t(n_views) * n_cap);
-    if (out_ncontrib)
+    if (out_ncontrib || out_nevals)
         hipLaunchKernelGGL(render_fwd_kernel<true>, dim3(total_tiles), dim3(kTilePix), 0, st, *s, proj, n_cap,
-                           srt, targets, n_targets, out_rgb, out_T, out_last, out_ncontrib);
+                           srt, targets, n_targets, out_rgb, out_T, out_last, out_ncontrib, out_nevals);
     else
         hipLaunchKernelGGL(render_fwd_kernel<false>, dim3(total_tiles), dim3(kTilePix), 0, st, *s, proj, n_cap,
-                           srt, targets, n_targets, out_rgb, out_T, out_last, out_ncontrib);
+                           srt, targets, n_targets, out_rgb, out_T, out_last, nullptr, nullptr);
     GS_CHECK_LAUNCH();
     return GS_OK;
 }

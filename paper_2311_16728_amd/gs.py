@@ -73,7 +73,7 @@ def _load():
         "gs_workspace_query": ([S, i64, i32, T, i32, i64, C.POINTER(gs_sizes)], C.c_int),
         "gs_preprocess": ([S, vp, i64, i64, vp, i32, vp, vp], C.c_int),
         "gs_bin_sort": ([S, vp, i64, i64, i32, vp, i32, i32, vp, i64, vp, vp], C.c_int),
-        "gs_render_fwd": ([S, vp, i64, i32, vp, i64, vp, i32, i32, vp, vp, vp, vp, vp], C.c_int),
+        "gs_render_fwd": ([S, vp, i64, i32, vp, i64, vp, i32, i32, vp, vp, vp, vp, vp, vp], C.c_int),
         "gs_render_bwd": ([S, vp, i64, i64, vp, i32, vp, vp, i64, vp, i32, i32, vp, vp, vp, vp,
                            vp, vp], C.c_int),
         "gs_raster_bwd": ([S, vp, i64, i32, vp, i64, vp, i32, i32, vp, vp, vp, vp, vp], C.c_int),
@@ -265,11 +265,12 @@ def gs_bin_sort(settings, proj_ws, n, n_cap, n_views, targets_dev, n_targets, to
 
 
 def gs_render_fwd(settings, proj_ws, n_cap, n_views, sort_ws, pair_cap, targets_dev, n_targets,
-                  total_tiles, out_rgb, out_T, out_last, out_ncontrib=None, stream=None):
+                  total_tiles, out_rgb, out_T, out_last, out_ncontrib=None, stream=None, out_nevals=None):
     _check(_lib.gs_render_fwd(C.byref(settings), _p(proj_ws), n_cap, n_views, _p(sort_ws), pair_cap,
                               _p(targets_dev), n_targets, total_tiles, _f32(out_rgb, "out_rgb"),
                               _f32(out_T, "out_T"), _i32(out_last, "out_last"),
-                              _i32(out_ncontrib, "out_ncontrib"), _stream(stream)), "gs_render_fwd")
+                              _i32(out_ncontrib, "out_ncontrib"), _i32(out_nevals, "out_nevals"),
+                              _stream(stream)), "gs_render_fwd")
 
 
 def gs_render_bwd(settings, params, n, views_dev, n_views, proj_ws, sort_ws, pair_cap, targets_dev,

@@ -97,6 +97,7 @@ class RenderPlan:
         self.T = torch.empty(P, dtype=torch.float32, device=d)
         self.last = torch.empty(P, dtype=torch.int32, device=d)
         self.ncontrib = torch.empty(P, dtype=torch.int32, device=d)
+        self.nevals = torch.empty(P, dtype=torch.int32, device=d)
         self.status = torch.zeros(1, dtype=torch.int32, device=d)
         self.d_loss = torch.zeros(self.n_targets, dtype=torch.float32, device=d)
         self.d_total = torch.zeros(1, dtype=torch.float32, device=d)
@@ -132,7 +133,8 @@ class RenderPlan:
     def render_fwd(self, with_ncontrib: bool = False, stream=None):
         gs.gs_render_fwd(self.settings, self.proj_ws, self.n_cap, self.n_views, self.sort_ws,
                          self.pair_cap, self.targets_dev, self.n_targets, self.total_tiles, self.rgb,
-                         self.T, self.last, self.ncontrib if with_ncontrib else None, stream)
+                         self.T, self.last, self.ncontrib if with_ncontrib else None, stream,
+                         out_nevals=self.nevals if with_ncontrib else None)
 
     def render(self, params, n, with_ncontrib=False, stream=None):
         self.preprocess(params, n, stream)

@@ -90,7 +90,7 @@ def test_invalid_arguments_rejected():
     assert lib.gs_pyramid_build(None, 3, 10, 10, 3, None, None) == 1
     bad = gs.default_settings(batch=100)
     assert lib.gs_render_fwd(C.byref(bad), C.c_void_p(1), 256, 1, C.c_void_p(1), 1024, C.c_void_p(1),
-                             1, 16, C.c_void_p(1), C.c_void_p(1), C.c_void_p(1), None, None) == 1
+                             1, 16, C.c_void_p(1), C.c_void_p(1), C.c_void_p(1), None, None, None) == 1
     rule = gs.densify_rule(5.0)
     one = C.c_void_p(16)
     assert lib.gs_densify(C.byref(rule), None, one, one, one, one, 10, 256, one, one, one, 256, one, one,
@@ -205,11 +205,11 @@ def test_checked_mode_and_status_word():
     nv, ncap = 65, 1 << 26
     assert lib.gs_preprocess(C.byref(s), one, 10, ncap, one, nv, one, None) == INVALID
     assert lib.gs_render_fwd(C.byref(s), one, ncap, nv, one, 1024, one, 1, 16, one, one, one,
-                             None, None) == INVALID
+                             None, None, None) == INVALID
     assert lib.gs_raster_bwd(C.byref(s), one, ncap, nv, one, 1024, one, 1, 16, one, one, one, one,
                              None) == INVALID
     assert lib.gs_render_fwd(C.byref(s), one, 256, 1, one, 1 << 31, one, 1, 16, one, one, one,
-                             None, None) == INVALID
+                             None, None, None) == INVALID
     with pytest.raises(gs.GsError):
         gs.gs_workspace_query(s, ncap, nv, t, 1 << 10)
     with pytest.raises(gs.GsError):
