@@ -36,6 +36,57 @@ HBM_PEAK_GBS = 8000.0
 LANE_OP_PEAK_T = 256 * 64 * 2.4e9 / 1e12
 
 
+class TimingEvent:
+    """A HIP event recorded on the current stream with a device-scope release
+    (hipEventReleaseToDevice), so the span between two of them holds the
+    kernels in between without the system-scope cache write-back a default
+    event adds; same interface as torch.cuda.Event for timing."""
+    _hip = None
+
+    @classmethod
+    def _lib(cls):
+        if cls._hip is None:
+            import ctypes
+            import torch
+
+            # the HIP runtime torch itself uses (it ships its own)
+            path = os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so")
+            lib = ctypes.CDLL(path if os.path.exists(path) else "libamdhip64.so")
+            lib.hipEventCreateWithFlags.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint]
+            lib.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+            lib.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
+                                                ctypes.c_void_p]
+            lib.hipEventDestroy.argtypes = [ctypes.c_void_p]
+            cls._hip = lib
+        return cls._hip
+
+    def __init__(self, enable_timing=True):
+        import ctypes
+
+        self.h = ctypes.c_void_p()
+        if self._lib().hipEventCreateWithFlags(ctypes.byref(self.h), 0x40000000) != 0:
+            raise RuntimeError("hipEventCreateWithFlags failed")
+
+    def record(self):
+        import ctypes
+        import torch
+
+        if self._lib().hipEventRecord(self.h, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)) != 0:
+            raise RuntimeError("hipEventRecord failed")
+
+    def elapsed_time(self, other) -> float:
+        import ctypes
+
+        ms = ctypes.c_float()
+        if self._lib().hipEventElapsedTime(ctypes.byref(ms), self.h, other.h) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return float(ms.value)
+
+    def __del__(self):
+        if self._hip is not None and self.h:
+            self._hip.hipEventDestroy(self.h)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -56,7 +107,8 @@ def parse():
                     help="after timing, copy a 256 MiB buffer once (HBM counter calibration)")
     ap.add_argument("--cpu-sample", type=float, default=1.0,
                     help="fraction of pixels the oracle baseline renders and differentiates")
-    ap.add_argument("--workload", choices=("single", "batched", "densify", "loopfix", "gp-study", "realistic"),
+    ap.add_argument("--workload", choices=("single", "batched", "densify", "loopfix", "gp-study", "realistic",
+                                           "stress"),
                     default="single",
                     help="single: one 1200x680 keyframe; batched: 32 mixed keyframes x 3 pyramid "
                          "levels in one graph-captured iteration; densify: one split / clone / "
@@ -64,7 +116,8 @@ def parse():
                          "correction of a 1M-primitive map by 128 keyframe transforms; gp-study: online "
                          "mapping with 1-4 pyramid levels, with and without keypoint densification; "
                          "realistic: 500k Gaussians, 8 keyframes at 1200x680, 3-level pyramid, 100 "
-                         "iterations in Eq. 5 schedule mode and in all-levels mode")
+                         "iterations in Eq. 5 schedule mode and in all-levels mode; stress: 2M Gaussians at "
+                         "1200x680, recompute backward against the store-all variant (peak memory, time)")
     ap.add_argument("--psnr-compare", type=int, default=0, metavar="ROUNDS",
                     help="batched workload: also compare with the per-frame mapper at equal final "
                          "PSNR after ROUNDS visits of every keyframe")
@@ -73,7 +126,7 @@ def parse():
                     help="learning-rate multipliers tried for the batched mapper in --psnr-compare")
     args = ap.parse_args()
     if args.n is None:
-        args.n = 500_000 if args.workload == "realistic" else 1_000_000
+        args.n = {"realistic": 500_000, "stress": 2_000_000}.get(args.workload, 1_000_000)
     if args.steps is None:
         args.steps = 100 if args.workload == "realistic" else 50
     return args
@@ -797,7 +850,7 @@ def main_realistic(args, torch):
     bind(plan, 0)
     for _ in range(3):
         mp.step(plan, gts[0][0], LAMBDA)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(STAGES) + 1)]
+    ev = [TimingEvent() for _ in range(len(STAGES) + 1)]
     reps = 10
     stage_ms = np.zeros(len(STAGES))
     for _ in range(reps):
@@ -838,6 +891,128 @@ def main_realistic(args, torch):
     return 0
 
 
+def main_stress(args, torch):
+    """2M Gaussians in the room, one 1200x680 view at the walk's first pose,
+    loss <W, I> with W ~ U(-1, 1) (seeded).  Differentiation (projection,
+    binning, forward, raster backward, chain rule) with the recompute backward
+    (final transmittance and restart index, 8 B per pixel) and with the
+    store-all variant (the transmittance of every composited pair); for each,
+    the allocator's peak over the whole differentiation with every buffer it
+    needs (pair buffers sized from the measured pair count) and the time of
+    forward and backward."""
+    import scenes
+    from paper_2311_16728_amd import gs
+    from paper_2311_16728_amd.mapper import RenderPlan
+
+    n = args.n
+    p, _, cams = scenes.room_scene(args.seed, n, n_keyframes=1)
+    n_cap = p.shape[1]
+    spec = [(0, 0, (0.0, 0.0, 0.0), 1.0)]
+    P = torch.as_tensor(p).cuda()
+    probe = RenderPlan(cams, spec, n_cap, 1 << 27)
+    probe.render(P, n)
+    pairs = probe.pair_count()
+    if probe.overflowed():
+        raise SystemExit("pair buffer overflow in the sizing render")
+    del probe
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    pair_cap = int(pairs * 1.02) + 4096
+    H, W = cams[0]["height"], cams[0]["width"]
+    Wt = torch.as_tensor(np.random.default_rng(args.seed + 1).uniform(-1, 1, 3 * H * W).astype(np.float32)).cuda()
+    grads = {}
+    out = {}
+    reps = max(3, min(args.steps, 10))
+    for variant in ("recompute", "store_all"):
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        torch.cuda.reset_peak_memory_stats()
+        before = torch.cuda.memory_allocated()
+        plan = RenderPlan(cams, spec, n_cap, pair_cap)
+        grad = torch.zeros_like(P)
+        extra = {}
+        if variant == "store_all":
+            T_ = plan.total_tiles
+            extra["steps"] = torch.zeros(T_, dtype=torch.int32, device="cuda")
+            extra["base"] = torch.zeros(T_ + 1, dtype=torch.int64, device="cuda")
+            plan.preprocess(P, n)
+            plan.bin_sort(n)
+            one = torch.zeros(1, dtype=torch.float32, device="cuda")
+            gs.gs_render_fwd_store(plan.settings, plan.proj_ws, n_cap, 1, plan.sort_ws, pair_cap, plan.targets_dev,
+                                   1, T_, plan.rgb, plan.T, plan.last, plan.ncontrib, extra["steps"], extra["base"],
+                                   one)
+            torch.cuda.synchronize()
+            extra["store"] = torch.empty(int(extra["base"][T_].item()), dtype=torch.float32, device="cuda")
+
+        def forward():
+            plan.preprocess(P, n)
+            plan.bin_sort(n)
+            if variant == "recompute":
+                plan.render_fwd()
+            else:
+                gs.gs_render_fwd_store(plan.settings, plan.proj_ws, n_cap, 1, plan.sort_ws, pair_cap,
+                                       plan.targets_dev, 1, plan.total_tiles, plan.rgb, plan.T, plan.last,
+                                       plan.ncontrib, extra["steps"], extra["base"], extra["store"])
+
+        def backward():
+            gs.gs_fill(grad, 0.0)
+            if variant == "recompute":
+                plan.backward(P, n, Wt, grad)
+            else:
+                gs.gs_raster_bwd_stored(plan.settings, plan.proj_ws, n_cap, 1, plan.sort_ws, pair_cap,
+                                        plan.targets_dev, 1, plan.total_tiles, plan.last, plan.ncontrib,
+                                        extra["base"], extra["store"], Wt, plan.accum_ws)
+                gs.gs_project_bwd(plan.settings, P, n, plan.views_dev, 1, plan.accum_ws, grad)
+
+        forward()
+        backward()
+        torch.cuda.synchronize()
+        peak = torch.cuda.max_memory_allocated()
+        if plan.overflowed():
+            raise SystemExit("pair buffer overflow")
+        e = [TimingEvent() for _ in range(3)]
+        f_ms = b_ms = 0.0
+        for _ in range(reps):
+            e[0].record()
+            forward()
+            e[1].record()
+            backward()
+            e[2].record()
+            torch.cuda.synchronize()
+            f_ms += e[0].elapsed_time(e[1])
+            b_ms += e[1].elapsed_time(e[2])
+        grads[variant] = grad.cpu().numpy()
+        state = 8 * H * W
+        if variant == "store_all":
+            state += 4 * H * W + extra["store"].numel() * 4 + extra["base"].numel() * 8 + extra["steps"].numel() * 4
+        out[variant] = {"peak_bytes": int(peak), "peak_above_inputs_bytes": int(peak - before),
+                        "saved_state_bytes": int(state), "forward_ms": round(f_ms / reps, 4),
+                        "backward_ms": round(b_ms / reps, 4)}
+        if variant == "store_all":
+            composited = int(plan.ncontrib.sum().item())
+            out[variant]["store_floats"] = int(extra["store"].numel())
+            out[variant]["composited_pairs"] = composited
+            out[variant]["store_bytes_per_composited_pair"] = round(4 * extra["store"].numel() / composited, 3)
+        print(f"# {variant}: {out[variant]}", file=sys.stderr, flush=True)
+        del plan, grad, extra
+    a, b = grads["recompute"], grads["store_all"]
+    scale = np.abs(a).max(axis=1, keepdims=True) + 1e-30
+    res = {
+        "metric": "differentiation peak memory and time, recompute vs store-all backward, 2M Gaussians @1200x680",
+        "value": round(out["store_all"]["peak_above_inputs_bytes"] / out["recompute"]["peak_above_inputs_bytes"], 3),
+        "unit": "x (store-all / recompute peak above the parameters)", "n_gpus": 1, "steps": reps,
+        "warmup": 1, "ms_per_step": out["recompute"]["forward_ms"] + out["recompute"]["backward_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "2M Gaussians in a 10x4x10 m room, one 1200x680 view (f=600), loss <W, I>",
+                   "gaussians": n, "pairs": pairs, "pair_cap": pair_cap},
+        "recompute": out["recompute"], "store_all": out["store_all"],
+        "parameter_bytes": int(P.numel() * 4),
+        "gradient_max_rel_diff": float((np.abs(a - b) / scale).max()),
+    }
+    print(json.dumps(res), flush=True)
+    return 0
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -858,6 +1033,8 @@ def main():
         return main_gpstudy(args, torch)
     if args.workload == "realistic":
         return main_realistic(args, torch)
+    if args.workload == "stress":
+        return main_stress(args, torch)
     p, tp, cams, plan, mapper, target = build_workload(args, torch)
     from paper_2311_16728_amd.mapper import RenderPlan
 
@@ -885,9 +1062,9 @@ def main():
     if plan.overflowed():
         raise SystemExit("pair buffer overflow: raise --pair-cap")
 
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(STAGES) + 1)] for _ in range(args.steps)]
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
+    evs = [[TimingEvent() for _ in range(len(STAGES) + 1)] for _ in range(args.steps)]
+    start = TimingEvent()
+    stop = TimingEvent()
     torch.cuda.synchronize()
     t_wall = time.perf_counter()
     start.record()
@@ -908,8 +1085,8 @@ def main():
     for _ in range(3):
         plan.render(mapper.params, mapper.n)
     torch.cuda.synchronize()
-    r0 = torch.cuda.Event(enable_timing=True)
-    r1 = torch.cuda.Event(enable_timing=True)
+    r0 = TimingEvent()
+    r1 = TimingEvent()
     r0.record()
     for _ in range(args.steps):
         plan.render(mapper.params, mapper.n)

@@ -210,6 +210,39 @@ gs_status gs_raster_bwd(const gs_settings *s, const void *proj_ws, int64_t n_cap
                         const float *out_T, const int32_t *out_last, const float *dL_drgb,
                         void *accum_ws, void *stream);
 
+/* Store-all variant of the rasteriser, the comparison point of the recompute
+ * backward above (back-propagation of Eq. 3, Section 3.3): the forward keeps
+ * the transmittance in front of every composited (pixel, Gaussian) pair and
+ * the backward reads it instead of dividing it back out of the final
+ * transmittance.
+ *
+ * gs_render_fwd_store: the forward of gs_render_fwd (same out_rgb, out_T,
+ * out_last; out_ncontrib required), then the store.  tile_steps (device,
+ * int32 [total_tiles]) receives the largest composited count of each tile;
+ * store_base (device, int64 [total_tiles + 1]) the start of each tile's
+ * stretch of the store, base[total_tiles] being the floats the store needs.
+ * The transmittance in front of a pixel's k-th composited Gaussian is at
+ * store[base[tile] + 256 k + (pixel index in the tile)].  store (device,
+ * store_cap floats): when base[total_tiles] > store_cap nothing is stored
+ * (read base[total_tiles] after the stream has synchronised, re-size, call
+ * again).  The call runs the forward twice (counts, then the store).
+ *
+ * gs_raster_bwd_stored: gs_raster_bwd reading the store (out_last,
+ * out_ncontrib, store_base, store as left by gs_render_fwd_store).  When the
+ * store was too small it leaves accum_ws cleared. */
+gs_status gs_render_fwd_store(const gs_settings *s, const void *proj_ws, int64_t n_cap,
+                              int32_t n_views, const void *sort_ws, int64_t pair_cap,
+                              const gs_target *targets, int32_t n_targets, int32_t total_tiles,
+                              float *out_rgb, float *out_T, int32_t *out_last, int32_t *out_ncontrib,
+                              int32_t *tile_steps, int64_t *store_base, float *store, int64_t store_cap,
+                              void *stream);
+gs_status gs_raster_bwd_stored(const gs_settings *s, const void *proj_ws, int64_t n_cap,
+                               int32_t n_views, const void *sort_ws, int64_t pair_cap,
+                               const gs_target *targets, int32_t n_targets, int32_t total_tiles,
+                               const int32_t *out_last, const int32_t *out_ncontrib,
+                               const int64_t *store_base, const float *store, int64_t store_cap,
+                               const float *dL_drgb, void *accum_ws, void *stream);
+
 /* Chain rule from the per-view 2D gradients in accum_ws to the raw parameters
  * (through the 2D covariance, projection Jacobian with its field-of-view clamp,
  * rotation/scale, opacity sigmoid and the SH basis including its view

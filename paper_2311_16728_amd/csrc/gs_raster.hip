@@ -93,11 +93,27 @@ __device__ __forceinline__ float eval_power(const float4 &A, const float4 &B, fl
     return fmaf(-0.5f, q, -(A.w * dx * dy));
 }
 
-template <bool kCount>
+// Per-pixel transmittance store of the store-all variant (the comparison
+// point of the recompute backward): the transmittance in front of a pixel's
+// k-th composited Gaussian sits at base[tile] + k * 256 + (pixel in tile), so
+// each compositing step of a tile writes 256 consecutive floats.  base has
+// total_tiles + 1 entries (the last is the floats needed); nothing is stored
+// or read when that exceeds cap.
+struct TStore {
+    const int64_t *base;   // [total_tiles + 1]
+    const int64_t *need;   // base + total_tiles: floats the store needs
+    float *T;
+    int64_t cap;
+};
+
+// kCount: per-pixel composited and evaluated counts (and, with tile_max, the
+// largest composited count of each tile); kStore: the transmittance store.
+template <bool kCount, bool kStore = false>
 __global__ void __launch_bounds__(256) render_fwd_kernel(
     gs_settings s, Proj proj, int64_t n_cap, Sorted srt, const gs_target *__restrict__ targets,
     int n_targets, float *__restrict__ out_rgb, float *__restrict__ out_T,
-    int32_t *__restrict__ out_last, int32_t *__restrict__ out_nc, int32_t *__restrict__ out_ne) {
+    int32_t *__restrict__ out_last, int32_t *__restrict__ out_nc, int32_t *__restrict__ out_ne,
+    int32_t *__restrict__ tile_max = nullptr, TStore ts_store = TStore{nullptr, nullptr, nullptr, 0}) {
     __shared__ float4 sA[kTilePix];
     __shared__ float4 sB[kTilePix];
     __shared__ float2 sC[kTilePix];
@@ -119,6 +135,8 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
     int32_t nc = 0, ne = 0, last = 0;
     bool done = !inside;
+    float *store_at = nullptr;   // this pixel's first slot (kStore), or none
+    if (kStore && *ts_store.need <= ts_store.cap) store_at = ts_store.T + ts_store.base[tile] + tid;
     const int batch = s.batch;
     for (uint32_t b0 = range.x; b0 < range.y; b0 += batch) {
         if (__syncthreads_count(done) == kTilePix) break;
@@ -155,12 +173,13 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(
                 const float alpha = fminf(s.alpha_max, B.y * __expf(pw));
                 const float Tn = T * (1.f - alpha);
                 if (Tn < s.t_min) { done = true; break; }
+                if (kStore && store_at) store_at[int64_t(nc) * kTilePix] = T;
                 const float w = alpha * T;
                 C0 = fmaf(w, B.z, C0);
                 C1 = fmaf(w, B.w, C1);
                 C2 = fmaf(w, Cj.x, C2);
                 T = Tn;
-                if (kCount) ++nc;
+                if (kCount || kStore) ++nc;
                 lj = j;
             }
             // one past the list position of the last composited Gaussian
@@ -179,6 +198,46 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(
         if (kCount && out_nc) out_nc[t.pix_offset + pix] = nc;
         if (kCount && out_ne) out_ne[t.pix_offset + pix] = ne;
     }
+    if (kCount && tile_max) {
+        __shared__ int32_t tmax;
+        if (tid == 0) tmax = 0;
+        __syncthreads();
+        if (nc > 0) atomicMax(&tmax, nc);
+        __syncthreads();
+        if (tid == 0) tile_max[tile] = tmax;
+    }
+}
+
+// Exclusive scan of the per-tile store sizes (256 floats per compositing step
+// of the tile's deepest pixel) into base[0..total_tiles]; one workgroup.
+__global__ void __launch_bounds__(1024) store_base_kernel(const int32_t *__restrict__ tile_max,
+                                                          int64_t total_tiles, int64_t *__restrict__ base) {
+    __shared__ int64_t wsum[16];
+    const int64_t per = (total_tiles + 1023) / 1024;
+    const int64_t lo = int64_t(threadIdx.x) * per;
+    int64_t local = 0;
+    for (int64_t i = lo; i < lo + per && i < total_tiles; ++i) local += int64_t(tile_max[i]) * kTilePix;
+    // inclusive scan over the block in 64 bits
+    int64_t inc = local;
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int64_t u = __shfl_up(inc, d, kWave);
+        if (lane >= d) inc += u;
+    }
+    if (lane == kWave - 1) wsum[wave] = inc;
+    __syncthreads();
+    int64_t before = 0, all = 0;
+    for (int w = 0; w < 16; ++w) {
+        before += w < wave ? wsum[w] : 0;
+        all += wsum[w];
+    }
+    int64_t run = before + inc - local;
+    for (int64_t i = lo; i < lo + per && i < total_tiles; ++i) {
+        base[i] = run;
+        run += int64_t(tile_max[i]) * kTilePix;
+    }
+    if (threadIdx.x == 0) base[total_tiles] = all;
 }
 
 // Cross-lane add through DPP (full-rate VALU; rows are 16 lanes).
@@ -225,11 +284,15 @@ constexpr int kGroup = 7;                      // 7 * 9 = 63 values <= 64 lanes
 constexpr int kQuads = kWave / 4;
 constexpr int kTStride = kQuads + 1;           // odd row stride: conflict-free reads
 
-template <int kWaves>
+// kStored: the store-all variant, which reads each composited Gaussian's
+// transmittance from the forward's store (in_nc: per-pixel composited counts)
+// instead of dividing it back out.
+template <int kWaves, bool kStored = false>
 __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
     gs_settings s, Proj proj, int64_t n_cap, Sorted srt, const gs_target *__restrict__ targets,
     int n_targets, const float *__restrict__ in_T, const int32_t *__restrict__ in_last,
-    const float *__restrict__ dL_drgb, float *__restrict__ acc) {
+    const float *__restrict__ dL_drgb, float *__restrict__ acc,
+    const int32_t *__restrict__ in_nc = nullptr, TStore ts_store = TStore{nullptr, nullptr, nullptr, 0}) {
     constexpr int kThreads = 64 * kWaves;
     constexpr int kPix = kTilePix / kThreads;
     __shared__ float4 sA[kThreads];
@@ -259,6 +322,14 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
 
     float T[kPix], g0[kPix], g1[kPix], g2[kPix], B0[kPix], B1[kPix], B2[kPix], fpy[kPix];
     int32_t last[kPix];
+    int32_t kc[kPix];             // kStored: composited Gaussians not yet walked back
+    const float *srow = nullptr;  // kStored: this tile's store
+    int32_t steps = 0;            // kStored: compositing steps stored for the tile
+    if (kStored) {
+        if (!(*ts_store.need <= ts_store.cap)) return;   // the forward stored nothing
+        srow = ts_store.T + ts_store.base[tile];
+        steps = int32_t((ts_store.base[tile + 1] - ts_store.base[tile]) / kTilePix);
+    }
     // the tile width divides 64, so a lane keeps its column in every row it owns
     const float fpx = float(tid & (ts.w - 1));
     int my_max = 0;
@@ -269,9 +340,13 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
         fpy[i] = float(ly);
         const int px = tx * ts.w + (lp & (ts.w - 1)), py = ty * ts.h + ly;
         T[i] = 0.f; g0[i] = g1[i] = g2[i] = 0.f; last[i] = 0;
+        kc[i] = 0;
         if (px < t.width && py < t.height) {
             const int64_t pix = int64_t(py) * t.width + px;
-            T[i] = in_T[t.pix_offset + pix];
+            if (kStored)
+                kc[i] = min(in_nc[t.pix_offset + pix], steps);
+            else
+                T[i] = in_T[t.pix_offset + pix];
             last[i] = in_last[t.pix_offset + pix];
             g0[i] = dLt[pix];
             g1[i] = dLt[HW + pix];
@@ -350,7 +425,12 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
                     const float at = Bv.y * ep;
                     const float alpha = fminf(s.alpha_max, at);
                     const float oma = 1.f - alpha;
-                    T[i] = T[i] * __builtin_amdgcn_rcpf(oma);   // transmittance in front of it
+                    if (kStored) {   // transmittance in front of it, as stored
+                        kc[i] = max(kc[i] - 1, 0);
+                        T[i] = srow[int64_t(kc[i]) * kTilePix + tid + i * kThreads];
+                    } else {
+                        T[i] = T[i] * __builtin_amdgcn_rcpf(oma);   // transmittance in front of it
+                    }
                     const float r = Bv.z, gg = Bv.w, bb = Ck.x;
                     const float dal = T[i] * ((r - B0[i]) * g0[i] + (gg - B1[i]) * g1[i] + (bb - B2[i]) * g2[i]);
                     const float w = alpha * T[i];
@@ -530,6 +610,72 @@ extern "C" gs_status gs_raster_bwd(const gs_settings *s, const void *proj_ws, in
         default:
             hipLaunchKernelGGL(render_bwd_kernel<4>, dim3(total_tiles), dim3(256), 0, st, *s, proj, n_cap,
                                srt, targets, n_targets, out_T, out_last, dL_drgb, acc);
+            break;
+    }
+    GS_CHECK_LAUNCH();
+    return GS_OK;
+}
+
+extern "C" gs_status gs_render_fwd_store(const gs_settings *s, const void *proj_ws, int64_t n_cap,
+                                         int32_t n_views, const void *sort_ws, int64_t pair_cap,
+                                         const gs_target *targets, int32_t n_targets,
+                                         int32_t total_tiles, float *out_rgb, float *out_T,
+                                         int32_t *out_last, int32_t *out_ncontrib, int32_t *tile_steps,
+                                         int64_t *store_base, float *store, int64_t store_cap,
+                                         void *stream) {
+    using namespace gs;
+    if (!valid_settings(s) || !proj_ws || !sort_ws || !targets || n_cap <= 0 || n_cap % 64 ||
+        n_views <= 0 || n_targets <= 0 || total_tiles <= 0 || pair_cap <= 0 || !out_rgb || !out_T ||
+        !out_last || !out_ncontrib || !tile_steps || !store_base || !store || store_cap < 0 ||
+        pair_cap > kMaxPairs || int64_t(n_views) * n_cap > kMaxRecords)
+        return GS_ERR_INVALID_ARGUMENT;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Sorted srt = sorted_at(sort_ws, n_views, n_targets, n_cap, pair_cap, total_tiles);
+    const Proj proj = proj_at(const_cast<void *>(proj_ws), int64_t(n_views) * n_cap);
+    // counts, the store layout, then the forward again writing the store
+    hipLaunchKernelGGL(render_fwd_kernel<true>, dim3(total_tiles), dim3(kTilePix), 0, st, *s, proj, n_cap, srt,
+                       targets, n_targets, out_rgb, out_T, out_last, out_ncontrib, nullptr, tile_steps,
+                       TStore{nullptr, nullptr, nullptr, 0});
+    hipLaunchKernelGGL(store_base_kernel, dim3(1), dim3(1024), 0, st, tile_steps, int64_t(total_tiles), store_base);
+    hipLaunchKernelGGL((render_fwd_kernel<false, true>), dim3(total_tiles), dim3(kTilePix), 0, st, *s, proj,
+                       n_cap, srt, targets, n_targets, out_rgb, out_T, out_last, nullptr, nullptr, nullptr,
+                       TStore{store_base, store_base + total_tiles, store, store_cap});
+    GS_CHECK_LAUNCH();
+    return GS_OK;
+}
+
+extern "C" gs_status gs_raster_bwd_stored(const gs_settings *s, const void *proj_ws, int64_t n_cap,
+                                          int32_t n_views, const void *sort_ws, int64_t pair_cap,
+                                          const gs_target *targets, int32_t n_targets,
+                                          int32_t total_tiles, const int32_t *out_last,
+                                          const int32_t *out_ncontrib, const int64_t *store_base,
+                                          const float *store, int64_t store_cap, const float *dL_drgb,
+                                          void *accum_ws, void *stream) {
+    using namespace gs;
+    if (!valid_settings(s) || !proj_ws || !sort_ws || !targets || !out_last || !out_ncontrib ||
+        !store_base || !store || store_cap < 0 || !dL_drgb || !accum_ws || n_cap <= 0 || n_cap % 64 ||
+        n_views <= 0 || n_targets <= 0 || total_tiles <= 0 || pair_cap <= 0 || pair_cap > kMaxPairs ||
+        int64_t(n_views) * n_cap > kMaxRecords)
+        return GS_ERR_INVALID_ARGUMENT;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t records = int64_t(n_views) * n_cap;
+    const Sorted srt = sorted_at(sort_ws, n_views, n_targets, n_cap, pair_cap, total_tiles);
+    const Proj proj = proj_at(const_cast<void *>(proj_ws), records);
+    float *acc = static_cast<float *>(accum_ws);
+    launch_fill(acc, int64_t(kAccRows) * records, 0.f, st);
+    const TStore ts{store_base, store_base + total_tiles, const_cast<float *>(store), store_cap};
+    switch (s->bwd_waves) {
+        case 1:
+            hipLaunchKernelGGL((render_bwd_kernel<1, true>), dim3(total_tiles), dim3(64), 0, st, *s, proj, n_cap,
+                               srt, targets, n_targets, nullptr, out_last, dL_drgb, acc, out_ncontrib, ts);
+            break;
+        case 2:
+            hipLaunchKernelGGL((render_bwd_kernel<2, true>), dim3(total_tiles), dim3(128), 0, st, *s, proj, n_cap,
+                               srt, targets, n_targets, nullptr, out_last, dL_drgb, acc, out_ncontrib, ts);
+            break;
+        default:
+            hipLaunchKernelGGL((render_bwd_kernel<4, true>), dim3(total_tiles), dim3(256), 0, st, *s, proj, n_cap,
+                               srt, targets, n_targets, nullptr, out_last, dL_drgb, acc, out_ncontrib, ts);
             break;
     }
     GS_CHECK_LAUNCH();

@@ -77,6 +77,10 @@ def _load():
         "gs_render_bwd": ([S, vp, i64, i64, vp, i32, vp, vp, i64, vp, i32, i32, vp, vp, vp, vp,
                            vp, vp], C.c_int),
         "gs_raster_bwd": ([S, vp, i64, i32, vp, i64, vp, i32, i32, vp, vp, vp, vp, vp], C.c_int),
+        "gs_render_fwd_store": ([S, vp, i64, i32, vp, i64, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, i64, vp],
+                                C.c_int),
+        "gs_raster_bwd_stored": ([S, vp, i64, i32, vp, i64, vp, i32, i32, vp, vp, vp, vp, i64, vp, vp, vp],
+                                 C.c_int),
         "gs_project_bwd": ([S, vp, i64, i64, vp, i32, vp, vp, vp], C.c_int),
         "gs_project_bwd_adam": ([S, vp, i64, i64, vp, i32, vp, vp, vp, C.POINTER(C.c_float), C.c_double,
                                  C.c_double, C.c_double, i32, vp, vp, vp], C.c_int),
@@ -118,7 +122,8 @@ def _load():
 
 _lib = _load()
 EXPORTED = ["gs_status_string", "gs_status_word", "gs_default_settings", "gs_targets_layout", "gs_workspace_query",
-            "gs_preprocess", "gs_bin_sort", "gs_render_fwd", "gs_raster_bwd", "gs_project_bwd",
+            "gs_preprocess", "gs_bin_sort", "gs_render_fwd", "gs_raster_bwd", "gs_render_fwd_store",
+            "gs_raster_bwd_stored", "gs_project_bwd",
             "gs_project_bwd_adam", "gs_render_bwd", "gs_render_bwd_adam",
             "gs_pyramid_build",
             "gs_pyramid_loss", "gs_adam_step", "gs_step_advance", "gs_fill", "gs_init_features",
@@ -288,6 +293,33 @@ def gs_raster_bwd(settings, proj_ws, n_cap, n_views, sort_ws, pair_cap, targets_
                               _p(targets_dev), n_targets, total_tiles, _f32(out_T, "out_T"),
                               _i32(out_last, "out_last"), _f32(dL_drgb, "dL_drgb"), _p(accum_ws),
                               _stream(stream)), "gs_raster_bwd")
+
+
+def gs_render_fwd_store(settings, proj_ws, n_cap, n_views, sort_ws, pair_cap, targets_dev, n_targets,
+                        total_tiles, out_rgb, out_T, out_last, out_ncontrib, tile_steps, store_base, store,
+                        stream=None):
+    if tile_steps.dtype != torch.int32 or tile_steps.numel() < total_tiles:
+        raise GsError("tile_steps must be int32 with total_tiles entries")
+    if store_base.dtype != torch.int64 or store_base.numel() < total_tiles + 1:
+        raise GsError("store_base must be int64 with total_tiles + 1 entries")
+    _check(_lib.gs_render_fwd_store(C.byref(settings), _p(proj_ws), n_cap, n_views, _p(sort_ws), pair_cap,
+                                    _p(targets_dev), n_targets, total_tiles, _f32(out_rgb, "out_rgb"),
+                                    _f32(out_T, "out_T"), _i32(out_last, "out_last"),
+                                    _i32(out_ncontrib, "out_ncontrib"), _p(tile_steps), _p(store_base),
+                                    _f32(store, "store"), store.numel(), _stream(stream)),
+           "gs_render_fwd_store")
+
+
+def gs_raster_bwd_stored(settings, proj_ws, n_cap, n_views, sort_ws, pair_cap, targets_dev, n_targets,
+                         total_tiles, out_last, out_ncontrib, store_base, store, dL_drgb, accum_ws,
+                         stream=None):
+    if store_base.dtype != torch.int64 or store_base.numel() < total_tiles + 1:
+        raise GsError("store_base must be int64 with total_tiles + 1 entries")
+    _check(_lib.gs_raster_bwd_stored(C.byref(settings), _p(proj_ws), n_cap, n_views, _p(sort_ws), pair_cap,
+                                     _p(targets_dev), n_targets, total_tiles, _i32(out_last, "out_last"),
+                                     _i32(out_ncontrib, "out_ncontrib"), _p(store_base),
+                                     _f32(store, "store"), store.numel(), _f32(dL_drgb, "dL_drgb"),
+                                     _p(accum_ws), _stream(stream)), "gs_raster_bwd_stored")
 
 
 def gs_project_bwd(settings, params, n, views_dev, n_views, accum_ws, grad, stream=None):
