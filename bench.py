@@ -101,6 +101,9 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--batch", type=int, default=None, help="forward LDS batch (skips autotuning)")
     ap.add_argument("--bwd-waves", type=int, default=None, help="backward waves per tile (skips autotuning)")
+    ap.add_argument("--schedule", type=int, default=None, choices=(0, 1, 2),
+                    help="raster launch: 0 one workgroup per tile, 1 persistent over the cost-ordered tile "
+                         "queue, 2 the queue in the backward only (skips autotuning)")
     ap.add_argument("--tile-w", type=int, default=None,
                     help="tile width, tiles of tile_w x 256/tile_w pixels (skips autotuning)")
     ap.add_argument("--calibrate", action="store_true",
@@ -412,12 +415,14 @@ def main_batched(args, torch):
     bm = BatchedMapper(torch.as_tensor(p).cuda(), n, cams, gt, 3, tile_w=args.tile_w or 16)
     torch.cuda.synchronize()
     tuned = None
-    if args.batch or args.bwd_waves or args.tile_w:
+    if args.batch or args.bwd_waves or args.tile_w or args.schedule is not None:
         bm.plan.settings.batch = args.batch or bm.plan.settings.batch
         bm.plan.settings.bwd_waves = args.bwd_waves or bm.plan.settings.bwd_waves
+        bm.plan.settings.schedule = args.schedule or 0
     elif not args.no_autotune:
         bm.plan, tuned = autotune.tune_tiles(bm.make_plan, bm.params, n, bm.target)
         print(f"# autotuned: tile_w={tuned['tile_w']} batch={tuned['batch']} bwd_waves={tuned['bwd_waves']} "
+              f"schedule={tuned['schedule']} "
               f"{tuned['ms']}", file=sys.stderr, flush=True)
     plan = bm.plan
     bm.invalidate()
@@ -472,6 +477,7 @@ def main_batched(args, torch):
         "megapixels_per_s": round(plan.total_pixels * 1e-3 / ms_step, 1),
         "stage_ms_eager": stage_ms,
         "launch": {"tile_w": plan.tile_w, "batch": plan.settings.batch, "bwd_waves": plan.settings.bwd_waves,
+                   "schedule": plan.settings.schedule,
                    "autotune_ms": tuned["ms"] if tuned else None},
     }
     if args.psnr_compare:
@@ -1043,17 +1049,19 @@ def main():
     torch.cuda.synchronize()
     print(f"# workload ready: pairs={plan.pair_count()}", file=sys.stderr, flush=True)
     tuned = None
-    if args.batch or args.bwd_waves or args.tile_w:
+    if args.batch or args.bwd_waves or args.tile_w or args.schedule is not None:
         if args.tile_w:
             plan = make_plan(args.tile_w)
         plan.settings.batch = args.batch or plan.settings.batch
         plan.settings.bwd_waves = args.bwd_waves or plan.settings.bwd_waves
+        plan.settings.schedule = args.schedule or 0
     elif not args.no_autotune:
         from paper_2311_16728_amd import autotune
 
         del plan
         plan, tuned = autotune.tune_tiles(make_plan, mapper.params, mapper.n, target)
         print(f"# autotuned: tile_w={tuned['tile_w']} batch={tuned['batch']} bwd_waves={tuned['bwd_waves']} "
+              f"schedule={tuned['schedule']} "
               f"{tuned['ms']}", file=sys.stderr, flush=True)
 
     for _ in range(max(1, args.warmup)):
@@ -1154,6 +1162,7 @@ def main():
         "efficiency": efficiency,
         "iteration_roofline": iteration_roofline(n, plan, composited, ms_step),
         "launch": {"tile_w": plan.tile_w, "batch": plan.settings.batch, "bwd_waves": plan.settings.bwd_waves,
+                   "schedule": plan.settings.schedule,
                    "autotune_ms": tuned["ms"] if tuned else None},
     }
     if not args.no_cpu_baseline:

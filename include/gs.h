@@ -70,7 +70,7 @@ typedef enum {
 
 /* Rasteriser settings.  Defaults (gs_default_settings): alpha_min 1/255,
  * alpha_max 0.99, t_min 1e-4, znear 0.2, dilation 0.3 px^2, fov_clamp 1.3,
- * sh_degree 3, batch 256, bwd_waves 2, checked 0.  A pixel composites a Gaussian iff its opacity
+ * sh_degree 3, batch 256, bwd_waves 2, checked 0, schedule 0.  A pixel composites a Gaussian iff its opacity
  * there, o * exp(power), reaches alpha_min; the contribution uses
  * min(alpha_max, .); compositing stops before the Gaussian that would take
  * the transmittance below t_min (Eq. 3).
@@ -90,6 +90,11 @@ typedef struct {
     int32_t batch;       /* forward: Gaussians staged per LDS round: 64, 128 or 256 */
     int32_t bwd_waves;   /* backward: waves per tile, 1, 2 or 4 (4, 2 or 1 pixels per lane) */
     int32_t checked;     /* 0 or 1: NaN / infinity guards */
+    int32_t schedule;    /* raster launch: 0 one workgroup per tile; 1 persistent workgroups
+                            taking tiles from a queue in order of decreasing list length
+                            in the forward and the backward; 2 the queue in the backward
+                            only.  The queue is built by gs_bin_sort called with schedule
+                            1 or 2, which gs_render_fwd / gs_raster_bwd then need */
     uint32_t *status;    /* (device) status word of the guards; NULL when checked = 0 */
 } gs_settings;
 

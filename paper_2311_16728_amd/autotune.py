@@ -3,7 +3,9 @@
 Candidates: tile shape (tile_w x 256/tile_w pixels, tile_w 8, 16, 32; one
 render plan per shape, built by the caller's factory) x forward LDS batch
 (64, 128, 256 Gaussians staged per round) x backward waves per tile (1, 2, 4;
-i.e. 4, 2, 1 pixels per lane).  Each candidate runs whole mapping iterations
+i.e. 4, 2, 1 pixels per lane); the best of those is then also timed with the
+persistent raster launch over the cost-ordered tile queue (schedule 1: forward
+and backward; 2: backward only) and keeps the fastest.  Each candidate runs whole mapping iterations
 (preprocess, sort, forward, loss, backward, Adam on a scratch copy of the
 parameters), timed with HIP events on the launch stream; the fastest is kept.
 The forward image does not depend on the choice (inclusion is per pixel and
@@ -64,16 +66,17 @@ def tune(plan, params: torch.Tensor, n: int, target: torch.Tensor, iters: int = 
     if key in _cache and not force:
         c = _cache[key]
         plan.settings.batch, plan.settings.bwd_waves = c["batch"], c["bwd_waves"]
+        plan.settings.schedule = c.get("schedule", 0)
         return c
-    base = (plan.settings.batch, plan.settings.bwd_waves)
     p = params.detach().clone()
     m = torch.zeros_like(p)
     v = torch.zeros_like(p)
     lr = [1e-4] * gs.NUM_ROWS
     timings = {}
     other, ref_img = ref_img, None
-    for batch, waves in itertools.product(BATCHES, BWD_WAVES):
-        plan.settings.batch, plan.settings.bwd_waves = batch, waves
+
+    def run(label):
+        nonlocal ref_img
         plan.render(params, n)
         torch.cuda.synchronize()
         img = plan.rgb.clone()
@@ -82,7 +85,7 @@ def tune(plan, params: torch.Tensor, n: int, target: torch.Tensor, iters: int = 
         if ref_img is None:
             ref_img = img
         elif not torch.equal(img, ref_img):
-            raise RuntimeError(f"forward differs for tile_w={plan.tile_w} batch={batch} bwd_waves={waves}: "
+            raise RuntimeError(f"forward differs for tile_w={plan.tile_w} {label}: "
                                "results must not depend on the launch shape")
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         step = 0
@@ -98,13 +101,25 @@ def tune(plan, params: torch.Tensor, n: int, target: torch.Tensor, iters: int = 
                                   lr, step)
         e1.record()
         torch.cuda.synchronize()
-        timings[f"{batch}x{waves}"] = e0.elapsed_time(e1) / iters
+        timings[label] = e0.elapsed_time(e1) / iters
+
+    plan.settings.schedule = 0
+    for batch, waves in itertools.product(BATCHES, BWD_WAVES):
+        plan.settings.batch, plan.settings.bwd_waves = batch, waves
+        run(f"{batch}x{waves}")
     best = min(timings, key=timings.get)
     b, w = (int(x) for x in best.split("x"))
     plan.settings.batch, plan.settings.bwd_waves = b, w
-    _cache[key] = {"batch": b, "bwd_waves": w, "ms": timings}
+    # the same launch shape over the cost-ordered tile queue: forward and
+    # backward (1), backward only (2)
+    label = {0: best, 1: f"{b}x{w}q", 2: f"{b}x{w}qb"}
+    for sched in (1, 2):
+        plan.settings.schedule = sched
+        run(label[sched])
+    sched = min((0, 1, 2), key=lambda k: timings[label[k]])
+    plan.settings.schedule = sched
+    _cache[key] = {"batch": b, "bwd_waves": w, "schedule": sched, "ms": timings}
     save(path)
-    del base
     return _cache[key]
 
 
@@ -122,14 +137,15 @@ def tune_tiles(make_plan, params: torch.Tensor, n: int, target: torch.Tensor,
             plan.render(params, n)
             torch.cuda.synchronize()
             ref_img = plan.rgb.clone()
-        ms = c["ms"][f"{c['batch']}x{c['bwd_waves']}"]
+        ms = c["ms"][f"{c['batch']}x{c['bwd_waves']}" + ("", "q", "qb")[c["schedule"]]]
         per_shape[tw] = c["ms"]
         if best is None or ms < best["best_ms"]:
             if best_plan is not None:
                 del best_plan
                 torch.cuda.empty_cache()
             best_plan = plan
-            best = {"tile_w": tw, "batch": c["batch"], "bwd_waves": c["bwd_waves"], "best_ms": ms}
+            best = {"tile_w": tw, "batch": c["batch"], "bwd_waves": c["bwd_waves"], "schedule": c["schedule"],
+                    "best_ms": ms}
         else:
             del plan
             torch.cuda.empty_cache()

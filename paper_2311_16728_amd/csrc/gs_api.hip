@@ -26,6 +26,7 @@ extern "C" void gs_default_settings(gs_settings *s) {
     s->batch = 256;
     s->bwd_waves = 2;
     s->checked = 0;
+    s->schedule = 0;
     s->status = nullptr;
 }
 

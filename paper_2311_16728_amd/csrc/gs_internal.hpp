@@ -44,7 +44,8 @@ static inline bool valid_settings(const gs_settings *s) {
            (s->bwd_waves == 1 || s->bwd_waves == 2 || s->bwd_waves == 4) && s->alpha_min > 0.f &&
            s->alpha_max <= 1.f && s->alpha_max >= s->alpha_min && s->t_min > 0.f &&
            s->dilation >= 0.f && s->fov_clamp > 0.f && s->znear > 0.f &&
-           (s->checked == 0 || (s->checked == 1 && s->status != nullptr));
+           (s->checked == 0 || (s->checked == 1 && s->status != nullptr)) &&
+           (s->schedule >= 0 && s->schedule <= 2);
 }
 
 // ---------------------------------------------------------------------------
@@ -77,6 +78,18 @@ static inline Proj proj_at(void *ws, int64_t records) {
                 reinterpret_cast<float4 *>(b + L.rgb_z)};
 }
 
+// Work queue of the persistent raster launches (settings.schedule 1 or 2): the
+// tiles in order of decreasing list length (order, built by gs_bin_sort) and
+// a control block: per length class (floor(log2(length)) + 1, 0 for empty)
+// its count and a cursor, then the next-item and finished-workgroup counters
+// of the forward and the backward.  The last workgroup of a launch resets its
+// two counters, so every launch starts at item 0.
+constexpr int kQueueClasses = 34;
+enum QueueWord {
+    kQueueCount = 0, kQueueCursor = kQueueClasses, kQueueNextFwd = 2 * kQueueClasses, kQueueDoneFwd,
+    kQueueNextBwd, kQueueDoneBwd, kQueueWords = 128
+};
+
 // Counters at the head of the sort workspace.
 enum Counter { kVisible = 0, kPairs = 1, kPairsClamped = 2, kNumCounters = 16 };
 
@@ -86,7 +99,7 @@ static inline int64_t pair_chunks(int64_t pair_cap) { return (pair_cap + 255) / 
 struct SortLayout {
     size_t counters, counts, rects, vis_key0, vis_key1, vis_val0, vis_val1, vis_off, pair_key0,
         pair_key1, pair_val0, pair_val1, ranges, bsum, hist, digit, chunk_first, view_off, view_list,
-        bytes;
+        order, queue, bytes;
     int64_t sources, pair_cap, max_blocks;
     // sources: (view, Gaussian) records, n_views * n_cap; rects: one per
     // (target, Gaussian), n_targets * n_cap
@@ -122,6 +135,8 @@ struct SortLayout {
         // targets of each view (CSR)
         L.view_off = take(sizeof(uint32_t) * (n_views + 1));
         L.view_list = take(sizeof(uint32_t) * n_targets);
+        L.order = take(sizeof(uint32_t) * (total_tiles > 0 ? total_tiles : 1));
+        L.queue = take(sizeof(uint32_t) * kQueueWords);
         L.bytes = o;
         return L;
     }
@@ -144,6 +159,8 @@ static inline TileSortPlan tile_sort_plan(int32_t total_tiles) {
 struct Sorted {
     const uint32_t *pair_val;   // record index view * n_cap + g, per pair
     const uint2 *ranges;        // [start, end) of each global tile
+    const uint32_t *order;      // tiles by decreasing list length (schedule 1)
+    uint32_t *queue;            // work-queue control block (schedule 1)
 };
 
 static inline Sorted sorted_at(const void *ws, int64_t n_views, int64_t n_targets, int64_t n_cap,
@@ -152,8 +169,9 @@ static inline Sorted sorted_at(const void *ws, int64_t n_views, int64_t n_target
     const char *b = static_cast<const char *>(ws);
     const int passes = tile_sort_plan(total_tiles).passes;
     size_t val = (passes & 1) ? L.pair_val1 : L.pair_val0;
-    return Sorted{reinterpret_cast<const uint32_t *>(b + val),
-                  reinterpret_cast<const uint2 *>(b + L.ranges)};
+    return Sorted{reinterpret_cast<const uint32_t *>(b + val), reinterpret_cast<const uint2 *>(b + L.ranges),
+                  reinterpret_cast<const uint32_t *>(b + L.order),
+                  reinterpret_cast<uint32_t *>(const_cast<char *>(b) + L.queue)};
 }
 
 // Per-row learning rates (kernel argument).
@@ -215,6 +233,19 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
         if (lane >= d) v += u;
     }
     return v;
+}
+
+// End of a persistent launch over the work queue: each workgroup counts
+// itself out once it has found the queue empty; the last one resets the
+// next-item and finished counters for the next launch.
+__device__ __forceinline__ void queue_retire(uint32_t *queue, int next, int done) {
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&queue[done], 1u) == gridDim.x - 1) {
+            queue[next] = 0u;
+            queue[done] = 0u;
+        }
+    }
 }
 
 template <typename T>

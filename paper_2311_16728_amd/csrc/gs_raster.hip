@@ -15,6 +15,8 @@
 // with one atomic per quantity per tile.
 #include "gs_internal.hpp"
 
+#include <atomic>
+
 namespace gs {
 
 // Finds the target owning global tile `tile` (targets sorted by tile_offset).
@@ -108,104 +110,122 @@ struct TStore {
 
 // kCount: per-pixel composited and evaluated counts (and, with tile_max, the
 // largest composited count of each tile); kStore: the transmittance store.
-template <bool kCount, bool kStore = false>
+template <bool kCount, bool kStore = false, bool kQueued = false>
 __global__ void __launch_bounds__(256) render_fwd_kernel(
     gs_settings s, Proj proj, int64_t n_cap, Sorted srt, const gs_target *__restrict__ targets,
     int n_targets, float *__restrict__ out_rgb, float *__restrict__ out_T,
     int32_t *__restrict__ out_last, int32_t *__restrict__ out_nc, int32_t *__restrict__ out_ne,
-    int32_t *__restrict__ tile_max = nullptr, TStore ts_store = TStore{nullptr, nullptr, nullptr, 0}) {
+    int32_t *__restrict__ tile_max = nullptr, TStore ts_store = TStore{nullptr, nullptr, nullptr, 0},
+    const uint32_t *__restrict__ order = nullptr, uint32_t *__restrict__ queue = nullptr, int total_tiles = 0) {
     __shared__ float4 sA[kTilePix];
     __shared__ float4 sB[kTilePix];
     __shared__ float2 sC[kTilePix];
     __shared__ int32_t sPos[kTilePix];
     __shared__ uint32_t scan_lds[8];
-    const int tile = blockIdx.x;
-    const int tid = threadIdx.x;
-    const gs_target t = targets[find_target(targets, n_targets, tile)];
-    const int local = tile - t.tile_offset;
-    const int tx = local % t.tiles_x, ty = local / t.tiles_x;
-    const TileShape ts = tile_shape(t.tile_w);
-    const int lxp = tid & (ts.w - 1), lyp = tid >> ts.wlog;   // pixel inside the tile
-    const int px = tx * ts.w + lxp, py = ty * ts.h + lyp;
-    const bool inside = px < t.width && py < t.height;
-    const uint2 range = srt.ranges[tile];
-    const double ox = double(tx * ts.w), oy = double(ty * ts.h);
-    const float fpx = float(lxp), fpy = float(lyp);   // relative to the tile origin
+    constexpr bool queued = kQueued;
+    for (int round = 0;; ++round) {
+        int tile;
+        if (queued) {   // next tile of the cost-ordered queue
+            __shared__ int s_item;
+            if (threadIdx.x == 0) s_item = int(atomicAdd(&queue[kQueueNextFwd], 1u));
+            __syncthreads();
+            const int item = s_item;
+            __syncthreads();
+            if (item >= total_tiles) break;
+            tile = int(order[item]);
+            if (tile < 0 || tile >= total_tiles) continue;   // not a tile: order not built
+        } else {
+            if (round > 0) break;
+            tile = blockIdx.x;
+        }
+        const int tid = threadIdx.x;
+        const gs_target t = targets[find_target(targets, n_targets, tile)];
+        const int local = tile - t.tile_offset;
+        const int tx = local % t.tiles_x, ty = local / t.tiles_x;
+        const TileShape ts = tile_shape(t.tile_w);
+        const int lxp = tid & (ts.w - 1), lyp = tid >> ts.wlog;   // pixel inside the tile
+        const int px = tx * ts.w + lxp, py = ty * ts.h + lyp;
+        const bool inside = px < t.width && py < t.height;
+        const uint2 range = srt.ranges[tile];
+        const double ox = double(tx * ts.w), oy = double(ty * ts.h);
+        const float fpx = float(lxp), fpy = float(lyp);   // relative to the tile origin
 
-    float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-    int32_t nc = 0, ne = 0, last = 0;
-    bool done = !inside;
-    float *store_at = nullptr;   // this pixel's first slot (kStore), or none
-    if (kStore && *ts_store.need <= ts_store.cap) store_at = ts_store.T + ts_store.base[tile] + tid;
-    const int batch = s.batch;
-    for (uint32_t b0 = range.x; b0 < range.y; b0 += batch) {
-        if (__syncthreads_count(done) == kTilePix) break;
-        // stage the batch, keeping only Gaussians whose cutoff ellipse meets the tile
-        const uint32_t idx = b0 + tid;
-        float4 A, B;
-        float2 Cc;
-        int64_t rec;
-        bool keep = false;
-        if (tid < batch && idx < range.y) {
-            stage_record(s, proj, n_cap, t.view, t.level, ox, oy, srt.pair_val[idx], A, B, Cc, rec);
-            keep = touches_tile(A, B, Cc, ts);
-        }
-        uint32_t cnt;
-        const uint32_t at_pos = block_exclusive_scan(keep ? 1u : 0u, scan_lds, &cnt);
-        if (keep) {
-            sA[at_pos] = A;
-            sB[at_pos] = B;
-            sC[at_pos] = Cc;
-            sPos[at_pos] = int32_t(idx - range.x);
-        }
-        __syncthreads();
-        if (!done) {
-            int lj = -1;   // staged index of this batch's last composited Gaussian
-#pragma unroll 4
-            for (int j = 0; j < int(cnt); ++j) {
-                const float4 A = sA[j];
-                const float4 B = sB[j];
-                const float2 Cj = sC[j];
-                const float dx = A.x - fpx, dy = A.y - fpy;
-                const float pw = eval_power(A, B, dx, dy);
-                if (kCount) ++ne;
-                if (pw < Cj.y) continue;
-                const float alpha = fminf(s.alpha_max, B.y * __expf(pw));
-                const float Tn = T * (1.f - alpha);
-                if (Tn < s.t_min) { done = true; break; }
-                if (kStore && store_at) store_at[int64_t(nc) * kTilePix] = T;
-                const float w = alpha * T;
-                C0 = fmaf(w, B.z, C0);
-                C1 = fmaf(w, B.w, C1);
-                C2 = fmaf(w, Cj.x, C2);
-                T = Tn;
-                if (kCount || kStore) ++nc;
-                lj = j;
+        float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+        int32_t nc = 0, ne = 0, last = 0;
+        bool done = !inside;
+        float *store_at = nullptr;   // this pixel's first slot (kStore), or none
+        if (kStore && *ts_store.need <= ts_store.cap) store_at = ts_store.T + ts_store.base[tile] + tid;
+        const int batch = s.batch;
+        for (uint32_t b0 = range.x; b0 < range.y; b0 += batch) {
+            if (__syncthreads_count(done) == kTilePix) break;
+            // stage the batch, keeping only Gaussians whose cutoff ellipse meets the tile
+            const uint32_t idx = b0 + tid;
+            float4 A, B;
+            float2 Cc;
+            int64_t rec;
+            bool keep = false;
+            if (tid < batch && idx < range.y) {
+                stage_record(s, proj, n_cap, t.view, t.level, ox, oy, srt.pair_val[idx], A, B, Cc, rec);
+                keep = touches_tile(A, B, Cc, ts);
             }
-            // one past the list position of the last composited Gaussian
-            if (lj >= 0) last = sPos[lj] + 1;
+            uint32_t cnt;
+            const uint32_t at_pos = block_exclusive_scan(keep ? 1u : 0u, scan_lds, &cnt);
+            if (keep) {
+                sA[at_pos] = A;
+                sB[at_pos] = B;
+                sC[at_pos] = Cc;
+                sPos[at_pos] = int32_t(idx - range.x);
+            }
+            __syncthreads();
+            if (!done) {
+                int lj = -1;   // staged index of this batch's last composited Gaussian
+    #pragma unroll 4
+                for (int j = 0; j < int(cnt); ++j) {
+                    const float4 A = sA[j];
+                    const float4 B = sB[j];
+                    const float2 Cj = sC[j];
+                    const float dx = A.x - fpx, dy = A.y - fpy;
+                    const float pw = eval_power(A, B, dx, dy);
+                    if (kCount) ++ne;
+                    if (pw < Cj.y) continue;
+                    const float alpha = fminf(s.alpha_max, B.y * __expf(pw));
+                    const float Tn = T * (1.f - alpha);
+                    if (Tn < s.t_min) { done = true; break; }
+                    if (kStore && store_at) store_at[int64_t(nc) * kTilePix] = T;
+                    const float w = alpha * T;
+                    C0 = fmaf(w, B.z, C0);
+                    C1 = fmaf(w, B.w, C1);
+                    C2 = fmaf(w, Cj.x, C2);
+                    T = Tn;
+                    if (kCount || kStore) ++nc;
+                    lj = j;
+                }
+                // one past the list position of the last composited Gaussian
+                if (lj >= 0) last = sPos[lj] + 1;
+            }
+        }
+        if (inside) {
+            const int64_t HW = int64_t(t.width) * t.height;
+            const int64_t pix = int64_t(py) * t.width + px;
+            float *rgb = out_rgb + 3 * t.pix_offset;
+            rgb[pix] = fmaf(T, t.bg[0], C0);
+            rgb[HW + pix] = fmaf(T, t.bg[1], C1);
+            rgb[2 * HW + pix] = fmaf(T, t.bg[2], C2);
+            out_T[t.pix_offset + pix] = T;
+            out_last[t.pix_offset + pix] = last;
+            if (kCount && out_nc) out_nc[t.pix_offset + pix] = nc;
+            if (kCount && out_ne) out_ne[t.pix_offset + pix] = ne;
+        }
+        if (kCount && tile_max) {
+            __shared__ int32_t tmax;
+            if (tid == 0) tmax = 0;
+            __syncthreads();
+            if (nc > 0) atomicMax(&tmax, nc);
+            __syncthreads();
+            if (tid == 0) tile_max[tile] = tmax;
         }
     }
-    if (inside) {
-        const int64_t HW = int64_t(t.width) * t.height;
-        const int64_t pix = int64_t(py) * t.width + px;
-        float *rgb = out_rgb + 3 * t.pix_offset;
-        rgb[pix] = fmaf(T, t.bg[0], C0);
-        rgb[HW + pix] = fmaf(T, t.bg[1], C1);
-        rgb[2 * HW + pix] = fmaf(T, t.bg[2], C2);
-        out_T[t.pix_offset + pix] = T;
-        out_last[t.pix_offset + pix] = last;
-        if (kCount && out_nc) out_nc[t.pix_offset + pix] = nc;
-        if (kCount && out_ne) out_ne[t.pix_offset + pix] = ne;
-    }
-    if (kCount && tile_max) {
-        __shared__ int32_t tmax;
-        if (tid == 0) tmax = 0;
-        __syncthreads();
-        if (nc > 0) atomicMax(&tmax, nc);
-        __syncthreads();
-        if (tid == 0) tile_max[tile] = tmax;
-    }
+    if (queued) queue_retire(queue, kQueueNextFwd, kQueueDoneFwd);
 }
 
 // Exclusive scan of the per-tile store sizes (256 floats per compositing step
@@ -287,12 +307,13 @@ constexpr int kTStride = kQuads + 1;           // odd row stride: conflict-free 
 // kStored: the store-all variant, which reads each composited Gaussian's
 // transmittance from the forward's store (in_nc: per-pixel composited counts)
 // instead of dividing it back out.
-template <int kWaves, bool kStored = false>
+template <int kWaves, bool kStored = false, bool kQueued = false>
 __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
     gs_settings s, Proj proj, int64_t n_cap, Sorted srt, const gs_target *__restrict__ targets,
     int n_targets, const float *__restrict__ in_T, const int32_t *__restrict__ in_last,
     const float *__restrict__ dL_drgb, float *__restrict__ acc,
-    const int32_t *__restrict__ in_nc = nullptr, TStore ts_store = TStore{nullptr, nullptr, nullptr, 0}) {
+    const int32_t *__restrict__ in_nc = nullptr, TStore ts_store = TStore{nullptr, nullptr, nullptr, 0},
+    const uint32_t *__restrict__ order = nullptr, uint32_t *__restrict__ queue = nullptr, int total_tiles = 0) {
     constexpr int kThreads = 64 * kWaves;
     constexpr int kPix = kTilePix / kThreads;
     __shared__ float4 sA[kThreads];
@@ -305,222 +326,239 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
     __shared__ float tbuf[kWaves][kGroup * kAccRows * kTStride];
     __shared__ int32_t sK[kWaves][kGroup];
     __shared__ int sMaxLast;
-    const int tile = blockIdx.x;
-    const int tid = threadIdx.x;
-    const int wave = tid / kWave;
-    const int lane = lane_id();
-    const gs_target t = targets[find_target(targets, n_targets, tile)];
-    const int local = tile - t.tile_offset;
-    const int tx = local % t.tiles_x, ty = local / t.tiles_x;
-    const TileShape ts = tile_shape(t.tile_w);
-    const uint2 range = srt.ranges[tile];
-    const double ox = double(tx * ts.w), oy = double(ty * ts.h);
-    const float sc = ldexpf(1.f, -t.level);
-    const int64_t HW = int64_t(t.width) * t.height;
-    const float *dLt = dL_drgb + 3 * t.pix_offset;
-    float *tb = tbuf[wave];
+    if (kStored && !(*ts_store.need <= ts_store.cap)) return;   // the forward stored nothing
+    constexpr bool queued = kQueued;
+    for (int round = 0;; ++round) {
+        int tile;
+        if (queued) {   // next tile of the cost-ordered queue
+            __shared__ int s_item;
+            if (threadIdx.x == 0) s_item = int(atomicAdd(&queue[kQueueNextBwd], 1u));
+            __syncthreads();
+            const int item = s_item;
+            __syncthreads();
+            if (item >= total_tiles) break;
+            tile = int(order[item]);
+            if (tile < 0 || tile >= total_tiles) continue;   // not a tile: order not built
+        } else {
+            if (round > 0) break;
+            tile = blockIdx.x;
+        }
+        const int tid = threadIdx.x;
+        const int wave = tid / kWave;
+        const int lane = lane_id();
+        const gs_target t = targets[find_target(targets, n_targets, tile)];
+        const int local = tile - t.tile_offset;
+        const int tx = local % t.tiles_x, ty = local / t.tiles_x;
+        const TileShape ts = tile_shape(t.tile_w);
+        const uint2 range = srt.ranges[tile];
+        const double ox = double(tx * ts.w), oy = double(ty * ts.h);
+        const float sc = ldexpf(1.f, -t.level);
+        const int64_t HW = int64_t(t.width) * t.height;
+        const float *dLt = dL_drgb + 3 * t.pix_offset;
+        float *tb = tbuf[wave];
 
-    float T[kPix], g0[kPix], g1[kPix], g2[kPix], B0[kPix], B1[kPix], B2[kPix], fpy[kPix];
-    int32_t last[kPix];
-    int32_t kc[kPix];             // kStored: composited Gaussians not yet walked back
-    const float *srow = nullptr;  // kStored: this tile's store
-    int32_t steps = 0;            // kStored: compositing steps stored for the tile
-    if (kStored) {
-        if (!(*ts_store.need <= ts_store.cap)) return;   // the forward stored nothing
-        srow = ts_store.T + ts_store.base[tile];
-        steps = int32_t((ts_store.base[tile + 1] - ts_store.base[tile]) / kTilePix);
-    }
-    // the tile width divides 64, so a lane keeps its column in every row it owns
-    const float fpx = float(tid & (ts.w - 1));
-    int my_max = 0;
-#pragma unroll
-    for (int i = 0; i < kPix; ++i) {
-        const int lp = tid + i * kThreads;   // tile-local pixel index
-        const int ly = lp >> ts.wlog;
-        fpy[i] = float(ly);
-        const int px = tx * ts.w + (lp & (ts.w - 1)), py = ty * ts.h + ly;
-        T[i] = 0.f; g0[i] = g1[i] = g2[i] = 0.f; last[i] = 0;
-        kc[i] = 0;
-        if (px < t.width && py < t.height) {
-            const int64_t pix = int64_t(py) * t.width + px;
-            if (kStored)
-                kc[i] = min(in_nc[t.pix_offset + pix], steps);
-            else
-                T[i] = in_T[t.pix_offset + pix];
-            last[i] = in_last[t.pix_offset + pix];
-            g0[i] = dLt[pix];
-            g1[i] = dLt[HW + pix];
-            g2[i] = dLt[2 * HW + pix];
+        float T[kPix], g0[kPix], g1[kPix], g2[kPix], B0[kPix], B1[kPix], B2[kPix], fpy[kPix];
+        int32_t last[kPix];
+        int32_t kc[kPix];             // kStored: composited Gaussians not yet walked back
+        const float *srow = nullptr;  // kStored: this tile's store
+        int32_t steps = 0;            // kStored: compositing steps stored for the tile
+        if (kStored) {
+            srow = ts_store.T + ts_store.base[tile];
+            steps = int32_t((ts_store.base[tile + 1] - ts_store.base[tile]) / kTilePix);
         }
-        // a restart position never exceeds the tile's list (guards stale input)
-        last[i] = min(last[i], int32_t(range.y - range.x));
-        my_max = max(my_max, last[i]);
-        B0[i] = t.bg[0]; B1[i] = t.bg[1]; B2[i] = t.bg[2];   // colour behind, unit transmittance
-    }
-    if (tid == 0) sMaxLast = 0;
-    __syncthreads();
-    if (my_max > 0) atomicMax(&sMaxLast, my_max);
-    __syncthreads();
-    const int max_last = sMaxLast;
+        // the tile width divides 64, so a lane keeps its column in every row it owns
+        const float fpx = float(tid & (ts.w - 1));
+        int my_max = 0;
+    #pragma unroll
+        for (int i = 0; i < kPix; ++i) {
+            const int lp = tid + i * kThreads;   // tile-local pixel index
+            const int ly = lp >> ts.wlog;
+            fpy[i] = float(ly);
+            const int px = tx * ts.w + (lp & (ts.w - 1)), py = ty * ts.h + ly;
+            T[i] = 0.f; g0[i] = g1[i] = g2[i] = 0.f; last[i] = 0;
+            kc[i] = 0;
+            if (px < t.width && py < t.height) {
+                const int64_t pix = int64_t(py) * t.width + px;
+                if (kStored)
+                    kc[i] = min(in_nc[t.pix_offset + pix], steps);
+                else
+                    T[i] = in_T[t.pix_offset + pix];
+                last[i] = in_last[t.pix_offset + pix];
+                g0[i] = dLt[pix];
+                g1[i] = dLt[HW + pix];
+                g2[i] = dLt[2 * HW + pix];
+            }
+            // a restart position never exceeds the tile's list (guards stale input)
+            last[i] = min(last[i], int32_t(range.y - range.x));
+            my_max = max(my_max, last[i]);
+            B0[i] = t.bg[0]; B1[i] = t.bg[1]; B2[i] = t.bg[2];   // colour behind, unit transmittance
+        }
+        if (tid == 0) sMaxLast = 0;
+        __syncthreads();
+        if (my_max > 0) atomicMax(&sMaxLast, my_max);
+        __syncthreads();
+        const int max_last = sMaxLast;
 
-    // Orders this wave's LDS accesses around a hand-over between its lanes.
-    auto wave_sync = [] {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    };
-    // sums the buffered Gaussians' values: lane m < n * 9 owns value m
-    auto flush = [&](int n) {
-        wave_sync();
-        if (lane < n * kAccRows) {
-            const float *row = tb + lane * kTStride;
-            float sum = 0.f;
-#pragma unroll
-            for (int q = 0; q < kQuads; ++q) sum += row[q];
-            const int slot = lane / kAccRows;
-            red[wave][sK[wave][slot]][lane - slot * kAccRows] = sum;
-        }
-        wave_sync();
-    };
-
-    for (int end = max_last; end > 0; end -= kThreads) {
-        const int start = max(0, end - kThreads);
-        __syncthreads();
-        float4 A, Bv;
-        float2 Cc;
-        int64_t rec;
-        bool keep = false;
-        if (tid < end - start) {
-            stage_record(s, proj, n_cap, t.view, t.level, ox, oy, srt.pair_val[range.x + start + tid],
-                         A, Bv, Cc, rec);
-            keep = touches_tile(A, Bv, Cc, ts);
-        }
-        uint32_t cnt;
-        const uint32_t at_pos = block_scan_n<kThreads>(keep ? 1u : 0u, scan_lds, &cnt);
-        if (keep) {
-            sA[at_pos] = A;
-            sB[at_pos] = Bv;
-            sC[at_pos] = Cc;
-            sR[at_pos] = uint32_t(rec);
-            sPos[at_pos] = start + tid;
-        }
-        __syncthreads();
-        int slots = 0;   // Gaussians buffered in tb (wave-uniform)
-        for (int k = int(cnt) - 1; k >= 0; --k) {
-            const float4 A = sA[k];
-            const float4 Bv = sB[k];
-            const float2 Ck = sC[k];
-            const int pos = sPos[k];
-            float v[kAccRows];
-#pragma unroll
-            for (int i = 0; i < kAccRows; ++i) v[i] = 0.f;
-            bool any = false;
-#pragma unroll
-            for (int i = 0; i < kPix; ++i) {
-                const float dx = A.x - fpx, dy = A.y - fpy[i];
-                const float pw = eval_power(A, Bv, dx, dy);
-                if (pos < last[i] && !(pw < Ck.y)) {
-                    any = true;
-                    const float ep = __expf(pw);
-                    const float at = Bv.y * ep;
-                    const float alpha = fminf(s.alpha_max, at);
-                    const float oma = 1.f - alpha;
-                    if (kStored) {   // transmittance in front of it, as stored
-                        kc[i] = max(kc[i] - 1, 0);
-                        T[i] = srow[int64_t(kc[i]) * kTilePix + tid + i * kThreads];
-                    } else {
-                        T[i] = T[i] * __builtin_amdgcn_rcpf(oma);   // transmittance in front of it
-                    }
-                    const float r = Bv.z, gg = Bv.w, bb = Ck.x;
-                    const float dal = T[i] * ((r - B0[i]) * g0[i] + (gg - B1[i]) * g1[i] + (bb - B2[i]) * g2[i]);
-                    const float w = alpha * T[i];
-                    v[6] += w * g0[i];
-                    v[7] += w * g1[i];
-                    v[8] += w * g2[i];
-                    B0[i] = fmaf(alpha, r, oma * B0[i]);
-                    B1[i] = fmaf(alpha, gg, oma * B1[i]);
-                    B2[i] = fmaf(alpha, bb, oma * B2[i]);
-                    const float dat = (at < s.alpha_max) ? dal : 0.f;
-                    v[5] += ep * dat;
-                    const float dp = at * dat;
-                    v[0] -= dp * (A.z * dx + A.w * dy);
-                    v[1] -= dp * (A.w * dx + Bv.x * dy);
-                    v[2] -= 0.5f * dp * dx * dx;
-                    v[3] -= dp * dx * dy;
-                    v[4] -= 0.5f * dp * dy * dy;
-                }
-            }
-            const uint64_t act = __ballot(any);
-            float *slot_out = red[wave][k];
-            if (act == 0) {
-                if (lane == kWave - 1) {
-#pragma unroll
-                    for (int i = 0; i < kAccRows; ++i) slot_out[i] = 0.f;
-                }
-                continue;
-            }
-            if (__popcll(act) == 1) {
-                // one lane of this wave touches the Gaussian: it holds the sums
-                if (act & (uint64_t(1) << lane)) {
-#pragma unroll
-                    for (int i = 0; i < kAccRows; ++i) slot_out[i] = v[i];
-                }
-                continue;
-            }
-            // quad sums, then one lane per quad into the transpose buffer
-#pragma unroll
-            for (int i = 0; i < kAccRows; ++i) {
-                v[i] = dpp_add<0xB1, 0xf>(v[i]);   // quad_perm [1,0,3,2]
-                v[i] = dpp_add<0x4E, 0xf>(v[i]);   // quad_perm [2,3,0,1]
-            }
-            if ((lane & 3) == 0) {
-                float *col = tb + slots * kAccRows * kTStride + (lane >> 2);
-#pragma unroll
-                for (int i = 0; i < kAccRows; ++i) col[i * kTStride] = v[i];
-            }
-            if (lane == 0) sK[wave][slots] = k;
-            if (++slots == kGroup) {
-                flush(kGroup);
-                slots = 0;
-            }
-        }
-        if (slots > 0) flush(slots);
-        __syncthreads();
-        // The waves' sums are added, the conic gradient becomes the gradient of
-        // the dilated covariance (-K dK K), and both go back to level-0 units
-        // (in place, in red[0]) ...
-        for (int k = tid; k < int(cnt); k += kThreads) {
-            float v[kAccRows];
-#pragma unroll
-            for (int i = 0; i < kAccRows; ++i) {
+        // Orders this wave's LDS accesses around a hand-over between its lanes.
+        auto wave_sync = [] {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        };
+        // sums the buffered Gaussians' values: lane m < n * 9 owns value m
+        auto flush = [&](int n) {
+            wave_sync();
+            if (lane < n * kAccRows) {
+                const float *row = tb + lane * kTStride;
                 float sum = 0.f;
-#pragma unroll
-                for (int w = 0; w < kWaves; ++w) sum += red[w][k][i];
-                v[i] = sum;
+    #pragma unroll
+                for (int q = 0; q < kQuads; ++q) sum += row[q];
+                const int slot = lane / kAccRows;
+                red[wave][sK[wave][slot]][lane - slot * kAccRows] = sum;
             }
-            const float a = sA[k].z, b = sA[k].w, c = sB[k].x;
-            const float ga = v[2], gb = 0.5f * v[3], gc = v[4];
-            const float k00 = a * ga + b * gb, k01 = a * gb + b * gc;
-            const float k10 = b * ga + c * gb, k11 = b * gb + c * gc;
-            const float s2 = sc * sc;
-            v[0] *= sc;
-            v[1] *= sc;
-            v[2] = -(k00 * a + k01 * b) * s2;
-            v[3] = -(k00 * b + k01 * c) * s2;
-            v[4] = -(k10 * b + k11 * c) * s2;
-#pragma unroll
-            for (int i = 0; i < kAccRows; ++i) red[0][k][i] = v[i];
-        }
-        __syncthreads();
-        // ... then one atomic per (Gaussian, quantity) for the whole tile, with
-        // consecutive threads on consecutive accumulators of a record (a
-        // record's nine accumulators are contiguous)
-        for (int idx = tid; idx < int(cnt) * kAccRows; idx += kThreads) {
-            const int k = idx / kAccRows, i = idx - k * kAccRows;
-            const float v = red[0][k][i];
-            if (v != 0.f) atomicAdd(&acc[int64_t(sR[k]) * kAccRows + i], v);   // sR unsigned
+            wave_sync();
+        };
+
+        for (int end = max_last; end > 0; end -= kThreads) {
+            const int start = max(0, end - kThreads);
+            __syncthreads();
+            float4 A, Bv;
+            float2 Cc;
+            int64_t rec;
+            bool keep = false;
+            if (tid < end - start) {
+                stage_record(s, proj, n_cap, t.view, t.level, ox, oy, srt.pair_val[range.x + start + tid],
+                             A, Bv, Cc, rec);
+                keep = touches_tile(A, Bv, Cc, ts);
+            }
+            uint32_t cnt;
+            const uint32_t at_pos = block_scan_n<kThreads>(keep ? 1u : 0u, scan_lds, &cnt);
+            if (keep) {
+                sA[at_pos] = A;
+                sB[at_pos] = Bv;
+                sC[at_pos] = Cc;
+                sR[at_pos] = uint32_t(rec);
+                sPos[at_pos] = start + tid;
+            }
+            __syncthreads();
+            int slots = 0;   // Gaussians buffered in tb (wave-uniform)
+            for (int k = int(cnt) - 1; k >= 0; --k) {
+                const float4 A = sA[k];
+                const float4 Bv = sB[k];
+                const float2 Ck = sC[k];
+                const int pos = sPos[k];
+                float v[kAccRows];
+    #pragma unroll
+                for (int i = 0; i < kAccRows; ++i) v[i] = 0.f;
+                bool any = false;
+    #pragma unroll
+                for (int i = 0; i < kPix; ++i) {
+                    const float dx = A.x - fpx, dy = A.y - fpy[i];
+                    const float pw = eval_power(A, Bv, dx, dy);
+                    if (pos < last[i] && !(pw < Ck.y)) {
+                        any = true;
+                        const float ep = __expf(pw);
+                        const float at = Bv.y * ep;
+                        const float alpha = fminf(s.alpha_max, at);
+                        const float oma = 1.f - alpha;
+                        if (kStored) {   // transmittance in front of it, as stored
+                            kc[i] = max(kc[i] - 1, 0);
+                            T[i] = srow[int64_t(kc[i]) * kTilePix + tid + i * kThreads];
+                        } else {
+                            T[i] = T[i] * __builtin_amdgcn_rcpf(oma);   // transmittance in front of it
+                        }
+                        const float r = Bv.z, gg = Bv.w, bb = Ck.x;
+                        const float dal = T[i] * ((r - B0[i]) * g0[i] + (gg - B1[i]) * g1[i] + (bb - B2[i]) * g2[i]);
+                        const float w = alpha * T[i];
+                        v[6] += w * g0[i];
+                        v[7] += w * g1[i];
+                        v[8] += w * g2[i];
+                        B0[i] = fmaf(alpha, r, oma * B0[i]);
+                        B1[i] = fmaf(alpha, gg, oma * B1[i]);
+                        B2[i] = fmaf(alpha, bb, oma * B2[i]);
+                        const float dat = (at < s.alpha_max) ? dal : 0.f;
+                        v[5] += ep * dat;
+                        const float dp = at * dat;
+                        v[0] -= dp * (A.z * dx + A.w * dy);
+                        v[1] -= dp * (A.w * dx + Bv.x * dy);
+                        v[2] -= 0.5f * dp * dx * dx;
+                        v[3] -= dp * dx * dy;
+                        v[4] -= 0.5f * dp * dy * dy;
+                    }
+                }
+                const uint64_t act = __ballot(any);
+                float *slot_out = red[wave][k];
+                if (act == 0) {
+                    if (lane == kWave - 1) {
+    #pragma unroll
+                        for (int i = 0; i < kAccRows; ++i) slot_out[i] = 0.f;
+                    }
+                    continue;
+                }
+                if (__popcll(act) == 1) {
+                    // one lane of this wave touches the Gaussian: it holds the sums
+                    if (act & (uint64_t(1) << lane)) {
+    #pragma unroll
+                        for (int i = 0; i < kAccRows; ++i) slot_out[i] = v[i];
+                    }
+                    continue;
+                }
+                // quad sums, then one lane per quad into the transpose buffer
+    #pragma unroll
+                for (int i = 0; i < kAccRows; ++i) {
+                    v[i] = dpp_add<0xB1, 0xf>(v[i]);   // quad_perm [1,0,3,2]
+                    v[i] = dpp_add<0x4E, 0xf>(v[i]);   // quad_perm [2,3,0,1]
+                }
+                if ((lane & 3) == 0) {
+                    float *col = tb + slots * kAccRows * kTStride + (lane >> 2);
+    #pragma unroll
+                    for (int i = 0; i < kAccRows; ++i) col[i * kTStride] = v[i];
+                }
+                if (lane == 0) sK[wave][slots] = k;
+                if (++slots == kGroup) {
+                    flush(kGroup);
+                    slots = 0;
+                }
+            }
+            if (slots > 0) flush(slots);
+            __syncthreads();
+            // The waves' sums are added, the conic gradient becomes the gradient of
+            // the dilated covariance (-K dK K), and both go back to level-0 units
+            // (in place, in red[0]) ...
+            for (int k = tid; k < int(cnt); k += kThreads) {
+                float v[kAccRows];
+    #pragma unroll
+                for (int i = 0; i < kAccRows; ++i) {
+                    float sum = 0.f;
+    #pragma unroll
+                    for (int w = 0; w < kWaves; ++w) sum += red[w][k][i];
+                    v[i] = sum;
+                }
+                const float a = sA[k].z, b = sA[k].w, c = sB[k].x;
+                const float ga = v[2], gb = 0.5f * v[3], gc = v[4];
+                const float k00 = a * ga + b * gb, k01 = a * gb + b * gc;
+                const float k10 = b * ga + c * gb, k11 = b * gb + c * gc;
+                const float s2 = sc * sc;
+                v[0] *= sc;
+                v[1] *= sc;
+                v[2] = -(k00 * a + k01 * b) * s2;
+                v[3] = -(k00 * b + k01 * c) * s2;
+                v[4] = -(k10 * b + k11 * c) * s2;
+    #pragma unroll
+                for (int i = 0; i < kAccRows; ++i) red[0][k][i] = v[i];
+            }
+            __syncthreads();
+            // ... then one atomic per (Gaussian, quantity) for the whole tile, with
+            // consecutive threads on consecutive accumulators of a record (a
+            // record's nine accumulators are contiguous)
+            for (int idx = tid; idx < int(cnt) * kAccRows; idx += kThreads) {
+                const int k = idx / kAccRows, i = idx - k * kAccRows;
+                const float v = red[0][k][i];
+                if (v != 0.f) atomicAdd(&acc[int64_t(sR[k]) * kAccRows + i], v);   // sR unsigned
+            }
         }
     }
+    if (queued) queue_retire(queue, kQueueNextBwd, kQueueDoneBwd);
 }
 
 __global__ void fill_f32_kernel(float *p, int64_t count, float v) {
@@ -537,6 +575,26 @@ __global__ void fill_f32x4_kernel(float *p, int64_t count, float v) {
     } else {
         for (int64_t k = e; k < count; ++k) p[k] = v;
     }
+}
+
+// Workgroups of a persistent launch: as many as the chip holds at once (CUs x
+// resident workgroups per CU for the kernel), looked up once per kernel.  Any
+// count is correct (workgroups only take tiles from the queue); this one
+// keeps every CU busy with no workgroup left waiting for a slot.
+template <class Kernel>
+static int persistent_grid(Kernel kernel, int threads) {
+    static std::atomic<int> cached{0};
+    int g = cached.load(std::memory_order_relaxed);
+    if (g > 0) return g;
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || cus <= 0 ||
+        per_cu <= 0)
+        return 2048;
+    g = cus * per_cu;
+    cached.store(g, std::memory_order_relaxed);
+    return g;
 }
 
 static void launch_fill(float *p, int64_t count, float v, hipStream_t st) {
@@ -573,6 +631,11 @@ extern "C" gs_status gs_render_fwd(const gs_settings *s, const void *proj_ws, in
     if (out_ncontrib || out_nevals)
         hipLaunchKernelGGL(render_fwd_kernel<true>, dim3(total_tiles), dim3(kTilePix), 0, st, *s, proj, n_cap,
                            srt, targets, n_targets, out_rgb, out_T, out_last, out_ncontrib, out_nevals);
+    else if (s->schedule == 1)
+        hipLaunchKernelGGL((render_fwd_kernel<false, false, true>),
+                           dim3(persistent_grid(render_fwd_kernel<false, false, true>, kTilePix)), dim3(kTilePix), 0, st, *s,
+                           proj, n_cap, srt, targets, n_targets, out_rgb, out_T, out_last, nullptr, nullptr,
+                           nullptr, TStore{nullptr, nullptr, nullptr, 0}, srt.order, srt.queue, total_tiles);
     else
         hipLaunchKernelGGL(render_fwd_kernel<false>, dim3(total_tiles), dim3(kTilePix), 0, st, *s, proj, n_cap,
                            srt, targets, n_targets, out_rgb, out_T, out_last, nullptr, nullptr);
@@ -598,19 +661,43 @@ extern "C" gs_status gs_raster_bwd(const gs_settings *s, const void *proj_ws, in
     float *acc = static_cast<float *>(accum_ws);
     const int64_t acc_n = int64_t(kAccRows) * records;
     launch_fill(acc, acc_n, 0.f, st);
-    switch (s->bwd_waves) {
-        case 1:
-            hipLaunchKernelGGL(render_bwd_kernel<1>, dim3(total_tiles), dim3(64), 0, st, *s, proj, n_cap,
-                               srt, targets, n_targets, out_T, out_last, dL_drgb, acc);
-            break;
-        case 2:
-            hipLaunchKernelGGL(render_bwd_kernel<2>, dim3(total_tiles), dim3(128), 0, st, *s, proj, n_cap,
-                               srt, targets, n_targets, out_T, out_last, dL_drgb, acc);
-            break;
-        default:
-            hipLaunchKernelGGL(render_bwd_kernel<4>, dim3(total_tiles), dim3(256), 0, st, *s, proj, n_cap,
-                               srt, targets, n_targets, out_T, out_last, dL_drgb, acc);
-            break;
+    const TStore none{nullptr, nullptr, nullptr, 0};
+    if (s->schedule >= 1) {   // persistent workgroups over the cost-ordered tile queue
+        switch (s->bwd_waves) {
+            case 1:
+                hipLaunchKernelGGL((render_bwd_kernel<1, false, true>),
+                                   dim3(persistent_grid(render_bwd_kernel<1, false, true>, 64)), dim3(64), 0, st,
+                                   *s, proj, n_cap, srt, targets, n_targets, out_T, out_last, dL_drgb, acc,
+                                   nullptr, none, srt.order, srt.queue, total_tiles);
+                break;
+            case 2:
+                hipLaunchKernelGGL((render_bwd_kernel<2, false, true>),
+                                   dim3(persistent_grid(render_bwd_kernel<2, false, true>, 128)), dim3(128), 0, st,
+                                   *s, proj, n_cap, srt, targets, n_targets, out_T, out_last, dL_drgb, acc,
+                                   nullptr, none, srt.order, srt.queue, total_tiles);
+                break;
+            default:
+                hipLaunchKernelGGL((render_bwd_kernel<4, false, true>),
+                                   dim3(persistent_grid(render_bwd_kernel<4, false, true>, 256)), dim3(256), 0, st,
+                                   *s, proj, n_cap, srt, targets, n_targets, out_T, out_last, dL_drgb, acc,
+                                   nullptr, none, srt.order, srt.queue, total_tiles);
+                break;
+        }
+    } else {
+        switch (s->bwd_waves) {
+            case 1:
+                hipLaunchKernelGGL(render_bwd_kernel<1>, dim3(total_tiles), dim3(64), 0, st, *s, proj, n_cap,
+                                   srt, targets, n_targets, out_T, out_last, dL_drgb, acc);
+                break;
+            case 2:
+                hipLaunchKernelGGL(render_bwd_kernel<2>, dim3(total_tiles), dim3(128), 0, st, *s, proj, n_cap,
+                                   srt, targets, n_targets, out_T, out_last, dL_drgb, acc);
+                break;
+            default:
+                hipLaunchKernelGGL(render_bwd_kernel<4>, dim3(total_tiles), dim3(256), 0, st, *s, proj, n_cap,
+                                   srt, targets, n_targets, out_T, out_last, dL_drgb, acc);
+                break;
+        }
     }
     GS_CHECK_LAUNCH();
     return GS_OK;

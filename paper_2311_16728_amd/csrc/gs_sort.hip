@@ -65,12 +65,14 @@ __global__ void __launch_bounds__(256) sort_setup_kernel(const gs_target *__rest
                                                          uint32_t *__restrict__ counters,
                                                          uint32_t *__restrict__ view_off,
                                                          uint32_t *__restrict__ view_list,
-                                                         uint2 *__restrict__ ranges, int64_t total_tiles) {
+                                                         uint2 *__restrict__ ranges, int64_t total_tiles,
+                                                         uint32_t *__restrict__ queue) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < total_tiles) ranges[i] = make_uint2(0u, 0u);
     if (blockIdx.x != 0) return;
     const int tid = threadIdx.x;
     if (tid < kNumCounters) counters[tid] = 0u;
+    if (tid < kQueueWords) queue[tid] = 0u;
     __shared__ int32_t tv[kSetupChunk];
     auto stage = [&](int32_t c0) {
         __syncthreads();
@@ -744,10 +746,55 @@ __global__ void __launch_bounds__(256) radix_scatter_kernel(
     }
 }
 
+// Work queue of the persistent raster launches: tiles in order of decreasing
+// list length, by length class floor(log2(length)) + 1 (0 for an empty tile),
+// larger classes first; the order inside a class is arbitrary (any order
+// gives the same images: tiles are independent).
+__device__ __forceinline__ int length_class(uint2 r) {
+    const uint32_t len = r.y - r.x;
+    return len ? 32 - __clz(len) : 0;
+}
+
+__global__ void __launch_bounds__(256) tile_class_count_kernel(const uint2 *__restrict__ ranges, int64_t T,
+                                                               uint32_t *__restrict__ queue) {
+    __shared__ uint32_t h[kQueueClasses];
+    if (threadIdx.x < kQueueClasses) h[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < T) atomicAdd(&h[length_class(ranges[i])], 1u);
+    __syncthreads();
+    if (threadIdx.x < kQueueClasses && h[threadIdx.x]) atomicAdd(&queue[kQueueCount + threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ void __launch_bounds__(256) tile_order_kernel(const uint2 *__restrict__ ranges, int64_t T,
+                                                         uint32_t *__restrict__ queue, uint32_t *__restrict__ order) {
+    __shared__ uint32_t h[kQueueClasses], start[kQueueClasses];
+    if (threadIdx.x < kQueueClasses) {
+        h[threadIdx.x] = 0u;
+        uint32_t before = 0;   // tiles of the larger classes
+        for (int c = kQueueClasses - 1; c > int(threadIdx.x); --c) before += queue[kQueueCount + c];
+        start[threadIdx.x] = before;
+    }
+    __syncthreads();
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int c = 0;
+    uint32_t rank = 0;
+    if (i < T) {
+        c = length_class(ranges[i]);
+        rank = atomicAdd(&h[c], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < kQueueClasses && h[threadIdx.x])
+        start[threadIdx.x] += atomicAdd(&queue[kQueueCursor + threadIdx.x], h[threadIdx.x]);
+    __syncthreads();
+    if (i < T) order[start[c] + rank] = uint32_t(i);
+}
+
 struct SortBufs {
     uint32_t *counters, *counts, *vk[2], *vv[2], *voff, *pk[2], *pv[2], *bsum, *hist, *digit, *chunk_first,
         *view_off, *view_list;
     uint2 *ranges, *rects;
+    uint32_t *order, *queue;
     int64_t max_blocks;
 };
 
@@ -773,6 +820,8 @@ static SortBufs sort_bufs(void *ws, int32_t n_views, int32_t n_targets, int64_t 
     B.ranges = reinterpret_cast<uint2 *>(b + L.ranges);
     B.rects = reinterpret_cast<uint2 *>(b + L.rects);
     B.max_blocks = L.max_blocks;
+    B.order = u(L.order);
+    B.queue = u(L.queue);
     return B;
 }
 
@@ -848,7 +897,8 @@ extern "C" gs_status gs_bin_sort(const gs_settings *s, const void *proj_ws, int6
     Proj proj = proj_at(const_cast<void *>(proj_ws), S);
 
     hipLaunchKernelGGL(sort_setup_kernel, dim3((int64_t(total_tiles) + 255) / 256), dim3(256), 0, st, targets,
-                       n_targets, n_views, B.counters, B.view_off, B.view_list, B.ranges, int64_t(total_tiles));
+                       n_targets, n_views, B.counters, B.view_off, B.view_list, B.ranges, int64_t(total_tiles),
+                       B.queue);
     hipLaunchKernelGGL(count_kernel, dim3((n_cap + 255) / 256, n_views), dim3(256), 0, st, *s, proj, n, n_cap,
                        targets, B.view_off, B.view_list, B.counts, B.rects);
     // compact visible records
@@ -889,6 +939,13 @@ extern "C" gs_status gs_bin_sort(const gs_settings *s, const void *proj_ws, int6
                        : radix_sort<16, 8>(B.counters + kPairsClamped, B.pk, B.pv, 0, 0, plan.passes, pair_cap, B, st);
     hipLaunchKernelGGL(ranges_kernel, dim3(n_chunks < persistent ? n_chunks : persistent), dim3(256), 0, st,
                        B.counters, B.pk[pc], B.ranges);
+    if (s->schedule >= 1) {   // the raster work queue
+        const int64_t tg = (int64_t(total_tiles) + 255) / 256;
+        hipLaunchKernelGGL(tile_class_count_kernel, dim3(tg), dim3(256), 0, st, B.ranges, int64_t(total_tiles),
+                           B.queue);
+        hipLaunchKernelGGL(tile_order_kernel, dim3(tg), dim3(256), 0, st, B.ranges, int64_t(total_tiles), B.queue,
+                           B.order);
+    }
     GS_CHECK_LAUNCH();
     return GS_OK;
 }

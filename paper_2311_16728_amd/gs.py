@@ -30,7 +30,7 @@ class gs_settings(C.Structure):
     _fields_ = [("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float),
                 ("znear", C.c_float), ("dilation", C.c_float), ("fov_clamp", C.c_float),
                 ("sh_degree", C.c_int32), ("batch", C.c_int32), ("bwd_waves", C.c_int32),
-                ("checked", C.c_int32), ("status", C.c_void_p)]
+                ("checked", C.c_int32), ("schedule", C.c_int32), ("status", C.c_void_p)]
 
 
 class gs_view(C.Structure):

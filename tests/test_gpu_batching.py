@@ -169,3 +169,40 @@ def test_many_targets_equal_per_target_bitwise():
         assert torch.equal(one.plane(one.T, 0), big.plane(big.T, k)), k
     # the renders are not all background
     assert float(big.rgb.abs().sum()) > 0
+
+
+@pytest.mark.parametrize("waves", [1, 2, 4])
+def test_queue_schedule_matches_grid(waves):
+    """Persistent raster workgroups over the cost-ordered tile queue (schedule
+    1: forward and backward; 2: backward only) render bitwise what one
+    workgroup per tile renders, on every launch in a row (the queue resets
+    itself), and their gradients agree to FP32 summation order."""
+    from paper_2311_16728_amd import gs
+
+    p, n, cams = _two_views()
+    P = _dev(p)
+    rng = np.random.default_rng(5)
+    out = {}
+    for sched in (0, 1, 2):
+        s = gs.default_settings(batch=128, bwd_waves=waves, schedule=sched)
+        plan = plan_for(cams, levels=(0, 1, 2), n_cap=p.shape[1], settings=s)
+        W = _dev(rng.uniform(-1, 1, 3 * plan.total_pixels).astype(np.float32)) if sched == 0 else out[0][4]
+        runs = []
+        for rep in range(3):   # the second and third launches reuse the reset queue
+            plan.preprocess(P, n)
+            plan.bin_sort(n)
+            for _ in range(2):   # two forwards on one binning
+                plan.render_fwd()
+            grad = torch.zeros_like(P)
+            plan.backward(P, n, W, grad)
+            torch.cuda.synchronize()
+            runs.append((plan.rgb.clone(), plan.T.clone(), plan.last.clone(), grad.cpu().numpy()))
+        for r in runs[1:]:
+            assert torch.equal(r[0], runs[0][0]) and torch.equal(r[2], runs[0][2])
+        out[sched] = runs[0] + (W,) if sched == 0 else runs[0]
+    r0, t0, l0, g0, _ = out[0]
+    scale = np.abs(g0).max(axis=1, keepdims=True) + 1e-30
+    for sched in (1, 2):
+        r1, t1, l1, g1 = out[sched]
+        assert torch.equal(r0, r1) and torch.equal(t0, t1) and torch.equal(l0, l1)
+        assert (np.abs(g1 - g0) / scale).max() <= 1e-5
