@@ -56,11 +56,11 @@ def _mat_to_quat(R: np.ndarray) -> np.ndarray:
 class Case:
     """One seeded scene with held-out keypoints in each keyframe."""
 
-    def __init__(self, seed: int, n: int = 500_000, n_kf: int = 8, per_kf: int = 1280,
+    def __init__(self, seed: int, n: int = 500_000, n_kf: int = 8, per_kf: int = 4096,
                  width: int = 1200, height: int = 680, f: float = 600.0, perturb_map: bool = False,
-                 device="cuda"):
+                 kf_stride: int = 10, min_weight: float = 0.1, device="cuda"):
         self.seed, self.device = seed, device
-        gt, pert, cams = scenes.room_scene(seed, n, n_kf, width, height, f)
+        gt, pert, cams = scenes.room_scene(seed, n, n_kf, width, height, f, kf_stride=kf_stride)
         self.cams = cams
         rng = np.random.default_rng(seed + 104729)
         Pgt = torch.as_tensor(gt).to(device)
@@ -88,7 +88,8 @@ class Case:
             z = xc[:, 2]
             u = cam["fx"] * xc[:, 0] / np.maximum(z, 1e-9) + cam["cx"]
             vv = cam["fy"] * xc[:, 1] / np.maximum(z, 1e-9) + cam["cy"]
-            ok = (weight >= 1.0) & (z > 0.3) & (u >= 4) & (u < width - 4) & (vv >= 4) & (vv < height - 4) & ~taken
+            ok = ((weight >= min_weight) & (z > 0.3) & (u >= 4) & (u < width - 4) & (vv >= 4) &
+                  (vv < height - 4) & ~taken)
             cand = np.nonzero(ok)[0]
             pick = np.sort(rng.choice(cand, size=min(per_kf, cand.size), replace=False))
             taken[pick] = True
@@ -298,7 +299,7 @@ def main(argv=None):
     a = ap.parse_args(argv)
     kw = {}
     if a.quick:
-        kw = dict(n=200_000, n_kf=4, per_kf=1024)
+        kw = dict(n=200_000, n_kf=4, per_kf=1024, kf_stride=1, min_weight=1.0)
         a.train_seeds, a.eval_seeds, a.steps = 6, 3, 1500
     t0 = time.time()
     X, Y, H = generate(range(a.train_seeds), a.iters, **kw)

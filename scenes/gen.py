@@ -131,15 +131,16 @@ ROOM_HI = (5.0, 2.0, 5.0)
 
 
 def room_scene(seed: int, n: int, n_keyframes: int = 1, width: int = 1200, height: int = 680,
-               f: float = 600.0, n_cap: int | None = None):
+               f: float = 600.0, n_cap: int | None = None, kf_stride: int = 1):
     """A room-sized map (10 x 4 x 10 m) with keyframes on a smooth random walk.
 
-    Returns (params, target_params, cams).
+    With kf_stride k the walk has n_keyframes * k poses and every k-th one is a
+    keyframe (keyframes k steps apart).  Returns (params, target_params, cams).
     """
     rng = np.random.default_rng(seed)
     p = draw_gaussians(rng, n, ROOM_LO, ROOM_HI, n_cap)
     tgt = perturb(rng, p, n)
-    poses = random_walk(rng, n_keyframes, ROOM_LO, ROOM_HI)
+    poses = random_walk(rng, n_keyframes * kf_stride, ROOM_LO, ROOM_HI)[::kf_stride]
     cams = [pinhole(width, height, f, f, width / 2.0, height / 2.0, R, t) for R, t in poses]
     return p, tgt, cams
 

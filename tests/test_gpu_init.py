@@ -285,7 +285,7 @@ def test_learned_initialiser_beats_heuristic():
     must be lower."""
     from paper_2311_16728_amd import init_pipeline as ip
 
-    kw = dict(n=200_000, n_kf=4, per_kf=1024)
+    kw = dict(n=200_000, n_kf=4, per_kf=1024, kf_stride=1, min_weight=1.0)
     X, Y, H = ip.generate(range(6), 100, log=None, **kw)
     val = torch.arange(X.shape[0], device=X.device) % 10 == 0
     net, first, last = ip.train(X[~val].contiguous(), Y[~val].contiguous(), 1500, log=None)
