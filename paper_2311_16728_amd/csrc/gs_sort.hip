@@ -680,21 +680,41 @@ __global__ void __launch_bounds__(256) radix_scatter_kernel(
             val[k] = valid ? vin[e] : 0u;
             car[k] = (kCarry && valid) ? cin[e] : 0u;
         }
+        // The lowest lane of each digit group adds the group's size to the
+        // wave's running count of that digit and gets the count before it.
+        // A wave's LDS atomics execute in program order, so the counts follow
+        // the element order (stable) while the atomics of all items are in
+        // flight together; the leaders' counts then go to their groups.
+        // pos[k] holds, until the hand-over, the leader's count (bits 0-15; a
+        // wave's counts stay below kItems * 64), the leader lane (bits 16-21)
+        // and this lane's rank in its group (bits 24-29).
+        static_assert(kItems * kWave < (1 << 16), "counts fit 16 bits");
+        // (items in groups of kRankGroup, which bounds the registers in flight)
+        constexpr int kRankGroup = 4;
+        static_assert(kItems % kRankGroup == 0, "items in whole groups");
 #pragma unroll
-        for (int k = 0; k < kItems; ++k) {
-            const bool valid = wbase + k * kWave + lane < n;
-            const uint32_t d = (key[k] >> shift) & (kBins - 1);
-            uint64_t peers = __ballot(valid);
+        for (int k0 = 0; k0 < kItems; k0 += kRankGroup) {
 #pragma unroll
-            for (int bit = 0; bit < kBits; ++bit) {
-                const bool set = (d >> bit) & 1u;
-                const uint64_t m = __ballot(set);
-                peers &= set ? m : ~m;
+            for (int k = k0; k < k0 + kRankGroup; ++k) {
+                const bool valid = wbase + k * kWave + lane < n;
+                const uint32_t d = (key[k] >> shift) & (kBins - 1);
+                uint64_t peers = __ballot(valid);
+#pragma unroll
+                for (int bit = 0; bit < kBits; ++bit) {
+                    const bool set = (d >> bit) & 1u;
+                    const uint64_t m = __ballot(set);
+                    peers &= set ? m : ~m;
+                }
+                const uint32_t rank = uint32_t(mask_rank(peers));
+                const uint32_t leader = peers ? uint32_t(__builtin_ctzll(peers)) : uint32_t(lane);
+                const uint32_t c =
+                    (valid && rank == 0) ? atomicAdd(&wcnt[wave][d], uint32_t(__popcll(peers))) : 0u;
+                pos[k] = c | (leader << 16) | (rank << 24);
             }
-            const int rank = mask_rank(peers);
-            const uint32_t prior = valid ? wcnt[wave][d] : 0u;
-            pos[k] = prior + uint32_t(rank);
-            if (valid && rank == 0) wcnt[wave][d] = prior + uint32_t(__popcll(peers));
+#pragma unroll
+            for (int k = k0; k < k0 + kRankGroup; ++k)
+                pos[k] = (uint32_t(__shfl(int(pos[k]), int((pos[k] >> 16) & 63u), kWave)) & 0xffffu) +
+                         (pos[k] >> 24);
         }
         __syncthreads();
         {
