@@ -44,17 +44,27 @@ __device__ __forceinline__ int find_target_loss(const gs_target *__restrict__ ta
 // Tile geometry of the loss kernels: the target's raster tile (TW x TH
 // pixels, TW * TH = 256) plus an R-pixel halo, HX x HY.  Each kernel
 // dispatches on the target's tile width to a body compiled for that shape;
-// LDS is sized for the largest (8 x 32 and 32 x 8: 756-float halo; 32 x 8:
-// 18 x 32 horizontal pass).
-constexpr int kHaloMax = (32 + 2 * kR) * (8 + 2 * kR);
+// LDS is sized for the largest (16 x 16: 48 x 26 halo with its padded rows;
+// 32 x 8: 18 x 32 horizontal pass).
+// LDS row stride of a halo window: the horizontal passes read 32 / TW rows of
+// TW consecutive floats per half wave; row strides that put those rows on
+// disjoint banks keep the reads conflict-free (16-wide: 48, two rows 16
+// banks apart; 8-wide: 24, four rows at bank offsets 0, 24, 16, 8).
+template <int TW>
+__host__ __device__ constexpr int halo_stride() {
+    return TW == 16 ? 48 : TW == 8 ? 24 : TW + 2 * kR;
+}
+constexpr int kHaloMax = 48 * (16 + 2 * kR);   // the largest of the three shapes (16 x 16)
+static_assert(halo_stride<8>() * (32 + 2 * kR) <= kHaloMax && halo_stride<32>() * (8 + 2 * kR) <= kHaloMax,
+              "halo buffers");
 constexpr int kHPassMax = 32 * (8 + 2 * kR);
 
 // Loads the HX x HY window of one channel plane around the tile into LDS
-// (row stride HX), zero outside the image.
+// (row stride halo_stride<TW>()), zero outside the image.
 template <int TW>
 __device__ __forceinline__ void load_halo(const float *__restrict__ plane, int W, int H, int x0,
                                           int y0, float *dst) {
-    constexpr int TH = kTilePix / TW, HX = TW + 2 * kR, HY = TH + 2 * kR;
+    constexpr int TH = kTilePix / TW, HX = TW + 2 * kR, HY = TH + 2 * kR, HS = halo_stride<TW>();
     constexpr int kRounds = (HX * HY + kTilePix - 1) / kTilePix;
     // all of a thread's loads are issued before its first LDS store
     float v[kRounds];
@@ -68,7 +78,7 @@ __device__ __forceinline__ void load_halo(const float *__restrict__ plane, int W
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
         const int i = threadIdx.x + r * kTilePix;
-        if (i < HX * HY) dst[i] = v[r];
+        if (i < HX * HY) dst[(i / HX) * HS + i % HX] = v[r];
     }
 }
 
@@ -84,7 +94,7 @@ __device__ __forceinline__ void ssim_fwd_tile(const float *__restrict__ render,
                                               const float *__restrict__ target, const gs_target &t,
                                               int tile, const Window &win, float *__restrict__ maps,
                                               float *__restrict__ partial, SsimLds &L) {
-    constexpr int TH = kTilePix / TW, HX = TW + 2 * kR, HY = TH + 2 * kR;
+    constexpr int TH = kTilePix / TW, HY = TH + 2 * kR, HS = halo_stride<TW>();
     const float C1 = 0.01f * 0.01f, C2 = 0.03f * 0.03f;
     const int tid = threadIdx.x;
     const int local = tile - t.tile_offset;
@@ -104,7 +114,7 @@ __device__ __forceinline__ void ssim_fwd_tile(const float *__restrict__ render,
         __syncthreads();
         for (int i = tid; i < HY * TW; i += blockDim.x) {
             const int r = i / TW, cc = i % TW;
-            const float *rx = L.sx + r * HX + cc, *ry = L.sy + r * HX + cc;
+            const float *rx = L.sx + r * HS + cc, *ry = L.sy + r * HS + cc;
             float m1 = 0, m2 = 0, e11 = 0, e22 = 0, e12 = 0;
 #pragma unroll
             for (int k = 0; k < 2 * kR + 1; ++k) {
@@ -136,7 +146,7 @@ __device__ __forceinline__ void ssim_fwd_tile(const float *__restrict__ render,
             const float iB1B2 = 1.f / (B1 * B2);
             const float S = A1 * A2 * iB1B2;
             ss += S;
-            const int ci = (ly + kR) * HX + lx + kR;
+            const int ci = (ly + kR) * HS + lx + kR;
             l1 += fabsf(L.sx[ci] - L.sy[ci]);
             float *mp = maps + 9 * t.pix_offset + (3 * c) * HW;
             mp[pix] = 2.f * my * (A2 - A1) * iB1B2 - 2.f * mx * S * (1.f / B1 - 1.f / B2);
@@ -184,7 +194,7 @@ __device__ __forceinline__ void ssim_bwd_tile(const float *__restrict__ render,
                                               int tile, const Window &win, float lambda,
                                               const float *__restrict__ maps, float *__restrict__ dL,
                                               SsimBwdLds &L) {
-    constexpr int TH = kTilePix / TW, HX = TW + 2 * kR, HY = TH + 2 * kR;
+    constexpr int TH = kTilePix / TW, HY = TH + 2 * kR, HS = halo_stride<TW>();
     const int tid = threadIdx.x;
     const int local = tile - t.tile_offset;
     const int x0 = (local % t.tiles_x) * TW, y0 = (local / t.tiles_x) * TH;
@@ -201,7 +211,7 @@ __device__ __forceinline__ void ssim_bwd_tile(const float *__restrict__ render,
         __syncthreads();
         for (int i = tid; i < HY * TW; i += blockDim.x) {
             const int r = i / TW, cc = i % TW;
-            const int o = r * HX + cc;
+            const int o = r * HS + cc;
             float a0 = 0, a1 = 0, a2 = 0;
 #pragma unroll
             for (int k = 0; k < 2 * kR + 1; ++k) {
