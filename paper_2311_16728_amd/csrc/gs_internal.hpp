@@ -29,6 +29,12 @@ constexpr int kScanTile = kScanThreads * kScanItems;   // 4096 elements per bloc
 constexpr int kRadixBitsMax = 9;              // widest radix digit (depth sort, large tile sorts)
 constexpr int kRadixBinsMax = 1 << kRadixBitsMax;
 constexpr int kRadixPersist = 2048;           // workgroups of the grid-stride radix kernels
+// Tile counting sort: one stable pass whose digit is the whole tile index,
+// for up to kTileCountMax tiles (one LDS table), over blocks of kTileSortN
+// pairs (kTileSortItems per thread).
+constexpr int kTileCountMax = 4096;
+constexpr int kTileSortItems = 32;
+constexpr int kTileSortN = kTileSortItems * kScanThreads;   // 8192 pairs per block
 
 static constexpr size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -99,8 +105,12 @@ static inline int64_t pair_chunks(int64_t pair_cap) { return (pair_cap + 255) / 
 struct SortLayout {
     size_t counters, counts, rects, vis_key0, vis_key1, vis_val0, vis_val1, vis_off, pair_key0,
         pair_key1, pair_val0, pair_val1, ranges, bsum, hist, digit, chunk_first, view_off, view_list,
-        order, queue, bytes;
+        order, queue, thist, bytes;
     int64_t sources, pair_cap, max_blocks;
+    // tile counting sort: blocks of pairs and the row stride of its per-block
+    // tile counts (rows of tile_stride >= total_tiles entries; 0 when the
+    // tiles are too many for it)
+    int64_t tile_blocks, tile_stride;
     // sources: (view, Gaussian) records, n_views * n_cap; rects: one per
     // (target, Gaussian), n_targets * n_cap
     static SortLayout make(int64_t n_views, int64_t n_targets, int64_t n_cap, int64_t pair_cap,
@@ -129,7 +139,7 @@ struct SortLayout {
         L.ranges = take(sizeof(uint32_t) * 2 * (total_tiles > 0 ? total_tiles : 1));
         L.bsum = take(sizeof(uint32_t) * (L.max_blocks + 1));
         L.hist = take(sizeof(uint32_t) * kRadixBinsMax * L.max_blocks);
-        L.digit = take(sizeof(uint32_t) * (kRadixBinsMax + 1));
+        L.digit = take(sizeof(uint32_t) * ((kRadixBinsMax > kTileCountMax ? kRadixBinsMax : kTileCountMax) + 1));
         // first sorted record of every 256-pair emission chunk
         L.chunk_first = take(sizeof(uint32_t) * (pair_chunks(pair_cap) + 1));
         // targets of each view (CSR)
@@ -137,22 +147,30 @@ struct SortLayout {
         L.view_list = take(sizeof(uint32_t) * n_targets);
         L.order = take(sizeof(uint32_t) * (total_tiles > 0 ? total_tiles : 1));
         L.queue = take(sizeof(uint32_t) * kQueueWords);
+        const bool counting = total_tiles > 0 && total_tiles <= kTileCountMax;
+        L.tile_blocks = (pair_cap + kTileSortN - 1) / kTileSortN;
+        L.tile_stride = counting ? int64_t(align_up(size_t(total_tiles), 64)) : 0;
+        L.thist = take(counting ? sizeof(uint32_t) * L.tile_blocks * L.tile_stride : sizeof(uint32_t));
         L.bytes = o;
         return L;
     }
 };
 
-// Digit width and number of stable radix passes that order global tile
-// indices < total_tiles: 8-bit digits, or 9-bit ones where they save a pass
-// (17 or 18 bits: two passes instead of three).
+// How the pairs are put in tile order.  Up to kTileCountMax tiles: one
+// counting pass whose digit is the whole tile index (bits = the index width,
+// counting = true).  Beyond: stable radix passes over the global tile index,
+// 8-bit digits, or 9-bit ones where they save a pass (17 or 18 bits: two
+// passes instead of three).
 struct TileSortPlan {
     int bits, passes;
+    bool counting;
 };
 static inline TileSortPlan tile_sort_plan(int32_t total_tiles) {
     int bits = 1;
     while ((int64_t(1) << bits) < total_tiles) ++bits;
+    if (total_tiles <= kTileCountMax) return TileSortPlan{bits, 1, true};
     const int p8 = (bits + 7) / 8, p9 = (bits + 8) / 9;
-    return p9 < p8 ? TileSortPlan{9, p9} : TileSortPlan{8, p8};
+    return p9 < p8 ? TileSortPlan{9, p9, false} : TileSortPlan{8, p8, false};
 }
 
 // Sorted pair buffers after binning: the tile sort ends in buffer (passes & 1).

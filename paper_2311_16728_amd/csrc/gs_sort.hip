@@ -2,15 +2,16 @@
 // Gaussian) whose cutoff ellipse touches a 16x16 tile becomes a (tile,
 // Gaussian) pair, and each tile's pairs are put in front-to-back order.
 //
-// The order is built in two stable LSD radix sorts instead of one wide-key
-// sort: (1) the visible (view, Gaussian) records (visible in any target of
-// the view: the pyramid levels of a keyframe share one record and one depth)
-// are compacted and sorted by their camera depth (32-bit keys, four 8-bit
+// The order is built in two stable sorts instead of one wide-key sort:
+// (1) the visible (view, Gaussian) records (visible in any target of the
+// view: the pyramid levels of a keyframe share one record and one depth) are
+// compacted and radix-sorted by their camera depth (27-bit keys, three 9-bit
 // passes over V records); (2) the records emit their pairs, for every target
-// of their view, in that depth order and the pairs are sorted by
-// global tile index alone (ceil(log2(tiles)/8) passes, two at 1200x680).
-// Because both sorts are stable and records are compacted in (view, Gaussian)
-// order, each tile's list is ordered by (depth, Gaussian index).
+// of their view, in that depth order and the pairs are sorted by global tile
+// index alone: one counting pass whose digit is the whole tile index up to
+// 4096 tiles (3225 at 1200x680), else 8- or 9-bit radix passes.  Because
+// both sorts are stable and records are compacted in (view, Gaussian) order,
+// each tile's list is ordered by (depth, Gaussian index).
 // Pair counts are data dependent; every kernel reads them from device
 // counters so the whole sequence is launch-shape static and graph-capturable.
 #include "gs_internal.hpp"
@@ -421,6 +422,9 @@ emit_kernel(int64_t n_cap, int32_t n_views, const gs_target *__restrict__ target
         if (Pc != P && d_status) atomicOr(d_status, GS_STATUS_PAIR_OVERFLOW);
     }
     if (V == 0) return;   // no visible record, no pair (Pc == 0)
+    // the grid is sized for the pair capacity: workgroups without a chunk
+    // leave before staging the tables
+    if (int64_t(blockIdx.x) * kEmitChunk >= int64_t(Pc)) return;
     const int tid = threadIdx.x;
     // lim_v / lim_t entries are in LDS, the rest in global memory
     uint32_t lim_v = 0, lim_t = 0;
@@ -766,6 +770,278 @@ __global__ void __launch_bounds__(256) radix_scatter_kernel(
     }
 }
 
+// ---------------------------------------------------------------------------
+// Tile counting sort: one stable pass over the emitted pairs whose digit is
+// the whole tile index (up to kTileCountMax tiles).  Blocks of kTileSortN
+// consecutive pairs; hist[b * stride + t] counts the pairs of tile t in block
+// b.  Rows are contiguous, so a block writes its counts in one coalesced
+// sweep; tile_colscan_kernel turns every column into the exclusive count over
+// the blocks before b and leaves the tile totals in digit[].  The scatter
+// ranks each block's pairs per tile (per wave, in order) and writes the values
+// straight to their final slots; its workgroup 0 also writes every tile's
+// range.  Keys >= total_tiles (never emitted) are dropped by both sides, and
+// total_tiles <= 2^bits, so `bits` ballots tell every two tiles apart.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) tile_hist_kernel(const uint32_t *__restrict__ n_ptr,
+                                                        const uint32_t *__restrict__ keys, int32_t total_tiles,
+                                                        int64_t stride, uint32_t *__restrict__ hist) {
+    __shared__ uint32_t h[kTileCountMax];
+    const uint32_t n = *n_ptr;
+    const int64_t nb = (int64_t(n) + kTileSortN - 1) / kTileSortN;
+    const int tid = threadIdx.x;
+    for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        __syncthreads();
+        for (int i = tid; i < stride; i += kScanThreads) h[i] = 0u;
+        __syncthreads();
+        const int64_t base = b * kTileSortN;
+        uint32_t kk[kTileSortItems];   // every key load in flight before the first LDS atomic
+#pragma unroll
+        for (int k = 0; k < kTileSortItems; ++k) {
+            const int64_t e = base + k * kScanThreads + tid;
+            kk[k] = e < n ? keys[e] : 0xffffffffu;
+        }
+#pragma unroll
+        for (int k = 0; k < kTileSortItems; ++k)
+            if (kk[k] < uint32_t(total_tiles)) atomicAdd(&h[kk[k]], 1u);
+        __syncthreads();
+        uint32_t *row = hist + b * stride;
+        for (int i = tid; i < stride; i += kScanThreads) row[i] = h[i];
+    }
+}
+
+// Exclusive scan of every column of hist over the active blocks, in place;
+// column totals to digit[t].  A workgroup takes 64 tiles, one per lane, so
+// each load is a contiguous 256-byte piece of a row, and its kColWaves waves
+// take consecutive runs of blocks.  Each wave sums its run, the run sums are
+// scanned across the waves in LDS, and the wave writes the prefixes.  Runs of
+// up to kColHold blocks stay in registers between the two steps (one batch of
+// loads); longer runs are read twice, kColBatch loads at a time.
+// Grid: stride / 64 workgroups.
+constexpr int kColWaves = 16, kColHold = 32, kColBatch = 16;
+__global__ void __launch_bounds__(kColWaves * kWave) tile_colscan_kernel(const uint32_t *__restrict__ n_ptr,
+                                                                         uint32_t *__restrict__ hist,
+                                                                         int64_t stride,
+                                                                         uint32_t *__restrict__ digit) {
+    __shared__ uint32_t wsum[kColWaves][kWave];
+    const uint32_t n = *n_ptr;
+    const int64_t nb = (int64_t(n) + kTileSortN - 1) / kTileSortN;
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    uint32_t *col = hist + int64_t(blockIdx.x) * kWave + lane;
+    const int64_t per = (nb + kColWaves - 1) / kColWaves;
+    const int64_t b0 = wave * per, b1 = b0 + per < nb ? b0 + per : nb;
+    auto cross_waves = [&](uint32_t s, uint32_t &run, uint32_t &all) {
+        wsum[wave][lane] = s;
+        __syncthreads();
+        run = 0u;
+        all = 0u;
+#pragma unroll
+        for (int w = 0; w < kColWaves; ++w) {
+            const uint32_t x = wsum[w][lane];
+            run += w < wave ? x : 0u;
+            all += x;
+        }
+    };
+    uint32_t run, all;
+    if (per <= kColHold) {   // uniform over the workgroup
+        // 32-bit element offsets from the run's first entry (a run spans at
+        // most kColHold rows of at most kTileCountMax entries)
+        uint32_t *c0 = col + b0 * stride;
+        const uint32_t st = uint32_t(stride), cnt = uint32_t(b1 > b0 ? b1 - b0 : 0);
+        uint32_t v[kColHold], s = 0u;
+#pragma unroll
+        for (int j = 0; j < kColHold; ++j) {
+            v[j] = uint32_t(j) < cnt ? c0[uint32_t(j) * st] : 0u;
+            s += v[j];
+        }
+        cross_waves(s, run, all);
+#pragma unroll
+        for (int j = 0; j < kColHold; ++j) {
+            if (uint32_t(j) < cnt) c0[uint32_t(j) * st] = run;
+            run += v[j];
+        }
+    } else {
+        uint32_t s = 0u;
+        for (int64_t b = b0; b < b1; b += kColBatch) {
+            uint32_t v[kColBatch];
+#pragma unroll
+            for (int j = 0; j < kColBatch; ++j) v[j] = b + j < b1 ? col[(b + j) * stride] : 0u;
+#pragma unroll
+            for (int j = 0; j < kColBatch; ++j) s += v[j];
+        }
+        cross_waves(s, run, all);
+        for (int64_t b = b0; b < b1; b += kColBatch) {
+            uint32_t v[kColBatch];
+#pragma unroll
+            for (int j = 0; j < kColBatch; ++j) v[j] = b + j < b1 ? col[(b + j) * stride] : 0u;
+#pragma unroll
+            for (int j = 0; j < kColBatch; ++j) {
+                if (b + j < b1) col[(b + j) * stride] = run;
+                run += v[j];
+            }
+        }
+    }
+    if (wave == 0) digit[int64_t(blockIdx.x) * kWave + lane] = all;
+}
+
+// Scatter of the counting sort.  Wave w of a block owns the contiguous
+// quarter [w * kTileSortItems * 64, (w + 1) * kTileSortItems * 64) and ranks
+// its pairs row by row (64 consecutive pairs per row), in element order, with
+// one LDS atomic per tile: the per-wave counts are 16-bit fields, two tiles to
+// a word (a wave holds 2048 pairs, a block 8192, so no field carries into its
+// neighbour).  Most rows hold each tile at most once (a row spans a few
+// records, whose tile rectangles seldom meet): every lane writes its lane
+// number into a per-wave tag byte of its tile and reads it back, and when no
+// lane finds another's number each lane adds 1 to its own tile's field.
+// Otherwise the row falls back to grouping equal tiles with `bits` ballots,
+// the lowest lane of a group adding the group's size (the radix scatter's
+// scheme).  A pair's slot = start of its tile + count of its tile in earlier
+// blocks (hist after the column scan) + in earlier waves of its block + its
+// rank in its wave.  All loads of a block are issued before the first wait.
+__global__ void __launch_bounds__(256) tile_scatter_kernel(
+    const uint32_t *__restrict__ n_ptr, const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+    uint32_t *__restrict__ vout, int32_t total_tiles, int64_t stride, int bits,
+    const uint32_t *__restrict__ hist, const uint32_t *__restrict__ digit, uint2 *__restrict__ ranges) {
+    constexpr int kWaves = kScanThreads / kWave, kPer = kTileCountMax / kScanThreads;
+    constexpr int kWaveN = kTileSortItems * kWave;
+    static_assert(kTileSortN < (1 << 16), "a block's counts fit 16 bits");
+    __shared__ uint32_t bstart[kTileCountMax];          // first slot of each tile's run of this block
+    __shared__ uint32_t wc[kWaves][kTileCountMax / 2];  // per-wave counts, then offsets (16-bit fields)
+    __shared__ uint8_t tags[kWaves][kTileCountMax];     // per-wave tile tags (lane numbers)
+    __shared__ uint32_t lds[8];
+    const uint32_t n = *n_ptr;
+    const int tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
+    const uint32_t nt = uint32_t(total_tiles);
+    const int64_t nb = (int64_t(n) + kTileSortN - 1) / kTileSortN;
+    // consecutive blocks to one XCD, whose runs of a tile meet in the same
+    // cache lines (as in the radix scatter).  The grid is sized for the pair
+    // capacity: workgroups without a block leave at once, except workgroup 0,
+    // which writes the ranges.
+    const int64_t nb8 = (nb + kXcds - 1) / kXcds * kXcds;
+    const int64_t T = nb8 < int64_t(gridDim.x) ? nb8 : int64_t(gridDim.x);
+    const int64_t w0 = int64_t(blockIdx.x) < T ? xcd_tile(blockIdx.x, T) : nb;
+    if (w0 >= nb && blockIdx.x != 0) return;   // uniform over the workgroup
+    const int half = int((stride + 1) / 2);
+    bool first = true;
+    for (int64_t b = w0; first || b < nb; b += T) {
+        const bool has = b < nb;   // false only for workgroup 0 with no block
+        // tile totals and this block's counts of tile t = tid * kPer + j, and
+        // the block's keys and values
+        // (16-byte loads: stride is a multiple of 64 and both arrays are
+        // 256-byte aligned).  Out-of-range lanes load entry 0 and discard it,
+        // so that every load is unconditional.
+        uint32_t dv[kPer], hv[kPer];
+        const uint32_t *hrow = hist + (has ? b : 0) * stride;
+#pragma unroll
+        for (int j = 0; j < kPer; j += 4) {
+            const int t = tid * kPer + j;
+            const bool tin = t < stride;
+            const uint4 d4 = *reinterpret_cast<const uint4 *>(digit + (tin ? t : 0));
+            const uint4 h4 = *reinterpret_cast<const uint4 *>(hrow + (tin ? t : 0));
+            const bool hin = has && tin;
+            dv[j] = tin ? d4.x : 0u; dv[j + 1] = tin ? d4.y : 0u;
+            dv[j + 2] = tin ? d4.z : 0u; dv[j + 3] = tin ? d4.w : 0u;
+            hv[j] = hin ? h4.x : 0u; hv[j + 1] = hin ? h4.y : 0u;
+            hv[j + 2] = hin ? h4.z : 0u; hv[j + 3] = hin ? h4.w : 0u;
+        }
+        const int64_t wbase = b * kTileSortN + int64_t(wave) * kWaveN;
+        uint32_t key[kTileSortItems], val[kTileSortItems], pos[kTileSortItems];
+#pragma unroll
+        for (int k = 0; k < kTileSortItems; ++k) {
+            const int64_t e = wbase + k * kWave + lane;
+            const bool in = has && e < n;
+            const int64_t ec = in ? e : 0;
+            const uint32_t kv = kin[ec], vv = vin[ec];
+            key[k] = in ? kv : 0xffffffffu;
+            val[k] = in ? vv : 0u;
+        }
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w)
+            for (int i = tid; i < half; i += kScanThreads) wc[w][i] = 0u;
+        {
+            uint32_t sum = 0, total;
+#pragma unroll
+            for (int j = 0; j < kPer; ++j) sum += dv[j];
+            uint32_t pre = block_exclusive_scan(sum, lds, &total);   // (barriers inside)
+#pragma unroll
+            for (int j = 0; j < kPer; ++j) {
+                const int t = tid * kPer + j;
+                if (first && blockIdx.x == 0 && t < total_tiles) ranges[t] = make_uint2(pre, pre + dv[j]);
+                bstart[t] = pre + hv[j];
+                pre += dv[j];
+            }
+        }
+        first = false;
+        if (!has) return;
+        __syncthreads();
+        constexpr int kRankGroup = 4;
+        static_assert(kTileSortItems % kRankGroup == 0, "items in whole groups");
+#pragma unroll
+        for (int k0 = 0; k0 < kTileSortItems; k0 += kRankGroup) {
+            // Each row writes its tags and reads them back before the next row
+            // writes (a wave's LDS operations execute in order; relaxed atomics
+            // keep the compiler from reusing the written value).  A tile held
+            // by several lanes of the row keeps one lane's number, so at least
+            // one of them reads another's: no clash is missed.
+            uint64_t clash[kRankGroup];
+#pragma unroll
+            for (int j = 0; j < kRankGroup; ++j) {
+                const uint32_t d = key[k0 + j];
+                if (d < nt)
+                    __hip_atomic_store(&tags[wave][d], uint8_t(lane), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                const uint8_t got = d < nt ? __hip_atomic_load(&tags[wave][d], __ATOMIC_RELAXED,
+                                                               __HIP_MEMORY_SCOPE_WORKGROUP)
+                                           : uint8_t(lane);
+                clash[j] = __ballot(got != uint8_t(lane));
+            }
+#pragma unroll
+            for (int j = 0; j < kRankGroup; ++j) {
+                const int k = k0 + j;
+                const uint32_t d = key[k];
+                const bool valid = d < nt;
+                const uint32_t sh = (d & 1u) * 16u;
+                if (clash[j] == 0) {
+                    pos[k] = valid ? (atomicAdd(&wc[wave][d >> 1], 1u << sh) >> sh) & 0xffffu : 0u;
+                } else {
+                    uint64_t peers = __ballot(valid);
+                    for (int bit = 0; bit < bits; ++bit) {
+                        const bool set = (d >> bit) & 1u;
+                        const uint64_t m = __ballot(set);
+                        peers &= set ? m : ~m;
+                    }
+                    const uint32_t rank = uint32_t(mask_rank(peers));
+                    const uint32_t leader = peers ? uint32_t(__builtin_ctzll(peers)) : uint32_t(lane);
+                    uint32_t c = 0u;
+                    if (valid && rank == 0)
+                        c = (atomicAdd(&wc[wave][d >> 1], uint32_t(__popcll(peers)) << sh) >> sh) & 0xffffu;
+                    pos[k] = (uint32_t(__shfl(int(c), int(leader), kWave)) & 0xffffu) + rank;
+                }
+            }
+        }
+        __syncthreads();
+        // per-wave counts -> counts of the earlier waves (both fields at once:
+        // a field's sum stays below 2^16)
+        for (int i = tid; i < half; i += kScanThreads) {
+            uint32_t r = 0u;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                const uint32_t c = wc[w][i];
+                wc[w][i] = r;
+                r += c;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kTileSortItems; ++k) {
+            const uint32_t d = key[k];
+            if (d < nt) {
+                const uint32_t before = (wc[wave][d >> 1] >> ((d & 1u) * 16u)) & 0xffffu;
+                vout[bstart[d] + before + pos[k]] = val[k];
+            }
+        }
+        __syncthreads();   // LDS reads done before the next block's writes
+    }
+}
+
 // Work queue of the persistent raster launches: tiles in order of decreasing
 // list length, by length class floor(log2(length)) + 1 (0 for an empty tile),
 // larger classes first; the order inside a class is arbitrary (any order
@@ -814,8 +1090,8 @@ struct SortBufs {
     uint32_t *counters, *counts, *vk[2], *vv[2], *voff, *pk[2], *pv[2], *bsum, *hist, *digit, *chunk_first,
         *view_off, *view_list;
     uint2 *ranges, *rects;
-    uint32_t *order, *queue;
-    int64_t max_blocks;
+    uint32_t *order, *queue, *thist;
+    int64_t max_blocks, tile_blocks, tile_stride;
 };
 
 static SortBufs sort_bufs(void *ws, int32_t n_views, int32_t n_targets, int64_t n_cap, int64_t pair_cap,
@@ -840,6 +1116,9 @@ static SortBufs sort_bufs(void *ws, int32_t n_views, int32_t n_targets, int64_t 
     B.ranges = reinterpret_cast<uint2 *>(b + L.ranges);
     B.rects = reinterpret_cast<uint2 *>(b + L.rects);
     B.max_blocks = L.max_blocks;
+    B.thist = u(L.thist);
+    B.tile_blocks = L.tile_blocks;
+    B.tile_stride = L.tile_stride;
     B.order = u(L.order);
     B.queue = u(L.queue);
     return B;
@@ -952,13 +1231,25 @@ extern "C" gs_status gs_bin_sort(const gs_settings *s, const void *proj_ws, int6
                        B.chunk_first, pair_cap, B.pk[0], B.pv[0], d_status);
     // tile order
     const TileSortPlan plan = tile_sort_plan(total_tiles);
-    // 9-bit digits come with many tiles and pairs: 8192-element sort blocks keep
-    // each digit's run per block long enough for full write segments
-    const int pc = plan.bits == 9
-                       ? radix_sort<32, 9>(B.counters + kPairsClamped, B.pk, B.pv, 0, 0, plan.passes, pair_cap, B, st)
-                       : radix_sort<16, 8>(B.counters + kPairsClamped, B.pk, B.pv, 0, 0, plan.passes, pair_cap, B, st);
-    hipLaunchKernelGGL(ranges_kernel, dim3(n_chunks < persistent ? n_chunks : persistent), dim3(256), 0, st,
-                       B.counters, B.pk[pc], B.ranges);
+    if (plan.counting) {   // one pass, pairs pk[0] / pv[0] -> values pv[1] and the ranges
+        const int64_t tb = B.tile_blocks < kRadixPersist ? B.tile_blocks : kRadixPersist;
+        hipLaunchKernelGGL(tile_hist_kernel, dim3(tb), dim3(256), 0, st, B.counters + kPairsClamped, B.pk[0],
+                           total_tiles, B.tile_stride, B.thist);
+        hipLaunchKernelGGL(tile_colscan_kernel, dim3(B.tile_stride / kWave), dim3(kColWaves * kWave), 0, st,
+                           B.counters + kPairsClamped, B.thist, B.tile_stride, B.digit);
+        hipLaunchKernelGGL(tile_scatter_kernel, dim3(xcd_grid(tb)), dim3(256), 0, st, B.counters + kPairsClamped,
+                           B.pk[0], B.pv[0], B.pv[1], total_tiles, B.tile_stride, plan.bits, B.thist, B.digit,
+                           B.ranges);
+    } else {
+        // 9-bit digits come with many tiles and pairs: 8192-element sort blocks keep
+        // each digit's run per block long enough for full write segments
+        const int pc = plan.bits == 9 ? radix_sort<32, 9>(B.counters + kPairsClamped, B.pk, B.pv, 0, 0,
+                                                          plan.passes, pair_cap, B, st)
+                                      : radix_sort<16, 8>(B.counters + kPairsClamped, B.pk, B.pv, 0, 0,
+                                                          plan.passes, pair_cap, B, st);
+        hipLaunchKernelGGL(ranges_kernel, dim3(n_chunks < persistent ? n_chunks : persistent), dim3(256), 0, st,
+                           B.counters, B.pk[pc], B.ranges);
+    }
     if (s->schedule >= 1) {   // the raster work queue
         const int64_t tg = (int64_t(total_tiles) + 255) / 256;
         hipLaunchKernelGGL(tile_class_count_kernel, dim3(tg), dim3(256), 0, st, B.ranges, int64_t(total_tiles),
