@@ -105,8 +105,11 @@ static inline int64_t pair_chunks(int64_t pair_cap) { return (pair_cap + 255) / 
 struct SortLayout {
     size_t counters, counts, rects, vis_key0, vis_key1, vis_val0, vis_val1, vis_off, pair_key0,
         pair_key1, pair_val0, pair_val1, ranges, bsum, hist, digit, chunk_first, view_off, view_list,
-        order, queue, thist, bytes;
+        order, queue, thist, whist, wdigit, bytes;
     int64_t sources, pair_cap, max_blocks;
+    // row stride of the pair-count sums per (digit, block) of the last depth
+    // pass (whist), which turn the counts into pair offsets
+    int64_t wstride;
     // tile counting sort: blocks of pairs and the row stride of its per-block
     // tile counts (rows of tile_stride >= total_tiles entries; 0 when the
     // tiles are too many for it)
@@ -151,6 +154,9 @@ struct SortLayout {
         L.tile_blocks = (pair_cap + kTileSortN - 1) / kTileSortN;
         L.tile_stride = counting ? int64_t(align_up(size_t(total_tiles), 64)) : 0;
         L.thist = take(counting ? sizeof(uint32_t) * L.tile_blocks * L.tile_stride : sizeof(uint32_t));
+        L.wstride = rb + 1;
+        L.whist = take(sizeof(uint32_t) * kRadixBinsMax * L.wstride);
+        L.wdigit = take(sizeof(uint32_t) * (kRadixBinsMax + 1));
         L.bytes = o;
         return L;
     }

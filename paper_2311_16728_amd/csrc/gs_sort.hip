@@ -204,6 +204,25 @@ __device__ __forceinline__ uint32_t sat32(uint64_t v) {
     return v > 0xffffffffull ? 0xffffffffu : uint32_t(v);
 }
 
+// Exclusive scan over a 256-thread block in 64 bits; block total to *total.
+// lds needs 4 words.
+__device__ __forceinline__ uint64_t block_exclusive_scan64(uint64_t v, uint64_t *lds, uint64_t *total) {
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    const uint64_t inc = wave_inclusive_scan64(v);
+    if (lane == kWave - 1) lds[wave] = inc;
+    __syncthreads();
+    uint64_t base = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / kWave; ++w) {
+        const uint64_t x = lds[w];
+        base += w < wave ? x : 0u;
+        all += x;
+    }
+    __syncthreads();
+    *total = all;
+    return base + inc - v;
+}
+
 // Exclusive scan of bsum[0..nb) in place (one block of 1024 threads); the
 // total goes to *total_out.  Sums are formed in 64 bits and stored saturated
 // at 2^32 - 1.
@@ -304,75 +323,6 @@ __global__ void __launch_bounds__(256) compact_scatter_kernel(const uint32_t *__
     }
 }
 
-// Exclusive scan of the pair counts over the depth-sorted visible list
-// (sorted_cnt: the counts carried through the depth sort, in list order).
-// Block sums in 64 bits, stored saturated.
-__global__ void __launch_bounds__(256) offsets_reduce_kernel(const uint32_t *__restrict__ n_ptr,
-                                                             const uint32_t *__restrict__ sorted_cnt,
-                                                             uint32_t *bsum) {
-    __shared__ uint64_t lds[kScanThreads / kWave];
-    const uint32_t n = *n_ptr;
-    const int64_t base = int64_t(blockIdx.x) * kScanTile;
-    if (base >= n) return;
-    uint64_t acc = 0;
-#pragma unroll 4
-    for (int k = 0; k < kScanItems; ++k) {
-        const int64_t e = base + k * kScanThreads + threadIdx.x;
-        if (e < n) acc += sorted_cnt[e];
-    }
-    acc = wave_inclusive_scan64(acc);
-    if (lane_id() == kWave - 1) lds[threadIdx.x / kWave] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t t = 0;
-        for (int w = 0; w < kScanThreads / kWave; ++w) t += lds[w];
-        bsum[blockIdx.x] = sat32(t);
-    }
-}
-
-__global__ void __launch_bounds__(256) offsets_scatter_kernel(const uint32_t *__restrict__ n_ptr,
-                                                              const uint32_t *__restrict__ sorted_cnt,
-                                                              const uint32_t *__restrict__ bsum,
-                                                              uint32_t *__restrict__ vis_off,
-                                                              uint32_t *__restrict__ chunk_first,
-                                                              int64_t n_chunks) {
-    __shared__ uint64_t wtot[kScanItems][kScanThreads / kWave];
-    const uint32_t n = *n_ptr;
-    const int64_t base = int64_t(blockIdx.x) * kScanTile;
-    if (base >= n) return;
-    const int wave = threadIdx.x / kWave, lane = lane_id();
-    uint32_t c[kScanItems];
-    uint64_t pre[kScanItems];
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const int64_t e = base + k * kScanThreads + threadIdx.x;
-        c[k] = e < int64_t(n) ? sorted_cnt[e] : 0u;
-        const uint64_t inc = wave_inclusive_scan64(c[k]);
-        pre[k] = inc - c[k];
-        if (lane == kWave - 1) wtot[k][wave] = inc;
-    }
-    __syncthreads();
-    if (threadIdx.x < kWave) {   // the (round, wave) totals in element order
-        const int k = threadIdx.x / (kScanThreads / kWave), w = threadIdx.x % (kScanThreads / kWave);
-        const uint64_t v = wtot[k][w];
-        wtot[k][w] = wave_inclusive_scan64(v) - v;
-    }
-    __syncthreads();
-    const uint64_t b0 = bsum[blockIdx.x];
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const int64_t e = base + k * kScanThreads + threadIdx.x;
-        if (e < int64_t(n)) {
-            const uint64_t o = b0 + wtot[k][wave] + pre[k];
-            vis_off[e] = sat32(o);
-            // this record holds the first slot of every chunk starting in [o, o + c)
-            const uint64_t end = o + c[k];
-            for (uint64_t q = (o + 255) / 256; q * 256 < end && int64_t(q) < n_chunks; ++q)
-                chunk_first[q] = uint32_t(e);
-        }
-    }
-}
-
 // q = k / w, r = k % w for k < 2^24, w >= 1: a float reciprocal estimate
 // corrected by one step (exact: the estimate is off by at most one).
 __device__ __forceinline__ void divmod_small(uint32_t k, uint32_t w, uint32_t &q, uint32_t &r) {
@@ -386,7 +336,7 @@ __device__ __forceinline__ void divmod_small(uint32_t k, uint32_t w, uint32_t &q
 // Pair emission over chunks of kEmitChunk consecutive pair slots, kEmitPer
 // consecutive slots per thread.  The records covering a chunk (at most one per
 // slot, each has >= 1 pair) start at chunk_first[] (one entry per 256 slots,
-// written by the offsets scan).  Every record after the first marks the slot
+// written by the last depth pass).  Every record after the first marks the slot
 // where it starts, and a block scan of the marks gives each slot its record,
 // so near-camera Gaussians that cover thousands of tiles are spread over many
 // threads; a thread reuses its record's data across its slots and stores its
@@ -567,47 +517,72 @@ emit_kernel(int64_t n_cap, int32_t n_views, const gs_target *__restrict__ target
 // The grids are grid-stride over the sort blocks, so a capacity-sized launch
 // does not start thousands of idle workgroups.
 // ---------------------------------------------------------------------------
-template <int kItems, int kBits>
+// Weighted (kW): also the sum of the weights w[] of each digit's elements per
+// block, formed in 64 bits and stored saturated at 2^32 - 1 in
+// whist[digit * wstride + block].
+template <int kItems, int kBits, bool kW = false>
 __global__ void __launch_bounds__(256) radix_hist_kernel(const uint32_t *__restrict__ n_ptr,
                                                          const uint32_t *__restrict__ keys, int shift,
                                                          uint32_t *__restrict__ hist,
-                                                         int64_t max_blocks) {
+                                                         int64_t max_blocks,
+                                                         const uint32_t *__restrict__ w = nullptr,
+                                                         uint32_t *__restrict__ whist = nullptr,
+                                                         int64_t wstride = 0) {
     constexpr int kBins = 1 << kBits, kTileN = kItems * kScanThreads;
     __shared__ uint32_t h[kBins];
+    __shared__ unsigned long long hw[kW ? kBins : 1];
     const uint32_t n = *n_ptr;
     const int64_t nb = (int64_t(n) + kTileN - 1) / kTileN;
     for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
         __syncthreads();
-        for (int i = threadIdx.x; i < kBins; i += kScanThreads) h[i] = 0;
+        for (int i = threadIdx.x; i < kBins; i += kScanThreads) {
+            h[i] = 0;
+            if (kW) hw[i] = 0ull;
+        }
         __syncthreads();
         const int64_t base = b * kTileN;
-        uint32_t kk[kItems];   // every key load in flight before the first LDS atomic
+        uint32_t kk[kItems], ww[kItems];   // every load in flight before the first LDS atomic
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             const int64_t e = base + k * kScanThreads + threadIdx.x;
             kk[k] = e < n ? keys[e] : 0u;
+            ww[k] = (kW && e < n) ? w[e] : 0u;
         }
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             const int64_t e = base + k * kScanThreads + threadIdx.x;
-            if (e < n) atomicAdd(&h[(kk[k] >> shift) & (kBins - 1)], 1u);
+            if (e < n) {
+                const uint32_t d = (kk[k] >> shift) & (kBins - 1);
+                atomicAdd(&h[d], 1u);
+                if (kW) atomicAdd(&hw[d], static_cast<unsigned long long>(ww[k]));
+            }
         }
         __syncthreads();
-        for (int i = threadIdx.x; i < kBins; i += kScanThreads) hist[int64_t(i) * max_blocks + b] = h[i];
+        for (int i = threadIdx.x; i < kBins; i += kScanThreads) {
+            hist[int64_t(i) * max_blocks + b] = h[i];
+            if (kW) whist[int64_t(i) * wstride + b] = sat32(hw[i]);
+        }
     }
 }
 
 // Block d: exclusive scan of row d of hist over the active blocks; row total
-// to digit[d].
-template <int kItems>
+// to digit[d].  Weighted (kW): the same for row d of whist, in 64 bits,
+// stored saturated, total to wdigit[d].
+template <int kItems, bool kW = false>
 __global__ void __launch_bounds__(256) radix_rowscan_kernel(const uint32_t *__restrict__ n_ptr,
                                                             uint32_t *__restrict__ hist,
                                                             int64_t max_blocks,
-                                                            uint32_t *__restrict__ digit) {
+                                                            uint32_t *__restrict__ digit,
+                                                            uint32_t *__restrict__ whist = nullptr,
+                                                            int64_t wstride = 0,
+                                                            uint32_t *__restrict__ wdigit = nullptr) {
     __shared__ uint32_t lds[8];
+    __shared__ uint64_t lds64[kScanThreads / kWave];
     const int64_t nb = (int64_t(*n_ptr) + kItems * kScanThreads - 1) / (kItems * kScanThreads);
     uint32_t *row = hist + int64_t(blockIdx.x) * max_blocks;
+    uint32_t *wrow = kW ? whist + int64_t(blockIdx.x) * wstride : nullptr;
     uint32_t run = 0;
+    uint64_t wrun = 0;
     for (int64_t c = 0; c < nb; c += 256) {
         const int64_t i = c + threadIdx.x;
         const uint32_t v = (i < nb) ? row[i] : 0u;
@@ -615,9 +590,31 @@ __global__ void __launch_bounds__(256) radix_rowscan_kernel(const uint32_t *__re
         const uint32_t pre = block_exclusive_scan(v, lds, &total);
         if (i < nb) row[i] = run + pre;
         run += total;
+        if (kW) {
+            const uint64_t x = (i < nb) ? wrow[i] : 0u;
+            uint64_t wtotal;
+            const uint64_t wpre = block_exclusive_scan64(x, lds64, &wtotal);
+            if (i < nb) wrow[i] = sat32(wrun + wpre);
+            wrun += wtotal;
+        }
     }
-    if (threadIdx.x == 0) digit[blockIdx.x] = run;
+    if (threadIdx.x == 0) {
+        digit[blockIdx.x] = run;
+        if (kW) wdigit[blockIdx.x] = sat32(wrun);
+    }
 }
+
+// Outputs of the last depth pass in offsets mode: the pair-count sums per
+// (digit, block) after their row scan and per digit, where the total pair
+// count goes, and the first record of every 256-slot emission chunk.
+struct PairOffsets {
+    const uint32_t *whist;
+    int64_t wstride;
+    const uint32_t *wdigit;
+    uint32_t *total;
+    uint32_t *chunk_first;
+    int64_t n_chunks;
+};
 
 // Scatter.  Ranks are found per wave with no workgroup barrier per element:
 // a wave walks its quarter in order, groups equal digits with kBits ballots,
@@ -627,13 +624,22 @@ __global__ void __launch_bounds__(256) radix_rowscan_kernel(const uint32_t *__re
 // consecutive addresses of each digit's run.  Order inside a digit is the
 // input order (stable).
 // kCarry: a second value array (cin -> cout) moves with the keys.
-template <int kItems, int kBits, bool kCarry>
+// kOffsets (with kCarry; the last pass of the record sort): cin holds the
+// records' pair counts, and cout receives instead each record's pair offset,
+// the exclusive sum of the counts in the final order: counts of smaller
+// digits (per-digit sums) + of the digit in earlier blocks (weighted row scan)
+// + of the digit's run in this block before the record (a block scan of the
+// counts laid out in digit order).  The record holding slot 256 q is written
+// to chunk_first[q], and workgroup 0 stores the total pair count.  Sums are
+// formed in 64 bits and stored saturated.
+template <int kItems, int kBits, bool kCarry, bool kOffsets = false>
 __global__ void __launch_bounds__(256) radix_scatter_kernel(
     const uint32_t *__restrict__ n_ptr, const uint32_t *__restrict__ kin,
     const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
     const uint32_t *__restrict__ cin, uint32_t *__restrict__ cout,
     int shift, const uint32_t *__restrict__ hist, int64_t max_blocks,
-    const uint32_t *__restrict__ digit) {
+    const uint32_t *__restrict__ digit, PairOffsets po = PairOffsets{}) {
+    static_assert(!kOffsets || kCarry, "offsets mode reads the counts as the carried values");
     constexpr int kBins = 1 << kBits, kPer = kBins / kScanThreads;
     constexpr int kWaves = kScanThreads / kWave;
     constexpr int kTileN = kItems * kScanThreads, kWaveN = kItems * kWave;
@@ -646,6 +652,10 @@ __global__ void __launch_bounds__(256) radix_scatter_kernel(
     __shared__ uint32_t sval[kTileN];
     __shared__ uint32_t scar[kCarry ? kTileN : 1];
     __shared__ uint32_t lds[8];
+    __shared__ uint64_t wdbase[kOffsets ? kBins : 1];   // pair offset of each digit's first record
+    __shared__ uint64_t wgbase[kOffsets ? kBins : 1];   // ... of its first record in this block
+    __shared__ uint64_t wstart[kOffsets ? kBins : 1];   // block-scan value at the run's start
+    __shared__ uint64_t lds64[kScanThreads / kWave];
     const uint32_t n = *n_ptr;
     const int64_t nb = (int64_t(n) + kTileN - 1) / kTileN;
     // each XCD takes consecutive sort blocks, whose digit runs meet in the same
@@ -666,6 +676,15 @@ __global__ void __launch_bounds__(256) radix_scatter_kernel(
         uint32_t pre = block_exclusive_scan(sum, lds, &total);
 #pragma unroll
         for (int j = 0; j < kPer; ++j) { dbase[tid * kPer + j] = pre; pre += v[j]; }
+    }
+    if constexpr (kOffsets) {
+        uint64_t v[kPer], sum = 0, total;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) { v[j] = po.wdigit[tid * kPer + j]; sum += v[j]; }
+        uint64_t pre = block_exclusive_scan64(sum, lds64, &total);
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) { wdbase[tid * kPer + j] = pre; pre += v[j]; }
+        if (blockIdx.x == 0 && tid == 0) *po.total = sat32(total);
     }
     for (int64_t b = w0; b < nb; b += T) {
         const int64_t base = b * kTileN;
@@ -742,6 +761,7 @@ __global__ void __launch_bounds__(256) radix_scatter_kernel(
                 const int d = tid * kPer + j;
                 lstart[d] = pre;
                 gbase[d] = dbase[d] + hist[int64_t(d) * max_blocks + b];
+                if (kOffsets) wgbase[d] = wdbase[d] + po.whist[int64_t(d) * po.wstride + b];
                 pre += cnt[j];
             }
         }
@@ -758,13 +778,54 @@ __global__ void __launch_bounds__(256) radix_scatter_kernel(
         }
         __syncthreads();
         const int cnt = int(min(int64_t(kTileN), int64_t(n) - base));
-        for (int i = tid; i < cnt; i += kScanThreads) {
-            const uint32_t k2 = skey[i];
-            const uint32_t d = (k2 >> shift) & (kBins - 1);
-            const uint32_t p = gbase[d] + (uint32_t(i) - lstart[d]);
-            kout[p] = k2;
-            vout[p] = sval[i];
-            if (kCarry) cout[p] = scar[i];
+        if constexpr (kOffsets) {
+            // element i = tid * kItems + j of the block in digit order
+            static_assert(kTileN == kItems * kScanThreads, "block layout");
+            uint64_t wl[kItems], wp[kItems], s = 0, tot;
+#pragma unroll
+            for (int j = 0; j < kItems; ++j) {
+                const int i = tid * kItems + j;
+                wl[j] = i < cnt ? scar[i] : 0u;
+                s += wl[j];
+            }
+            uint64_t pre = block_exclusive_scan64(s, lds64, &tot);
+#pragma unroll
+            for (int j = 0; j < kItems; ++j) {
+                const int i = tid * kItems + j;
+                wp[j] = pre;
+                pre += wl[j];
+                if (i < cnt) {
+                    const uint32_t d = (skey[i] >> shift) & (kBins - 1);
+                    if (uint32_t(i) == lstart[d]) wstart[d] = wp[j];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < kItems; ++j) {
+                const int i = tid * kItems + j;
+                if (i < cnt) {
+                    const uint32_t k2 = skey[i];
+                    const uint32_t d = (k2 >> shift) & (kBins - 1);
+                    const uint32_t p = gbase[d] + (uint32_t(i) - lstart[d]);
+                    kout[p] = k2;
+                    vout[p] = sval[i];
+                    const uint64_t o = wgbase[d] + (wp[j] - wstart[d]);
+                    cout[p] = sat32(o);
+                    // this record holds the first slot of every chunk starting in [o, o + count)
+                    const uint64_t end = o + wl[j];
+                    for (uint64_t q = (o + 255) / 256; q * 256 < end && int64_t(q) < po.n_chunks; ++q)
+                        po.chunk_first[q] = p;
+                }
+            }
+        } else {
+            for (int i = tid; i < cnt; i += kScanThreads) {
+                const uint32_t k2 = skey[i];
+                const uint32_t d = (k2 >> shift) & (kBins - 1);
+                const uint32_t p = gbase[d] + (uint32_t(i) - lstart[d]);
+                kout[p] = k2;
+                vout[p] = sval[i];
+                if (kCarry) cout[p] = scar[i];
+            }
         }
         __syncthreads();
     }
@@ -1090,8 +1151,8 @@ struct SortBufs {
     uint32_t *counters, *counts, *vk[2], *vv[2], *voff, *pk[2], *pv[2], *bsum, *hist, *digit, *chunk_first,
         *view_off, *view_list;
     uint2 *ranges, *rects;
-    uint32_t *order, *queue, *thist;
-    int64_t max_blocks, tile_blocks, tile_stride;
+    uint32_t *order, *queue, *thist, *whist, *wdigit;
+    int64_t max_blocks, tile_blocks, tile_stride, wstride;
 };
 
 static SortBufs sort_bufs(void *ws, int32_t n_views, int32_t n_targets, int64_t n_cap, int64_t pair_cap,
@@ -1117,6 +1178,9 @@ static SortBufs sort_bufs(void *ws, int32_t n_views, int32_t n_targets, int64_t 
     B.rects = reinterpret_cast<uint2 *>(b + L.rects);
     B.max_blocks = L.max_blocks;
     B.thist = u(L.thist);
+    B.whist = u(L.whist);
+    B.wdigit = u(L.wdigit);
+    B.wstride = L.wstride;
     B.tile_blocks = L.tile_blocks;
     B.tile_stride = L.tile_stride;
     B.order = u(L.order);
@@ -1136,13 +1200,13 @@ static int radix_sort(const uint32_t *n_ptr, uint32_t *kbuf[2], uint32_t *vbuf[2
     for (int p = 0; p < passes; ++p) {
         const int shift = first_bit + p * kBits;
         hipLaunchKernelGGL((radix_hist_kernel<kItems, kBits>), dim3(grid), dim3(256), 0, st, n_ptr,
-                           kbuf[cur], shift, B.hist, B.max_blocks);
-        hipLaunchKernelGGL(radix_rowscan_kernel<kItems>, dim3(1 << kBits), dim3(256), 0, st, n_ptr, B.hist,
-                           B.max_blocks, B.digit);
+                           kbuf[cur], shift, B.hist, B.max_blocks, nullptr, nullptr, int64_t(0));
+        hipLaunchKernelGGL((radix_rowscan_kernel<kItems>), dim3(1 << kBits), dim3(256), 0, st, n_ptr, B.hist,
+                           B.max_blocks, B.digit, nullptr, int64_t(0), nullptr);
         hipLaunchKernelGGL((radix_scatter_kernel<kItems, kBits, kCarry>), dim3(xcd_grid(grid)), dim3(256), 0, st,
                            n_ptr, kbuf[cur], vbuf[cur], kbuf[cur ^ 1], vbuf[cur ^ 1],
                            kCarry ? cbuf[cur] : nullptr, kCarry ? cbuf[cur ^ 1] : nullptr, shift, B.hist,
-                           B.max_blocks, B.digit);
+                           B.max_blocks, B.digit, PairOffsets{});
         cur ^= 1;
     }
     return cur;
@@ -1211,23 +1275,31 @@ extern "C" gs_status gs_bin_sort(const gs_settings *s, const void *proj_ws, int6
     uint32_t *cnt_buf[2] = {B.voff, B.counts};
     hipLaunchKernelGGL(compact_scatter_kernel, dim3(sblocks), dim3(256), 0, st, B.counts, S, proj, s->znear,
                        B.bsum, B.vk[0], B.vv[0], cnt_buf[0]);
-    // depth order (three 9-bit passes over the 27-bit keys)
+    // depth order (three 9-bit passes over the 27-bit keys); the last pass
+    // also turns the pair counts into pair offsets (in `counts`), writes the
+    // emission chunks' first records and the total pair count
     static_assert(kDepthKeyBits == 3 * 9, "depth key width");
-    int cur = radix_sort<4, 9, true>(B.counters + kVisible, B.vk, B.vv, 0, 0, 3, S, B, st, cnt_buf);
-    // an odd number of passes leaves the counts in `counts`, so the offsets
-    // scan reads them there while it writes vis_off
-    const uint32_t *sorted_cnt = cnt_buf[cur];
-    hipLaunchKernelGGL(offsets_reduce_kernel, dim3(sblocks), dim3(256), 0, st, B.counters + kVisible,
-                       sorted_cnt, B.bsum);
-    hipLaunchKernelGGL(scan_bsums_kernel, dim3(1), dim3(1024), 0, st, B.counters + kVisible, B.bsum,
-                       B.counters + kPairs, int64_t(0));
+    int cur = radix_sort<4, 9, true>(B.counters + kVisible, B.vk, B.vv, 0, 0, 2, S, B, st, cnt_buf);
     const int64_t n_chunks = pair_chunks(pair_cap);
-    hipLaunchKernelGGL(offsets_scatter_kernel, dim3(sblocks), dim3(256), 0, st, B.counters + kVisible,
-                       sorted_cnt, B.bsum, B.voff, B.chunk_first, n_chunks);
+    {
+        const int64_t blocks = (S + 1023) / 1024;
+        const int64_t grid = blocks < kRadixPersist ? blocks : kRadixPersist;
+        const uint32_t *nv = B.counters + kVisible;
+        hipLaunchKernelGGL((radix_hist_kernel<4, 9, true>), dim3(grid), dim3(256), 0, st, nv, B.vk[cur], 18, B.hist,
+                           B.max_blocks, cnt_buf[cur], B.whist, B.wstride);
+        hipLaunchKernelGGL((radix_rowscan_kernel<4, true>), dim3(512), dim3(256), 0, st, nv, B.hist, B.max_blocks,
+                           B.digit, B.whist, B.wstride, B.wdigit);
+        const PairOffsets po{B.whist, B.wstride, B.wdigit, B.counters + kPairs, B.chunk_first, n_chunks};
+        hipLaunchKernelGGL((radix_scatter_kernel<4, 9, true, true>), dim3(xcd_grid(grid)), dim3(256), 0, st, nv,
+                           B.vk[cur], B.vv[cur], B.vk[cur ^ 1], B.vv[cur ^ 1], cnt_buf[cur], cnt_buf[cur ^ 1], 18,
+                           B.hist, B.max_blocks, B.digit, po);
+        cur ^= 1;
+    }
+    const uint32_t *vis_off = cnt_buf[cur];
     const int64_t persistent = 256 * 16;   // 16 workgroups per CU, grid-stride beyond
     const int64_t emit_chunks = (pair_cap + kEmitChunk - 1) / kEmitChunk;
     hipLaunchKernelGGL(emit_kernel, dim3(emit_chunks < persistent ? emit_chunks : persistent), dim3(256), 0, st,
-                       n_cap, n_views, targets, B.counters, B.vv[cur], B.voff, B.rects, B.view_off, B.view_list,
+                       n_cap, n_views, targets, B.counters, B.vv[cur], vis_off, B.rects, B.view_off, B.view_list,
                        B.chunk_first, pair_cap, B.pk[0], B.pv[0], d_status);
     // tile order
     const TileSortPlan plan = tile_sort_plan(total_tiles);
