@@ -140,7 +140,9 @@ struct SortLayout {
         L.pair_val0 = take(sizeof(uint32_t) * pair_cap);
         L.pair_val1 = take(sizeof(uint32_t) * pair_cap);
         L.ranges = take(sizeof(uint32_t) * 2 * (total_tiles > 0 ? total_tiles : 1));
-        L.bsum = take(sizeof(uint32_t) * (L.max_blocks + 1));
+        // block sums; also one visible-record count per workgroup of the count grid
+        const int64_t groups = n_views * ((n_cap + 255) / 256);
+        L.bsum = take(sizeof(uint32_t) * ((L.max_blocks > groups ? L.max_blocks : groups) + 1));
         L.hist = take(sizeof(uint32_t) * kRadixBinsMax * L.max_blocks);
         L.digit = take(sizeof(uint32_t) * ((kRadixBinsMax > kTileCountMax ? kRadixBinsMax : kTileCountMax) + 1));
         // first sorted record of every 256-pair emission chunk

@@ -125,6 +125,31 @@ __device__ __forceinline__ uint32_t rect_count(uint2 rc) {
     return w * h;
 }
 
+// Index of this workgroup in the count and compaction grids (n_cap / 256
+// rounded up, n_views) of 256-thread workgroups: workgroups in record order.
+__device__ __forceinline__ int64_t group_slot() {
+    return int64_t(blockIdx.y) * gridDim.x + blockIdx.x;
+}
+
+// Number of lanes of the workgroup where `flag` holds, summed over the waves
+// before this one (*before) and over all of them (returned).  Every thread
+// of the workgroup takes part.
+__device__ __forceinline__ uint32_t group_count(bool flag, uint32_t *lds4, uint32_t *before) {
+    const int wave = threadIdx.x / kWave;
+    const uint32_t c = uint32_t(__popcll(__ballot(flag)));
+    if (lane_id() == 0) lds4[wave] = c;
+    __syncthreads();
+    uint32_t b = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / kWave; ++w) {
+        const uint32_t x = lds4[w];
+        b += w < wave ? x : 0u;
+        all += x;
+    }
+    *before = b;
+    return all;
+}
+
 // For record (v, g): counts[v * n_cap + g] = its number of tiles over the
 // targets of view v, and its tile rectangle in the q-th target packed as
 // (x0 | x1 << 16, y0 | y1 << 16) (empty when it touches none) at
@@ -135,13 +160,14 @@ __global__ void __launch_bounds__(256) count_kernel(gs_settings s, Proj proj, in
                                                     const uint32_t *__restrict__ view_off,
                                                     const uint32_t *__restrict__ view_list,
                                                     uint32_t *__restrict__ counts,
-                                                    uint2 *__restrict__ rects) {
+                                                    uint2 *__restrict__ rects,
+                                                    uint32_t *__restrict__ group_vis) {
+    __shared__ uint32_t lds4[kScanThreads / kWave];
     const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int v = blockIdx.y;
-    if (g >= n_cap) return;
     const int64_t r = int64_t(v) * n_cap + g;
     uint32_t total = 0;
-    if (g < n) {
+    if (g < n) {   // (n <= n_cap)
         const double2 md = proj.mean[r];
         const float4 co = proj.cov_o[r];
         const uint32_t q0 = view_off[v], m = view_off[v + 1] - q0;
@@ -158,35 +184,15 @@ __global__ void __launch_bounds__(256) count_kernel(gs_settings s, Proj proj, in
             out[q] = packed;   // streamed for every record: cheaper than sparse writes
         }
     }
-    counts[r] = total;
+    if (g < n_cap) counts[r] = total;
+    uint32_t before;
+    const uint32_t vis = group_count(total != 0u, lds4, &before);
+    if (threadIdx.x == 0) group_vis[group_slot()] = vis;
 }
 
 // ---------------------------------------------------------------------------
-// Block-sum / scan machinery over blocks of kScanTile elements.  Element e of
-// block b is processed in round e / 256 by thread e % 256, so loads are
-// coalesced and the block order is the element order.
+// Scan helpers
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int64_t active_blocks(uint32_t n) {
-    return (int64_t(n) + kScanTile - 1) / kScanTile;
-}
-
-// Per-block sum of f(e) for e < n; f is a value functor.
-template <typename F>
-__device__ __forceinline__ void block_reduce_to(uint32_t n, uint32_t *bsum, F f) {
-    __shared__ uint32_t lds[8];
-    const int64_t base = int64_t(blockIdx.x) * kScanTile;
-    if (base >= n) return;
-    uint32_t acc = 0;
-#pragma unroll 4
-    for (int k = 0; k < kScanItems; ++k) {
-        const int64_t e = base + k * kScanThreads + threadIdx.x;
-        if (e < n) acc += f(e);
-    }
-    uint32_t total;
-    block_exclusive_scan(acc, lds, &total);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
-}
-
 // 64-bit wave scans for the pair offsets: a sum of per-record pair counts may
 // pass 2^32, and is then saturated (a total past pair_cap <= 2^31 - 1 is an
 // overflow, reported as such) instead of wrapping.
@@ -223,60 +229,58 @@ __device__ __forceinline__ uint64_t block_exclusive_scan64(uint64_t v, uint64_t 
     return base + inc - v;
 }
 
-// Exclusive scan of bsum[0..nb) in place (one block of 1024 threads); the
-// total goes to *total_out.  Sums are formed in 64 bits and stored saturated
-// at 2^32 - 1.
-__global__ void __launch_bounds__(1024) scan_bsums_kernel(const uint32_t *__restrict__ n_ptr,
-                                                          uint32_t *bsum, uint32_t *total_out,
-                                                          int64_t n_fixed) {
-    __shared__ uint64_t lds[16];
-    const uint32_t n = n_ptr ? *n_ptr : uint32_t(n_fixed);
-    const int64_t nb = active_blocks(n);
-    const int64_t per = (nb + 1023) / 1024;
-    const int64_t lo = int64_t(threadIdx.x) * per;
-    uint64_t local = 0;
-    for (int64_t i = lo; i < lo + per && i < nb; ++i) local += bsum[i];
-    // block scan over 1024 threads (16 waves)
+// Exclusive scan of the per-workgroup visible-record counts bsum[0..nb) in
+// place (one block of 1024 threads); the total goes to *total_out.  Every
+// partial sum counts records, so it fits 32 bits.  Wave w takes the w-th of
+// 16 consecutive runs of 64-entry chunks, its lanes reading consecutive
+// entries; chunks are loaded kBsumBatch at a time.
+constexpr int kBsumWaves = 16, kBsumBatch = 16;
+__global__ void __launch_bounds__(kBsumWaves * kWave) scan_bsums_kernel(uint32_t *bsum, int64_t nb,
+                                                                       uint32_t *total_out) {
+    __shared__ uint32_t lds[kBsumWaves];
     const int lane = lane_id(), wave = threadIdx.x / kWave;
-    const uint64_t inc = wave_inclusive_scan64(local);
-    if (lane == kWave - 1) lds[wave] = inc;
+    const int64_t chunks = (nb + kWave - 1) / kWave;
+    const int64_t per = (chunks + kBsumWaves - 1) / kBsumWaves;   // chunks per wave
+    const int64_t c0 = wave * per, c1 = c0 + per < chunks ? c0 + per : chunks;
+    uint32_t local = 0;
+    for (int64_t c = c0; c < c1; c += kBsumBatch) {
+        uint32_t v[kBsumBatch];
+#pragma unroll
+        for (int j = 0; j < kBsumBatch; ++j) {
+            const int64_t i = (c + j) * kWave + lane;
+            v[j] = (c + j < c1 && i < nb) ? bsum[i] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kBsumBatch; ++j) local += v[j];
+    }
+    const uint32_t wtotal = wave_sum(local);
+    if (lane == 0) lds[wave] = wtotal;
     __syncthreads();
-    uint64_t wbase = 0, all = 0;
-    for (int w = 0; w < 16; ++w) {
-        const uint64_t v = lds[w];
-        wbase += (w < wave) ? v : 0u;
-        all += v;
+    uint32_t run = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < kBsumWaves; ++w) {
+        const uint32_t x = lds[w];
+        run += w < wave ? x : 0u;
+        all += x;
     }
-    uint64_t run = wbase + inc - local;
-    for (int64_t i = lo; i < lo + per && i < nb; ++i) {
-        const uint32_t v = bsum[i];
-        bsum[i] = sat32(run);
-        run += v;
+    for (int64_t c = c0; c < c1; c += kBsumBatch) {
+        uint32_t v[kBsumBatch];
+#pragma unroll
+        for (int j = 0; j < kBsumBatch; ++j) {
+            const int64_t i = (c + j) * kWave + lane;
+            v[j] = (c + j < c1 && i < nb) ? bsum[i] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kBsumBatch; ++j) {
+            const int64_t i = (c + j) * kWave + lane;
+            const uint32_t inc = wave_inclusive_scan(v[j]);
+            if (c + j < c1 && i < nb) bsum[i] = run + inc - v[j];
+            run += uint32_t(__builtin_amdgcn_readlane(int(inc), kWave - 1));
+        }
     }
-    if (threadIdx.x == 0) *total_out = sat32(all);
+    if (threadIdx.x == 0) *total_out = all;
 }
 
-// Compaction of visible sources: flags from counts, values = source index,
-// keys = depth bits (positive floats order like their bit patterns).
-__global__ void __launch_bounds__(256) compact_reduce_kernel(const uint32_t *__restrict__ counts,
-                                                             int64_t S, uint32_t *bsum) {
-    block_reduce_to(uint32_t(S), bsum, [&](int64_t e) { return counts[e] ? 1u : 0u; });
-}
-
-// Scatter side of the two block scans below.  Element e = base + k * 256 +
-// t (k < kScanItems) is read by thread t in round k, so loads and stores are
-// coalesced; ranks inside a wave come from a wave scan (or a ballot), and the
-// (round, wave) totals, in element order, are scanned by one wave.
-__device__ __forceinline__ void round_wave_offsets(uint32_t (*wtot)[kScanThreads / kWave]) {
-    __syncthreads();
-    if (threadIdx.x < kWave) {
-        const int lane = threadIdx.x, k = lane / (kScanThreads / kWave), w = lane % (kScanThreads / kWave);
-        const uint32_t v = wtot[k][w];
-        wtot[k][w] = wave_inclusive_scan(v) - v;
-    }
-    __syncthreads();
-}
-static_assert(kScanItems * (kScanThreads / kWave) == kWave, "one wave scans the round totals");
 
 // Depth sort key of a visible record: the bit pattern of its (positive,
 // float) depth minus that of the near plane, which orders depths exactly as
@@ -290,36 +294,28 @@ __device__ __forceinline__ uint32_t depth_key(float z, float znear) {
     return d < (1u << kDepthKeyBits) ? d : (1u << kDepthKeyBits) - 1u;
 }
 
+// Compaction of the visible records (pair count > 0) in record order: keys =
+// depth keys, values = record indices, and the counts alongside.  Same grid
+// as count_kernel; a workgroup's records land after those of the workgroups
+// before it (group_vis after its exclusive scan) in thread order.
 __global__ void __launch_bounds__(256) compact_scatter_kernel(const uint32_t *__restrict__ counts,
-                                                              int64_t S, Proj proj, float znear,
-                                                              const uint32_t *__restrict__ bsum,
+                                                              int64_t n_cap, Proj proj, float znear,
+                                                              const uint32_t *__restrict__ group_vis,
                                                               uint32_t *__restrict__ vis_key,
                                                               uint32_t *__restrict__ vis_val,
                                                               uint32_t *__restrict__ vis_cnt) {
-    __shared__ uint32_t wtot[kScanItems][kScanThreads / kWave];
-    const int64_t base = int64_t(blockIdx.x) * kScanTile;
-    if (base >= S) return;
-    const int wave = threadIdx.x / kWave, lane = lane_id();
-    uint64_t masks[kScanItems];
-    uint32_t c[kScanItems];
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const int64_t e = base + k * kScanThreads + threadIdx.x;
-        c[k] = e < S ? counts[e] : 0u;
-        masks[k] = __ballot(c[k] != 0u);
-        if (lane == 0) wtot[k][wave] = uint32_t(__popcll(masks[k]));
-    }
-    round_wave_offsets(wtot);
-    const uint32_t b0 = bsum[blockIdx.x];
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        if ((masks[k] >> lane) & 1u) {
-            const int64_t e = base + k * kScanThreads + threadIdx.x;
-            const uint32_t at = b0 + wtot[k][wave] + uint32_t(mask_rank(masks[k]));
-            vis_key[at] = depth_key(proj.rgb_z[e].w, znear);
-            vis_val[at] = uint32_t(e);
-            vis_cnt[at] = c[k];
-        }
+    __shared__ uint32_t lds4[kScanThreads / kWave];
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t r = int64_t(blockIdx.y) * n_cap + g;
+    const uint32_t c = g < n_cap ? counts[r] : 0u;
+    uint32_t before;
+    group_count(c != 0u, lds4, &before);
+    const uint64_t mask = __ballot(c != 0u);
+    if (c != 0u) {
+        const uint32_t at = group_vis[group_slot()] + before + uint32_t(mask_rank(mask));
+        vis_key[at] = depth_key(proj.rgb_z[r].w, znear);
+        vis_val[at] = uint32_t(r);
+        vis_cnt[at] = c;
     }
 }
 
@@ -1262,18 +1258,17 @@ extern "C" gs_status gs_bin_sort(const gs_settings *s, const void *proj_ws, int6
     hipLaunchKernelGGL(sort_setup_kernel, dim3((int64_t(total_tiles) + 255) / 256), dim3(256), 0, st, targets,
                        n_targets, n_views, B.counters, B.view_off, B.view_list, B.ranges, int64_t(total_tiles),
                        B.queue);
-    hipLaunchKernelGGL(count_kernel, dim3((n_cap + 255) / 256, n_views), dim3(256), 0, st, *s, proj, n, n_cap,
-                       targets, B.view_off, B.view_list, B.counts, B.rects);
-    // compact visible records
-    const int64_t sblocks = (S + kScanTile - 1) / kScanTile;
-    hipLaunchKernelGGL(compact_reduce_kernel, dim3(sblocks), dim3(256), 0, st, B.counts, S, B.bsum);
-    hipLaunchKernelGGL(scan_bsums_kernel, dim3(1), dim3(1024), 0, st, nullptr, B.bsum,
-                       B.counters + kVisible, S);
+    const int64_t cgx = (n_cap + 255) / 256;   // count / compaction grid: (cgx, n_views)
+    hipLaunchKernelGGL(count_kernel, dim3(cgx, n_views), dim3(256), 0, st, *s, proj, n, n_cap, targets, B.view_off,
+                       B.view_list, B.counts, B.rects, B.bsum);
+    // compact visible records: the count kernel left each workgroup's number
+    // of visible records in bsum; their exclusive scan places the workgroups
+    hipLaunchKernelGGL(scan_bsums_kernel, dim3(1), dim3(1024), 0, st, B.bsum, cgx * n_views, B.counters + kVisible);
     // the visible records' pair counts move with them through compaction and
     // the depth sort, in two S-sized buffers that are free meanwhile: vis_off
-    // (written only after the sort) and counts (read only by the compaction)
+    // (written by no other step) and counts (read only by the compaction)
     uint32_t *cnt_buf[2] = {B.voff, B.counts};
-    hipLaunchKernelGGL(compact_scatter_kernel, dim3(sblocks), dim3(256), 0, st, B.counts, S, proj, s->znear,
+    hipLaunchKernelGGL(compact_scatter_kernel, dim3(cgx, n_views), dim3(256), 0, st, B.counts, n_cap, proj, s->znear,
                        B.bsum, B.vk[0], B.vv[0], cnt_buf[0]);
     // depth order (three 9-bit passes over the 27-bit keys); the last pass
     // also turns the pair counts into pair offsets (in `counts`), writes the
