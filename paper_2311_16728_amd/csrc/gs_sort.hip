@@ -344,6 +344,9 @@ constexpr int kEmitTab = 256;   // views and listed targets staged in LDS
 
 // 64 VGPRs: eight waves per SIMD for this latency-bound kernel (66 and seven
 // waves otherwise, measured slower in spite of a small spill)
+// kOne: a single target in the call, so every visible record has exactly one
+// rectangle, rects[g] with g = record - target view * n_cap.
+template <bool kOne>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
 emit_kernel(int64_t n_cap, int32_t n_views, const gs_target *__restrict__ targets,
             uint32_t *__restrict__ counters,
@@ -374,7 +377,13 @@ emit_kernel(int64_t n_cap, int32_t n_views, const gs_target *__restrict__ target
     const int tid = threadIdx.x;
     // lim_v / lim_t entries are in LDS, the rest in global memory
     uint32_t lim_v = 0, lim_t = 0;
-    {
+    uint32_t one_toff = 0, one_tx = 0, one_vbase = 0;   // kOne: the target
+    if (kOne) {
+        const gs_target t0 = targets[0];
+        one_toff = uint32_t(t0.tile_offset);
+        one_tx = uint32_t(t0.tiles_x);
+        one_vbase = uint32_t(t0.view) * uint32_t(n_cap);   // (records are indexed by uint32)
+    } else {
         const int nv = n_views < kEmitTab ? n_views : kEmitTab;
         for (int i = tid; i <= nv; i += kScanThreads) s_voff[i] = view_off[i];
         const uint32_t listed = view_off[n_views];   // targets in the lists
@@ -441,6 +450,21 @@ emit_kernel(int64_t n_cap, int32_t n_views, const gs_target *__restrict__ target
             key[i] = 0u;
             val[i] = 0u;
             if (o >= Pc) continue;
+            if (kOne) {
+                if (rec != cur) {
+                    cur = rec;
+                    src = srcs[rec];
+                    base = off[rec];
+                    rcc[0] = rects[src - one_vbase];
+                }
+                const uint32_t k = o - base;
+                const uint32_t x0 = rcc[0].x & 0xffffu, x1 = rcc[0].x >> 16, y0 = rcc[0].y & 0xffffu;
+                uint32_t dy, dx;
+                divmod_small(k, x1 - x0 + 1, dy, dx);
+                key[i] = one_toff + (y0 + dy) * one_tx + x0 + dx;
+                val[i] = src;
+                continue;
+            }
             if (rec != cur) {   // first slot of this thread in a record
                 cur = rec;
                 src = srcs[rec];   // record v * n_cap + g
@@ -1293,9 +1317,15 @@ extern "C" gs_status gs_bin_sort(const gs_settings *s, const void *proj_ws, int6
     const uint32_t *vis_off = cnt_buf[cur];
     const int64_t persistent = 256 * 16;   // 16 workgroups per CU, grid-stride beyond
     const int64_t emit_chunks = (pair_cap + kEmitChunk - 1) / kEmitChunk;
-    hipLaunchKernelGGL(emit_kernel, dim3(emit_chunks < persistent ? emit_chunks : persistent), dim3(256), 0, st,
-                       n_cap, n_views, targets, B.counters, B.vv[cur], vis_off, B.rects, B.view_off, B.view_list,
-                       B.chunk_first, pair_cap, B.pk[0], B.pv[0], d_status);
+    const dim3 egrid(emit_chunks < persistent ? emit_chunks : persistent);
+    if (n_targets == 1)
+        hipLaunchKernelGGL(emit_kernel<true>, egrid, dim3(256), 0, st, n_cap, n_views, targets, B.counters,
+                           B.vv[cur], vis_off, B.rects, B.view_off, B.view_list, B.chunk_first, pair_cap, B.pk[0],
+                           B.pv[0], d_status);
+    else
+        hipLaunchKernelGGL(emit_kernel<false>, egrid, dim3(256), 0, st, n_cap, n_views, targets, B.counters,
+                           B.vv[cur], vis_off, B.rects, B.view_off, B.view_list, B.chunk_first, pair_cap, B.pk[0],
+                           B.pv[0], d_status);
     // tile order
     const TileSortPlan plan = tile_sort_plan(total_tiles);
     if (plan.counting) {   // one pass, pairs pk[0] / pv[0] -> values pv[1] and the ranges
