@@ -241,16 +241,28 @@ def efficiency_ratios(plan, composited, evaluated):
     return out
 
 
-def cpu_baseline(p, n, cams, target_np, frac, seed=0):
-    """The FP64 oracle on the host: one mapping iteration estimated from a random
-    pixel sample (render + backward on `frac` of the pixels, loss and Adam in
-    full); per-call set-up (projection of all Gaussians, candidate bins) is timed
-    separately and counted once per call."""
+def cpu_model() -> str:
+    """The host CPU's model name."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def oracle_iteration(p, n, cam, target_np, frac, rng):
+    """Times one oracle mapping iteration from a random pixel sample (render +
+    backward on `frac` of the pixels, loss and Adam in full); per-call set-up
+    (projection of all Gaussians, candidate bins) is timed separately and
+    counted once per call.  Returns (seconds per iteration, seconds per render,
+    set-up seconds, sampled fraction, seconds spent)."""
     import oracle
 
-    cam = cams[0]
     H, W = cam["height"], cam["width"]
-    rng = np.random.default_rng(seed)
     mask = (rng.uniform(size=(H, W)) < frac).astype(np.uint8)
     empty = np.zeros((H, W), np.uint8)
     t0 = time.perf_counter()
@@ -270,17 +282,37 @@ def cpu_baseline(p, n, cams, target_np, frac, seed=0):
     t0 = time.perf_counter()
     oracle.adam(p, g, np.zeros_like(g), np.zeros_like(g), n, np.full(59, 1e-3), 1)
     t_adam = time.perf_counter() - t0
-    f = mask.mean()
+    f = float(mask.mean())
     t_iter = 2 * t_setup + (t_render - t_setup) / f + (t_bwd - t_setup) / f + t_loss + t_adam
     t_render_full = t_setup + (t_render - t_setup) / f
-    sampled = t_setup * 3 + t_render + t_bwd + t_loss + t_adam
-    return dict(value=1.0 / t_iter, unit="iters/s", cores=oracle.num_threads(), kind="oracle",
-                render_fps=1.0 / t_render_full,
+    spent = t_setup * 3 + t_render + t_bwd + t_loss + t_adam
+    return t_iter, t_render_full, t_setup, f, spent
+
+
+def cpu_baseline(p, n, cams, target_np, frac, seed=0):
+    """The FP64 oracle on the host, with all of its threads and with one: one
+    mapping iteration estimated from random pixel samples (oracle_iteration;
+    the one-thread sample is an eighth as large)."""
+    import oracle
+
+    rng = np.random.default_rng(seed)
+    threads = oracle.num_threads()
+    t_iter, t_render_full, t_setup, f, spent = oracle_iteration(p, n, cams[0], target_np, frac, rng)
+    oracle.set_threads(1)
+    try:
+        t1, _, t1_setup, f1, spent1 = oracle_iteration(p, n, cams[0], target_np, frac / 8, rng)
+    finally:
+        oracle.set_threads(threads)
+    return dict(value=1.0 / t_iter, unit="iters/s", cores=threads, kind="oracle",
+                render_fps=1.0 / t_render_full, cpu_model=cpu_model(),
+                single_thread={"value": 1.0 / t1, "unit": "iters/s", "cores": 1,
+                               "sample": f"random {100 * f1:.2f}% pixel sample, set-up {t1_setup:.2f} s, "
+                                         f"{spent1:.1f} s of CPU work"},
                 sample=("FP64 oracle, one iteration at the same workload: render and backward "
                         + ("over the whole image" if f >= 1.0 else
                            f"on a random {100 * f:.1f}% pixel sample scaled to the full image")
                         + f", loss and Adam in full, projection/binning set-up {t_setup:.2f} s per call "
-                          f"counted once; {sampled:.1f} s of CPU work"))
+                          f"counted once; {spent:.1f} s of CPU work"))
 
 
 def iteration_roofline(n, plan, composited, ms_step):
@@ -289,14 +321,15 @@ def iteration_roofline(n, plan, composited, ms_step):
     operations at the unpacked vector rate (256 CUs x 64 lanes x 2.4 GHz =
     39.3 T lane-op/s).  Bytes: chain rule + Adam 1416 B per Gaussian (read
     and write parameters, m and v); ground truth 12 B per pixel; pairs 8 B written at emission plus
-    two radix passes of 4 B (histogram) + 16 B (scatter).  Lane operations:
+    one counting pass over the tiles (4 B read by its histogram, 8 B read and
+    4 B written by its scatter).  Lane operations:
     18 per composited pair forward, 55 backward, ~330 per pixel for the loss
     (five moments with two 11-tap passes per channel, forward and backward)."""
     lane_rate = 256 * 64 * 2.4e9
     bw = HBM_PEAK_GBS * 1e9
     pairs = plan.pair_count()
     terms = {
-        "bin_sort": (8.0 + 2 * 20.0) * pairs / bw,
+        "bin_sort": (8.0 + 4.0 + 12.0) * pairs / bw,
         "render_fwd": 18.0 * composited / lane_rate,
         "loss": max(12.0 * plan.total_pixels / bw, 330.0 * 3 * plan.total_pixels / lane_rate),
         "raster_bwd": 55.0 * composited / lane_rate,

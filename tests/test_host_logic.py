@@ -100,3 +100,21 @@ def test_tile_shapes_in_layout():
         gs.gs_targets_layout(views, [(0, 0, (0, 0, 0), 1.0)], 12)
     with pytest.raises(gs.GsError):
         gs.gs_targets_layout(views, [(0, 0, (0, 0, 0), 1.0)], 64)
+
+
+def test_cpu_baseline_reports_threads_model_and_single_thread_rate():
+    """The oracle baseline of the benchmark line names the CPU and reports a
+    one-thread rate beside the all-threads one (tiny scene, whole image)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    import oracle
+
+    p, _, cam = scenes.tiny_scene(0, n=300)
+    target = np.zeros((3, cam["height"], cam["width"]))
+    threads = oracle.num_threads()
+    out = bench.cpu_baseline(p, 300, [cam], target, 1.0)
+    assert oracle.num_threads() == threads   # restored after the one-thread run
+    assert out["kind"] == "oracle" and out["cores"] == threads and out["value"] > 0
+    assert isinstance(out["cpu_model"], str) and out["cpu_model"]
+    st = out["single_thread"]
+    assert st["cores"] == 1 and st["value"] > 0 and st["unit"] == "iters/s"
