@@ -977,7 +977,12 @@ __global__ void __launch_bounds__(kColWaves * kWave) tile_colscan_kernel(const u
 // the lowest lane of a group adding the group's size (the radix scatter's
 // scheme).  A pair's slot = start of its tile + count of its tile in earlier
 // blocks (hist after the column scan) + in earlier waves of its block + its
-// rank in its wave.  All loads of a block are issued before the first wait.
+// rank in its wave.  The values are then laid out in LDS in slot order with
+// their slots, and written by consecutive threads: each tile's run of the
+// block goes out as consecutive addresses.  All loads of a block are issued
+// before the first wait.  LDS: one 64 KB pool holding the tile starts, the
+// per-wave counts and the tags while ranking, then the block-local tile
+// starts, then the staged values and slots.
 __global__ void __launch_bounds__(256) tile_scatter_kernel(
     const uint32_t *__restrict__ n_ptr, const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     uint32_t *__restrict__ vout, int32_t total_tiles, int64_t stride, int bits,
@@ -985,9 +990,17 @@ __global__ void __launch_bounds__(256) tile_scatter_kernel(
     constexpr int kWaves = kScanThreads / kWave, kPer = kTileCountMax / kScanThreads;
     constexpr int kWaveN = kTileSortItems * kWave;
     static_assert(kTileSortN < (1 << 16), "a block's counts fit 16 bits");
-    __shared__ uint32_t bstart[kTileCountMax];          // first slot of each tile's run of this block
-    __shared__ uint32_t wc[kWaves][kTileCountMax / 2];  // per-wave counts, then offsets (16-bit fields)
-    __shared__ uint8_t tags[kWaves][kTileCountMax];     // per-wave tile tags (lane numbers)
+    __shared__ uint32_t pool[2 * kTileSortN];
+    static_assert(kTileCountMax + kWaves * kTileCountMax / 2 + kWaves * kTileCountMax / 4 == 2 * kTileSortN,
+                  "pool layout");
+    uint32_t *bstart = pool;                              // first slot of each tile's run of this block
+    uint32_t (*wc)[kTileCountMax / 2] =                   // per-wave counts, then offsets (16-bit fields)
+        reinterpret_cast<uint32_t (*)[kTileCountMax / 2]>(pool + kTileCountMax);
+    uint32_t *tag_words = pool + kTileCountMax + kWaves * kTileCountMax / 2;
+    uint8_t (*tags)[kTileCountMax] =                      // per-wave tile tags (lane numbers) ...
+        reinterpret_cast<uint8_t (*)[kTileCountMax]>(tag_words);
+    uint32_t *lstart = tag_words;                         // ... then block-local tile starts
+    uint32_t *sval = pool, *sdst = pool + kTileSortN;     // finally the values in slot order
     __shared__ uint32_t lds[8];
     const uint32_t n = *n_ptr;
     const int tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
@@ -1100,25 +1113,58 @@ __global__ void __launch_bounds__(256) tile_scatter_kernel(
         }
         __syncthreads();
         // per-wave counts -> counts of the earlier waves (both fields at once:
-        // a field's sum stays below 2^16)
-        for (int i = tid; i < half; i += kScanThreads) {
-            uint32_t r = 0u;
+        // a field's sum stays below 2^16), and the block-local start of every
+        // tile (thread tid takes words [8 tid, 8 tid + 8): tiles 16 tid ...)
+        constexpr int kWords = kTileCountMax / 2 / kScanThreads;
+        uint32_t placed;   // the block's pairs with a valid tile
+        {
+            uint32_t tot[kWords], sum = 0u;
 #pragma unroll
-            for (int w = 0; w < kWaves; ++w) {
-                const uint32_t c = wc[w][i];
-                wc[w][i] = r;
-                r += c;
+            for (int j = 0; j < kWords; ++j) {
+                const int i = tid * kWords + j;
+                uint32_t r = 0u;
+                if (i < half) {
+#pragma unroll
+                    for (int w = 0; w < kWaves; ++w) {
+                        const uint32_t c = wc[w][i];
+                        wc[w][i] = r;
+                        r += c;
+                    }
+                }
+                tot[j] = r;
+                sum += (r & 0xffffu) + (r >> 16);
+            }
+            uint32_t pre = block_exclusive_scan(sum, lds, &placed);   // (barriers inside)
+#pragma unroll
+            for (int j = 0; j < kWords; ++j) {
+                const int i = tid * kWords + j;
+                lstart[2 * i] = pre;
+                pre += tot[j] & 0xffffu;
+                lstart[2 * i + 1] = pre;
+                pre += tot[j] >> 16;
             }
         }
         __syncthreads();
+        uint32_t li[kTileSortItems];   // slot inside the block's staging
 #pragma unroll
         for (int k = 0; k < kTileSortItems; ++k) {
             const uint32_t d = key[k];
             if (d < nt) {
                 const uint32_t before = (wc[wave][d >> 1] >> ((d & 1u) * 16u)) & 0xffffu;
-                vout[bstart[d] + before + pos[k]] = val[k];
+                li[k] = lstart[d] + before + pos[k];
+                pos[k] = bstart[d] + before + pos[k];   // the global slot
             }
         }
+        __syncthreads();   // the pool is free: stage the values in slot order
+#pragma unroll
+        for (int k = 0; k < kTileSortItems; ++k) {
+            if (key[k] < nt) {
+                sval[li[k]] = val[k];
+                sdst[li[k]] = pos[k];
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < placed; i += kScanThreads) vout[sdst[i]] = sval[i];
         __syncthreads();   // LDS reads done before the next block's writes
     }
 }
