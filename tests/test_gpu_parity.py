@@ -122,20 +122,39 @@ def test_render_background_and_empty(orc):
     assert np.all(plan.plane(plan.T, 0).cpu().numpy() == 1.0)
 
 
-@pytest.mark.parametrize("case", ["tiny", "degenerate"])
+def _tile_order_result(tiles: int) -> str:
+    """Pair buffer that holds the tile-ordered values: one counting pass up to
+    4096 tiles, else radix passes over the tile index (8-bit digits, or 9-bit
+    ones where they save a pass); an odd number of passes ends in pv1."""
+    if tiles <= 4096:
+        return "pv1"
+    bits = max(1, int(np.ceil(np.log2(tiles))))
+    passes = min((bits + 7) // 8, (bits + 8) // 9)
+    return "pv1" if passes & 1 else "pv0"
+
+
+@pytest.mark.parametrize("case", ["tiny", "degenerate", "tiles4096", "tiles4225"])
 def test_tile_lists_sorted_and_complete(orc, case):
     """Every tile list is in (depth, index) order without repeats and holds every
     Gaussian the oracle composites at any of the tile's pixels (exact depth ties
-    of the degenerate scene in index order)."""
+    of the degenerate scene in index order).  tiles4096 / tiles4225: the tiny
+    scene seen at 1024 x 1024 (the largest grid of the one-pass tile counting
+    sort) and 1040 x 1040 (the smallest beyond it, radix passes)."""
     if case == "tiny":
         p, _, cam = scenes.tiny_scene(1)
         n = 2000
+    elif case.startswith("tiles"):
+        p, _, _ = scenes.tiny_scene(1)
+        n = 2000
+        w = 1024 if case == "tiles4096" else 1040
+        cam = scenes.pinhole(w, w, float(w))
     else:
         p, cam, kinds = scenes.degenerate_scene(0)
         n = kinds.size
-    plan = plan_for([cam], n_cap=p.shape[1])
+    plan = plan_for([cam], n_cap=p.shape[1], pair_cap=1 << 22)
     plan.render(_dev(p), n)
     torch.cuda.synchronize()
+    assert not plan.overflowed()
     from paper_2311_16728_amd import gs as _g  # noqa: F401
 
     rec = orc.preprocess(p, n, cam)
@@ -154,8 +173,7 @@ def test_tile_lists_sorted_and_complete(orc, case):
     ws = plan.sort_ws.cpu()
     npairs = int(ws[offs["counters"]:offs["counters"] + 64].view(torch.int32)[2])
     tt = plan.total_tiles
-    passes = 1 if tt <= 256 else 2          # 8-bit radix passes over tile indices
-    key = "pv1" if passes & 1 else "pv0"
+    key = _tile_order_result(tt)
     vals = ws[offs[key]:offs[key] + 4 * plan.pair_cap].view(torch.int32).numpy()
     ranges = ws[offs["ranges"]:offs["ranges"] + 8 * tt].view(torch.int32).numpy().reshape(tt, 2)
     assert ranges[:, 1].max() == npairs
@@ -163,7 +181,12 @@ def test_tile_lists_sorted_and_complete(orc, case):
     tx_n = (W + 15) // 16
     rng = np.random.default_rng(0)
     ties = 0
-    for tile in (rng.choice(tt, size=12, replace=False) if case == "tiny" else range(tt)):
+    picks = rng.choice(tt, size=12, replace=False)
+    if case.startswith("tiles"):
+        assert tt == (4096 if case == "tiles4096" else 4225)
+        busy = np.flatnonzero(ranges[:, 1] > ranges[:, 0])
+        picks = np.concatenate([rng.choice(busy, size=12, replace=False), picks[:4]])
+    for tile in (range(tt) if case == "degenerate" else picks):
         a, b = ranges[tile]
         ids = vals[a:b] % plan.n_cap
         assert len(set(ids.tolist())) == len(ids)
