@@ -155,25 +155,42 @@ __device__ __forceinline__ uint32_t group_count(bool flag, uint32_t *lds4, uint3
 // (x0 | x1 << 16, y0 | y1 << 16) (empty when it touches none) at
 // rects[view_off[v] * n_cap + g * m_v + q] (m_v targets in view v: a record's
 // rectangles are adjacent).
+// kOne: a single target in the call.  Its view's list is that target, and
+// the count kernel also does the set-up's other work (counters, the work
+// queue and the tile ranges to zero), so no set-up kernel runs.
+template <bool kOne>
 __global__ void __launch_bounds__(256) count_kernel(gs_settings s, Proj proj, int64_t n, int64_t n_cap,
                                                     const gs_target *__restrict__ targets,
                                                     const uint32_t *__restrict__ view_off,
                                                     const uint32_t *__restrict__ view_list,
                                                     uint32_t *__restrict__ counts,
                                                     uint2 *__restrict__ rects,
-                                                    uint32_t *__restrict__ group_vis) {
+                                                    uint32_t *__restrict__ group_vis,
+                                                    uint32_t *__restrict__ counters, uint32_t *__restrict__ queue,
+                                                    uint2 *__restrict__ ranges, int64_t total_tiles) {
     __shared__ uint32_t lds4[kScanThreads / kWave];
     const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int v = blockIdx.y;
     const int64_t r = int64_t(v) * n_cap + g;
+    int one_view = -1;   // kOne: the target's view (-1: outside [0, n_views), no list)
+    if (kOne) {
+        const int64_t gid = group_slot() * blockDim.x + threadIdx.x;
+        const int64_t nthreads = int64_t(gridDim.x) * gridDim.y * blockDim.x;
+        for (int64_t i = gid; i < total_tiles; i += nthreads) ranges[i] = make_uint2(0u, 0u);
+        if (gid < kNumCounters) counters[gid] = 0u;
+        if (gid < kQueueWords) queue[gid] = 0u;
+        const int tv = targets[0].view;
+        one_view = (tv >= 0 && tv < int(gridDim.y)) ? tv : -1;
+    }
     uint32_t total = 0;
     if (g < n) {   // (n <= n_cap)
         const double2 md = proj.mean[r];
         const float4 co = proj.cov_o[r];
-        const uint32_t q0 = view_off[v], m = view_off[v + 1] - q0;
+        const uint32_t q0 = kOne ? uint32_t(one_view >= 0 && v > one_view) : view_off[v];
+        const uint32_t m = kOne ? uint32_t(v == one_view) : view_off[v + 1] - q0;
         uint2 *out = rects + int64_t(q0) * n_cap + g * m;
         for (uint32_t q = 0; q < m; ++q) {
-            const gs_target t = targets[view_list[q0 + q]];
+            const gs_target t = targets[kOne ? 0u : view_list[q0 + q]];
             Rect rc;
             uint2 packed = make_uint2(kEmptyRectX, 0u);
             if (tile_rect(s, md, co, t, rc)) {
@@ -233,7 +250,8 @@ __device__ __forceinline__ uint64_t block_exclusive_scan64(uint64_t v, uint64_t 
 // place (one block of 1024 threads); the total goes to *total_out.  Every
 // partial sum counts records, so it fits 32 bits.  Wave w takes the w-th of
 // 16 consecutive runs of 64-entry chunks, its lanes reading consecutive
-// entries; chunks are loaded kBsumBatch at a time.
+// entries.  Runs of up to kBsumBatch chunks are loaded once and kept in
+// registers; longer ones are read twice, kBsumBatch chunks at a time.
 constexpr int kBsumWaves = 16, kBsumBatch = 16;
 __global__ void __launch_bounds__(kBsumWaves * kWave) scan_bsums_kernel(uint32_t *bsum, int64_t nb,
                                                                        uint32_t *total_out) {
@@ -242,40 +260,56 @@ __global__ void __launch_bounds__(kBsumWaves * kWave) scan_bsums_kernel(uint32_t
     const int64_t chunks = (nb + kWave - 1) / kWave;
     const int64_t per = (chunks + kBsumWaves - 1) / kBsumWaves;   // chunks per wave
     const int64_t c0 = wave * per, c1 = c0 + per < chunks ? c0 + per : chunks;
-    uint32_t local = 0;
-    for (int64_t c = c0; c < c1; c += kBsumBatch) {
-        uint32_t v[kBsumBatch];
+    auto load = [&](int64_t c, uint32_t (&v)[kBsumBatch]) {
 #pragma unroll
         for (int j = 0; j < kBsumBatch; ++j) {
             const int64_t i = (c + j) * kWave + lane;
             v[j] = (c + j < c1 && i < nb) ? bsum[i] : 0u;
         }
-#pragma unroll
-        for (int j = 0; j < kBsumBatch; ++j) local += v[j];
-    }
-    const uint32_t wtotal = wave_sum(local);
-    if (lane == 0) lds[wave] = wtotal;
-    __syncthreads();
-    uint32_t run = 0, all = 0;
-#pragma unroll
-    for (int w = 0; w < kBsumWaves; ++w) {
-        const uint32_t x = lds[w];
-        run += w < wave ? x : 0u;
-        all += x;
-    }
-    for (int64_t c = c0; c < c1; c += kBsumBatch) {
-        uint32_t v[kBsumBatch];
-#pragma unroll
-        for (int j = 0; j < kBsumBatch; ++j) {
-            const int64_t i = (c + j) * kWave + lane;
-            v[j] = (c + j < c1 && i < nb) ? bsum[i] : 0u;
-        }
+    };
+    auto store = [&](int64_t c, const uint32_t (&v)[kBsumBatch], uint32_t &run) {
 #pragma unroll
         for (int j = 0; j < kBsumBatch; ++j) {
             const int64_t i = (c + j) * kWave + lane;
             const uint32_t inc = wave_inclusive_scan(v[j]);
             if (c + j < c1 && i < nb) bsum[i] = run + inc - v[j];
             run += uint32_t(__builtin_amdgcn_readlane(int(inc), kWave - 1));
+        }
+    };
+    auto cross_waves = [&](uint32_t local, uint32_t &run, uint32_t &all) {
+        const uint32_t wtotal = wave_sum(local);
+        if (lane == 0) lds[wave] = wtotal;
+        __syncthreads();
+        run = 0u;
+        all = 0u;
+#pragma unroll
+        for (int w = 0; w < kBsumWaves; ++w) {
+            const uint32_t x = lds[w];
+            run += w < wave ? x : 0u;
+            all += x;
+        }
+    };
+    uint32_t run, all;
+    if (per <= kBsumBatch) {   // uniform: every wave holds its run
+        uint32_t v[kBsumBatch], local = 0u;
+        load(c0, v);
+#pragma unroll
+        for (int j = 0; j < kBsumBatch; ++j) local += v[j];
+        cross_waves(local, run, all);
+        store(c0, v, run);
+    } else {
+        uint32_t local = 0u;
+        for (int64_t c = c0; c < c1; c += kBsumBatch) {
+            uint32_t v[kBsumBatch];
+            load(c, v);
+#pragma unroll
+            for (int j = 0; j < kBsumBatch; ++j) local += v[j];
+        }
+        cross_waves(local, run, all);
+        for (int64_t c = c0; c < c1; c += kBsumBatch) {
+            uint32_t v[kBsumBatch];
+            load(c, v);
+            store(c, v, run);
         }
     }
     if (threadIdx.x == 0) *total_out = all;
@@ -1325,12 +1359,19 @@ extern "C" gs_status gs_bin_sort(const gs_settings *s, const void *proj_ws, int6
     SortBufs B = sort_bufs(sort_ws, n_views, n_targets, n_cap, pair_cap, total_tiles);
     Proj proj = proj_at(const_cast<void *>(proj_ws), S);
 
-    hipLaunchKernelGGL(sort_setup_kernel, dim3((int64_t(total_tiles) + 255) / 256), dim3(256), 0, st, targets,
-                       n_targets, n_views, B.counters, B.view_off, B.view_list, B.ranges, int64_t(total_tiles),
-                       B.queue);
     const int64_t cgx = (n_cap + 255) / 256;   // count / compaction grid: (cgx, n_views)
-    hipLaunchKernelGGL(count_kernel, dim3(cgx, n_views), dim3(256), 0, st, *s, proj, n, n_cap, targets, B.view_off,
-                       B.view_list, B.counts, B.rects, B.bsum);
+    if (n_targets == 1) {   // the set-up folded into the count kernel
+        hipLaunchKernelGGL(count_kernel<true>, dim3(cgx, n_views), dim3(256), 0, st, *s, proj, n, n_cap, targets,
+                           B.view_off, B.view_list, B.counts, B.rects, B.bsum, B.counters, B.queue, B.ranges,
+                           int64_t(total_tiles));
+    } else {
+        hipLaunchKernelGGL(sort_setup_kernel, dim3((int64_t(total_tiles) + 255) / 256), dim3(256), 0, st, targets,
+                           n_targets, n_views, B.counters, B.view_off, B.view_list, B.ranges, int64_t(total_tiles),
+                           B.queue);
+        hipLaunchKernelGGL(count_kernel<false>, dim3(cgx, n_views), dim3(256), 0, st, *s, proj, n, n_cap, targets,
+                           B.view_off, B.view_list, B.counts, B.rects, B.bsum, B.counters, B.queue, B.ranges,
+                           int64_t(0));
+    }
     // compact visible records: the count kernel left each workgroup's number
     // of visible records in bsum; their exclusive scan places the workgroups
     hipLaunchKernelGGL(scan_bsums_kernel, dim3(1), dim3(1024), 0, st, B.bsum, cgx * n_views, B.counters + kVisible);
