@@ -179,6 +179,11 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(
             __syncthreads();
             if (!done) {
                 int lj = -1;   // staged index of this batch's last composited Gaussian
+                // Straight-line body: every lane evaluates every staged
+                // Gaussian and keeps the result only where it composites (a
+                // wave runs the exponential whenever one of its lanes does);
+                // a lane that stops compositing stays in the loop as a no-op
+                // until all of the wave's lanes have stopped.
     #pragma unroll 4
                 for (int j = 0; j < int(cnt); ++j) {
                     const float4 A = sA[j];
@@ -186,19 +191,22 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(
                     const float2 Cj = sC[j];
                     const float dx = A.x - fpx, dy = A.y - fpy;
                     const float pw = eval_power(A, B, dx, dy);
-                    if (kCount) ++ne;
-                    if (pw < Cj.y) continue;
+                    if (kCount) ne += done ? 0 : 1;
+                    const bool hit = !done && !(pw < Cj.y);
                     const float alpha = fminf(s.alpha_max, B.y * __expf(pw));
                     const float Tn = T * (1.f - alpha);
-                    if (Tn < s.t_min) { done = true; break; }
-                    if (kStore && store_at) store_at[int64_t(nc) * kTilePix] = T;
+                    const bool stop = hit && Tn < s.t_min;
+                    const bool comp = hit && !stop;
+                    if (kStore && store_at && comp) store_at[int64_t(nc) * kTilePix] = T;
                     const float w = alpha * T;
-                    C0 = fmaf(w, B.z, C0);
-                    C1 = fmaf(w, B.w, C1);
-                    C2 = fmaf(w, Cj.x, C2);
-                    T = Tn;
-                    if (kCount || kStore) ++nc;
-                    lj = j;
+                    C0 = comp ? fmaf(w, B.z, C0) : C0;
+                    C1 = comp ? fmaf(w, B.w, C1) : C1;
+                    C2 = comp ? fmaf(w, Cj.x, C2) : C2;
+                    T = comp ? Tn : T;
+                    if (kCount || kStore) nc += comp ? 1 : 0;
+                    lj = comp ? j : lj;
+                    done = done || stop;
+                    if ((j & 3) == 3 && __all(done)) break;
                 }
                 // one past the list position of the last composited Gaussian
                 if (lj >= 0) last = sPos[lj] + 1;
