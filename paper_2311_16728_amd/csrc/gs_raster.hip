@@ -418,7 +418,7 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
             wave_sync();
             if (lane < n * kAccRows) {
                 const float *row = tb + lane * kTStride;
-                float sum = 0.f;
+                float sum = -0.f;
     #pragma unroll
                 for (int q = 0; q < kQuads; ++q) sum += row[q];
                 const int slot = lane / kAccRows;
@@ -455,9 +455,12 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
                 const float4 Bv = sB[k];
                 const float2 Ck = sC[k];
                 const int pos = sPos[k];
+                // sums start at -0: -0 + x and -0 - x are exactly x and -x,
+                // so the first pixel's terms need no add (from +0 they would:
+                // +0 + -0 is +0)
                 float v[kAccRows];
     #pragma unroll
-                for (int i = 0; i < kAccRows; ++i) v[i] = 0.f;
+                for (int i = 0; i < kAccRows; ++i) v[i] = -0.f;
                 bool any = false;
     #pragma unroll
                 for (int i = 0; i < kPix; ++i) {
@@ -537,7 +540,7 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
                 float v[kAccRows];
     #pragma unroll
                 for (int i = 0; i < kAccRows; ++i) {
-                    float sum = 0.f;
+                    float sum = -0.f;
     #pragma unroll
                     for (int w = 0; w < kWaves; ++w) sum += red[w][k][i];
                     v[i] = sum;
