@@ -479,23 +479,27 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
                         } else {
                             T[i] = T[i] * __builtin_amdgcn_rcpf(oma);   // transmittance in front of it
                         }
+                        // (the gradient sums use explicit FMAs: the build does
+                        // not contract, so that both passes take the cutoff
+                        // decisions with the same instructions)
                         const float r = Bv.z, gg = Bv.w, bb = Ck.x;
-                        const float dal = T[i] * ((r - B0[i]) * g0[i] + (gg - B1[i]) * g1[i] + (bb - B2[i]) * g2[i]);
+                        const float dal =
+                            T[i] * fmaf(r - B0[i], g0[i], fmaf(gg - B1[i], g1[i], (bb - B2[i]) * g2[i]));
                         const float w = alpha * T[i];
-                        v[6] += w * g0[i];
-                        v[7] += w * g1[i];
-                        v[8] += w * g2[i];
+                        v[6] = fmaf(w, g0[i], v[6]);
+                        v[7] = fmaf(w, g1[i], v[7]);
+                        v[8] = fmaf(w, g2[i], v[8]);
                         B0[i] = fmaf(alpha, r, oma * B0[i]);
                         B1[i] = fmaf(alpha, gg, oma * B1[i]);
                         B2[i] = fmaf(alpha, bb, oma * B2[i]);
                         const float dat = (at < s.alpha_max) ? dal : 0.f;
-                        v[5] += ep * dat;
-                        const float dp = at * dat;
-                        v[0] -= dp * (A.z * dx + A.w * dy);
-                        v[1] -= dp * (A.w * dx + Bv.x * dy);
-                        v[2] -= 0.5f * dp * dx * dx;
-                        v[3] -= dp * dx * dy;
-                        v[4] -= 0.5f * dp * dy * dy;
+                        v[5] = fmaf(ep, dat, v[5]);
+                        const float ndp = -(at * dat);
+                        v[0] = fmaf(ndp, fmaf(A.z, dx, A.w * dy), v[0]);
+                        v[1] = fmaf(ndp, fmaf(A.w, dx, Bv.x * dy), v[1]);
+                        v[2] = fmaf(0.5f * ndp * dx, dx, v[2]);
+                        v[3] = fmaf(ndp * dx, dy, v[3]);
+                        v[4] = fmaf(0.5f * ndp * dy, dy, v[4]);
                     }
                 }
                 const uint64_t act = __ballot(any);
