@@ -123,6 +123,8 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(
     __shared__ int32_t sPos[kTilePix];
     __shared__ uint32_t scan_lds[8];
     constexpr bool queued = kQueued;
+    // alpha_max as a canonical float, so fminf needs no per-use quieting
+    const float amax = __builtin_canonicalizef(s.alpha_max);
     for (int round = 0;; ++round) {
         int tile;
         if (queued) {   // next tile of the cost-ordered queue
@@ -193,7 +195,7 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(
                     const float pw = eval_power(A, B, dx, dy);
                     if (kCount) ne += done ? 0 : 1;
                     const bool hit = !done && !(pw < Cj.y);
-                    const float alpha = fminf(s.alpha_max, B.y * __expf(pw));
+                    const float alpha = fminf(amax, B.y * __expf(pw));
                     const float Tn = T * (1.f - alpha);
                     const bool stop = hit && Tn < s.t_min;
                     const bool comp = hit && !stop;
@@ -337,6 +339,8 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
     __shared__ int sMaxLast;
     if (kStored && !(*ts_store.need <= ts_store.cap)) return;   // the forward stored nothing
     constexpr bool queued = kQueued;
+    // alpha_max as a canonical float, so fminf needs no per-use quieting
+    const float amax = __builtin_canonicalizef(s.alpha_max);
     for (int round = 0;; ++round) {
         int tile;
         if (queued) {   // next tile of the cost-ordered queue
@@ -471,7 +475,7 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
                         any = true;
                         const float ep = __expf(pw);
                         const float at = Bv.y * ep;
-                        const float alpha = fminf(s.alpha_max, at);
+                        const float alpha = fminf(amax, at);
                         const float oma = 1.f - alpha;
                         if (kStored) {   // transmittance in front of it, as stored
                             kc[i] = max(kc[i] - 1, 0);
@@ -492,7 +496,7 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
                         B0[i] = fmaf(alpha, r, oma * B0[i]);
                         B1[i] = fmaf(alpha, gg, oma * B1[i]);
                         B2[i] = fmaf(alpha, bb, oma * B2[i]);
-                        const float dat = (at < s.alpha_max) ? dal : 0.f;
+                        const float dat = (at < amax) ? dal : 0.f;
                         v[5] = fmaf(ep, dat, v[5]);
                         const float ndp = -(at * dat);
                         v[0] = fmaf(ndp, fmaf(A.z, dx, A.w * dy), v[0]);
