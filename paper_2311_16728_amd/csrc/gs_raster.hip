@@ -87,6 +87,13 @@ __device__ __forceinline__ bool touches_tile(const float4 &A, const float4 &B, c
     return qmin_tile(A, B, float(ts.w - 1), float(ts.h - 1)) <= tq * 1.0001f + 1e-3f;
 }
 
+// alpha = min(opacity x exp(power), alpha_max) for the non-negative first
+// argument, as one median instruction (an fminf canonicalises its operands
+// on every use); forward and backward use the same instruction.
+__device__ __forceinline__ float clamp_alpha(float at, float amax) {
+    return __builtin_amdgcn_fmed3f(at, 0.f, amax);
+}
+
 // Opacity of a staged Gaussian at offset (dx, dy) = mean - pixel.  The same
 // instruction sequence serves the forward and the backward, so both take the
 // same alpha_min decision.
@@ -123,8 +130,7 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(
     __shared__ int32_t sPos[kTilePix];
     __shared__ uint32_t scan_lds[8];
     constexpr bool queued = kQueued;
-    // alpha_max as a canonical float, so fminf needs no per-use quieting
-    const float amax = __builtin_canonicalizef(s.alpha_max);
+    const float amax = __builtin_canonicalizef(s.alpha_max);   // (once per launch)
     for (int round = 0;; ++round) {
         int tile;
         if (queued) {   // next tile of the cost-ordered queue
@@ -185,9 +191,9 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(
                 // Gaussian and keeps the result only where it composites (a
                 // wave runs the exponential whenever one of its lanes does);
                 // a lane that stops compositing stays in the loop as a no-op
-                // until all of the wave's lanes have stopped.
-    #pragma unroll 4
-                for (int j = 0; j < int(cnt); ++j) {
+                // until all of the wave's lanes have stopped (checked every
+                // four Gaussians; the loop is unrolled by hand, four at a time).
+                auto step = [&](int j) {
                     const float4 A = sA[j];
                     const float4 B = sB[j];
                     const float2 Cj = sC[j];
@@ -195,7 +201,7 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(
                     const float pw = eval_power(A, B, dx, dy);
                     if (kCount) ne += done ? 0 : 1;
                     const bool hit = !done && !(pw < Cj.y);
-                    const float alpha = fminf(amax, B.y * __expf(pw));
+                    const float alpha = clamp_alpha(B.y * __expf(pw), amax);
                     const float Tn = T * (1.f - alpha);
                     const bool stop = hit && Tn < s.t_min;
                     const bool comp = hit && !stop;
@@ -208,8 +214,17 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(
                     if (kCount || kStore) nc += comp ? 1 : 0;
                     lj = comp ? j : lj;
                     done = done || stop;
-                    if ((j & 3) == 3 && __all(done)) break;
+                };
+                const int n_staged = __builtin_amdgcn_readfirstlane(int(cnt));   // (uniform)
+                int j = 0;
+                for (; j + 4 <= n_staged; j += 4) {
+                    step(j);
+                    step(j + 1);
+                    step(j + 2);
+                    step(j + 3);
+                    if (__all(done)) break;
                 }
+                for (; j < n_staged && !__all(done); ++j) step(j);
                 // one past the list position of the last composited Gaussian
                 if (lj >= 0) last = sPos[lj] + 1;
             }
@@ -339,8 +354,7 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
     __shared__ int sMaxLast;
     if (kStored && !(*ts_store.need <= ts_store.cap)) return;   // the forward stored nothing
     constexpr bool queued = kQueued;
-    // alpha_max as a canonical float, so fminf needs no per-use quieting
-    const float amax = __builtin_canonicalizef(s.alpha_max);
+    const float amax = __builtin_canonicalizef(s.alpha_max);   // (once per launch)
     for (int round = 0;; ++round) {
         int tile;
         if (queued) {   // next tile of the cost-ordered queue
@@ -475,7 +489,7 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
                         any = true;
                         const float ep = __expf(pw);
                         const float at = Bv.y * ep;
-                        const float alpha = fminf(amax, at);
+                        const float alpha = clamp_alpha(at, amax);
                         const float oma = 1.f - alpha;
                         if (kStored) {   // transmittance in front of it, as stored
                             kc[i] = max(kc[i] - 1, 0);
