@@ -118,7 +118,7 @@ struct TStore {
 // kCount: per-pixel composited and evaluated counts (and, with tile_max, the
 // largest composited count of each tile); kStore: the transmittance store.
 template <bool kCount, bool kStore = false, bool kQueued = false>
-__global__ void __launch_bounds__(256) render_fwd_kernel(
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) render_fwd_kernel(
     gs_settings s, Proj proj, int64_t n_cap, Sorted srt, const gs_target *__restrict__ targets,
     int n_targets, float *__restrict__ out_rgb, float *__restrict__ out_T,
     int32_t *__restrict__ out_last, int32_t *__restrict__ out_nc, int32_t *__restrict__ out_ne,
