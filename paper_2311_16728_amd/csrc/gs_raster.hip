@@ -350,7 +350,6 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
     __shared__ float red[kWaves][kThreads][kAccRows];
     __shared__ float tbuf[kWaves][kGroup * kAccRows * kTStride];
     __shared__ int32_t sK[kWaves][kGroup];
-    __shared__ float tscratch[kWaves][kWave + (kAccRows - 1) * kTStride];
     __shared__ int sMaxLast;
     if (kStored && !(*ts_store.need <= ts_store.cap)) return;   // the forward stored nothing
     constexpr bool queued = kQueued;
@@ -543,12 +542,12 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
                     v[i] = dpp_add<0xB1, 0xf>(v[i]);   // quad_perm [1,0,3,2]
                     v[i] = dpp_add<0x4E, 0xf>(v[i]);   // quad_perm [2,3,0,1]
                 }
-                {   // every lane stores, the three others of a quad into a scratch
-                    // row of their own: the second DPP add then stays one
-                    // instruction for the whole wave (kept behind a branch of
-                    // the quads' first lanes it became a move, a copy and an add)
-                    float *col = (lane & 3) == 0 ? tb + slots * kAccRows * kTStride + (lane >> 2)
-                                                 : tscratch[wave] + lane;
+                {   // all four lanes of a quad hold the same bits ((a+b)+(c+d) and
+                    // its reorderings by commutation) and all store them to the
+                    // quad's slot: the second DPP add then stays one instruction
+                    // for the whole wave (kept behind a branch of the quads'
+                    // first lanes it became a move, a copy and an add)
+                    float *col = tb + slots * kAccRows * kTStride + (lane >> 2);
     #pragma unroll
                     for (int i = 0; i < kAccRows; ++i) col[i * kTStride] = v[i];
                 }
