@@ -140,9 +140,10 @@ struct SortLayout {
         L.pair_val0 = take(sizeof(uint32_t) * pair_cap);
         L.pair_val1 = take(sizeof(uint32_t) * pair_cap);
         L.ranges = take(sizeof(uint32_t) * 2 * (total_tiles > 0 ? total_tiles : 1));
-        // block sums; also one visible-record count per workgroup of the count grid
+        // block sums; also one visible-record count per workgroup of the count
+        // grid (padded to whole 16-byte pieces, which the compaction reads)
         const int64_t groups = n_views * ((n_cap + 255) / 256);
-        L.bsum = take(sizeof(uint32_t) * ((L.max_blocks > groups ? L.max_blocks : groups) + 1));
+        L.bsum = take(sizeof(uint32_t) * ((L.max_blocks > groups ? L.max_blocks : groups) + 4));
         L.hist = take(sizeof(uint32_t) * kRadixBinsMax * L.max_blocks);
         L.digit = take(sizeof(uint32_t) * ((kRadixBinsMax > kTileCountMax ? kRadixBinsMax : kTileCountMax) + 1));
         // first sorted record of every 256-pair emission chunk
@@ -251,13 +252,26 @@ __device__ __forceinline__ void report_numeric(uint32_t *status, bool bad) {
     if (b != 0 && lane_id() == __builtin_ctzll(b)) atomicOr(status, GS_STATUS_NUMERIC);
 }
 
+// Cross-lane move through DPP: lanes whose source is outside their row, or
+// whose row kRowMask leaves out, read 0.  Control words: row_shr:n = 0x110 + n
+// (within rows of 16 lanes), row_bcast:15 = 0x142 (lane 15 of each row to the
+// next row), row_bcast:31 = 0x143 (lane 31 to rows 2 and 3).
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+    return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), kCtrl, kRowMask, 0xf, false));
+}
+
+// Inclusive scan over the wave in six DPP adds (no LDS round trips): prefix
+// sums inside each row of 16 lanes by shifts of 1, 2, 4 and 8, then row 0's
+// total into row 1 and row 2's into row 3, then the first two rows' total
+// into rows 2 and 3.
 __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        uint32_t u = __shfl_up(v, d, kWave);
-        if (lane >= d) v += u;
-    }
+    v += dpp_u32<0x111, 0xf>(v);
+    v += dpp_u32<0x112, 0xf>(v);
+    v += dpp_u32<0x114, 0xf>(v);
+    v += dpp_u32<0x118, 0xf>(v);
+    v += dpp_u32<0x142, 0xa>(v);
+    v += dpp_u32<0x143, 0xc>(v);
     return v;
 }
 

@@ -183,6 +183,39 @@ __global__ void __launch_bounds__(256) ssim_fwd_kernel(const float *__restrict__
     }
 }
 
+// One block: per-target means from the tile partials (fixed order), then the
+// weighted total.
+// Eq. 4 per target (one workgroup each, tile partials summed in double in a
+// fixed order), then the weighted sum over targets in target order.
+__device__ __forceinline__ void loss_of_target(const gs_target *__restrict__ targets, int ti,
+                                               float lambda, const float *__restrict__ partial,
+                                               double *__restrict__ tloss, float *__restrict__ d_loss) {
+    __shared__ double red[2][kTilePix / kWave];
+    const gs_target t = targets[ti];
+    const int nt = t.tiles_x * t.tiles_y;
+    double a = 0, b = 0;
+    // unrolled so that the loads of several tiles are in flight; the sums keep
+    // their order
+#pragma unroll 8
+    for (int i = threadIdx.x; i < nt; i += blockDim.x) {
+        a += partial[2 * int64_t(t.tile_offset + i)];
+        b += partial[2 * int64_t(t.tile_offset + i) + 1];
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (lane_id() == 0) { red[0][threadIdx.x / kWave] = a; red[1][threadIdx.x / kWave] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sa = 0, sb = 0;
+        for (int w = 0; w < kTilePix / kWave; ++w) { sa += red[0][w]; sb += red[1][w]; }
+        const double n = 3.0 * double(t.width) * double(t.height);
+        const double L = (1.0 - lambda) * sa / n + lambda * (1.0 - sb / n);
+        tloss[ti] = double(t.weight) * L;
+        if (d_loss) d_loss[ti] = float(L);
+    }
+    __syncthreads();   // red is reused by the next call
+}
+
 struct SsimBwdLds {
     float sm[3][kHaloMax];
     float h[3][kHPassMax];
@@ -244,14 +277,31 @@ __device__ __forceinline__ void ssim_bwd_tile(const float *__restrict__ render,
     }
 }
 
+// A few targets (kFold): workgroup 0 also forms the per-target losses and the
+// total from the forward's tile partials before its tile (the sums and order
+// of loss_few_kernel, one launch fewer).
+constexpr int kLossOneBlockTargets = 8;
+template <bool kFold>
 __global__ void __launch_bounds__(256) ssim_bwd_kernel(const float *__restrict__ render,
                                                        const float *__restrict__ target,
                                                        const gs_target *__restrict__ targets,
                                                        int n_targets, int total_tiles, Window win,
                                                        float lambda,
                                                        const float *__restrict__ maps,
-                                                       float *__restrict__ dL) {
+                                                       float *__restrict__ dL,
+                                                       const float *__restrict__ partial,
+                                                       double *__restrict__ tloss,
+                                                       float *__restrict__ d_loss,
+                                                       float *__restrict__ d_total) {
     __shared__ SsimBwdLds L;
+    if (kFold && blockIdx.x == 0) {   // uniform over the workgroup
+        for (int ti = 0; ti < n_targets; ++ti) loss_of_target(targets, ti, lambda, partial, tloss, d_loss);
+        if (threadIdx.x == 0 && d_total) {
+            double total = 0.0;
+            for (int ti = 0; ti < n_targets; ++ti) total += tloss[ti];
+            *d_total = float(total);
+        }
+    }
     const int tile = int(xcd_tile(blockIdx.x, total_tiles));
     if (tile >= total_tiles) return;
     const gs_target t = targets[find_target_loss(targets, n_targets, tile)];
@@ -260,39 +310,6 @@ __global__ void __launch_bounds__(256) ssim_bwd_kernel(const float *__restrict__
         case 32: ssim_bwd_tile<32>(render, target, t, tile, win, lambda, maps, dL, L); break;
         default: ssim_bwd_tile<16>(render, target, t, tile, win, lambda, maps, dL, L); break;
     }
-}
-
-// One block: per-target means from the tile partials (fixed order), then the
-// weighted total.
-// Eq. 4 per target (one workgroup each, tile partials summed in double in a
-// fixed order), then the weighted sum over targets in target order.
-__device__ __forceinline__ void loss_of_target(const gs_target *__restrict__ targets, int ti,
-                                               float lambda, const float *__restrict__ partial,
-                                               double *__restrict__ tloss, float *__restrict__ d_loss) {
-    __shared__ double red[2][kTilePix / kWave];
-    const gs_target t = targets[ti];
-    const int nt = t.tiles_x * t.tiles_y;
-    double a = 0, b = 0;
-    // unrolled so that the loads of several tiles are in flight; the sums keep
-    // their order
-#pragma unroll 8
-    for (int i = threadIdx.x; i < nt; i += blockDim.x) {
-        a += partial[2 * int64_t(t.tile_offset + i)];
-        b += partial[2 * int64_t(t.tile_offset + i) + 1];
-    }
-    a = wave_sum(a);
-    b = wave_sum(b);
-    if (lane_id() == 0) { red[0][threadIdx.x / kWave] = a; red[1][threadIdx.x / kWave] = b; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double sa = 0, sb = 0;
-        for (int w = 0; w < kTilePix / kWave; ++w) { sa += red[0][w]; sb += red[1][w]; }
-        const double n = 3.0 * double(t.width) * double(t.height);
-        const double L = (1.0 - lambda) * sa / n + lambda * (1.0 - sb / n);
-        tloss[ti] = double(t.weight) * L;
-        if (d_loss) d_loss[ti] = float(L);
-    }
-    __syncthreads();   // red is reused by the next call
 }
 
 __global__ void __launch_bounds__(256) loss_target_kernel(const gs_target *__restrict__ targets,
@@ -305,7 +322,6 @@ __global__ void __launch_bounds__(256) loss_target_kernel(const gs_target *__res
 
 // A few targets: one workgroup takes them in order and forms the total
 // (the same sums in the same order as the two kernels above and below).
-constexpr int kLossOneBlockTargets = 8;
 __global__ void __launch_bounds__(256) loss_few_kernel(const gs_target *__restrict__ targets,
                                                        int n_targets, float lambda,
                                                        const float *__restrict__ partial,
@@ -411,11 +427,18 @@ extern "C" gs_status gs_pyramid_loss(const float *render, const float *target,
     const int64_t grid = xcd_grid(total_tiles);
     hipLaunchKernelGGL(ssim_fwd_kernel, dim3(grid), dim3(kTilePix), 0, st, render, target, targets,
                        n_targets, total_tiles, win, maps, partial);
-    if (dL_drender)
-        hipLaunchKernelGGL(ssim_bwd_kernel, dim3(grid), dim3(kTilePix), 0, st, render, target, targets,
-                           n_targets, total_tiles, win, lambda, maps, dL_drender);
     double *tloss = reinterpret_cast<double *>(b + L.tloss);
-    if (n_targets <= kLossOneBlockTargets) {
+    const bool few = n_targets <= kLossOneBlockTargets;
+    if (dL_drender && few) {
+        hipLaunchKernelGGL(ssim_bwd_kernel<true>, dim3(grid), dim3(kTilePix), 0, st, render, target, targets,
+                           n_targets, total_tiles, win, lambda, maps, dL_drender, partial, tloss, d_loss, d_total);
+        GS_CHECK_LAUNCH();
+        return GS_OK;
+    }
+    if (dL_drender)
+        hipLaunchKernelGGL(ssim_bwd_kernel<false>, dim3(grid), dim3(kTilePix), 0, st, render, target, targets,
+                           n_targets, total_tiles, win, lambda, maps, dL_drender, partial, tloss, d_loss, d_total);
+    if (few) {
         hipLaunchKernelGGL(loss_few_kernel, dim3(1), dim3(256), 0, st, targets, n_targets, lambda, partial,
                            tloss, d_loss, d_total);
     } else {

@@ -291,18 +291,20 @@ __device__ __forceinline__ float dpp_add(float v) {
     return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, kRowMask, 0xf, false));
 }
 
-// Block-wide exclusive scan for kThreads threads (a multiple of 64).
+// Block-wide count of `flag` for kThreads threads (a multiple of 64): the
+// number of threads before this one where it holds (ballots, no scan), and
+// the block total.
 template <int kThreads>
-__device__ __forceinline__ uint32_t block_scan_n(uint32_t v, uint32_t *lds, uint32_t *total) {
+__device__ __forceinline__ uint32_t block_count_n(bool flag, uint32_t *lds, uint32_t *total) {
     constexpr int kW = kThreads / kWave;
-    const int lane = lane_id();
-    const int wave = threadIdx.x / kWave;
-    const uint32_t inc = wave_inclusive_scan(v);
+    const uint64_t m = __ballot(flag);
+    const uint32_t below = uint32_t(mask_rank(m));
     if (kW == 1) {
-        *total = __shfl(inc, kWave - 1, kWave);
-        return inc - v;
+        *total = uint32_t(__popcll(m));
+        return below;
     }
-    if (lane == kWave - 1) lds[wave] = inc;
+    const int wave = threadIdx.x / kWave;
+    if (lane_id() == 0) lds[wave] = uint32_t(__popcll(m));
     __syncthreads();
     uint32_t base = 0, all = 0;
 #pragma unroll
@@ -313,7 +315,7 @@ __device__ __forceinline__ uint32_t block_scan_n(uint32_t v, uint32_t *lds, uint
     }
     __syncthreads();
     *total = all;
-    return base + inc - v;
+    return base + below;
 }
 
 // Backward raster with kWaves waves per 16x16 tile; every lane owns
@@ -458,7 +460,7 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
                 keep = touches_tile(A, Bv, Cc, ts);
             }
             uint32_t cnt;
-            const uint32_t at_pos = block_scan_n<kThreads>(keep ? 1u : 0u, scan_lds, &cnt);
+            const uint32_t at_pos = block_count_n<kThreads>(keep, scan_lds, &cnt);
             if (keep) {
                 sA[at_pos] = A;
                 sB[at_pos] = Bv;

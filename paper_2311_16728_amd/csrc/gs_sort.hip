@@ -213,14 +213,18 @@ __global__ void __launch_bounds__(256) count_kernel(gs_settings s, Proj proj, in
 // 64-bit wave scans for the pair offsets: a sum of per-record pair counts may
 // pass 2^32, and is then saturated (a total past pair_cap <= 2^31 - 1 is an
 // overflow, reported as such) instead of wrapping.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+    return (uint64_t(dpp_u32<kCtrl, kRowMask>(uint32_t(v >> 32))) << 32) | dpp_u32<kCtrl, kRowMask>(uint32_t(v));
+}
+// (the DPP steps of wave_inclusive_scan, on both halves)
 __device__ __forceinline__ uint64_t wave_inclusive_scan64(uint64_t v) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t lo = __shfl_up(uint32_t(v), d, kWave);
-        const uint32_t hi = __shfl_up(uint32_t(v >> 32), d, kWave);
-        if (lane >= d) v += (uint64_t(hi) << 32) | lo;
-    }
+    v += dpp_u64<0x111, 0xf>(v);
+    v += dpp_u64<0x112, 0xf>(v);
+    v += dpp_u64<0x114, 0xf>(v);
+    v += dpp_u64<0x118, 0xf>(v);
+    v += dpp_u64<0x142, 0xa>(v);
+    v += dpp_u64<0x143, 0xc>(v);
     return v;
 }
 __device__ __forceinline__ uint32_t sat32(uint64_t v) {
@@ -331,22 +335,61 @@ __device__ __forceinline__ uint32_t depth_key(float z, float znear) {
 // Compaction of the visible records (pair count > 0) in record order: keys =
 // depth keys, values = record indices, and the counts alongside.  Same grid
 // as count_kernel; a workgroup's records land after those of the workgroups
-// before it (group_vis after its exclusive scan) in thread order.
+// before it, in thread order.
+// kFold (at most kFoldGroups count workgroups): each workgroup sums the
+// visible counts of the workgroups before it itself (at most four 16-byte
+// loads per thread, from L2), and the last one stores the number of visible
+// records to *n_visible, so no scan of the counts runs in between.
+// Otherwise group_vis holds the counts' exclusive scan (scan_bsums_kernel).
+constexpr int64_t kFoldGroups = 4096;
+template <bool kFold>
 __global__ void __launch_bounds__(256) compact_scatter_kernel(const uint32_t *__restrict__ counts,
                                                               int64_t n_cap, Proj proj, float znear,
                                                               const uint32_t *__restrict__ group_vis,
+                                                              int64_t groups,
                                                               uint32_t *__restrict__ vis_key,
                                                               uint32_t *__restrict__ vis_val,
-                                                              uint32_t *__restrict__ vis_cnt) {
+                                                              uint32_t *__restrict__ vis_cnt,
+                                                              uint32_t *__restrict__ n_visible) {
     __shared__ uint32_t lds4[kScanThreads / kWave];
+    __shared__ uint32_t fold4[kScanThreads / kWave];
     const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t r = int64_t(blockIdx.y) * n_cap + g;
+    const int64_t gs = group_slot();
     const uint32_t c = g < n_cap ? counts[r] : 0u;
+    if constexpr (kFold) {
+        // entries [0, gs) in 16-byte pieces (group_vis is 256-byte aligned and
+        // padded to a multiple of 4 entries); pieces past gs read piece 0
+        constexpr int kIt = int(kFoldGroups / (4 * kScanThreads));
+        const uint4 *gv = reinterpret_cast<const uint4 *>(group_vis);
+        uint4 q[kIt];
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) {
+            const int64_t j = threadIdx.x + k * kScanThreads;
+            q[k] = gv[4 * j < gs ? j : 0];
+        }
+        uint32_t sum = 0u;
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) {
+            const int64_t i = 4 * (threadIdx.x + k * kScanThreads);
+            sum += (i < gs ? q[k].x : 0u) + (i + 1 < gs ? q[k].y : 0u) + (i + 2 < gs ? q[k].z : 0u) +
+                   (i + 3 < gs ? q[k].w : 0u);
+        }
+        sum = wave_sum(sum);
+        if (lane_id() == 0) fold4[threadIdx.x / kWave] = sum;   // (read after group_count's barrier)
+    }
     uint32_t before;
-    group_count(c != 0u, lds4, &before);
+    const uint32_t all = group_count(c != 0u, lds4, &before);
+    uint32_t gbase;
+    if constexpr (kFold) {
+        gbase = fold4[0] + fold4[1] + fold4[2] + fold4[3];
+        if (gs == groups - 1 && threadIdx.x == 0) *n_visible = gbase + all;
+    } else {
+        gbase = group_vis[gs];
+    }
     const uint64_t mask = __ballot(c != 0u);
     if (c != 0u) {
-        const uint32_t at = group_vis[group_slot()] + before + uint32_t(mask_rank(mask));
+        const uint32_t at = gbase + before + uint32_t(mask_rank(mask));
         vis_key[at] = depth_key(proj.rgb_z[r].w, znear);
         vis_val[at] = uint32_t(r);
         vis_cnt[at] = c;
@@ -1373,14 +1416,21 @@ extern "C" gs_status gs_bin_sort(const gs_settings *s, const void *proj_ws, int6
                            int64_t(0));
     }
     // compact visible records: the count kernel left each workgroup's number
-    // of visible records in bsum; their exclusive scan places the workgroups
-    hipLaunchKernelGGL(scan_bsums_kernel, dim3(1), dim3(1024), 0, st, B.bsum, cgx * n_views, B.counters + kVisible);
+    // of visible records in bsum, which place the workgroups (summed by the
+    // compaction itself up to kFoldGroups workgroups, else scanned first)
     // the visible records' pair counts move with them through compaction and
     // the depth sort, in two S-sized buffers that are free meanwhile: vis_off
     // (written by no other step) and counts (read only by the compaction)
     uint32_t *cnt_buf[2] = {B.voff, B.counts};
-    hipLaunchKernelGGL(compact_scatter_kernel, dim3(cgx, n_views), dim3(256), 0, st, B.counts, n_cap, proj, s->znear,
-                       B.bsum, B.vk[0], B.vv[0], cnt_buf[0]);
+    const int64_t groups = cgx * n_views;
+    if (groups <= kFoldGroups) {
+        hipLaunchKernelGGL(compact_scatter_kernel<true>, dim3(cgx, n_views), dim3(256), 0, st, B.counts, n_cap, proj,
+                           s->znear, B.bsum, groups, B.vk[0], B.vv[0], cnt_buf[0], B.counters + kVisible);
+    } else {
+        hipLaunchKernelGGL(scan_bsums_kernel, dim3(1), dim3(1024), 0, st, B.bsum, groups, B.counters + kVisible);
+        hipLaunchKernelGGL(compact_scatter_kernel<false>, dim3(cgx, n_views), dim3(256), 0, st, B.counts, n_cap, proj,
+                           s->znear, B.bsum, groups, B.vk[0], B.vv[0], cnt_buf[0], B.counters + kVisible);
+    }
     // depth order (three 9-bit passes over the 27-bit keys); the last pass
     // also turns the pair counts into pair offsets (in `counts`), writes the
     // emission chunks' first records and the total pair count
