@@ -59,26 +59,48 @@ static_assert(halo_stride<8>() * (32 + 2 * kR) <= kHaloMax && halo_stride<32>() 
               "halo buffers");
 constexpr int kHPassMax = 32 * (8 + 2 * kR);
 
-// Loads the HX x HY window of one channel plane around the tile into LDS
-// (row stride halo_stride<TW>()), zero outside the image.
+// The HX x HY window of kP channel planes around the tile, zero outside the
+// image: fetched into registers (kHaloRounds values per plane and thread,
+// every load unconditional at a clamped address, so all are in flight
+// together), then put into LDS (row stride halo_stride<TW>()).  Fetching
+// the next channel while the current one is filtered hides the loads.
 template <int TW>
-__device__ __forceinline__ void load_halo(const float *__restrict__ plane, int W, int H, int x0,
-                                          int y0, float *dst) {
-    constexpr int TH = kTilePix / TW, HX = TW + 2 * kR, HY = TH + 2 * kR, HS = halo_stride<TW>();
-    constexpr int kRounds = (HX * HY + kTilePix - 1) / kTilePix;
-    // all of a thread's loads are issued before its first LDS store
-    float v[kRounds];
+__host__ __device__ constexpr int halo_rounds() {
+    return ((TW + 2 * kR) * (kTilePix / TW + 2 * kR) + kTilePix - 1) / kTilePix;
+}
+template <int TW, int kP>
+struct Halo {
+    float v[kP][halo_rounds<TW>()];
+};
+template <int TW, int kP>
+__device__ __forceinline__ void fetch_halo(const float *const (&planes)[kP], int W, int H, int x0, int y0,
+                                           Halo<TW, kP> &hv) {
+    constexpr int TH = kTilePix / TW, HX = TW + 2 * kR, HY = TH + 2 * kR;
+    constexpr int kRounds = halo_rounds<TW>();
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
         const int i = threadIdx.x + r * kTilePix;
         const int yy = i / HX, xx = i % HX;
         const int gx = x0 - kR + xx, gy = y0 - kR + yy;
-        v[r] = (i < HX * HY && gx >= 0 && gx < W && gy >= 0 && gy < H) ? plane[int64_t(gy) * W + gx] : 0.f;
-    }
+        const bool in = i < HX * HY && gx >= 0 && gx < W && gy >= 0 && gy < H;
+        const int64_t at = int64_t(min(max(gy, 0), H - 1)) * W + min(max(gx, 0), W - 1);
 #pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
+        for (int p = 0; p < kP; ++p) {
+            const float x = planes[p][at];
+            hv.v[p][r] = in ? x : 0.f;
+        }
+    }
+}
+template <int TW, int kP>
+__device__ __forceinline__ void put_halo(const Halo<TW, kP> &hv, float *const (&dst)[kP]) {
+    constexpr int HX = TW + 2 * kR, HY = kTilePix / TW + 2 * kR, HS = halo_stride<TW>();
+#pragma unroll
+    for (int r = 0; r < halo_rounds<TW>(); ++r) {
         const int i = threadIdx.x + r * kTilePix;
-        if (i < HX * HY) dst[(i / HX) * HS + i % HX] = v[r];
+        if (i < HX * HY) {
+#pragma unroll
+            for (int p = 0; p < kP; ++p) dst[p][(i / HX) * HS + i % HX] = hv.v[p][r];
+        }
     }
 }
 
@@ -105,14 +127,20 @@ __device__ __forceinline__ void ssim_fwd_tile(const float *__restrict__ render,
     const int64_t HW = int64_t(t.width) * t.height;
     const int64_t pix = int64_t(py) * t.width + px;
     float l1 = 0.f, ss = 0.f;
+    Halo<TW, 2> hv;
+    auto fetch = [&](int c) {
+        const float *const planes[2] = {render + 3 * t.pix_offset + c * HW, target + 3 * t.pix_offset + c * HW};
+        fetch_halo<TW, 2>(planes, t.width, t.height, x0, y0, hv);
+    };
+    float *const dst[2] = {L.sx, L.sy};
+    fetch(0);
     for (int c = 0; c < 3; ++c) {
-        const float *xp = render + 3 * t.pix_offset + c * HW;
-        const float *yp = target + 3 * t.pix_offset + c * HW;
+        __syncthreads();   // the previous channel's reads of the windows are done
+        put_halo<TW, 2>(hv, dst);
         __syncthreads();
-        load_halo<TW>(xp, t.width, t.height, x0, y0, L.sx);
-        load_halo<TW>(yp, t.width, t.height, x0, y0, L.sy);
-        __syncthreads();
-        for (int i = tid; i < HY * TW; i += blockDim.x) {
+        if (c + 1 < 3) fetch(c + 1);
+#pragma unroll
+        for (int i = tid; i < HY * TW; i += kTilePix) {
             const int r = i / TW, cc = i % TW;
             const float *rx = L.sx + r * HS + cc, *ry = L.sy + r * HS + cc;
             float m1 = 0, m2 = 0, e11 = 0, e22 = 0, e12 = 0;
@@ -237,12 +265,21 @@ __device__ __forceinline__ void ssim_bwd_tile(const float *__restrict__ render,
     const int64_t HW = int64_t(t.width) * t.height;
     const int64_t pix = int64_t(py) * t.width + px;
     const float inv = 1.f / (3.f * float(HW));
-    for (int c = 0; c < 3; ++c) {
+    Halo<TW, 3> hv;
+    auto fetch = [&](int c) {
         const float *mp = maps + 9 * t.pix_offset + (3 * c) * HW;
+        const float *const planes[3] = {mp, mp + HW, mp + 2 * HW};
+        fetch_halo<TW, 3>(planes, t.width, t.height, x0, y0, hv);
+    };
+    float *const dst[3] = {L.sm[0], L.sm[1], L.sm[2]};
+    fetch(0);
+    for (int c = 0; c < 3; ++c) {
+        __syncthreads();   // the previous channel's reads of the windows are done
+        put_halo<TW, 3>(hv, dst);
         __syncthreads();
-        for (int k = 0; k < 3; ++k) load_halo<TW>(mp + k * HW, t.width, t.height, x0, y0, L.sm[k]);
-        __syncthreads();
-        for (int i = tid; i < HY * TW; i += blockDim.x) {
+        if (c + 1 < 3) fetch(c + 1);
+#pragma unroll
+        for (int i = tid; i < HY * TW; i += kTilePix) {
             const int r = i / TW, cc = i % TW;
             const int o = r * HS + cc;
             float a0 = 0, a1 = 0, a2 = 0;
@@ -282,7 +319,9 @@ __device__ __forceinline__ void ssim_bwd_tile(const float *__restrict__ render,
 // of loss_few_kernel, one launch fewer).
 constexpr int kLossOneBlockTargets = 8;
 template <bool kFold>
-__global__ void __launch_bounds__(256) ssim_bwd_kernel(const float *__restrict__ render,
+// (62 VGPRs: seven workgroups per CU, as many as its LDS allows; without the
+// hint the prefetched windows take it to 95 and five)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) ssim_bwd_kernel(const float *__restrict__ render,
                                                        const float *__restrict__ target,
                                                        const gs_target *__restrict__ targets,
                                                        int n_targets, int total_tiles, Window win,

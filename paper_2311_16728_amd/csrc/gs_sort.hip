@@ -434,6 +434,7 @@ emit_kernel(int64_t n_cap, int32_t n_views, const gs_target *__restrict__ target
             uint32_t *__restrict__ d_status) {
     __shared__ uint32_t off[kEmitChunk];
     __shared__ uint32_t srcs[kEmitChunk];            // record ids, staged with the offsets
+    __shared__ uint2 srect[kOne ? kEmitChunk : 1];   // kOne: the records' tile rectangles
     __shared__ uint32_t mark[kEmitChunk / 32];       // bit per slot: a record starts there
     __shared__ uint32_t lds[8];
     // the view offsets and, per listed target, its tile offset and row length,
@@ -488,13 +489,25 @@ emit_kernel(int64_t n_cap, int32_t n_views, const gs_target *__restrict__ target
                                 : V - 1u;
         __syncthreads();
         if (tid < kEmitChunk / 32) mark[tid] = 0u;
+        uint32_t sv[kEmitPer];
 #pragma unroll
         for (int r = 0; r < kEmitPer; ++r) {
             const int i = tid + r * kScanThreads;
             const uint32_t j = j0 + uint32_t(i);
             const bool in = j <= j1 && j < V;
             off[i] = in ? vis_off[j] : 0xffffffffu;
-            srcs[i] = in ? vis_val[j] : 0u;
+            sv[r] = in ? vis_val[j] : 0u;
+            srcs[i] = sv[r];
+        }
+        if (kOne) {   // every record's rectangle, loaded once per chunk with the others in flight
+#pragma unroll
+            for (int r = 0; r < kEmitPer; ++r) {
+                const int i = tid + r * kScanThreads;
+                const uint32_t j = j0 + uint32_t(i);
+                const bool in = j <= j1 && j < V;
+                const uint2 rc = rects[in ? sv[r] - one_vbase : 0u];
+                srect[i] = in ? rc : make_uint2(kEmptyRectX, 0u);
+            }
         }
         __syncthreads();
         // records after the first start strictly after o0
@@ -532,7 +545,7 @@ emit_kernel(int64_t n_cap, int32_t n_views, const gs_target *__restrict__ target
                     cur = rec;
                     src = srcs[rec];
                     base = off[rec];
-                    rcc[0] = rects[src - one_vbase];
+                    rcc[0] = srect[rec];
                 }
                 const uint32_t k = o - base;
                 const uint32_t x0 = rcc[0].x & 0xffffu, x1 = rcc[0].x >> 16, y0 = rcc[0].y & 0xffffu;
