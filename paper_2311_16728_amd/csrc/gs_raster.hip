@@ -94,12 +94,25 @@ __device__ __forceinline__ float clamp_alpha(float at, float amax) {
     return __builtin_amdgcn_fmed3f(at, 0.f, amax);
 }
 
-// Opacity of a staged Gaussian at offset (dx, dy) = mean - pixel.  The same
-// instruction sequence serves the forward and the backward, so both take the
-// same alpha_min decision.
+// Staged records hold the conic in exponent form: A.z = -a / 2, A.w = -b,
+// B.x = -c / 2 for the conic (a, b, c) of stage_record (exact: a power of two
+// and a sign), so the exponent -(a dx^2 + 2 b dx dy + c dy^2) / 2 takes five
+// operations.  conic_a/b/c give the conic back, exactly.
+__device__ __forceinline__ void to_exponent_form(float4 &A, float4 &B) {
+    A.z *= -0.5f;
+    A.w = -A.w;
+    B.x *= -0.5f;
+}
+__device__ __forceinline__ float conic_a(const float4 &A) { return -2.f * A.z; }
+__device__ __forceinline__ float conic_b(const float4 &A) { return -A.w; }
+__device__ __forceinline__ float conic_c(const float4 &B) { return -2.f * B.x; }
+
+// Exponent of a staged Gaussian at offset (dx, dy) = mean - pixel:
+// dx (A.z dx) + dy (A.w dx + B.x dy).  The same instruction sequence serves
+// the forward and the backward, so both take the same alpha_min decision.
 __device__ __forceinline__ float eval_power(const float4 &A, const float4 &B, float dx, float dy) {
-    const float q = fmaf(A.z * dx, dx, B.x * dy * dy);
-    return fmaf(-0.5f, q, -(A.w * dx * dy));
+    const float u = fmaf(A.w, dx, B.x * dy);
+    return fmaf(A.z * dx, dx, u * dy);
 }
 
 // Per-pixel transmittance store of the store-all variant (the comparison
@@ -175,6 +188,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) r
             if (tid < batch && idx < range.y) {
                 stage_record(s, proj, n_cap, t.view, t.level, ox, oy, srt.pair_val[idx], A, B, Cc, rec);
                 keep = touches_tile(A, B, Cc, ts);
+                to_exponent_form(A, B);
             }
             uint32_t cnt;
             const uint32_t at_pos = block_exclusive_scan(keep ? 1u : 0u, scan_lds, &cnt);
@@ -206,10 +220,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) r
                     const bool stop = hit && Tn < s.t_min;
                     const bool comp = hit && !stop;
                     if (kStore && store_at && comp) store_at[int64_t(nc) * kTilePix] = T;
-                    const float w = alpha * T;
-                    C0 = comp ? fmaf(w, B.z, C0) : C0;
-                    C1 = comp ? fmaf(w, B.w, C1) : C1;
-                    C2 = comp ? fmaf(w, Cj.x, C2) : C2;
+                    // a Gaussian that does not composite adds 0 x colour:
+                    // colours and sums are finite and >= 0, so the sums keep
+                    // their bits
+                    const float w = comp ? alpha * T : 0.f;
+                    C0 = fmaf(w, B.z, C0);
+                    C1 = fmaf(w, B.w, C1);
+                    C2 = fmaf(w, Cj.x, C2);
                     T = comp ? Tn : T;
                     if (kCount || kStore) nc += comp ? 1 : 0;
                     lj = comp ? j : lj;
@@ -458,6 +475,7 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
                 stage_record(s, proj, n_cap, t.view, t.level, ox, oy, srt.pair_val[range.x + start + tid],
                              A, Bv, Cc, rec);
                 keep = touches_tile(A, Bv, Cc, ts);
+                to_exponent_form(A, Bv);
             }
             uint32_t cnt;
             const uint32_t at_pos = block_count_n<kThreads>(keep, scan_lds, &cnt);
@@ -475,6 +493,7 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
                 const float4 Bv = sB[k];
                 const float2 Ck = sC[k];
                 const int pos = sPos[k];
+                const float ca = conic_a(A), cb = conic_b(A), cc = conic_c(Bv);
                 // sums start at -0: -0 + x and -0 - x are exactly x and -x,
                 // so the first pixel's terms need no add (from +0 they would:
                 // +0 + -0 is +0)
@@ -514,8 +533,8 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
                         const float dat = (at < amax) ? dal : 0.f;
                         v[5] = fmaf(ep, dat, v[5]);
                         const float ndp = -(at * dat);
-                        v[0] = fmaf(ndp, fmaf(A.z, dx, A.w * dy), v[0]);
-                        v[1] = fmaf(ndp, fmaf(A.w, dx, Bv.x * dy), v[1]);
+                        v[0] = fmaf(ndp, fmaf(ca, dx, cb * dy), v[0]);
+                        v[1] = fmaf(ndp, fmaf(cb, dx, cc * dy), v[1]);
                         v[2] = fmaf(0.5f * ndp * dx, dx, v[2]);
                         v[3] = fmaf(ndp * dx, dy, v[3]);
                         v[4] = fmaf(0.5f * ndp * dy, dy, v[4]);
@@ -573,7 +592,7 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
                     for (int w = 0; w < kWaves; ++w) sum += red[w][k][i];
                     v[i] = sum;
                 }
-                const float a = sA[k].z, b = sA[k].w, c = sB[k].x;
+                const float a = conic_a(sA[k]), b = conic_b(sA[k]), c = conic_c(sB[k]);
                 const float ga = v[2], gb = 0.5f * v[3], gc = v[4];
                 const float k00 = a * ga + b * gb, k01 = a * gb + b * gc;
                 const float k10 = b * ga + c * gb, k11 = b * gb + c * gc;

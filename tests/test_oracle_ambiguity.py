@@ -232,8 +232,11 @@ def _evaluate(rec, cam, settings, mode, rng=None, plain=None):
             dx = (mx - (px % 16).astype(F32)[:, None]).astype(F32)
             dy = (my - (py % 16).astype(F32)[:, None]).astype(F32)
             A, B, Cc = a[sel][None, :], b[sel][None, :], c[sel][None, :]
-            q = _fma32((A * dx).astype(F32), dx, (Cc * dy * dy).astype(F32))
-            pw = _fma32(np.full_like(q, F32(-0.5)), q, -(B * dx * dy).astype(F32))
+            # the conic in exponent form (-a/2, -b, -c/2: exact), then the
+            # kernels' five operations dx (A dx) + dy (B dx + C dy)
+            Ae, Be, Ce = (F32(-0.5) * A).astype(F32), (-B).astype(F32), (F32(-0.5) * Cc).astype(F32)
+            u = _fma32(np.broadcast_to(Be, dx.shape), dx, (Ce * dy).astype(F32))
+            pw = _fma32((Ae * dx).astype(F32), dx, (u * dy).astype(F32))
             contrib = pw >= thr[sel][None, :]
             at = (o[sel][None, :] * np.exp(pw).astype(F32)).astype(F32)
             alpha = np.where(contrib, np.minimum(F32(a_max), at), F32(0)).astype(F32)
