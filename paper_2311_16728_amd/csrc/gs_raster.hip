@@ -115,6 +115,33 @@ __device__ __forceinline__ float eval_power(const float4 &A, const float4 &B, fl
     return fmaf(A.z * dx, dx, u * dy);
 }
 
+// Block-wide count of `flag` for kThreads threads (a multiple of 64): the
+// number of threads before this one where it holds (ballots, no scan), and
+// the block total.
+template <int kThreads>
+__device__ __forceinline__ uint32_t block_count_n(bool flag, uint32_t *lds, uint32_t *total) {
+    constexpr int kW = kThreads / kWave;
+    const uint64_t m = __ballot(flag);
+    const uint32_t below = uint32_t(mask_rank(m));
+    if (kW == 1) {
+        *total = uint32_t(__popcll(m));
+        return below;
+    }
+    const int wave = threadIdx.x / kWave;
+    if (lane_id() == 0) lds[wave] = uint32_t(__popcll(m));
+    __syncthreads();
+    uint32_t base = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < kW; ++w) {
+        const uint32_t s = lds[w];
+        base += (w < wave) ? s : 0u;
+        all += s;
+    }
+    __syncthreads();
+    *total = all;
+    return base + below;
+}
+
 // Per-pixel transmittance store of the store-all variant (the comparison
 // point of the recompute backward): the transmittance in front of a pixel's
 // k-th composited Gaussian sits at base[tile] + k * 256 + (pixel in tile), so
@@ -191,7 +218,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) r
                 to_exponent_form(A, B);
             }
             uint32_t cnt;
-            const uint32_t at_pos = block_exclusive_scan(keep ? 1u : 0u, scan_lds, &cnt);
+            const uint32_t at_pos = block_count_n<kTilePix>(keep, scan_lds, &cnt);
             if (keep) {
                 sA[at_pos] = A;
                 sB[at_pos] = B;
@@ -308,32 +335,6 @@ __device__ __forceinline__ float dpp_add(float v) {
     return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, kRowMask, 0xf, false));
 }
 
-// Block-wide count of `flag` for kThreads threads (a multiple of 64): the
-// number of threads before this one where it holds (ballots, no scan), and
-// the block total.
-template <int kThreads>
-__device__ __forceinline__ uint32_t block_count_n(bool flag, uint32_t *lds, uint32_t *total) {
-    constexpr int kW = kThreads / kWave;
-    const uint64_t m = __ballot(flag);
-    const uint32_t below = uint32_t(mask_rank(m));
-    if (kW == 1) {
-        *total = uint32_t(__popcll(m));
-        return below;
-    }
-    const int wave = threadIdx.x / kWave;
-    if (lane_id() == 0) lds[wave] = uint32_t(__popcll(m));
-    __syncthreads();
-    uint32_t base = 0, all = 0;
-#pragma unroll
-    for (int w = 0; w < kW; ++w) {
-        const uint32_t s = lds[w];
-        base += (w < wave) ? s : 0u;
-        all += s;
-    }
-    __syncthreads();
-    *total = all;
-    return base + below;
-}
 
 // Backward raster with kWaves waves per 16x16 tile; every lane owns
 // kPix = 4 / kWaves pixels (rows spaced by 4 * kWaves), so the per-Gaussian

@@ -145,6 +145,29 @@ def test_wide_tile_sort_equals_per_target():
         assert torch.equal(one.plane(one.T, 0), big.plane(big.T, v)), v
 
 
+def test_group_scan_path_equals_per_target_bitwise():
+    """Two room views of 600k Gaussians: 4,688 count workgroups, more than the
+    compaction sums by itself (4,096), so the two-view binning scans the
+    workgroup counts first, while each view alone (2,344 workgroups) takes the
+    self-summing path.  Images and transmittance agree bitwise."""
+    n = 600_000
+    p, _, cams = scenes.room_scene(3, n, n_keyframes=2, width=320, height=180, f=160.0)
+    P = _dev(p)
+    big = plan_for(cams, n_cap=p.shape[1], pair_cap=1 << 23)
+    assert big.n_views * ((big.n_cap + 255) // 256) > 4096
+    big.render(P, n)
+    torch.cuda.synchronize()
+    assert not big.overflowed()
+    for v, cam in enumerate(cams):
+        one = plan_for([cam], n_cap=p.shape[1], pair_cap=1 << 23)
+        one.render(P, n)
+        torch.cuda.synchronize()
+        assert not one.overflowed()
+        assert torch.equal(one.image(one.rgb, 0), big.image(big.rgb, v)), v
+        assert torch.equal(one.plane(one.T, 0), big.plane(big.T, v)), v
+    assert float(big.rgb.abs().sum()) > 0
+
+
 def test_many_targets_equal_per_target_bitwise():
     """400 views x 3 levels = 1,200 targets: more views and listed targets than
     the binning keeps in LDS (256) and more targets than one staging pass of
