@@ -94,20 +94,25 @@ __device__ __forceinline__ float clamp_alpha(float at, float amax) {
     return __builtin_amdgcn_fmed3f(at, 0.f, amax);
 }
 
-// Staged records hold the conic in exponent form: A.z = -a / 2, A.w = -b,
-// B.x = -c / 2 for the conic (a, b, c) of stage_record (exact: a power of two
-// and a sign), so the exponent -(a dx^2 + 2 b dx dy + c dy^2) / 2 takes five
-// operations.  conic_a/b/c give the conic back, exactly.
-__device__ __forceinline__ void to_exponent_form(float4 &A, float4 &B) {
-    A.z *= -0.5f;
-    A.w = -A.w;
-    B.x *= -0.5f;
+// Staged records hold the conic in base-2 exponent form: A.z = -a log2(e) / 2,
+// A.w = -b log2(e), B.x = -c log2(e) / 2 for the conic (a, b, c) of
+// stage_record, and the cutoff C.y = ln(alpha_min / opacity) log2(e), so the
+// exponent in base 2, -(a dx^2 + 2 b dx dy + c dy^2) log2(e) / 2, takes five
+// operations and goes to the hardware exp2 as it is.  conic_a/b/c give the
+// conic back (to a rounding or two: the gradients use it, the compositing
+// decisions do not).
+constexpr float kLog2e = 1.44269504088896341f, kLn2 = 0.693147180559945309f;
+__device__ __forceinline__ void to_exponent_form(float4 &A, float4 &B, float2 &C) {
+    A.z *= -0.5f * kLog2e;
+    A.w *= -kLog2e;
+    B.x *= -0.5f * kLog2e;
+    C.y *= kLog2e;
 }
-__device__ __forceinline__ float conic_a(const float4 &A) { return -2.f * A.z; }
-__device__ __forceinline__ float conic_b(const float4 &A) { return -A.w; }
-__device__ __forceinline__ float conic_c(const float4 &B) { return -2.f * B.x; }
+__device__ __forceinline__ float conic_a(const float4 &A) { return A.z * (-2.f * kLn2); }
+__device__ __forceinline__ float conic_b(const float4 &A) { return A.w * -kLn2; }
+__device__ __forceinline__ float conic_c(const float4 &B) { return B.x * (-2.f * kLn2); }
 
-// Exponent of a staged Gaussian at offset (dx, dy) = mean - pixel:
+// Base-2 exponent of a staged Gaussian at offset (dx, dy) = mean - pixel:
 // dx (A.z dx) + dy (A.w dx + B.x dy).  The same instruction sequence serves
 // the forward and the backward, so both take the same alpha_min decision.
 __device__ __forceinline__ float eval_power(const float4 &A, const float4 &B, float dx, float dy) {
@@ -215,7 +220,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) r
             if (tid < batch && idx < range.y) {
                 stage_record(s, proj, n_cap, t.view, t.level, ox, oy, srt.pair_val[idx], A, B, Cc, rec);
                 keep = touches_tile(A, B, Cc, ts);
-                to_exponent_form(A, B);
+                to_exponent_form(A, B, Cc);
             }
             uint32_t cnt;
             const uint32_t at_pos = block_count_n<kTilePix>(keep, scan_lds, &cnt);
@@ -242,7 +247,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) r
                     const float pw = eval_power(A, B, dx, dy);
                     if (kCount) ne += done ? 0 : 1;
                     const bool hit = !done && !(pw < Cj.y);
-                    const float alpha = clamp_alpha(B.y * __expf(pw), amax);
+                    const float alpha = clamp_alpha(B.y * __builtin_amdgcn_exp2f(pw), amax);
                     const float Tn = T * (1.f - alpha);
                     const bool stop = hit && Tn < s.t_min;
                     const bool comp = hit && !stop;
@@ -476,7 +481,7 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
                 stage_record(s, proj, n_cap, t.view, t.level, ox, oy, srt.pair_val[range.x + start + tid],
                              A, Bv, Cc, rec);
                 keep = touches_tile(A, Bv, Cc, ts);
-                to_exponent_form(A, Bv);
+                to_exponent_form(A, Bv, Cc);
             }
             uint32_t cnt;
             const uint32_t at_pos = block_count_n<kThreads>(keep, scan_lds, &cnt);
@@ -508,7 +513,7 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
                     const float pw = eval_power(A, Bv, dx, dy);
                     if (pos < last[i] && !(pw < Ck.y)) {
                         any = true;
-                        const float ep = __expf(pw);
+                        const float ep = __builtin_amdgcn_exp2f(pw);
                         const float at = Bv.y * ep;
                         const float alpha = clamp_alpha(at, amax);
                         const float oma = 1.f - alpha;

@@ -72,6 +72,9 @@ def _cases(orc):
     yield ("saturated",) + _room_view()
 
 
+LOG2E = 1.4426950408889634
+
+
 def _fma32(a, b, c):
     """float32 fused multiply-add: the float32 product is exact in float64."""
     return (a.astype(np.float64) * b.astype(np.float64) + c.astype(np.float64)).astype(F32)
@@ -232,13 +235,16 @@ def _evaluate(rec, cam, settings, mode, rng=None, plain=None):
             dx = (mx - (px % 16).astype(F32)[:, None]).astype(F32)
             dy = (my - (py % 16).astype(F32)[:, None]).astype(F32)
             A, B, Cc = a[sel][None, :], b[sel][None, :], c[sel][None, :]
-            # the conic in exponent form (-a/2, -b, -c/2: exact), then the
-            # kernels' five operations dx (A dx) + dy (B dx + C dy)
-            Ae, Be, Ce = (F32(-0.5) * A).astype(F32), (-B).astype(F32), (F32(-0.5) * Cc).astype(F32)
+            # the conic and the cutoff in base-2 exponent form (scaled by
+            # -log2(e)/2, -log2(e), -log2(e)/2 and log2(e) in float32), then
+            # the kernels' five operations dx (A dx) + dy (B dx + C dy)
+            Ae = (F32(-0.5 * LOG2E) * A).astype(F32)
+            Be = (F32(-LOG2E) * B).astype(F32)
+            Ce = (F32(-0.5 * LOG2E) * Cc).astype(F32)
             u = _fma32(np.broadcast_to(Be, dx.shape), dx, (Ce * dy).astype(F32))
             pw = _fma32((Ae * dx).astype(F32), dx, (u * dy).astype(F32))
-            contrib = pw >= thr[sel][None, :]
-            at = (o[sel][None, :] * np.exp(pw).astype(F32)).astype(F32)
+            contrib = pw >= (thr[sel] * F32(LOG2E)).astype(F32)[None, :]
+            at = (o[sel][None, :] * np.exp2(pw).astype(F32)).astype(F32)
             alpha = np.where(contrib, np.minimum(F32(a_max), at), F32(0)).astype(F32)
         dtp = np.float64 if mode == "fp64" else F32
         fac = (dtp(1) - alpha).astype(dtp)
