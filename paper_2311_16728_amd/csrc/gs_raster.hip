@@ -408,7 +408,11 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
         const float *dLt = dL_drgb + 3 * t.pix_offset;
         float *tb = tbuf[wave];
 
-        float T[kPix], g0[kPix], g1[kPix], g2[kPix], B0[kPix], B1[kPix], B2[kPix], fpy[kPix];
+        // S: the colour behind the current Gaussian (what the pixel shows
+        // from there on, background included, at unit transmittance) dotted
+        // with dL/dC; only that dot product enters the gradient, so the
+        // colour itself is never formed
+        float T[kPix], g0[kPix], g1[kPix], g2[kPix], S[kPix], fpy[kPix];
         int32_t last[kPix];
         int32_t kc[kPix];             // kStored: composited Gaussians not yet walked back
         const float *srow = nullptr;  // kStored: this tile's store
@@ -442,7 +446,7 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
             // a restart position never exceeds the tile's list (guards stale input)
             last[i] = min(last[i], int32_t(range.y - range.x));
             my_max = max(my_max, last[i]);
-            B0[i] = t.bg[0]; B1[i] = t.bg[1]; B2[i] = t.bg[2];   // colour behind, unit transmittance
+            S[i] = fmaf(t.bg[0], g0[i], fmaf(t.bg[1], g1[i], t.bg[2] * g2[i]));   // the background
         }
         if (tid == 0) sMaxLast = 0;
         __syncthreads();
@@ -499,7 +503,6 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
                 const float4 Bv = sB[k];
                 const float2 Ck = sC[k];
                 const int pos = sPos[k];
-                const float ca = conic_a(A), cb = conic_b(A), cc = conic_c(Bv);
                 // sums start at -0: -0 + x and -0 - x are exactly x and -x,
                 // so the first pixel's terms need no add (from +0 they would:
                 // +0 + -0 is +0)
@@ -526,24 +529,27 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
                         // (the gradient sums use explicit FMAs: the build does
                         // not contract, so that both passes take the cutoff
                         // decisions with the same instructions)
-                        const float r = Bv.z, gg = Bv.w, bb = Ck.x;
-                        const float dal =
-                            T[i] * fmaf(r - B0[i], g0[i], fmaf(gg - B1[i], g1[i], (bb - B2[i]) * g2[i]));
+                        // dL/dalpha = T (c - colour behind) . dL/dC
+                        const float cg = fmaf(Bv.z, g0[i], fmaf(Bv.w, g1[i], Ck.x * g2[i]));
+                        const float dal = T[i] * (cg - S[i]);
                         const float w = alpha * T[i];
                         v[6] = fmaf(w, g0[i], v[6]);
                         v[7] = fmaf(w, g1[i], v[7]);
                         v[8] = fmaf(w, g2[i], v[8]);
-                        B0[i] = fmaf(alpha, r, oma * B0[i]);
-                        B1[i] = fmaf(alpha, gg, oma * B1[i]);
-                        B2[i] = fmaf(alpha, bb, oma * B2[i]);
+                        S[i] = fmaf(alpha, cg, oma * S[i]);
                         const float dat = (at < amax) ? dal : 0.f;
                         v[5] = fmaf(ep, dat, v[5]);
+                        // ndp = dL/d(exponent); the sums 0-4 are its moments
+                        // over the pixel offsets (sum ndp d, sum ndp d d^T),
+                        // which the conic turns into the mean and conic
+                        // gradients once per Gaussian
                         const float ndp = -(at * dat);
-                        v[0] = fmaf(ndp, fmaf(ca, dx, cb * dy), v[0]);
-                        v[1] = fmaf(ndp, fmaf(cb, dx, cc * dy), v[1]);
-                        v[2] = fmaf(0.5f * ndp * dx, dx, v[2]);
-                        v[3] = fmaf(ndp * dx, dy, v[3]);
-                        v[4] = fmaf(0.5f * ndp * dy, dy, v[4]);
+                        const float nx = ndp * dx, ny = ndp * dy;
+                        v[0] += nx;
+                        v[1] += ny;
+                        v[2] = fmaf(nx, dx, v[2]);
+                        v[3] = fmaf(nx, dy, v[3]);
+                        v[4] = fmaf(ny, dy, v[4]);
                     }
                 }
                 const uint64_t act = __ballot(any);
@@ -599,12 +605,14 @@ __global__ void __launch_bounds__(64 * kWaves) render_bwd_kernel(
                     v[i] = sum;
                 }
                 const float a = conic_a(sA[k]), b = conic_b(sA[k]), c = conic_c(sB[k]);
-                const float ga = v[2], gb = 0.5f * v[3], gc = v[4];
+                // mean gradient K (sum ndp d); conic gradient (sum ndp d d^T) / 2
+                const float P = v[0], Q = v[1];
+                const float ga = 0.5f * v[2], gb = 0.5f * v[3], gc = 0.5f * v[4];
                 const float k00 = a * ga + b * gb, k01 = a * gb + b * gc;
                 const float k10 = b * ga + c * gb, k11 = b * gb + c * gc;
                 const float s2 = sc * sc;
-                v[0] *= sc;
-                v[1] *= sc;
+                v[0] = (a * P + b * Q) * sc;
+                v[1] = (b * P + c * Q) * sc;
                 v[2] = -(k00 * a + k01 * b) * s2;
                 v[3] = -(k00 * b + k01 * c) * s2;
                 v[4] = -(k10 * b + k11 * c) * s2;
