@@ -70,13 +70,16 @@ __host__ __device__ constexpr int halo_rounds() {
 }
 template <int TW, int kP>
 struct Halo {
-    float v[kP][halo_rounds<TW>()];
+    float v[kP][halo_rounds<TW>()];   // as loaded (clamped address)
+    uint32_t in;                      // bit r: round r's pixel lies in the image
 };
 template <int TW, int kP>
 __device__ __forceinline__ void fetch_halo(const float *const (&planes)[kP], int W, int H, int x0, int y0,
                                            Halo<TW, kP> &hv) {
     constexpr int TH = kTilePix / TW, HX = TW + 2 * kR, HY = TH + 2 * kR;
     constexpr int kRounds = halo_rounds<TW>();
+    static_assert(kRounds <= 32, "one bit per round");
+    hv.in = 0u;
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
         const int i = threadIdx.x + r * kTilePix;
@@ -84,11 +87,10 @@ __device__ __forceinline__ void fetch_halo(const float *const (&planes)[kP], int
         const int gx = x0 - kR + xx, gy = y0 - kR + yy;
         const bool in = i < HX * HY && gx >= 0 && gx < W && gy >= 0 && gy < H;
         const int64_t at = int64_t(min(max(gy, 0), H - 1)) * W + min(max(gx, 0), W - 1);
+        hv.in |= uint32_t(in) << r;
+        // (zeroed when put, so that nothing waits for the loads before then)
 #pragma unroll
-        for (int p = 0; p < kP; ++p) {
-            const float x = planes[p][at];
-            hv.v[p][r] = in ? x : 0.f;
-        }
+        for (int p = 0; p < kP; ++p) hv.v[p][r] = planes[p][at];
     }
 }
 template <int TW, int kP>
@@ -98,8 +100,9 @@ __device__ __forceinline__ void put_halo(const Halo<TW, kP> &hv, float *const (&
     for (int r = 0; r < halo_rounds<TW>(); ++r) {
         const int i = threadIdx.x + r * kTilePix;
         if (i < HX * HY) {
+            const bool in = (hv.in >> r) & 1u;
 #pragma unroll
-            for (int p = 0; p < kP; ++p) dst[p][(i / HX) * HS + i % HX] = hv.v[p][r];
+            for (int p = 0; p < kP; ++p) dst[p][(i / HX) * HS + i % HX] = in ? hv.v[p][r] : 0.f;
         }
     }
 }
@@ -194,7 +197,8 @@ __device__ __forceinline__ void ssim_fwd_tile(const float *__restrict__ render,
     }
 }
 
-__global__ void __launch_bounds__(256) ssim_fwd_kernel(const float *__restrict__ render,
+// (seven workgroups per CU, as many as its LDS allows)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) ssim_fwd_kernel(const float *__restrict__ render,
                                                        const float *__restrict__ target,
                                                        const gs_target *__restrict__ targets,
                                                        int n_targets, int total_tiles, Window win,

@@ -9,10 +9,12 @@
 // pixel then reads the batch as LDS broadcasts.  The forward keeps, per
 // pixel, only the final transmittance and one past the list position of the
 // last composited Gaussian; the backward restarts from those, divides the
-// transmittance back out Gaussian by Gaussian, and keeps a running colour of
-// what lies behind, so no per-pixel list is stored.  Gradients of the nine 2D
-// quantities are summed over the tile in registers, DPP and LDS and committed
-// with one atomic per quantity per tile.
+// transmittance back out Gaussian by Gaussian, and keeps a running dot
+// product of what lies behind with dL/dC, so no per-pixel list is stored.
+// Per Gaussian it sums over the tile's pixels the moments of dL/d(exponent)
+// over the pixel offsets and the opacity and colour terms (registers, DPP
+// and LDS), turns the moments into the gradients of the nine 2D quantities,
+// and commits them with one atomic per quantity per tile.
 #include "gs_internal.hpp"
 
 #include <atomic>
