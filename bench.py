@@ -810,7 +810,8 @@ def main_realistic(args, torch):
     del ref
     view_dev = [gs.to_device_struct_array((gs.gs_view * 1)(gs.make_view(c)), torch.device("cuda"))
                 for c in cams]
-    settings = gs.default_settings(batch=args.batch or 128, bwd_waves=args.bwd_waves or 1)
+    # backward waves per tile: as given, else chosen per plan from its tile count
+    settings = gs.default_settings(batch=args.batch or 128, bwd_waves=args.bwd_waves or 0)
     # schedule mode: one plan per level; all-levels mode: one plan with the three levels
     lvl_plans = [RenderPlan([cams[0]], [(0, l, (0.0, 0.0, 0.0), 1.0)], n_cap, args.pair_cap, settings)
                  for l in range(levels)]
@@ -915,8 +916,10 @@ def main_realistic(args, torch):
         "schedule_mode": {"iters_per_s": round(args.steps / ms_gp * 1e3, 2),
                           "level_ms": {str(k): round(v, 4) for k, v in lv_ms.items()},
                           "levels_used": {str(l): sched_levels.count(l) for l in range(levels)},
+                          "bwd_waves": {str(l): lvl_plans[l].settings.bwd_waves for l in range(levels)},
                           "psnr_db": round(psnr_gp, 3)},
-        "all_levels_mode": {"iters_per_s": round(args.steps / ms_ml * 1e3, 2), "psnr_db": round(psnr_ml, 3)},
+        "all_levels_mode": {"iters_per_s": round(args.steps / ms_ml * 1e3, 2), "psnr_db": round(psnr_ml, 3),
+                            "bwd_waves": ml_plan.settings.bwd_waves},
         "start_psnr_db": round(psnr_start, 3),
         "stage_ms_level0": {k: round(float(v), 4) for k, v in zip(STAGES, stage_ms)},
         "roofline": roofline,

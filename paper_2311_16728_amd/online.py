@@ -44,6 +44,8 @@ class OnlineMapper:
         self.levels = levels
         self.schedule = PyramidSchedule(levels, tau)
         n_cap = params.shape[1]
+        if settings is None:   # the backward's waves per tile chosen per level (auto_bwd_waves)
+            settings = gs.default_settings(bwd_waves=0)
         self.plans = [RenderPlan([self.cams[0]], [(0, l, (0.0, 0.0, 0.0), 1.0)], n_cap, pair_cap, settings, dev)
                       for l in range(levels)]
         self.view_dev = [gs.to_device_struct_array((gs.gs_view * 1)(gs.make_view(c)), dev) for c in self.cams]

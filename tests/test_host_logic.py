@@ -87,6 +87,16 @@ def test_pyramid_schedule_coarse_to_fine():
         PyramidSchedule(levels=0)
 
 
+def test_auto_backward_waves_by_tile_count():
+    """Plans that leave the backward's waves per tile open get one wave from
+    1,536 tiles on, two from 512, else four (the three pyramid levels of a
+    1200x680 keyframe: 3,225 / 836 / 209 tiles)."""
+    from paper_2311_16728_amd.mapper import auto_bwd_waves
+
+    assert [auto_bwd_waves(t) for t in (3225, 836, 209)] == [1, 2, 4]
+    assert [auto_bwd_waves(t) for t in (1536, 1535, 512, 511, 1)] == [1, 2, 2, 4, 4]
+
+
 def test_tile_shapes_in_layout():
     from paper_2311_16728_amd import gs
 
