@@ -107,7 +107,7 @@ __device__ __forceinline__ void put_halo(const Halo<TW, kP> &hv, float *const (&
     }
 }
 
-struct SsimLds {
+struct alignas(16) SsimLds {
     float sx[kHaloMax];
     float sy[kHaloMax];
     float h[5][kHPassMax];
@@ -142,21 +142,37 @@ __device__ __forceinline__ void ssim_fwd_tile(const float *__restrict__ render,
         put_halo<TW, 2>(hv, dst);
         __syncthreads();
         if (c + 1 < 3) fetch(c + 1);
+        // two horizontally adjacent outputs per thread (one round for 16-
+        // and 8-wide tiles): each input and its products are formed once;
+        // every output sums its taps in the same order as one alone would
+        constexpr int kTaps = 2 * kR + 1;
 #pragma unroll
-        for (int i = tid; i < HY * TW; i += kTilePix) {
-            const int r = i / TW, cc = i % TW;
+        for (int s2 = tid; s2 < HY * (TW / 2); s2 += kTilePix) {
+            const int r = s2 / (TW / 2), cc = 2 * (s2 % (TW / 2));
             const float *rx = L.sx + r * HS + cc, *ry = L.sy + r * HS + cc;
-            float m1 = 0, m2 = 0, e11 = 0, e22 = 0, e12 = 0;
+            float m1[2] = {0, 0}, m2[2] = {0, 0}, e11[2] = {0, 0}, e22[2] = {0, 0}, e12[2] = {0, 0};
 #pragma unroll
-            for (int k = 0; k < 2 * kR + 1; ++k) {
-                const float a = rx[k], b = ry[k], w = win.w[k];
-                m1 = fmaf(w, a, m1);
-                m2 = fmaf(w, b, m2);
-                e11 = fmaf(w, a * a, e11);
-                e22 = fmaf(w, b * b, e22);
-                e12 = fmaf(w, a * b, e12);
+            for (int k = 0; k <= kTaps; ++k) {
+                const float a = rx[k], b = ry[k];
+                const float aa = a * a, bb = b * b, ab = a * b;
+#pragma unroll
+                for (int o = 0; o < 2; ++o) {
+                    const int t = k - o;   // tap of output o
+                    if (t < 0 || t >= kTaps) continue;
+                    const float w = win.w[t];
+                    m1[o] = fmaf(w, a, m1[o]);
+                    m2[o] = fmaf(w, b, m2[o]);
+                    e11[o] = fmaf(w, aa, e11[o]);
+                    e22[o] = fmaf(w, bb, e22[o]);
+                    e12[o] = fmaf(w, ab, e12[o]);
+                }
             }
-            L.h[0][i] = m1; L.h[1][i] = m2; L.h[2][i] = e11; L.h[3][i] = e22; L.h[4][i] = e12;
+            const int i = r * TW + cc;
+            *reinterpret_cast<float2 *>(&L.h[0][i]) = make_float2(m1[0], m1[1]);
+            *reinterpret_cast<float2 *>(&L.h[1][i]) = make_float2(m2[0], m2[1]);
+            *reinterpret_cast<float2 *>(&L.h[2][i]) = make_float2(e11[0], e11[1]);
+            *reinterpret_cast<float2 *>(&L.h[3][i]) = make_float2(e22[0], e22[1]);
+            *reinterpret_cast<float2 *>(&L.h[4][i]) = make_float2(e12[0], e12[1]);
         }
         __syncthreads();
         float mx = 0, my = 0, exx = 0, eyy = 0, exy = 0;
@@ -248,7 +264,7 @@ __device__ __forceinline__ void loss_of_target(const gs_target *__restrict__ tar
     __syncthreads();   // red is reused by the next call
 }
 
-struct SsimBwdLds {
+struct alignas(16) SsimBwdLds {
     float sm[3][kHaloMax];
     float h[3][kHPassMax];
 };
@@ -282,19 +298,30 @@ __device__ __forceinline__ void ssim_bwd_tile(const float *__restrict__ render,
         put_halo<TW, 3>(hv, dst);
         __syncthreads();
         if (c + 1 < 3) fetch(c + 1);
+        // two horizontally adjacent outputs per thread, each input read once
+        constexpr int kTaps = 2 * kR + 1;
 #pragma unroll
-        for (int i = tid; i < HY * TW; i += kTilePix) {
-            const int r = i / TW, cc = i % TW;
-            const int o = r * HS + cc;
-            float a0 = 0, a1 = 0, a2 = 0;
+        for (int s2 = tid; s2 < HY * (TW / 2); s2 += kTilePix) {
+            const int r = s2 / (TW / 2), cc = 2 * (s2 % (TW / 2));
+            const int base = r * HS + cc;
+            float a0[2] = {0, 0}, a1[2] = {0, 0}, a2[2] = {0, 0};
 #pragma unroll
-            for (int k = 0; k < 2 * kR + 1; ++k) {
-                const float w = win.w[k];
-                a0 = fmaf(w, L.sm[0][o + k], a0);
-                a1 = fmaf(w, L.sm[1][o + k], a1);
-                a2 = fmaf(w, L.sm[2][o + k], a2);
+            for (int k = 0; k <= kTaps; ++k) {
+                const float x0 = L.sm[0][base + k], x1 = L.sm[1][base + k], x2 = L.sm[2][base + k];
+#pragma unroll
+                for (int o = 0; o < 2; ++o) {
+                    const int t = k - o;
+                    if (t < 0 || t >= kTaps) continue;
+                    const float w = win.w[t];
+                    a0[o] = fmaf(w, x0, a0[o]);
+                    a1[o] = fmaf(w, x1, a1[o]);
+                    a2[o] = fmaf(w, x2, a2[o]);
+                }
             }
-            L.h[0][i] = a0; L.h[1][i] = a1; L.h[2][i] = a2;
+            const int i = r * TW + cc;
+            *reinterpret_cast<float2 *>(&L.h[0][i]) = make_float2(a0[0], a0[1]);
+            *reinterpret_cast<float2 *>(&L.h[1][i]) = make_float2(a1[0], a1[1]);
+            *reinterpret_cast<float2 *>(&L.h[2][i]) = make_float2(a2[0], a2[1]);
         }
         __syncthreads();
         float f0 = 0, f1 = 0, f2 = 0;
