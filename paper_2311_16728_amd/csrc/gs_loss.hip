@@ -190,14 +190,17 @@ __device__ __forceinline__ void ssim_fwd_tile(const float *__restrict__ render,
             const float vx = exx - mx * mx, vy = eyy - my * my, cxy = exy - mx * my;
             const float A1 = 2.f * mx * my + C1, A2 = 2.f * cxy + C2;
             const float B1 = mx * mx + my * my + C1, B2 = vx + vy + C2;
-            const float iB1B2 = 1.f / (B1 * B2);
+            // B1 >= C1 and B2 >= C2 (up to rounding of the variances): the
+            // hardware reciprocal (1 ulp) instead of four IEEE divisions
+            const float iB1 = __builtin_amdgcn_rcpf(B1), iB2 = __builtin_amdgcn_rcpf(B2);
+            const float iB1B2 = iB1 * iB2;
             const float S = A1 * A2 * iB1B2;
             ss += S;
             const int ci = (ly + kR) * HS + lx + kR;
             l1 += fabsf(L.sx[ci] - L.sy[ci]);
             float *mp = maps + 9 * t.pix_offset + (3 * c) * HW;
-            mp[pix] = 2.f * my * (A2 - A1) * iB1B2 - 2.f * mx * S * (1.f / B1 - 1.f / B2);
-            mp[HW + pix] = -S / B2;
+            mp[pix] = 2.f * my * (A2 - A1) * iB1B2 - 2.f * mx * S * (iB1 - iB2);
+            mp[HW + pix] = -S * iB2;
             mp[2 * HW + pix] = 2.f * A1 * iB1B2;
         }
     }
